@@ -1,0 +1,239 @@
+/*
+ * rcp.h -- C ABI of the recursive camera-painting renderer for MI355X (gfx950).
+ *
+ * Recursive camera painting (Akleman, Mullins, Morrison, Oh, "Recursive Camera
+ * Painting: A Method for Real-Time Painterly Renderings of 3D Scenes") renders
+ * K images I_1..I_K of one scene.  Every pixel (u,v) owns a camera: an eye
+ * P_e(u,v) and an image-plane point P_p(u,v), with ray direction
+ * N = (P_p - P_e) / |P_p - P_e| (Section 2).  Before pass n both points are
+ * displaced from their original positions by vectors computed from the
+ * previous image at the same pixel, I_n(u,v) = F(I_{n-1}(u,v), S)
+ * (Section 2).  The colour mapping of Section 3 uses
+ * V = lambda (2R-1, 2G-1, 2B-1) in the camera's local frame (R to the right,
+ * G up, B along the view axis), starting from the grey seed I_0 = 0.5, so
+ * I_1 is the ordinary ray-traced image.
+ *
+ * Conventions shared by every entry point:
+ *   - Images are float32, row-major [H][W][3] RGB, row 0 at the top of the
+ *     image.  K-image outputs are [K][H][W][3]; image 0 is I_1.
+ *   - Hit-ID planes are int32 [H][W] (or [K][H][W]): the index of the hit
+ *     triangle in the scene description, -1 where the ray missed.
+ *   - "device" pointers are HIP device allocations (hipMalloc, or torch CUDA
+ *     tensors on ROCm); "host" pointers are ordinary CPU memory.  Output
+ *     buffers are owned by the caller.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Rendering
+ *     calls are asynchronous: they enqueue work on the stream and return;
+ *     results are valid once the stream has been synchronised.  Argument
+ *     errors are reported before anything is enqueued.
+ *   - Every call returns an rcp_status; no exception crosses the ABI.
+ *     rcp_last_error() gives a message for the calling thread's last error.
+ *   - A scene may be used by one stream at a time: its render workspace is
+ *     shared by the calls made on it.
+ */
+#ifndef RCP_H
+#define RCP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RCP_OK = 0,
+    RCP_ERR_INVALID_ARGUMENT = 1,
+    RCP_ERR_OUT_OF_MEMORY = 2,
+    RCP_ERR_DEVICE = 3,
+    RCP_ERR_NOT_READY = 4,
+    RCP_ERR_QUEUE_FULL = 5,
+    RCP_ERR_INTERNAL = 6
+} rcp_status;
+
+/* Opaque scene: triangles, BVH and shading table resident in HBM. */
+typedef struct rcp_scene rcp_scene;
+
+/* Scene S of Section 2.  All pointers are HOST pointers; the data is copied
+ * during rcp_build_scene and may be freed afterwards.
+ *   verts      [n_verts][3] float32 positions
+ *   idx        [n_tris][3]  uint32 vertex indices (each < n_verts); the
+ *              geometric normal is cross(v1 - v0, v2 - v0)
+ *   tri_rgb    [n_tris][3]  float32 albedo per triangle
+ *   light_dir  unit vector pointing toward the directional light
+ *   k_a, k_d   ambient and diffuse weights of the Lambert shade
+ *   background colour of rays that hit nothing
+ * n_tris == 0 is allowed (every ray misses). */
+typedef struct {
+    const float* verts;
+    uint32_t n_verts;
+    const uint32_t* idx;
+    uint32_t n_tris;
+    const float* tri_rgb;
+    float light_dir[3];
+    float k_a, k_d;
+    float background[3];
+} rcp_scene_desc;
+
+/* Base pinhole camera: eye P_e, orthonormal basis (right, up, forward) and
+ * tan of half the vertical field of view.  The undisplaced image-plane point
+ * of pixel (x, y) is P_p = eye + forward + s right + t up with
+ * s = ((2x+1)/W - 1) tan_half_fovy W/H and t = (1 - (2y+1)/H) tan_half_fovy
+ * (the image plane sits one unit in front of the eye). */
+typedef struct {
+    float eye[3];
+    float right[3];
+    float up[3];
+    float forward[3];
+    float tan_half_fovy;
+} rcp_camera;
+
+/* Displacement mapping.  With w = (2R-1) right + (2G-1) up + (2B-1) forward
+ * computed from the previous colour of the pixel (Section 3):
+ *   V_e = lambda_eye w                  (eye displacement, Section 2)
+ *   V_p = (lambda_eye + lambda_dir) w   (image-plane displacement)
+ * so the displaced ray starts at eye + lambda_eye w with direction
+ * normalize(P_p - P_e + lambda_dir w).  Section 3's colour method keeps the
+ * eye fixed: (lambda_eye, lambda_dir) = (0, lambda).
+ * mode: RCP_MODE_COLOR (0) is the only mode; z0 is reserved and ignored.
+ * Valid ranges: finite, lambda_eye >= 0, 0 <= lambda_dir < 1. */
+typedef struct {
+    float lambda_eye;
+    float lambda_dir;
+    int32_t mode;
+    float z0;
+} rcp_displacement;
+
+#define RCP_MODE_COLOR 0
+
+/* Build options (NULL = defaults).  max_leaf: most triangles per BVH leaf
+ * (1..8, default 4); top_levels: BVH levels staged in LDS by the traversal
+ * (0..9, default 8); c_trav, c_isect: SAH costs of a node visit and a
+ * triangle test (defaults 1, 1). */
+typedef struct {
+    int32_t max_leaf;
+    int32_t top_levels;
+    float c_trav;
+    float c_isect;
+} rcp_build_options;
+
+/* Scene statistics filled by rcp_scene_info. */
+typedef struct {
+    uint32_t n_tris;
+    uint32_t n_nodes;        /* packed BVH2 nodes (64 B each) */
+    uint32_t n_leaves;
+    uint32_t top_count;      /* nodes staged in LDS */
+    uint32_t max_depth;      /* deepest node (root = 0) */
+    uint32_t max_leaf;
+    float sah_cost;          /* SAH cost of the packed tree, relative to the root box */
+    float build_ms;          /* device time of the build kernels */
+    uint64_t device_bytes;   /* HBM held by the scene */
+} rcp_scene_stats;
+
+/* ---------------------------------------------------------------------- */
+/* Scene                                                                   */
+/* ---------------------------------------------------------------------- */
+
+/* Copy the scene to the device and build its BVH (Morton codes, radix sort,
+ * binary radix tree, bottom-up refit with SAH leaf collapse, packing).  The
+ * call is synchronous: it returns once the scene is ready.  desc pointers
+ * are host pointers (see rcp_scene_desc); opts may be NULL.
+ * Errors: RCP_ERR_INVALID_ARGUMENT (NULL desc/out, idx >= n_verts, a
+ * non-finite vertex, light or background value, invalid options),
+ * RCP_ERR_OUT_OF_MEMORY, RCP_ERR_DEVICE.  On error *out is set to NULL. */
+rcp_status rcp_build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts,
+                           void* hip_stream, rcp_scene** out);
+
+/* Release the scene's device memory (synchronises the device first).
+ * NULL is ignored. */
+void rcp_destroy_scene(rcp_scene* scene);
+
+/* Fill *out with the scene's statistics (host pointer). */
+rcp_status rcp_scene_info(const rcp_scene* scene, rcp_scene_stats* out);
+
+/* ---------------------------------------------------------------------- */
+/* Rendering                                                               */
+/* ---------------------------------------------------------------------- */
+
+/* K-pass recursive camera painting (Section 2 recursion, Section 3 colour
+ * mapping): I_0 = 0.5 grey; for n = 1..K, every pixel's ray is displaced
+ * from the base camera using I_{n-1} at the same pixel, traced to the
+ * closest hit (nearest t, then lowest triangle index), and shaded.
+ *   out_images  device, [K][H][W][3] float32; receives I_1..I_K
+ *   out_ids     device, [K][H][W] int32 hit triangle or -1; may be NULL
+ * Pixels whose colour did not change between two passes keep it (the next
+ * ray would be identical) and drop out of the following passes.
+ * Requires W, H >= 1, 1 <= K <= 64, W * H <= 2^27, a unit orthogonal
+ * camera basis (|1 - |v|| <= 1e-5, |dot| <= 1e-5), tan_half_fovy > 0.
+ * Asynchronous on hip_stream. */
+rcp_status rcp_render(rcp_scene* scene, const rcp_camera* base_camera, int W, int H, int K,
+                      const rcp_displacement* disp, float* out_images, int32_t* out_ids,
+                      void* hip_stream);
+
+/* One pass of F: out = F(prev) for a caller-supplied previous image.
+ *   prev_rgb  device [H][W][3] float32, or NULL for the grey seed
+ *   out_rgb   device [H][W][3] float32
+ *   out_ids   device [H][W] int32 or NULL
+ * rcp_render's image k equals rcp_render_pass applied to image k-1.
+ * Asynchronous on hip_stream. */
+rcp_status rcp_render_pass(rcp_scene* scene, const rcp_camera* base_camera, int W, int H,
+                           const rcp_displacement* disp, const float* prev_rgb, float* out_rgb,
+                           int32_t* out_ids, void* hip_stream);
+
+/* rcp_render plus traversal counters (a separate instrumented kernel; not
+ * for timing).  counts: HOST [K][4] uint64: rays traced, inner nodes
+ * visited, triangles tested, rays appended for the next pass.  Synchronous. */
+rcp_status rcp_render_stats(rcp_scene* scene, const rcp_camera* base_camera, int W, int H, int K,
+                            const rcp_displacement* disp, float* out_images, int32_t* out_ids,
+                            uint64_t* counts, void* hip_stream);
+
+/* ---------------------------------------------------------------------- */
+/* Single steps of the path, for testing and measurement                   */
+/* ---------------------------------------------------------------------- */
+
+/* Displaced rays of every pixel (Section 2 ray and displacement, Section 3
+ * colour mapping) without tracing them.
+ *   prev_rgb  device [H][W][3] or NULL (grey seed: the pinhole rays)
+ *   out_org, out_dir  device [H][W][3] float32
+ * Asynchronous on hip_stream. */
+rcp_status rcp_generate_rays(const rcp_camera* base_camera, int W, int H,
+                             const rcp_displacement* disp, const float* prev_rgb,
+                             float* out_org, float* out_dir, void* hip_stream);
+
+/* Closest hit of n arbitrary rays (org, dir device [n][3]; dir need not be
+ * normalised but must be finite and non-zero).
+ *   out_t      device [n] float32 (+inf on a miss)
+ *   out_id     device [n] int32 triangle index or -1
+ *   out_front  device [n] int32: 1 when cross(v1-v0, v2-v0) faces the ray
+ * Asynchronous on hip_stream. */
+rcp_status rcp_trace_rays(rcp_scene* scene, const float* org, const float* dir, int n,
+                          float* out_t, int32_t* out_id, int32_t* out_front, void* hip_stream);
+
+/* Copy the packed BVH to HOST memory for inspection.
+ *   nodes    [n_nodes][16] 32-bit words per node (64 B), node 0 = root:
+ *            words 0-3   float child0 lo.x, hi.x, lo.y, hi.y
+ *            words 4-7   float child1 lo.x, hi.x, lo.y, hi.y
+ *            words 8-11  float child0 lo.z, hi.z, child1 lo.z, hi.z
+ *            words 12-13 child links; 14-15 zero.
+ *            A link with bit 31 clear is an inner node index; with bit 31
+ *            set it is a leaf: bits 3..30 = first packed triangle,
+ *            bits 0..2 = triangle count - 1.
+ *   tri_ids  [n_tris] original triangle index of each packed slot.
+ * Either pointer may be NULL.  Synchronous. */
+rcp_status rcp_export_bvh(const rcp_scene* scene, uint32_t* nodes, int32_t* tri_ids);
+
+/* Stable LSD radix sort of n (uint64 key, uint32 value) pairs in device
+ * memory, the sort used by the BVH build.  keys/vals are sorted in place.
+ * Synchronous. */
+rcp_status rcp_radix_sort_u64(uint64_t* keys, uint32_t* vals, int n, void* hip_stream);
+
+/* ---------------------------------------------------------------------- */
+/* Errors                                                                  */
+/* ---------------------------------------------------------------------- */
+
+const char* rcp_status_string(rcp_status s);
+/* Message of the calling thread's last error ("" if none). */
+const char* rcp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RCP_H */

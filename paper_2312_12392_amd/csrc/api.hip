@@ -1,0 +1,269 @@
+// C ABI of the renderer: argument validation, error reporting, dispatch.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "rcp_internal.hpp"
+
+namespace rcp {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+rcp_status hip_status(hipError_t e, const char* what, const char* file, int line) {
+    set_error("%s: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? RCP_ERR_OUT_OF_MEMORY : RCP_ERR_DEVICE;
+}
+
+}  // namespace rcp
+
+using namespace rcp;
+
+namespace {
+
+#define FAIL(...) do { set_error(__VA_ARGS__); return RCP_ERR_INVALID_ARGUMENT; } while (0)
+
+bool finite_n(const float* v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+rcp_status check_camera(const rcp_camera* c, Camera& out) {
+    if (!c) FAIL("camera is NULL");
+    if (!finite_n(c->eye, 3) || !finite_n(c->right, 3) || !finite_n(c->up, 3) || !finite_n(c->forward, 3) ||
+        !std::isfinite(c->tan_half_fovy))
+        FAIL("camera has a non-finite value");
+    if (!(c->tan_half_fovy > 0.0f)) FAIL("camera tan_half_fovy must be > 0");
+    const float* b[3] = {c->right, c->up, c->forward};
+    for (int i = 0; i < 3; ++i) {
+        double n = std::sqrt((double)b[i][0] * b[i][0] + (double)b[i][1] * b[i][1] + (double)b[i][2] * b[i][2]);
+        if (std::fabs(1.0 - n) > 1e-5) FAIL("camera basis vector %d is not unit length (|v| = %.9g)", i, n);
+        for (int j = i + 1; j < 3; ++j) {
+            double d = (double)b[i][0] * b[j][0] + (double)b[i][1] * b[j][1] + (double)b[i][2] * b[j][2];
+            if (std::fabs(d) > 1e-5) FAIL("camera basis vectors %d and %d are not orthogonal", i, j);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        out.eye[a] = c->eye[a];
+        out.right[a] = c->right[a];
+        out.up[a] = c->up[a];
+        out.forward[a] = c->forward[a];
+    }
+    out.th = c->tan_half_fovy;
+    return RCP_OK;
+}
+
+rcp_status check_disp(const rcp_displacement* d) {
+    if (!d) FAIL("displacement is NULL");
+    if (!std::isfinite(d->lambda_eye) || !std::isfinite(d->lambda_dir)) FAIL("displacement lambda is not finite");
+    if (d->lambda_eye < 0.0f) FAIL("lambda_eye must be >= 0");
+    if (!(d->lambda_dir >= 0.0f && d->lambda_dir < 1.0f)) FAIL("lambda_dir must be in [0, 1)");
+    if (d->mode != RCP_MODE_COLOR) FAIL("unknown displacement mode %d", (int)d->mode);
+    return RCP_OK;
+}
+
+rcp_status check_size(int W, int H) {
+    if (W < 1 || H < 1) FAIL("image size %dx%d: W and H must be >= 1", W, H);
+    if ((long long)W * (long long)H > (1ll << 27)) FAIL("image size %dx%d exceeds 2^27 pixels", W, H);
+    return RCP_OK;
+}
+
+rcp_status check_scene(const rcp_scene* s) {
+    if (!s) FAIL("scene is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("hipGetDevice failed");
+        return RCP_ERR_DEVICE;
+    }
+    if (dev != s->device) FAIL("scene lives on device %d but the current device is %d", s->device, dev);
+    return RCP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rcp_status_string(rcp_status s) {
+    switch (s) {
+        case RCP_OK: return "ok";
+        case RCP_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case RCP_ERR_OUT_OF_MEMORY: return "out of memory";
+        case RCP_ERR_DEVICE: return "device error";
+        case RCP_ERR_NOT_READY: return "not ready";
+        case RCP_ERR_QUEUE_FULL: return "queue full";
+        case RCP_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char* rcp_last_error(void) { return g_err; }
+
+rcp_status rcp_build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts, void* hip_stream,
+                           rcp_scene** out) {
+    clear_error();
+    if (out) *out = nullptr;
+    if (!desc || !out) FAIL("desc and out must not be NULL");
+    if (desc->n_tris > kMaxTris - 8) FAIL("n_tris %u exceeds the limit %u", desc->n_tris, kMaxTris - 8);
+    if (!finite_n(desc->light_dir, 3) || !finite_n(desc->background, 3) || !std::isfinite(desc->k_a) ||
+        !std::isfinite(desc->k_d))
+        FAIL("light, shading weights and background must be finite");
+    if (desc->n_tris > 0) {
+        if (!desc->verts || !desc->idx || !desc->tri_rgb) FAIL("verts, idx and tri_rgb must not be NULL");
+        if (desc->n_verts == 0) FAIL("n_verts is 0 but n_tris > 0");
+        for (size_t i = 0; i < 3 * (size_t)desc->n_tris; ++i)
+            if (desc->idx[i] >= desc->n_verts)
+                FAIL("idx[%zu] = %u is out of range (n_verts = %u)", i, desc->idx[i], desc->n_verts);
+        for (size_t i = 0; i < 3 * (size_t)desc->n_verts; ++i)
+            if (!std::isfinite(desc->verts[i])) FAIL("vertex coordinate %zu is not finite", i);
+        for (size_t i = 0; i < 3 * (size_t)desc->n_tris; ++i)
+            if (!std::isfinite(desc->tri_rgb[i])) FAIL("tri_rgb[%zu] is not finite", i);
+    }
+    if (opts) {
+        if (opts->max_leaf < 1 || opts->max_leaf > kMaxLeaf) FAIL("max_leaf must be in [1, %d]", kMaxLeaf);
+        if (opts->top_levels < 0 || opts->top_levels > kMaxTopLevels)
+            FAIL("top_levels must be in [0, %d]", kMaxTopLevels);
+        if (!(opts->c_trav > 0.0f) || !(opts->c_isect > 0.0f) || !std::isfinite(opts->c_trav) ||
+            !std::isfinite(opts->c_isect))
+            FAIL("SAH costs must be finite and > 0");
+    }
+    try {
+        return build_scene(desc, opts, (hipStream_t)hip_stream, out);
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return RCP_ERR_OUT_OF_MEMORY;
+    }
+}
+
+void rcp_destroy_scene(rcp_scene* s) {
+    if (!s) return;
+    (void)hipDeviceSynchronize();
+    if (s->nodes) (void)hipFree(s->nodes);
+    if (s->tris) (void)hipFree(s->tris);
+    if (s->shade) (void)hipFree(s->shade);
+    Workspace& w = s->ws;
+    for (int i = 0; i < 2; ++i) if (w.state[i]) (void)hipFree(w.state[i]);
+    if (w.counters) (void)hipFree(w.counters);
+    if (w.spill) (void)hipFree(w.spill);
+    if (w.stats) (void)hipFree(w.stats);
+    delete s;
+}
+
+rcp_status rcp_scene_info(const rcp_scene* s, rcp_scene_stats* out) {
+    clear_error();
+    if (!s || !out) FAIL("scene and out must not be NULL");
+    *out = s->stats;
+    return RCP_OK;
+}
+
+static rcp_status render_common(rcp_scene* scene, const rcp_camera* cam, int W, int H, int K,
+                                const rcp_displacement* disp, float* out_images, int32_t* out_ids,
+                                const float* prev, unsigned long long* counts, void* stream) {
+    clear_error();
+    rcp_status st = check_scene(scene);
+    if (st) return st;
+    Camera c;
+    if ((st = check_camera(cam, c))) return st;
+    if ((st = check_disp(disp))) return st;
+    if ((st = check_size(W, H))) return st;
+    if (K < 1 || K > kMaxPasses) FAIL("K = %d must be in [1, %d]", K, kMaxPasses);
+    if (!out_images) FAIL("out_images must not be NULL");
+    return render(scene, c, W, H, K, disp->lambda_eye, disp->lambda_dir, out_images, out_ids, prev, counts,
+                  (hipStream_t)stream);
+}
+
+rcp_status rcp_render(rcp_scene* scene, const rcp_camera* cam, int W, int H, int K, const rcp_displacement* disp,
+                      float* out_images, int32_t* out_ids, void* hip_stream) {
+    return render_common(scene, cam, W, H, K, disp, out_images, out_ids, nullptr, nullptr, hip_stream);
+}
+
+rcp_status rcp_render_pass(rcp_scene* scene, const rcp_camera* cam, int W, int H, const rcp_displacement* disp,
+                           const float* prev_rgb, float* out_rgb, int32_t* out_ids, void* hip_stream) {
+    return render_common(scene, cam, W, H, 1, disp, out_rgb, out_ids, prev_rgb, nullptr, hip_stream);
+}
+
+rcp_status rcp_render_stats(rcp_scene* scene, const rcp_camera* cam, int W, int H, int K,
+                            const rcp_displacement* disp, float* out_images, int32_t* out_ids, uint64_t* counts,
+                            void* hip_stream) {
+    if (!counts) {
+        clear_error();
+        FAIL("counts must not be NULL");
+    }
+    return render_common(scene, cam, W, H, K, disp, out_images, out_ids, nullptr,
+                         (unsigned long long*)counts, hip_stream);
+}
+
+rcp_status rcp_generate_rays(const rcp_camera* cam, int W, int H, const rcp_displacement* disp,
+                             const float* prev_rgb, float* out_org, float* out_dir, void* hip_stream) {
+    clear_error();
+    Camera c;
+    rcp_status st;
+    if ((st = check_camera(cam, c))) return st;
+    if ((st = check_disp(disp))) return st;
+    if ((st = check_size(W, H))) return st;
+    if (!out_org || !out_dir) FAIL("out_org and out_dir must not be NULL");
+    return generate_rays(c, W, H, disp->lambda_eye, disp->lambda_dir, prev_rgb, out_org, out_dir,
+                         (hipStream_t)hip_stream);
+}
+
+rcp_status rcp_trace_rays(rcp_scene* scene, const float* org, const float* dir, int n, float* out_t,
+                          int32_t* out_id, int32_t* out_front, void* hip_stream) {
+    clear_error();
+    rcp_status st = check_scene(scene);
+    if (st) return st;
+    if (n < 0) FAIL("n must be >= 0");
+    if (n > 0 && (!org || !dir || !out_t || !out_id)) FAIL("org, dir, out_t and out_id must not be NULL");
+    return trace_rays(scene, org, dir, n, out_t, out_id, out_front, (hipStream_t)hip_stream);
+}
+
+rcp_status rcp_export_bvh(const rcp_scene* s, uint32_t* nodes, int32_t* tri_ids) {
+    clear_error();
+    if (!s) FAIL("scene is NULL");
+    if (nodes && s->dev.n_nodes) {
+        hipError_t e = hipMemcpy(nodes, s->nodes, 64 * (size_t)s->dev.n_nodes, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_status(e, "export nodes", __FILE__, __LINE__);
+    }
+    if (tri_ids && s->dev.n_tris) {
+        // original index of each packed triangle: the w word of its first vertex
+        const size_t n = s->dev.n_tris;
+        float4* tmp = new float4[3 * n];
+        hipError_t e = hipMemcpy(tmp, s->tris, sizeof(float4) * 3 * n, hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            for (size_t j = 0; j < n; ++j) memcpy(&tri_ids[j], &tmp[3 * j].w, 4);
+        delete[] tmp;
+        if (e != hipSuccess) return hip_status(e, "export triangles", __FILE__, __LINE__);
+    }
+    return RCP_OK;
+}
+
+rcp_status rcp_radix_sort_u64(uint64_t* keys, uint32_t* vals, int n, void* hip_stream) {
+    clear_error();
+    if (n < 0) FAIL("n must be >= 0");
+    if (n > 0 && (!keys || !vals)) FAIL("keys and vals must not be NULL");
+    if (n <= 1) return RCP_OK;
+    uint64_t* k2 = nullptr;
+    uint32_t* v2 = nullptr;
+    hipError_t e = hipMalloc((void**)&k2, sizeof(uint64_t) * (size_t)n);
+    if (e != hipSuccess) return hip_status(e, "hipMalloc", __FILE__, __LINE__);
+    e = hipMalloc((void**)&v2, sizeof(uint32_t) * (size_t)n);
+    if (e != hipSuccess) {
+        (void)hipFree(k2);
+        return hip_status(e, "hipMalloc", __FILE__, __LINE__);
+    }
+    rcp_status st = radix_sort_pairs(keys, vals, k2, v2, n, 64, (hipStream_t)hip_stream);
+    (void)hipFree(k2);
+    (void)hipFree(v2);
+    return st;
+}
+
+}  // extern "C"

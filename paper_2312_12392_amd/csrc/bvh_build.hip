@@ -1,0 +1,665 @@
+// Device BVH build for the renderer's scenes.
+//
+// The paper does not say how its ray tracer built its acceleration structure
+// (Section 6 used a GPU ray-tracing engine), so this is a standard GPU build:
+//   1. per-triangle boxes and the centroid bounds (wave reductions + atomics)
+//   2. 63-bit Morton codes of the box centres (21 bits per axis)
+//   3. stable LSD radix sort of (code, triangle) pairs
+//   4. binary radix tree over the sorted codes, one thread per inner node
+//      (Karras, "Maximizing Parallelism in the Construction of BVHs, Octrees,
+//      and k-d Trees", HPG 2012), duplicate codes split by index
+//   5. bottom-up refit with per-node arrival counters; each node also gets its
+//      SAH cost and is collapsed into a leaf (<= max_leaf triangles) when that
+//      is cheaper than keeping the split
+//   6. layout: the top levels in breadth-first order (staged in LDS by the
+//      traversal), then every remaining subtree in depth-first order
+//   7. packing into 64-byte BVH2 nodes, 48-byte triangles and a per-triangle
+//      table of the two shaded colours.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rcp_internal.hpp"
+
+namespace rcp {
+namespace {
+
+constexpr int kB = 256;
+
+__device__ inline uint32_t f2o(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __host__ inline float o2f(uint32_t u) {
+    uint32_t b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+    float f;
+    memcpy(&f, &b, 4);
+    return f;
+}
+
+__device__ inline float3 ld3(const float* p, uint32_t i) {
+    return make_float3(p[3 * (size_t)i], p[3 * (size_t)i + 1], p[3 * (size_t)i + 2]);
+}
+
+__device__ inline float half_area(float3 lo, float3 hi) {
+    float dx = fmaxf(hi.x - lo.x, 0.0f), dy = fmaxf(hi.y - lo.y, 0.0f), dz = fmaxf(hi.z - lo.z, 0.0f);
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__device__ inline float wave_min(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline float wave_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// bounds[0..2] = ordered min of centres, bounds[3..5] = ordered max.
+__global__ void k_init_bounds(uint32_t* bounds) {
+    if (threadIdx.x < 3) bounds[threadIdx.x] = 0xFFFFFFFFu;
+    else if (threadIdx.x < 6) bounds[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(kB) void k_tri_prep(const float* __restrict__ verts, const uint32_t* __restrict__ idx,
+                                                  uint32_t n, float4* __restrict__ tlo, float4* __restrict__ thi,
+                                                  uint32_t* __restrict__ bounds) {
+    const uint32_t i = blockIdx.x * kB + threadIdx.x;
+    float3 c = make_float3(INFINITY, INFINITY, INFINITY);
+    float3 cmax = make_float3(-INFINITY, -INFINITY, -INFINITY);
+    if (i < n) {
+        float3 a = ld3(verts, idx[3 * (size_t)i]);
+        float3 b = ld3(verts, idx[3 * (size_t)i + 1]);
+        float3 d = ld3(verts, idx[3 * (size_t)i + 2]);
+        float3 lo = make_float3(fminf(fminf(a.x, b.x), d.x), fminf(fminf(a.y, b.y), d.y), fminf(fminf(a.z, b.z), d.z));
+        float3 hi = make_float3(fmaxf(fmaxf(a.x, b.x), d.x), fmaxf(fmaxf(a.y, b.y), d.y), fmaxf(fmaxf(a.z, b.z), d.z));
+        tlo[i] = make_float4(lo.x, lo.y, lo.z, 0.0f);
+        thi[i] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+        c = make_float3(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z));
+        cmax = c;
+    }
+    float m0 = wave_min(c.x), m1 = wave_min(c.y), m2 = wave_min(c.z);
+    float x0 = wave_max(cmax.x), x1 = wave_max(cmax.y), x2 = wave_max(cmax.z);
+    if ((threadIdx.x & 63) == 0 && m0 <= x0) {
+        atomicMin(&bounds[0], f2o(m0)); atomicMin(&bounds[1], f2o(m1)); atomicMin(&bounds[2], f2o(m2));
+        atomicMax(&bounds[3], f2o(x0)); atomicMax(&bounds[4], f2o(x1)); atomicMax(&bounds[5], f2o(x2));
+    }
+}
+
+__device__ inline uint64_t spread21(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ inline uint32_t quant21(float v, float lo, float scale) {
+    float q = (v - lo) * scale;
+    q = fminf(fmaxf(q, 0.0f), 2097151.0f);
+    return (uint32_t)q;
+}
+
+__global__ __launch_bounds__(kB) void k_morton(const float4* __restrict__ tlo, const float4* __restrict__ thi,
+                                                uint32_t n, const uint32_t* __restrict__ bounds,
+                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const uint32_t i = blockIdx.x * kB + threadIdx.x;
+    if (i >= n) return;
+    float lo[3], ext[3];
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = o2f(bounds[c]);
+        ext[c] = o2f(bounds[3 + c]) - lo[c];
+    }
+    float4 a = tlo[i], b = thi[i];
+    float cx = 0.5f * (a.x + b.x), cy = 0.5f * (a.y + b.y), cz = 0.5f * (a.z + b.z);
+    uint32_t qx = quant21(cx, lo[0], ext[0] > 0.0f ? 2097152.0f / ext[0] : 0.0f);
+    uint32_t qy = quant21(cy, lo[1], ext[1] > 0.0f ? 2097152.0f / ext[1] : 0.0f);
+    uint32_t qz = quant21(cz, lo[2], ext[2] > 0.0f ? 2097152.0f / ext[2] : 0.0f);
+    keys[i] = (spread21(qx) << 2) | (spread21(qy) << 1) | spread21(qz);
+    vals[i] = i;
+}
+
+// Length of the common prefix of sorted keys i and j, extended by the index
+// bits when the keys are equal; -1 outside [0, n).
+__device__ inline int prefix_len(const uint64_t* __restrict__ k, int n, int i, int j) {
+    if (j < 0 || j >= n) return -1;
+    uint64_t a = k[i], b = k[j];
+    if (a == b) return 64 + __clz((uint32_t)i ^ (uint32_t)j);
+    return __clzll(a ^ b);
+}
+
+// Children: >= 0 inner node, kLeafBit | j for sorted triangle j.
+__global__ __launch_bounds__(kB) void k_radix_tree(const uint64_t* __restrict__ keys, int n,
+                                                    int32_t* __restrict__ left, int32_t* __restrict__ right,
+                                                    int32_t* __restrict__ parent, int32_t* __restrict__ rfirst,
+                                                    int32_t* __restrict__ rlast) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = (prefix_len(keys, n, i, i + 1) - prefix_len(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = prefix_len(keys, n, i, i - d);
+    int lmax = 2;
+    while (prefix_len(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (prefix_len(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = prefix_len(keys, n, i, j);
+    int s = 0;
+    int t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (prefix_len(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int gamma = i + s * d + (d < 0 ? -1 : 0);
+    const int lo = min(i, j), hi = max(i, j);
+    int32_t lc = (lo == gamma) ? (int32_t)(kLeafBit | (uint32_t)gamma) : gamma;
+    int32_t rc = (hi == gamma + 1) ? (int32_t)(kLeafBit | (uint32_t)(gamma + 1)) : gamma + 1;
+    left[i] = lc;
+    right[i] = rc;
+    rfirst[i] = lo;
+    rlast[i] = hi;
+    // parents: inner nodes at [0, n-1), leaves at [n-1, 2n-1)
+    parent[lc < 0 ? (n - 1 + gamma) : lc] = i;
+    parent[rc < 0 ? (n - 1 + gamma + 1) : rc] = i;
+    if (i == 0) parent[0] = -1;
+}
+
+struct NodeData {
+    float4* lo;        // box lo, w unused
+    float4* hi;
+    float* cost;
+    int32_t* n_inner;  // emitted inner nodes in the subtree (0 when collapsed)
+    int32_t* collapse;
+};
+
+__device__ inline void child_info(int32_t c, const float4* __restrict__ tlo, const float4* __restrict__ thi,
+                                  const uint32_t* __restrict__ sorted, NodeData nd, float c_isect,
+                                  float3& lo, float3& hi, float& cost, int& ninner) {
+    if (c < 0) {
+        uint32_t t = sorted[(uint32_t)c & ~kLeafBit];
+        float4 a = tlo[t], b = thi[t];
+        lo = make_float3(a.x, a.y, a.z);
+        hi = make_float3(b.x, b.y, b.z);
+        cost = c_isect * half_area(lo, hi);
+        ninner = 0;
+    } else {
+        // written by the sibling's thread before its release fence
+        float4 a = nd.lo[c];
+        float4 b = nd.hi[c];
+        lo = make_float3(a.x, a.y, a.z);
+        hi = make_float3(b.x, b.y, b.z);
+        cost = nd.cost[c];
+        ninner = nd.n_inner[c];
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_refit(int n, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
+                                               const int32_t* __restrict__ parent, const int32_t* __restrict__ rfirst,
+                                               const int32_t* __restrict__ rlast, const float4* __restrict__ tlo,
+                                               const float4* __restrict__ thi, const uint32_t* __restrict__ sorted,
+                                               uint32_t* __restrict__ arrivals, NodeData nd, int max_leaf,
+                                               float c_trav, float c_isect) {
+    const int j = blockIdx.x * kB + threadIdx.x;
+    if (j >= n) return;
+    int node = parent[n - 1 + j];
+    while (node >= 0) {
+        __threadfence();
+        if (atomicAdd(&arrivals[node], 1u) == 0u) return;   // the sibling finishes this node
+        __threadfence();
+        float3 llo, lhi, rlo, rhi;
+        float cl, cr;
+        int nl, nr;
+        child_info(left[node], tlo, thi, sorted, nd, c_isect, llo, lhi, cl, nl);
+        child_info(right[node], tlo, thi, sorted, nd, c_isect, rlo, rhi, cr, nr);
+        float3 lo = make_float3(fminf(llo.x, rlo.x), fminf(llo.y, rlo.y), fminf(llo.z, rlo.z));
+        float3 hi = make_float3(fmaxf(lhi.x, rhi.x), fmaxf(lhi.y, rhi.y), fmaxf(lhi.z, rhi.z));
+        const int cnt = rlast[node] - rfirst[node] + 1;
+        const float a = half_area(lo, hi);
+        const float leaf_cost = c_isect * (float)cnt * a;
+        const float split_cost = c_trav * a + cl + cr;
+        const bool col = cnt <= max_leaf && leaf_cost <= split_cost;
+        nd.lo[node] = make_float4(lo.x, lo.y, lo.z, 0.0f);
+        nd.hi[node] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+        nd.cost[node] = col ? leaf_cost : split_cost;
+        nd.n_inner[node] = col ? 0 : 1 + nl + nr;
+        nd.collapse[node] = col ? 1 : 0;
+        node = parent[node];
+    }
+}
+
+// Summary read back by the host: [0] collapse(root), [1] n_inner(root),
+// [2] top count, [3] max depth of inner nodes; floats follow.
+struct Summary {
+    int32_t root_collapsed;
+    int32_t n_inner;
+    int32_t top_count;
+    int32_t max_depth;
+    float root_cost;
+    float root_area;
+    float bbox[6];
+};
+
+__global__ void k_summary_root(NodeData nd, Summary* sm) {
+    sm->root_collapsed = nd.collapse[0];
+    sm->n_inner = nd.n_inner[0];
+    sm->top_count = 0;
+    sm->max_depth = 0;
+    sm->root_cost = nd.cost[0];
+    float4 a = nd.lo[0], b = nd.hi[0];
+    sm->root_area = half_area(make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z));
+    sm->bbox[0] = a.x; sm->bbox[1] = a.y; sm->bbox[2] = a.z;
+    sm->bbox[3] = b.x; sm->bbox[4] = b.y; sm->bbox[5] = b.z;
+}
+
+// Depth-first index (among emitted inner nodes) and depth of each inner node,
+// by walking up to the root.  Nodes inside a collapsed subtree get -1.
+__global__ __launch_bounds__(kB) void k_layout_walk(int n, const int32_t* __restrict__ left,
+                                                     const int32_t* __restrict__ parent, NodeData nd,
+                                                     int top_levels, int32_t* __restrict__ dfs,
+                                                     int32_t* __restrict__ depth, int32_t* __restrict__ newidx,
+                                                     uint64_t* __restrict__ top_keys, Summary* sm) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= n - 1) return;
+    newidx[i] = -1;
+    if (nd.collapse[i]) return;
+    int x = i, idx = 0, dep = 0;
+    while (x != 0) {
+        const int p = parent[x];
+        if (nd.collapse[p]) return;
+        const int32_t lp = left[p];
+        idx += 1;
+        if (lp != x && lp >= 0) idx += nd.n_inner[lp];
+        ++dep;
+        x = p;
+    }
+    dfs[i] = idx;
+    depth[i] = dep;
+    atomicMax(&sm->max_depth, dep);
+    if (dep < top_levels) {
+        int slot = atomicAdd(&sm->top_count, 1);
+        top_keys[slot] = ((uint64_t)dep << 32) | (uint32_t)idx;
+    }
+}
+
+// One block: breadth-first ranks of the top nodes (sorted by depth, then
+// depth-first index), and their depth-first indices in ascending order.
+__global__ __launch_bounds__(512) void k_top_order(const uint64_t* __restrict__ top_keys, const Summary* sm,
+                                                    uint32_t* __restrict__ top_dfs_sorted,
+                                                    uint32_t* __restrict__ top_dfs_bfs) {
+    __shared__ uint64_t a[512];
+    const int m = sm->top_count;
+    const int t = threadIdx.x;
+    a[t] = t < m ? top_keys[t] : ~0ull;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int k = 2; k <= 512; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int p = t ^ j;
+                if (p > t) {
+                    const bool up = (t & k) == 0;
+                    uint64_t x = a[t], y = a[p];
+                    if ((x > y) == up) { a[t] = y; a[p] = x; }
+                }
+                __syncthreads();
+            }
+        }
+        if (pass == 0) {
+            if (t < m) top_dfs_bfs[t] = (uint32_t)a[t];        // BFS rank -> dfs index
+            __syncthreads();
+            a[t] = t < m ? (uint64_t)(uint32_t)a[t] : ~0ull;
+            __syncthreads();
+        } else if (t < m) {
+            top_dfs_sorted[t] = (uint32_t)a[t];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_layout_final(int n, const int32_t* __restrict__ dfs,
+                                                      const int32_t* __restrict__ depth, int top_levels,
+                                                      const uint32_t* __restrict__ top_dfs_sorted,
+                                                      const uint32_t* __restrict__ top_dfs_bfs,
+                                                      const Summary* sm, int32_t* __restrict__ newidx) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= n - 1 || dfs[i] < 0) return;     // inside or at a collapsed subtree
+    const int m = sm->top_count;
+    const uint32_t d = (uint32_t)dfs[i];
+    // number of top nodes with a smaller depth-first index
+    int lo = 0, hi = m;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (top_dfs_sorted[mid] < d) lo = mid + 1; else hi = mid;
+    }
+    if (depth[i] < top_levels) {
+        // breadth-first rank: position of d in top_dfs_bfs (linear scan, m <= 511)
+        for (int r = 0; r < m; ++r)
+            if (top_dfs_bfs[r] == d) { newidx[i] = r; return; }
+    } else {
+        newidx[i] = m + (int)d - lo;
+    }
+}
+
+__device__ inline float pad_lo(float v) { return v - (fabsf(v) * 4.8e-7f + 1e-30f); }
+__device__ inline float pad_hi(float v) { return v + (fabsf(v) * 4.8e-7f + 1e-30f); }
+
+__global__ __launch_bounds__(kB) void k_pack_nodes(int n, const int32_t* __restrict__ left,
+                                                    const int32_t* __restrict__ right,
+                                                    const int32_t* __restrict__ rfirst,
+                                                    const int32_t* __restrict__ rlast, const float4* __restrict__ tlo,
+                                                    const float4* __restrict__ thi, const uint32_t* __restrict__ sorted,
+                                                    NodeData nd, const int32_t* __restrict__ newidx,
+                                                    float4* __restrict__ nodes) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= n - 1) return;
+    const int ni = newidx[i];
+    if (ni < 0) return;
+    float3 lo[2], hi[2];
+    uint32_t link[2];
+    const int32_t ch[2] = {left[i], right[i]};
+    for (int c = 0; c < 2; ++c) {
+        const int32_t x = ch[c];
+        if (x < 0) {
+            const uint32_t j = (uint32_t)x & ~kLeafBit;
+            const uint32_t t = sorted[j];
+            float4 a = tlo[t], b = thi[t];
+            lo[c] = make_float3(a.x, a.y, a.z);
+            hi[c] = make_float3(b.x, b.y, b.z);
+            link[c] = leaf_link(j, 1);
+        } else {
+            float4 a = nd.lo[x], b = nd.hi[x];
+            lo[c] = make_float3(a.x, a.y, a.z);
+            hi[c] = make_float3(b.x, b.y, b.z);
+            if (nd.collapse[x]) link[c] = leaf_link((uint32_t)rfirst[x], (uint32_t)(rlast[x] - rfirst[x] + 1));
+            else link[c] = (uint32_t)newidx[x];
+        }
+    }
+    float4* o = nodes + 4 * (size_t)ni;
+    o[0] = make_float4(pad_lo(lo[0].x), pad_hi(hi[0].x), pad_lo(lo[0].y), pad_hi(hi[0].y));
+    o[1] = make_float4(pad_lo(lo[1].x), pad_hi(hi[1].x), pad_lo(lo[1].y), pad_hi(hi[1].y));
+    o[2] = make_float4(pad_lo(lo[0].z), pad_hi(hi[0].z), pad_lo(lo[1].z), pad_hi(hi[1].z));
+    o[3] = make_float4(__uint_as_float(link[0]), __uint_as_float(link[1]), 0.0f, 0.0f);
+}
+
+// Whole scene in one leaf (n <= max_leaf): a root whose two children are the
+// same leaf; visiting it twice cannot change the closest hit.
+__global__ void k_pack_single(int n, const float4* __restrict__ tlo, const float4* __restrict__ thi,
+                              float4* __restrict__ nodes) {
+    float3 lo = make_float3(INFINITY, INFINITY, INFINITY), hi = make_float3(-INFINITY, -INFINITY, -INFINITY);
+    for (int t = 0; t < n; ++t) {
+        float4 a = tlo[t], b = thi[t];
+        lo = make_float3(fminf(lo.x, a.x), fminf(lo.y, a.y), fminf(lo.z, a.z));
+        hi = make_float3(fmaxf(hi.x, b.x), fmaxf(hi.y, b.y), fmaxf(hi.z, b.z));
+    }
+    const uint32_t link = leaf_link(0, (uint32_t)n);
+    nodes[0] = make_float4(pad_lo(lo.x), pad_hi(hi.x), pad_lo(lo.y), pad_hi(hi.y));
+    nodes[1] = nodes[0];
+    nodes[2] = make_float4(pad_lo(lo.z), pad_hi(hi.z), pad_lo(lo.z), pad_hi(hi.z));
+    nodes[3] = make_float4(__uint_as_float(link), __uint_as_float(link), 0.0f, 0.0f);
+}
+
+__device__ inline float clamp01(float v) {
+    v = (v > 0.0f) ? v : 0.0f;   // NaN -> 0
+    return (v > 1.0f) ? 1.0f : v;
+}
+
+struct ShadeParams {
+    float light[3];
+    float k_a, k_d;
+};
+
+// Triangles in leaf order plus their two shaded colours.  Shading: two-sided
+// Lambert with the flat geometric normal n = cross(v1 - v0, v2 - v0) (flipped
+// for the back side), one directional light, clamped to [0, 1]; evaluated in
+// FP32 left to right without contraction.
+__global__ __launch_bounds__(kB) void k_pack_tris(uint32_t n, const float* __restrict__ verts,
+                                                   const uint32_t* __restrict__ idx, const float* __restrict__ albedo,
+                                                   const uint32_t* __restrict__ sorted, ShadeParams sp,
+                                                   float4* __restrict__ tris, float4* __restrict__ shade) {
+    const uint32_t j = blockIdx.x * kB + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t t = sorted ? sorted[j] : j;
+    const float3 a = ld3(verts, idx[3 * (size_t)t]);
+    const float3 b = ld3(verts, idx[3 * (size_t)t + 1]);
+    const float3 c = ld3(verts, idx[3 * (size_t)t + 2]);
+    tris[3 * (size_t)j + 0] = make_float4(a.x, a.y, a.z, __uint_as_float(t));
+    tris[3 * (size_t)j + 1] = make_float4(b.x, b.y, b.z, 0.0f);
+    tris[3 * (size_t)j + 2] = make_float4(c.x, c.y, c.z, 0.0f);
+
+    const float e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
+    const float e2x = c.x - a.x, e2y = c.y - a.y, e2z = c.z - a.z;
+    float nx = e1y * e2z - e1z * e2y;
+    float ny = e1z * e2x - e1x * e2z;
+    float nz = e1x * e2y - e1y * e2x;
+    const float len = sqrtf((nx * nx + ny * ny) + nz * nz);
+    nx = nx / len;
+    ny = ny / len;
+    nz = nz / len;
+    const float3 alb = ld3(albedo, t);
+    for (int side = 0; side < 2; ++side) {
+        const float sx = side ? -nx : nx, sy = side ? -ny : ny, sz = side ? -nz : nz;
+        const float dot = (sx * sp.light[0] + sy * sp.light[1]) + sz * sp.light[2];
+        const float diff = dot > 0.0f ? dot : 0.0f;
+        const float s = sp.k_a + sp.k_d * diff;
+        shade[2 * (size_t)j + side] = make_float4(clamp01(alb.x * s), clamp01(alb.y * s), clamp01(alb.z * s), 0.0f);
+    }
+}
+
+template <typename T>
+rcp_status dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return RCP_OK;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_status(e, "hipMalloc", __FILE__, __LINE__);
+    }
+    return RCP_OK;
+}
+
+struct TempSet {
+    std::vector<void*> ptrs;
+    ~TempSet() {
+        for (void* p : ptrs) if (p) (void)hipFree(p);
+    }
+    template <typename T>
+    rcp_status alloc(T** p, size_t count) {
+        rcp_status st = dalloc(p, count);
+        if (st == RCP_OK) ptrs.push_back((void*)*p);
+        return st;
+    }
+};
+
+#define RCP_TRY(expr) do { rcp_status st_ = (expr); if (st_ != RCP_OK) return st_; } while (0)
+
+inline unsigned blocks(long n) { return (unsigned)((n + kB - 1) / kB); }
+
+}  // namespace
+
+rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts, hipStream_t stream,
+                       rcp_scene** out) {
+    const uint32_t n = desc->n_tris;
+    const int max_leaf = opts ? opts->max_leaf : 4;
+    const int top_levels = opts ? opts->top_levels : 8;
+    const float c_trav = opts ? opts->c_trav : 1.0f;
+    const float c_isect = opts ? opts->c_isect : 1.0f;
+
+    rcp_scene* s = new rcp_scene();
+    struct Guard {
+        rcp_scene*& s;
+        bool ok = false;
+        ~Guard() {
+            if (!ok && s) {
+                if (s->nodes) (void)hipFree(s->nodes);
+                if (s->tris) (void)hipFree(s->tris);
+                if (s->shade) (void)hipFree(s->shade);
+                delete s;
+                s = nullptr;
+            }
+        }
+    } guard{s};
+
+    RCP_HIP(hipGetDevice(&s->device));
+    s->dev.bg[0] = desc->background[0];
+    s->dev.bg[1] = desc->background[1];
+    s->dev.bg[2] = desc->background[2];
+    s->stats.n_tris = n;
+    s->stats.max_leaf = (uint32_t)max_leaf;
+
+    hipEvent_t e0, e1;
+    RCP_HIP(hipEventCreate(&e0));
+    RCP_HIP(hipEventCreate(&e1));
+    struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } evg{e0, e1};
+
+    TempSet tmp;
+    float* d_verts = nullptr;
+    uint32_t* d_idx = nullptr;
+    float* d_rgb = nullptr;
+    if (n > 0) {
+        RCP_TRY(tmp.alloc(&d_verts, 3 * (size_t)desc->n_verts));
+        RCP_TRY(tmp.alloc(&d_idx, 3 * (size_t)n));
+        RCP_TRY(tmp.alloc(&d_rgb, 3 * (size_t)n));
+        RCP_HIP(hipMemcpyAsync(d_verts, desc->verts, sizeof(float) * 3 * (size_t)desc->n_verts,
+                               hipMemcpyHostToDevice, stream));
+        RCP_HIP(hipMemcpyAsync(d_idx, desc->idx, sizeof(uint32_t) * 3 * (size_t)n, hipMemcpyHostToDevice, stream));
+        RCP_HIP(hipMemcpyAsync(d_rgb, desc->tri_rgb, sizeof(float) * 3 * (size_t)n, hipMemcpyHostToDevice, stream));
+    }
+    RCP_HIP(hipEventRecord(e0, stream));
+
+    uint32_t n_nodes = 0, top_count = 0, max_depth = 0;
+    float sah = 0.0f;
+    uint32_t* sorted = nullptr;
+    float4 *tlo = nullptr, *thi = nullptr;
+    if (n > 0) {
+        uint32_t* bounds;
+        uint64_t *keys, *keys2;
+        uint32_t* vals2;
+        RCP_TRY(tmp.alloc(&tlo, n));
+        RCP_TRY(tmp.alloc(&thi, n));
+        RCP_TRY(tmp.alloc(&bounds, 8));
+        RCP_TRY(tmp.alloc(&keys, n));
+        RCP_TRY(tmp.alloc(&keys2, n));
+        RCP_TRY(tmp.alloc(&sorted, n));
+        RCP_TRY(tmp.alloc(&vals2, n));
+        hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, stream, bounds);
+        hipLaunchKernelGGL(k_tri_prep, dim3(blocks(n)), dim3(kB), 0, stream, (const float*)d_verts,
+                           (const uint32_t*)d_idx, n, tlo, thi, bounds);
+        hipLaunchKernelGGL(k_morton, dim3(blocks(n)), dim3(kB), 0, stream, (const float4*)tlo,
+                           (const float4*)thi, n, (const uint32_t*)bounds, keys, sorted);
+        RCP_CHECK_LAUNCH();
+        RCP_TRY(radix_sort_pairs(keys, sorted, keys2, vals2, (int)n, 64, stream));
+
+        Summary* sm;
+        RCP_TRY(tmp.alloc(&sm, 1));
+        Summary hs{};
+        bool single = n <= 1;
+        int32_t *left = nullptr, *right = nullptr, *parent = nullptr, *rfirst = nullptr, *rlast = nullptr;
+        NodeData nd{};
+        if (!single) {
+            const long ni = (long)n - 1;
+            uint32_t* arrivals;
+            RCP_TRY(tmp.alloc(&left, ni));
+            RCP_TRY(tmp.alloc(&right, ni));
+            RCP_TRY(tmp.alloc(&parent, 2 * (size_t)n - 1));
+            RCP_TRY(tmp.alloc(&rfirst, ni));
+            RCP_TRY(tmp.alloc(&rlast, ni));
+            RCP_TRY(tmp.alloc(&arrivals, ni));
+            RCP_TRY(tmp.alloc(&nd.lo, ni));
+            RCP_TRY(tmp.alloc(&nd.hi, ni));
+            RCP_TRY(tmp.alloc(&nd.cost, ni));
+            RCP_TRY(tmp.alloc(&nd.n_inner, ni));
+            RCP_TRY(tmp.alloc(&nd.collapse, ni));
+            RCP_HIP(hipMemsetAsync(arrivals, 0, sizeof(uint32_t) * ni, stream));
+            hipLaunchKernelGGL(k_radix_tree, dim3(blocks(ni)), dim3(kB), 0, stream, (const uint64_t*)keys, (int)n,
+                               left, right, parent, rfirst, rlast);
+            hipLaunchKernelGGL(k_refit, dim3(blocks(n)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
+                               (const int32_t*)right, (const int32_t*)parent, (const int32_t*)rfirst,
+                               (const int32_t*)rlast, (const float4*)tlo, (const float4*)thi,
+                               (const uint32_t*)sorted, arrivals, nd, max_leaf, c_trav, c_isect);
+            hipLaunchKernelGGL(k_summary_root, dim3(1), dim3(1), 0, stream, nd, sm);
+            RCP_CHECK_LAUNCH();
+            RCP_HIP(hipMemcpyAsync(&hs, sm, sizeof(Summary), hipMemcpyDeviceToHost, stream));
+            RCP_HIP(hipStreamSynchronize(stream));
+            single = hs.root_collapsed != 0;
+        }
+        if (single) {
+            n_nodes = 1;
+            RCP_TRY(dalloc(&s->nodes, 4));
+            hipLaunchKernelGGL(k_pack_single, dim3(1), dim3(1), 0, stream, (int)n, (const float4*)tlo,
+                               (const float4*)thi, s->nodes);
+            RCP_CHECK_LAUNCH();
+            sah = 1.0f;   // filled below for the single-leaf case
+            top_count = top_levels > 0 ? 1 : 0;
+            max_depth = 1;
+        } else {
+            const long ni = (long)n - 1;
+            int32_t *dfs, *depth, *newidx;
+            uint64_t* top_keys;
+            uint32_t *top_sorted, *top_bfs;
+            RCP_TRY(tmp.alloc(&dfs, ni));
+            RCP_TRY(tmp.alloc(&depth, ni));
+            RCP_TRY(tmp.alloc(&newidx, ni));
+            RCP_TRY(tmp.alloc(&top_keys, 512));
+            RCP_TRY(tmp.alloc(&top_sorted, 512));
+            RCP_TRY(tmp.alloc(&top_bfs, 512));
+            RCP_HIP(hipMemsetAsync(dfs, 0xFF, sizeof(int32_t) * ni, stream));
+            RCP_HIP(hipMemsetAsync(depth, 0xFF, sizeof(int32_t) * ni, stream));
+            hipLaunchKernelGGL(k_layout_walk, dim3(blocks(ni)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
+                               (const int32_t*)parent, nd, top_levels, dfs, depth, newidx, top_keys, sm);
+            hipLaunchKernelGGL(k_top_order, dim3(1), dim3(512), 0, stream, (const uint64_t*)top_keys,
+                               (const Summary*)sm, top_sorted, top_bfs);
+            hipLaunchKernelGGL(k_layout_final, dim3(blocks(ni)), dim3(kB), 0, stream, (int)n,
+                               (const int32_t*)dfs, (const int32_t*)depth, top_levels,
+                               (const uint32_t*)top_sorted, (const uint32_t*)top_bfs, (const Summary*)sm, newidx);
+            RCP_CHECK_LAUNCH();
+            n_nodes = (uint32_t)hs.n_inner;
+            RCP_TRY(dalloc(&s->nodes, 4 * (size_t)n_nodes));
+            hipLaunchKernelGGL(k_pack_nodes, dim3(blocks(ni)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
+                               (const int32_t*)right, (const int32_t*)rfirst, (const int32_t*)rlast,
+                               (const float4*)tlo, (const float4*)thi, (const uint32_t*)sorted, nd,
+                               (const int32_t*)newidx, s->nodes);
+            RCP_CHECK_LAUNCH();
+            Summary hs2{};
+            RCP_HIP(hipMemcpyAsync(&hs2, sm, sizeof(Summary), hipMemcpyDeviceToHost, stream));
+            RCP_HIP(hipStreamSynchronize(stream));
+            top_count = (uint32_t)hs2.top_count;
+            max_depth = (uint32_t)hs2.max_depth + 1;   // leaves sit one level below the deepest inner node
+            sah = hs.root_area > 0.0f ? hs.root_cost / hs.root_area : 0.0f;
+        }
+        RCP_TRY(dalloc(&s->tris, 3 * (size_t)n));
+        RCP_TRY(dalloc(&s->shade, 2 * (size_t)n));
+        ShadeParams sp{{desc->light_dir[0], desc->light_dir[1], desc->light_dir[2]}, desc->k_a, desc->k_d};
+        hipLaunchKernelGGL(k_pack_tris, dim3(blocks(n)), dim3(kB), 0, stream, n, (const float*)d_verts,
+                           (const uint32_t*)d_idx, (const float*)d_rgb, (const uint32_t*)sorted, sp, s->tris,
+                           s->shade);
+        RCP_CHECK_LAUNCH();
+        if (single) {
+            // SAH of one leaf holding every triangle, relative to its own box
+            sah = c_isect * (float)n;
+        }
+    }
+    RCP_HIP(hipEventRecord(e1, stream));
+    RCP_HIP(hipStreamSynchronize(stream));
+    float ms = 0.0f;
+    RCP_HIP(hipEventElapsedTime(&ms, e0, e1));
+
+    s->dev.nodes = s->nodes;
+    s->dev.tris = s->tris;
+    s->dev.shade = s->shade;
+    s->dev.n_nodes = n_nodes;
+    s->dev.n_tris = n;
+    s->dev.top_count = top_count;
+    s->dev.max_depth = max_depth;
+    s->stats.n_nodes = n_nodes;
+    s->stats.n_leaves = n_nodes ? n_nodes + 1 : 0;
+    s->stats.top_count = top_count;
+    s->stats.max_depth = max_depth;
+    s->stats.sah_cost = sah;
+    s->stats.build_ms = ms;
+    s->stats.device_bytes = 64ull * n_nodes + 48ull * n + 32ull * n;
+    guard.ok = true;
+    *out = s;
+    return RCP_OK;
+}
+
+}  // namespace rcp

@@ -1,0 +1,114 @@
+// Internal declarations of the recursive camera-painting library (gfx950).
+//
+// Data in HBM for a built scene (all arrays in the BVH's leaf order):
+//   nodes  float4[n_nodes][4]   BVH2 node, 64 B: both children's boxes + links
+//   tris   float4[n_tris][3]    v0.xyz + original index bits in w, v1, v2
+//   shade  float4[n_tris][2]    shaded RGB seen from the front / back side
+// The first top_count nodes are the BVH's top levels in breadth-first order;
+// the traversal stages them in LDS.  The rest follow in depth-first order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "rcp.h"
+
+// The path's results must match a plain FP32 evaluation bit for bit: no
+// contraction of a*b+c into fused multiply-adds anywhere in the library.
+#pragma clang fp contract(off)
+
+namespace rcp {
+
+// ---- link encoding of BVH children ---------------------------------------
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr int kMaxLeaf = 8;                // 3 bits of count
+constexpr uint32_t kMaxTris = 1u << 28;    // 28 bits of first triangle
+constexpr int kMaxTopLevels = 9;
+constexpr int kMaxTopNodes = (1 << kMaxTopLevels) - 1;
+constexpr int32_t kSentinel = 0x7FFFFFFF;  // "stack empty" / traversal done
+
+__host__ __device__ inline uint32_t leaf_link(uint32_t first, uint32_t count) {
+    return kLeafBit | (first << 3) | (count - 1u);
+}
+
+// ---- errors ----------------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+rcp_status hip_status(hipError_t e, const char* what, const char* file, int line);
+
+#define RCP_HIP(call)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess) return ::rcp::hip_status(e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define RCP_CHECK_LAUNCH()                                                     \
+    do {                                                                       \
+        hipError_t e_ = hipGetLastError();                                     \
+        if (e_ != hipSuccess) return ::rcp::hip_status(e_, "kernel launch", __FILE__, __LINE__); \
+    } while (0)
+
+// ---- device view of a scene -------------------------------------------------
+struct DevScene {
+    const float4* nodes;
+    const float4* tris;
+    const float4* shade;
+    uint32_t n_nodes;
+    uint32_t n_tris;
+    uint32_t top_count;
+    uint32_t max_depth;
+    float bg[3];
+};
+
+struct Camera {
+    float eye[3], right[3], up[3], forward[3];
+    float th;
+};
+
+// Per-render workspace (grown on demand, owned by the scene).
+struct Workspace {
+    float4* state[2] = {nullptr, nullptr};    // compact {pix, rgb} lists
+    size_t state_cap = 0;                      // entries per list
+    uint32_t* counters = nullptr;              // [2 * kMaxPasses + 8]
+    int32_t* spill = nullptr;                  // traversal stack overflow
+    size_t spill_cap = 0;                      // int32 entries
+    unsigned long long* stats = nullptr;       // [kMaxPasses][4]
+};
+
+constexpr int kMaxPasses = 64;
+
+}  // namespace rcp
+
+struct rcp_scene {
+    int device = 0;
+    rcp::DevScene dev{};
+    float4* nodes = nullptr;
+    float4* tris = nullptr;
+    float4* shade = nullptr;
+    rcp_scene_stats stats{};
+    rcp::Workspace ws;
+};
+
+namespace rcp {
+
+// Stable LSD radix sort of (u64 key, u32 value) pairs over bits [0, end_bit).
+// tmp_keys / tmp_vals: n entries each.  Result ends in keys / vals.
+rcp_status radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
+                            int n, int end_bit, hipStream_t stream);
+
+rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts, hipStream_t stream,
+                       rcp_scene** out);
+
+rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, float lambda_eye,
+                  float lambda_dir, float* out_images, int32_t* out_ids, const float* prev_rgb,
+                  unsigned long long* host_counts, hipStream_t stream);
+
+rcp_status generate_rays(const Camera& cam, int W, int H, float lambda_eye, float lambda_dir,
+                         const float* prev_rgb, float* org, float* dir, hipStream_t stream);
+
+rcp_status trace_rays(rcp_scene* s, const float* org, const float* dir, int n, float* out_t,
+                      int32_t* out_id, int32_t* out_front, hipStream_t stream);
+
+}  // namespace rcp

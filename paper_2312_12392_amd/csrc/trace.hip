@@ -1,0 +1,550 @@
+// The K-pass render: one persistent kernel launch per pass.
+//
+// Per pass, every wave repeatedly takes 64 work items from a pass counter.
+// A work item is a pixel still being painted: at pass 0 the pixels in 8x8
+// tiles (with the grey seed, or a caller-supplied previous image), later the
+// compact list {pixel, previous RGB} appended by the pass before.  For each
+// item the lane
+//   1. builds the pixel's displaced camera ray from its previous colour
+//      (Section 2 ray and displacements, Section 3 colour mapping),
+//   2. traverses the BVH (top levels from LDS, a short per-lane stack in LDS
+//      that overflows into a per-lane global area) and runs the watertight
+//      ray/triangle test at the leaves, keeping the nearest hit and, at equal
+//      distance, the lowest triangle index,
+//   3. looks the shaded colour up in the per-triangle table and writes
+//      image k (and its hit ID),
+//   4. compares the colour with the previous one: changed pixels are
+//      appended to the next pass's list with one ballot, one mbcnt and one
+//      atomic per wave; unchanged pixels would get the identical ray again, so
+//      their colour is written to every remaining image now.
+//
+// Everything that decides a result (ray generation, the triangle test, the
+// shade table) is FP32 evaluated left to right without contraction, with
+// correctly rounded division and square root.  The box tests only prune and
+// are widened so that they never reject a box the exact test would accept.
+#include <climits>
+
+#include "rcp_internal.hpp"
+
+namespace rcp {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kStack = 16;                       // per-lane LDS stack entries
+constexpr float kSlack = 1.0f + 1.0f / 65536.0f; // widening of box intervals
+
+struct PassArgs {
+    DevScene sc;
+    Camera cam;
+    int W, H, K, k;
+    float le, ld;
+    uint32_t n_items0;              // pass-0 items (8x8 tiles * 64)
+    int tiles_x;
+    const float4* state_in;         // pass > 0: {pix bits, r, g, b}
+    const float* prev_img;          // pass 0: previous image or NULL (grey seed)
+    float4* state_out;              // NULL: no following pass
+    uint32_t* counters;             // [kMaxPasses] list sizes, [kMaxPasses..] fetch
+    float* out;                     // [K][H][W][3]
+    int32_t* ids;                   // [K][H][W] or NULL
+    int32_t* spill;
+    uint32_t spill_stride;          // threads in the grid
+    unsigned long long* stats;      // [kMaxPasses][4] or NULL
+};
+
+__device__ inline float sel3(float x, float y, float z, int k) {
+    return k == 0 ? x : (k == 1 ? y : z);
+}
+
+__device__ inline uint32_t lanes_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Ray of pixel (x, y): P'_e = P_e + V_e, N = normalize(P'_p - P'_e) with the
+// colour mapping w = (2R-1) right + (2G-1) up + (2B-1) forward.
+__device__ inline void make_ray(const Camera& c, int W, int H, int x, int y, float pr, float pg, float pb,
+                                float le, float ld, float o[3], float d[3]) {
+    const float fx = (float)(2 * x + 1) / (float)W - 1.0f;
+    const float fy = 1.0f - (float)(2 * y + 1) / (float)H;
+    const float aspect = (float)W / (float)H;
+    const float s = fx * (c.th * aspect);
+    const float t = fy * c.th;
+    const float mr = 2.0f * pr - 1.0f;
+    const float mg = 2.0f * pg - 1.0f;
+    const float mb = 2.0f * pb - 1.0f;
+    float dp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float q = (c.forward[a] + s * c.right[a]) + t * c.up[a];
+        const float w = (mr * c.right[a] + mg * c.up[a]) + mb * c.forward[a];
+        o[a] = c.eye[a] + le * w;
+        dp[a] = q + ld * w;
+    }
+    const float len = sqrtf((dp[0] * dp[0] + dp[1] * dp[1]) + dp[2] * dp[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = dp[a] / len;
+}
+
+// Ray constants of the watertight test (Woop, Benthin, Wald, JCGT 2013):
+// the dominant direction axis kz (first of equal magnitudes), kx and ky
+// following it cyclically and swapped when d[kz] < 0, and the shear.
+struct RayW {
+    int kx, ky, kz;
+    float Sx, Sy, Sz;
+    float ox, oy, oz;     // origin components along kx, ky, kz
+};
+
+__device__ inline RayW ray_setup(const float o[3], const float d[3]) {
+    RayW r;
+    int kz = 0;
+    if (fabsf(d[1]) > fabsf(d[0])) kz = 1;
+    if (fabsf(d[2]) > fabsf(sel3(d[0], d[1], d[2], kz))) kz = 2;
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    const float dz = sel3(d[0], d[1], d[2], kz);
+    if (dz < 0.0f) { int t = kx; kx = ky; ky = t; }
+    r.kx = kx; r.ky = ky; r.kz = kz;
+    r.Sx = sel3(d[0], d[1], d[2], kx) / dz;
+    r.Sy = sel3(d[0], d[1], d[2], ky) / dz;
+    r.Sz = 1.0f / dz;
+    r.ox = sel3(o[0], o[1], o[2], kx);
+    r.oy = sel3(o[0], o[1], o[2], ky);
+    r.oz = sel3(o[0], o[1], o[2], kz);
+    return r;
+}
+
+// Watertight test against triangle (v0, v1, v2).  On a hit with t > 0
+// returns true with t and front (det > 0: the normal cross(v1-v0, v2-v0)
+// faces against the ray).
+__device__ inline bool hit_triangle(const RayW& r, const float4& v0, const float4& v1, const float4& v2,
+                                    float& t_out, bool& front) {
+    const float Akx = sel3(v0.x, v0.y, v0.z, r.kx) - r.ox;
+    const float Aky = sel3(v0.x, v0.y, v0.z, r.ky) - r.oy;
+    const float Akz = sel3(v0.x, v0.y, v0.z, r.kz) - r.oz;
+    const float Bkx = sel3(v1.x, v1.y, v1.z, r.kx) - r.ox;
+    const float Bky = sel3(v1.x, v1.y, v1.z, r.ky) - r.oy;
+    const float Bkz = sel3(v1.x, v1.y, v1.z, r.kz) - r.oz;
+    const float Ckx = sel3(v2.x, v2.y, v2.z, r.kx) - r.ox;
+    const float Cky = sel3(v2.x, v2.y, v2.z, r.ky) - r.oy;
+    const float Ckz = sel3(v2.x, v2.y, v2.z, r.kz) - r.oz;
+    const float Ax = Akx - r.Sx * Akz;
+    const float Ay = Aky - r.Sy * Akz;
+    const float Bx = Bkx - r.Sx * Bkz;
+    const float By = Bky - r.Sy * Bkz;
+    const float Cx = Ckx - r.Sx * Ckz;
+    const float Cy = Cky - r.Sy * Ckz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        // exact products in FP64, one rounding of each difference
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    const float det = U + V + W;
+    if (det == 0.0f) return false;
+    const float Az = r.Sz * Akz;
+    const float Bz = r.Sz * Bkz;
+    const float Cz = r.Sz * Ckz;
+    const float T = U * Az + V * Bz + W * Cz;
+    const float t = T / det;
+    if (!(t > 0.0f)) return false;
+    t_out = t;
+    front = det > 0.0f;
+    return true;
+}
+
+struct Hit {
+    float t;
+    int32_t id;        // original triangle index, INT_MAX when none
+    uint32_t slot;     // packed triangle index
+    bool front;
+};
+
+// Per-lane traversal stack: the newest kStack entries live in LDS (column
+// `lane_col` of the block's stack area), older ones in the lane's global
+// overflow area.
+struct Stack {
+    int32_t* lds;       // &stack_area[tid]; entry e at lds[(e % kStack) * kBlock]
+    int32_t* spill;     // &spill[gtid]; entry e at spill[e * stride]
+    uint32_t stride;
+    int sp, lo;         // entries [0, lo) spilled, [lo, sp) in LDS
+
+    __device__ inline void push(int32_t v) {
+        if (sp - lo == kStack) {
+            spill[(size_t)lo * stride] = lds[(lo & (kStack - 1)) * kBlock];
+            ++lo;
+        }
+        lds[(sp & (kStack - 1)) * kBlock] = v;
+        ++sp;
+    }
+    __device__ inline int32_t pop() {
+        if (sp == 0) return -1;
+        --sp;
+        if (sp < lo) {       // the LDS part is empty: take the newest spilled entry
+            lo = sp;
+            return spill[(size_t)sp * stride];
+        }
+        return lds[(sp & (kStack - 1)) * kBlock];
+    }
+};
+
+template <bool STATS>
+__device__ inline void traverse(const DevScene& sc, const float4* __restrict__ top, const float o[3],
+                                const float d[3], Stack& st, Hit& h, uint32_t& n_nodes, uint32_t& n_tris) {
+    const RayW rw = ray_setup(o, d);
+    float inv[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float da = fabsf(d[a]) > 1e-20f ? d[a] : copysignf(1e-20f, d[a]);
+        inv[a] = 1.0f / da;
+    }
+    const float ox = o[0], oy = o[1], oz = o[2];
+    const float ix = inv[0], iy = inv[1], iz = inv[2];
+    int32_t node = 0;
+    st.sp = 0;
+    st.lo = 0;
+    // Every node and leaf is entered at most once per ray; the bound only
+    // guarantees termination should the tree ever be malformed.
+    uint32_t budget = 2u * sc.n_nodes + 16u;
+    for (;;) {
+        while (node >= 0) {
+            if (--budget == 0u) return;
+            float4 n0, n1, n2, n3;
+            if ((uint32_t)node < sc.top_count) {
+                n0 = top[4 * node + 0];
+                n1 = top[4 * node + 1];
+                n2 = top[4 * node + 2];
+                n3 = top[4 * node + 3];
+            } else {
+                const float4* p = sc.nodes + 4 * (size_t)node;
+                n0 = p[0];
+                n1 = p[1];
+                n2 = p[2];
+                n3 = p[3];
+            }
+            if (STATS) ++n_nodes;
+            const float lim = h.t * kSlack;
+            // child 0
+            const float a0 = (n0.x - ox) * ix, a1 = (n0.y - ox) * ix;
+            const float a2 = (n0.z - oy) * iy, a3 = (n0.w - oy) * iy;
+            const float a4 = (n2.x - oz) * iz, a5 = (n2.y - oz) * iz;
+            const float tmin0 = fmaxf(fmaxf(fminf(a0, a1), fminf(a2, a3)), fmaxf(fminf(a4, a5), 0.0f));
+            const float tmax0 = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
+            // child 1
+            const float b0 = (n1.x - ox) * ix, b1 = (n1.y - ox) * ix;
+            const float b2 = (n1.z - oy) * iy, b3 = (n1.w - oy) * iy;
+            const float b4 = (n2.z - oz) * iz, b5 = (n2.w - oz) * iz;
+            const float tmin1 = fmaxf(fmaxf(fminf(b0, b1), fminf(b2, b3)), fmaxf(fminf(b4, b5), 0.0f));
+            const float tmax1 = fminf(fminf(fmaxf(b0, b1), fmaxf(b2, b3)), fmaxf(b4, b5)) * kSlack;
+            const bool hit0 = tmin0 <= tmax0 && tmin0 <= lim;
+            const bool hit1 = tmin1 <= tmax1 && tmin1 <= lim;
+            const int32_t c0 = __float_as_int(n3.x);
+            const int32_t c1 = __float_as_int(n3.y);
+            if (hit0 && hit1) {
+                const bool first0 = tmin0 <= tmin1;
+                st.push(first0 ? c1 : c0);
+                node = first0 ? c0 : c1;
+            } else if (hit0) {
+                node = c0;
+            } else if (hit1) {
+                node = c1;
+            } else {
+                node = st.pop();
+            }
+        }
+        if (node == -1) break;
+        // leaf: triangles [first, first + count)
+        const uint32_t first = ((uint32_t)node >> 3) & 0x0FFFFFFFu;
+        const uint32_t count = ((uint32_t)node & 7u) + 1u;
+        for (uint32_t j = 0; j < count; ++j) {
+            const float4* tp = sc.tris + 3 * (size_t)(first + j);
+            const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
+            if (STATS) ++n_tris;
+            float t;
+            bool front;
+            if (hit_triangle(rw, v0, v1, v2, t, front)) {
+                const int32_t id = __float_as_int(v0.w);
+                if (t < h.t || (t == h.t && id < h.id)) {
+                    h.t = t;
+                    h.id = id;
+                    h.slot = first + j;
+                    h.front = front;
+                }
+            }
+        }
+        node = st.pop();
+    }
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
+    extern __shared__ float4 smem[];
+    float4* top = smem;                                               // top_count * 4 float4
+    int32_t* stack_area = (int32_t*)(smem + 4 * a.sc.top_count);      // kStack * kBlock ints
+
+    for (uint32_t i = threadIdx.x; i < 4 * a.sc.top_count; i += kBlock) top[i] = a.sc.nodes[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
+    Stack st;
+    st.lds = stack_area + threadIdx.x;
+    st.spill = a.spill + gtid;
+    st.stride = a.spill_stride;
+
+    const uint32_t P = (uint32_t)a.W * (uint32_t)a.H;
+    const uint32_t n_items = a.k == 0 ? a.n_items0 : a.counters[a.k];
+    uint32_t* fetch = &a.counters[kMaxPasses + a.k];
+    float* out_k = a.out + (size_t)a.k * P * 3;
+    uint32_t s_nodes = 0, s_tris = 0, s_rays = 0, s_app = 0;
+
+    for (;;) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(fetch, 64u);
+        base = __shfl(base, 0);
+        if (base >= n_items) break;
+        const uint32_t item = base + lane;
+        bool valid = item < n_items;
+        uint32_t pix = 0;
+        float pr = 0.5f, pg = 0.5f, pb = 0.5f;
+        int x = 0, y = 0;
+        if (a.k == 0) {
+            const uint32_t tile = item >> 6;
+            const uint32_t l = item & 63u;
+            x = (int)((tile % (uint32_t)a.tiles_x) * 8u + (l & 7u));
+            y = (int)((tile / (uint32_t)a.tiles_x) * 8u + (l >> 3));
+            valid = valid && x < a.W && y < a.H;
+            pix = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
+            if (valid && a.prev_img) {
+                pr = a.prev_img[3 * (size_t)pix];
+                pg = a.prev_img[3 * (size_t)pix + 1];
+                pb = a.prev_img[3 * (size_t)pix + 2];
+            }
+        } else if (valid) {
+            const float4 s = a.state_in[item];
+            pix = __float_as_uint(s.x);
+            pr = s.y;
+            pg = s.z;
+            pb = s.w;
+            y = (int)(pix / (uint32_t)a.W);
+            x = (int)(pix - (uint32_t)y * (uint32_t)a.W);
+        }
+
+        Hit h;
+        h.t = INFINITY;
+        h.id = INT_MAX;
+        h.slot = 0;
+        h.front = false;
+        float rgb[3];
+        if (valid) {
+            float o[3], d[3];
+            make_ray(a.cam, a.W, a.H, x, y, pr, pg, pb, a.le, a.ld, o, d);
+            if (a.sc.n_nodes > 0) traverse<STATS>(a.sc, top, o, d, st, h, s_nodes, s_tris);
+            if (STATS) ++s_rays;
+            if (h.id != INT_MAX) {
+                const float4 c = a.sc.shade[2 * (size_t)h.slot + (h.front ? 0 : 1)];
+                rgb[0] = c.x; rgb[1] = c.y; rgb[2] = c.z;
+            } else {
+                rgb[0] = a.sc.bg[0]; rgb[1] = a.sc.bg[1]; rgb[2] = a.sc.bg[2];
+            }
+            const int32_t hid = h.id != INT_MAX ? h.id : -1;
+            float* o3 = out_k + 3 * (size_t)pix;
+            o3[0] = rgb[0]; o3[1] = rgb[1]; o3[2] = rgb[2];
+            if (a.ids) a.ids[(size_t)a.k * P + pix] = hid;
+            h.id = hid;
+        }
+
+        if (a.state_out) {
+            const bool changed = valid && (__float_as_uint(rgb[0]) != __float_as_uint(pr) ||
+                                           __float_as_uint(rgb[1]) != __float_as_uint(pg) ||
+                                           __float_as_uint(rgb[2]) != __float_as_uint(pb));
+            const unsigned long long m = __ballot(changed);
+            uint32_t wbase = 0;
+            if (lane == 0 && m) wbase = atomicAdd(&a.counters[a.k + 1], (uint32_t)__popcll(m));
+            wbase = __shfl(wbase, 0);
+            if (changed) {
+                a.state_out[wbase + lanes_below(m)] = make_float4(__uint_as_float(pix), rgb[0], rgb[1], rgb[2]);
+                if (STATS) ++s_app;
+            } else if (valid) {
+                // same colour -> same ray -> same result in every later pass
+                for (int kk = a.k + 1; kk < a.K; ++kk) {
+                    float* q = a.out + ((size_t)kk * P + pix) * 3;
+                    q[0] = rgb[0]; q[1] = rgb[1]; q[2] = rgb[2];
+                    if (a.ids) a.ids[(size_t)kk * P + pix] = h.id;
+                }
+            }
+        }
+    }
+    if (STATS) {
+        unsigned long long* sk = a.stats + 4 * a.k;
+        atomicAdd(&sk[0], (unsigned long long)s_rays);
+        atomicAdd(&sk[1], (unsigned long long)s_nodes);
+        atomicAdd(&sk[2], (unsigned long long)s_tris);
+        atomicAdd(&sk[3], (unsigned long long)s_app);
+    }
+}
+
+__global__ void k_clear_counters(uint32_t* c, int n, unsigned long long* stats) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0u;
+    if (stats)
+        for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gen_rays(Camera cam, int W, int H, float le, float ld,
+                                                      const float* __restrict__ prev, float* __restrict__ org,
+                                                      float* __restrict__ dir) {
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= (uint32_t)W * (uint32_t)H) return;
+    const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * (uint32_t)W);
+    float pr = 0.5f, pg = 0.5f, pb = 0.5f;
+    if (prev) { pr = prev[3 * (size_t)p]; pg = prev[3 * (size_t)p + 1]; pb = prev[3 * (size_t)p + 2]; }
+    float o[3], d[3];
+    make_ray(cam, W, H, x, y, pr, pg, pb, le, ld, o, d);
+    for (int c = 0; c < 3; ++c) { org[3 * (size_t)p + c] = o[c]; dir[3 * (size_t)p + c] = d[c]; }
+}
+
+__global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float* __restrict__ org,
+                                                        const float* __restrict__ dir, int n, float* __restrict__ out_t,
+                                                        int32_t* __restrict__ out_id, int32_t* __restrict__ out_front,
+                                                        int32_t* __restrict__ spill, uint32_t stride) {
+    extern __shared__ float4 smem[];
+    float4* top = smem;
+    int32_t* stack_area = (int32_t*)(smem + 4 * sc.top_count);
+    for (uint32_t i = threadIdx.x; i < 4 * sc.top_count; i += kBlock) top[i] = sc.nodes[i];
+    __syncthreads();
+    const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
+    Stack st;
+    st.lds = stack_area + threadIdx.x;
+    st.spill = spill + gtid;
+    st.stride = stride;
+    for (uint32_t r = gtid; r < (uint32_t)n; r += gridDim.x * kBlock) {
+        float o[3], d[3];
+        for (int c = 0; c < 3; ++c) { o[c] = org[3 * (size_t)r + c]; d[c] = dir[3 * (size_t)r + c]; }
+        Hit h;
+        h.t = INFINITY; h.id = INT_MAX; h.slot = 0; h.front = false;
+        uint32_t dn = 0, dt = 0;
+        if (sc.n_nodes > 0) traverse<false>(sc, top, o, d, st, h, dn, dt);
+        const bool hit = h.id != INT_MAX;
+        out_t[r] = hit ? h.t : INFINITY;
+        out_id[r] = hit ? h.id : -1;
+        if (out_front) out_front[r] = hit && h.front ? 1 : 0;
+    }
+}
+
+rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t spill_entries) {
+    Workspace& w = s->ws;
+    if (!w.counters) {
+        RCP_HIP(hipMalloc((void**)&w.counters, sizeof(uint32_t) * (2 * kMaxPasses + 8)));
+        RCP_HIP(hipMalloc((void**)&w.stats, sizeof(unsigned long long) * 4 * kMaxPasses));
+    }
+    if (n_state > w.state_cap) {
+        for (int i = 0; i < 2; ++i) {
+            if (w.state[i]) { RCP_HIP(hipFree(w.state[i])); w.state[i] = nullptr; }
+        }
+        w.state_cap = 0;
+        for (int i = 0; i < 2; ++i) RCP_HIP(hipMalloc((void**)&w.state[i], sizeof(float4) * n_state));
+        w.state_cap = n_state;
+    }
+    if (spill_entries > w.spill_cap) {
+        if (w.spill) { RCP_HIP(hipFree(w.spill)); w.spill = nullptr; }
+        w.spill_cap = 0;
+        RCP_HIP(hipMalloc((void**)&w.spill, sizeof(int32_t) * spill_entries));
+        w.spill_cap = spill_entries;
+    }
+    return RCP_OK;
+}
+
+struct GridInfo {
+    int blocks = 0;
+    size_t smem = 0;
+};
+
+template <typename KernelT>
+rcp_status persistent_grid(KernelT kernel, const DevScene& sc, GridInfo& g) {
+    g.smem = sizeof(float4) * 4 * (size_t)sc.top_count + sizeof(int32_t) * kStack * kBlock;
+    int per_cu = 0;
+    RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, g.smem));
+    int dev = 0, cus = 0;
+    RCP_HIP(hipGetDevice(&dev));
+    RCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (per_cu < 1) per_cu = 1;
+    g.blocks = per_cu * cus;
+    return RCP_OK;
+}
+
+}  // namespace
+
+rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, float le, float ld, float* out_images,
+                  int32_t* out_ids, const float* prev_rgb, unsigned long long* host_counts, hipStream_t stream) {
+    const bool stats = host_counts != nullptr;
+    GridInfo g;
+    if (stats) { rcp_status st = persistent_grid(k_pass<true>, s->dev, g); if (st) return st; }
+    else { rcp_status st = persistent_grid(k_pass<false>, s->dev, g); if (st) return st; }
+    const uint32_t threads = (uint32_t)g.blocks * kBlock;
+    const size_t P = (size_t)W * (size_t)H;
+    const size_t spill_depth = s->dev.max_depth > (uint32_t)kStack ? s->dev.max_depth - kStack + 1 : 1;
+    rcp_status st = ensure_workspace(s, K > 1 ? P : 1, spill_depth * threads);
+    if (st != RCP_OK) return st;
+    Workspace& w = s->ws;
+    hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(256), 0, stream, w.counters, 2 * kMaxPasses + 8,
+                       stats ? w.stats : (unsigned long long*)nullptr);
+    RCP_CHECK_LAUNCH();
+    const int tiles_x = (W + 7) / 8, tiles_y = (H + 7) / 8;
+    PassArgs a{};
+    a.sc = s->dev;
+    a.cam = cam;
+    a.W = W; a.H = H; a.K = K;
+    a.le = le; a.ld = ld;
+    a.n_items0 = (uint32_t)tiles_x * (uint32_t)tiles_y * 64u;
+    a.tiles_x = tiles_x;
+    a.counters = w.counters;
+    a.out = out_images;
+    a.ids = out_ids;
+    a.spill = w.spill;
+    a.spill_stride = threads;
+    a.stats = stats ? w.stats : nullptr;
+    for (int k = 0; k < K; ++k) {
+        a.k = k;
+        a.state_in = k == 0 ? nullptr : w.state[(k - 1) & 1];
+        a.prev_img = k == 0 ? prev_rgb : nullptr;
+        a.state_out = k + 1 < K ? w.state[k & 1] : nullptr;
+        if (stats) hipLaunchKernelGGL(k_pass<true>, dim3(g.blocks), dim3(kBlock), g.smem, stream, a);
+        else hipLaunchKernelGGL(k_pass<false>, dim3(g.blocks), dim3(kBlock), g.smem, stream, a);
+        RCP_CHECK_LAUNCH();
+    }
+    if (stats) {
+        RCP_HIP(hipMemcpyAsync(host_counts, w.stats, sizeof(unsigned long long) * 4 * K, hipMemcpyDeviceToHost,
+                               stream));
+        RCP_HIP(hipStreamSynchronize(stream));
+    }
+    return RCP_OK;
+}
+
+rcp_status generate_rays(const Camera& cam, int W, int H, float le, float ld, const float* prev_rgb, float* org,
+                         float* dir, hipStream_t stream) {
+    const size_t P = (size_t)W * (size_t)H;
+    hipLaunchKernelGGL(k_gen_rays, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, cam, W, H,
+                       le, ld, prev_rgb, org, dir);
+    RCP_CHECK_LAUNCH();
+    return RCP_OK;
+}
+
+rcp_status trace_rays(rcp_scene* s, const float* org, const float* dir, int n, float* out_t, int32_t* out_id,
+                      int32_t* out_front, hipStream_t stream) {
+    if (n == 0) return RCP_OK;
+    GridInfo g;
+    rcp_status st = persistent_grid(k_trace_rays, s->dev, g);
+    if (st != RCP_OK) return st;
+    const uint32_t threads = (uint32_t)g.blocks * kBlock;
+    const size_t spill_depth = s->dev.max_depth > (uint32_t)kStack ? s->dev.max_depth - kStack + 1 : 1;
+    st = ensure_workspace(s, 1, spill_depth * threads);
+    if (st != RCP_OK) return st;
+    hipLaunchKernelGGL(k_trace_rays, dim3(g.blocks), dim3(kBlock), g.smem, stream, s->dev, org, dir, n, out_t,
+                       out_id, out_front, s->ws.spill, threads);
+    RCP_CHECK_LAUNCH();
+    return RCP_OK;
+}
+
+}  // namespace rcp

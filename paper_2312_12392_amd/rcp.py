@@ -1,0 +1,306 @@
+"""ctypes binding of librcp.so (the C ABI in include/rcp.h).
+
+Argument marshalling only: every step of the render runs in the library's
+HIP kernels.  Device buffers are passed as torch CUDA tensors (or raw device
+addresses as ints); streams as torch streams, raw hipStream_t ints, or None
+for torch's current stream.  Functions keep the C names; each raises
+``RcpError`` when the call returns a status other than RCP_OK.
+
+There is no fallback: if librcp.so has not been built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librcp.so")
+
+RCP_OK = 0
+RCP_ERR_INVALID_ARGUMENT = 1
+RCP_ERR_OUT_OF_MEMORY = 2
+RCP_ERR_DEVICE = 3
+RCP_ERR_NOT_READY = 4
+RCP_ERR_QUEUE_FULL = 5
+RCP_ERR_INTERNAL = 6
+RCP_MODE_COLOR = 0
+
+# Every symbol include/rcp.h declares.
+EXPORTED = [
+    "rcp_build_scene", "rcp_destroy_scene", "rcp_scene_info", "rcp_render", "rcp_render_pass",
+    "rcp_render_stats", "rcp_generate_rays", "rcp_trace_rays", "rcp_export_bvh", "rcp_radix_sort_u64",
+    "rcp_status_string", "rcp_last_error",
+]
+
+
+class RcpError(RuntimeError):
+    def __init__(self, status: int, func: str, msg: str):
+        super().__init__(f"{func}: status {status} ({status_string(status)}): {msg}")
+        self.status = status
+
+
+class rcp_scene_desc(ctypes.Structure):
+    _fields_ = [("verts", ctypes.c_void_p), ("n_verts", ctypes.c_uint32), ("idx", ctypes.c_void_p),
+                ("n_tris", ctypes.c_uint32), ("tri_rgb", ctypes.c_void_p), ("light_dir", ctypes.c_float * 3),
+                ("k_a", ctypes.c_float), ("k_d", ctypes.c_float), ("background", ctypes.c_float * 3)]
+
+
+class rcp_camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("right", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("forward", ctypes.c_float * 3), ("tan_half_fovy", ctypes.c_float)]
+
+
+class rcp_displacement(ctypes.Structure):
+    _fields_ = [("lambda_eye", ctypes.c_float), ("lambda_dir", ctypes.c_float), ("mode", ctypes.c_int32),
+                ("z0", ctypes.c_float)]
+
+
+class rcp_build_options(ctypes.Structure):
+    _fields_ = [("max_leaf", ctypes.c_int32), ("top_levels", ctypes.c_int32), ("c_trav", ctypes.c_float),
+                ("c_isect", ctypes.c_float)]
+
+
+class rcp_scene_stats(ctypes.Structure):
+    _fields_ = [("n_tris", ctypes.c_uint32), ("n_nodes", ctypes.c_uint32), ("n_leaves", ctypes.c_uint32),
+                ("top_count", ctypes.c_uint32), ("max_depth", ctypes.c_uint32), ("max_leaf", ctypes.c_uint32),
+                ("sah_cost", ctypes.c_float), ("build_ms", ctypes.c_float), ("device_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load librcp.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build the HIP library first (python __graft_entry__.py build)")
+    L = ctypes.CDLL(p)
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int
+    st = ctypes.c_int
+    sig = {
+        "rcp_build_scene": (st, [ctypes.POINTER(rcp_scene_desc), ctypes.POINTER(rcp_build_options), P,
+                                 ctypes.POINTER(P)]),
+        "rcp_destroy_scene": (None, [P]),
+        "rcp_scene_info": (st, [P, ctypes.POINTER(rcp_scene_stats)]),
+        "rcp_render": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, i32, ctypes.POINTER(rcp_displacement), P, P, P]),
+        "rcp_render_pass": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, ctypes.POINTER(rcp_displacement), P, P, P,
+                                 P]),
+        "rcp_render_stats": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, i32, ctypes.POINTER(rcp_displacement), P,
+                                  P, P, P]),
+        "rcp_generate_rays": (st, [ctypes.POINTER(rcp_camera), i32, i32, ctypes.POINTER(rcp_displacement), P, P, P,
+                                   P]),
+        "rcp_trace_rays": (st, [P, P, P, i32, P, P, P, P]),
+        "rcp_export_bvh": (st, [P, P, P]),
+        "rcp_radix_sort_u64": (st, [P, P, i32, P]),
+        "rcp_status_string": (ctypes.c_char_p, [st]),
+        "rcp_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def status_string(s: int) -> str:
+    return load().rcp_status_string(int(s)).decode()
+
+
+def last_error() -> str:
+    return load().rcp_last_error().decode()
+
+
+def _check(status: int, func: str):
+    if status != RCP_OK:
+        raise RcpError(status, func, last_error())
+
+
+def _dev_ptr(t):
+    """Device address of a torch tensor (or an int address); None -> NULL."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("expected a device (CUDA/HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _f3(v):
+    return [float(x) for x in np.asarray(v, dtype=np.float32).reshape(3)]
+
+
+def make_camera(cam) -> rcp_camera:
+    """From any object with eye/right/up/forward/tan_half_fovy."""
+    c = rcp_camera()
+    c.eye[:] = _f3(cam.eye)
+    c.right[:] = _f3(cam.right)
+    c.up[:] = _f3(cam.up)
+    c.forward[:] = _f3(cam.forward)
+    c.tan_half_fovy = float(np.float32(cam.tan_half_fovy))
+    return c
+
+
+def make_displacement(lambda_eye: float, lambda_dir: float, mode: int = RCP_MODE_COLOR) -> rcp_displacement:
+    d = rcp_displacement()
+    d.lambda_eye = float(lambda_eye)
+    d.lambda_dir = float(lambda_dir)
+    d.mode = int(mode)
+    d.z0 = 0.0
+    return d
+
+
+# ---------------------------------------------------------------------------
+# The C entry points, one to one
+# ---------------------------------------------------------------------------
+
+def rcp_build_scene(scene, opts: rcp_build_options | None = None, stream=None) -> int:
+    """Build a device scene from host arrays (verts, idx, rgb, light, k_a,
+    k_d, background attributes).  Returns the opaque handle (int)."""
+    L = load()
+    verts = np.ascontiguousarray(scene.verts, dtype=np.float32)
+    idx = np.ascontiguousarray(scene.idx, dtype=np.uint32)
+    rgb = np.ascontiguousarray(scene.rgb, dtype=np.float32)
+    d = rcp_scene_desc()
+    d.verts = verts.ctypes.data
+    d.n_verts = verts.shape[0]
+    d.idx = idx.ctypes.data
+    d.n_tris = idx.shape[0]
+    d.tri_rgb = rgb.ctypes.data
+    d.light_dir[:] = _f3(scene.light)
+    d.k_a = float(scene.k_a)
+    d.k_d = float(scene.k_d)
+    d.background[:] = _f3(scene.background)
+    out = ctypes.c_void_p()
+    st = L.rcp_build_scene(ctypes.byref(d), ctypes.byref(opts) if opts is not None else None,
+                           _stream(stream), ctypes.byref(out))
+    _check(st, "rcp_build_scene")
+    return out.value
+
+
+def rcp_destroy_scene(handle: int) -> None:
+    load().rcp_destroy_scene(handle)
+
+
+def rcp_scene_info(handle: int) -> dict:
+    s = rcp_scene_stats()
+    _check(load().rcp_scene_info(handle, ctypes.byref(s)), "rcp_scene_info")
+    return s.as_dict()
+
+
+def rcp_render(handle: int, cam, W: int, H: int, K: int, disp: rcp_displacement, out_images, out_ids=None,
+               stream=None) -> None:
+    c = make_camera(cam)
+    st = load().rcp_render(handle, ctypes.byref(c), int(W), int(H), int(K), ctypes.byref(disp),
+                           _dev_ptr(out_images), _dev_ptr(out_ids), _stream(stream))
+    _check(st, "rcp_render")
+
+
+def rcp_render_pass(handle: int, cam, W: int, H: int, disp: rcp_displacement, prev_rgb, out_rgb, out_ids=None,
+                    stream=None) -> None:
+    c = make_camera(cam)
+    st = load().rcp_render_pass(handle, ctypes.byref(c), int(W), int(H), ctypes.byref(disp), _dev_ptr(prev_rgb),
+                                _dev_ptr(out_rgb), _dev_ptr(out_ids), _stream(stream))
+    _check(st, "rcp_render_pass")
+
+
+def rcp_render_stats(handle: int, cam, W: int, H: int, K: int, disp: rcp_displacement, out_images, out_ids=None,
+                     stream=None) -> np.ndarray:
+    """Returns uint64 [K][4]: rays traced, inner nodes visited, triangles
+    tested, rays appended for the next pass."""
+    c = make_camera(cam)
+    counts = np.zeros((K, 4), dtype=np.uint64)
+    st = load().rcp_render_stats(handle, ctypes.byref(c), int(W), int(H), int(K), ctypes.byref(disp),
+                                 _dev_ptr(out_images), _dev_ptr(out_ids), counts.ctypes.data, _stream(stream))
+    _check(st, "rcp_render_stats")
+    return counts
+
+
+def rcp_generate_rays(cam, W: int, H: int, disp: rcp_displacement, prev_rgb, out_org, out_dir, stream=None) -> None:
+    c = make_camera(cam)
+    st = load().rcp_generate_rays(ctypes.byref(c), int(W), int(H), ctypes.byref(disp), _dev_ptr(prev_rgb),
+                                  _dev_ptr(out_org), _dev_ptr(out_dir), _stream(stream))
+    _check(st, "rcp_generate_rays")
+
+
+def rcp_trace_rays(handle: int, org, dirs, n: int, out_t, out_id, out_front=None, stream=None) -> None:
+    st = load().rcp_trace_rays(handle, _dev_ptr(org), _dev_ptr(dirs), int(n), _dev_ptr(out_t), _dev_ptr(out_id),
+                               _dev_ptr(out_front), _stream(stream))
+    _check(st, "rcp_trace_rays")
+
+
+def rcp_export_bvh(handle: int):
+    """Returns (nodes uint32 [n_nodes][16], tri_ids int32 [n_tris]) on the host."""
+    info = rcp_scene_info(handle)
+    nodes = np.zeros((info["n_nodes"], 16), dtype=np.uint32)
+    tri_ids = np.zeros(info["n_tris"], dtype=np.int32)
+    st = load().rcp_export_bvh(handle, nodes.ctypes.data if nodes.size else None,
+                               tri_ids.ctypes.data if tri_ids.size else None)
+    _check(st, "rcp_export_bvh")
+    return nodes, tri_ids
+
+
+def rcp_radix_sort_u64(keys, vals, n: int, stream=None) -> None:
+    st = load().rcp_radix_sort_u64(_dev_ptr(keys), _dev_ptr(vals), int(n), _stream(stream))
+    _check(st, "rcp_radix_sort_u64")
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper
+# ---------------------------------------------------------------------------
+
+def build_options(max_leaf: int = 4, top_levels: int = 8, c_trav: float = 1.0, c_isect: float = 1.0):
+    o = rcp_build_options()
+    o.max_leaf, o.top_levels, o.c_trav, o.c_isect = int(max_leaf), int(top_levels), float(c_trav), float(c_isect)
+    return o
+
+
+class Scene:
+    """Device scene owned by Python; destroyed with the object."""
+
+    def __init__(self, scene, opts: rcp_build_options | None = None, stream=None):
+        self.handle = rcp_build_scene(scene, opts, stream)
+
+    def info(self) -> dict:
+        return rcp_scene_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            rcp_destroy_scene(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def render(self, cam, W, H, K, lambda_eye, lambda_dir, with_ids=True, stream=None):
+        """Allocate outputs with torch and render; returns (images, ids)."""
+        import torch
+        imgs = torch.empty((K, H, W, 3), dtype=torch.float32, device="cuda")
+        ids = torch.empty((K, H, W), dtype=torch.int32, device="cuda") if with_ids else None
+        rcp_render(self.handle, cam, W, H, K, make_displacement(lambda_eye, lambda_dir), imgs, ids, stream)
+        return imgs, ids
