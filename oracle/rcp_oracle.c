@@ -56,6 +56,7 @@ struct orc_scene {
     float light[3];
     float k_a, k_d;
     float background[3];
+    double radius;         /* largest |coordinate| of any vertex */
     obvh_node* nodes;      /* NULL => brute force */
     int32_t n_nodes, n_leaves, max_depth;
     int32_t* order;        /* triangle IDs in leaf order */
@@ -193,6 +194,8 @@ orc_scene* orc_scene_create(const orc_scene_desc* d, int use_bvh) {
             if (!finite3(&d->verts[3 * v])) { orc_scene_destroy(s); return NULL; }
         }
         memcpy(&s->rgb[3 * i], &d->rgb[3 * i], 3 * sizeof(float));
+        for (int k = 0; k < 9; ++k)
+            if (fabs((double)s->tri[9 * i + k]) > s->radius) s->radius = fabs((double)s->tri[9 * i + k]);
     }
     memcpy(s->light, d->light, sizeof s->light);
     s->k_a = d->k_a;
@@ -351,13 +354,18 @@ static int closest_brute(const orc_scene* s, const float o[3], const float d[3],
     return found;
 }
 
-/* Conservative slab test in double with generous slack: the BVH only prunes
- * boxes that the ray cannot reach before the current best hit. */
-static int slab(const obvh_node* nd, const double o[3], const double inv[3], double tmax_prune,
-                double* tenter) {
-    double t0 = 0.0, t1 = INFINITY;
+/* The BVH only speeds up the brute-force definition, so its box tests must
+ * never reject a box holding the closest watertight hit:
+ *  - the float watertight test accepts rays passing within a few ulp of
+ *    (|v| + |o|) of a triangle, so boxes are widened by 2^-18 (R + max|o|);
+ *  - a box is skipped as "farther than the best hit" only by the entry of the
+ *    slab of the ray's dominant axis kz: the watertight t is a weighted mean
+ *    of the vertices' kz distances, never below that entry, whatever the
+ *    ray's angle (the full box entry is no such bound for grazing rays). */
+static int slab(const obvh_node* nd, const double o[3], const double inv[3], double pad, int kz,
+                double tmax_prune) {
+    double t0 = 0.0, t1 = INFINITY, tk = -INFINITY;
     for (int c = 0; c < 3; ++c) {
-        double pad = 1e-6 * (fabs((double)nd->lo[c]) + fabs((double)nd->hi[c])) + 1e-12;
         double lo = (double)nd->lo[c] - pad, hi = (double)nd->hi[c] + pad;
         double a, b;
         if (isinf(inv[c])) {
@@ -369,34 +377,37 @@ static int slab(const obvh_node* nd, const double o[3], const double inv[3], dou
         if (a > b) { double tmp = a; a = b; b = tmp; }
         if (a > t0) t0 = a;
         if (b < t1) t1 = b;
+        if (c == kz) tk = a;
     }
-    t0 = t0 * (1.0 - 1e-6) - 1e-12;
-    t1 = t1 * (1.0 + 1e-6) + 1e-12;
-    if (t0 > t1 || t0 > tmax_prune) return 0;
-    *tenter = t0;
+    if (t0 > t1 * (1.0 + 1e-9)) return 0;
+    if (tk > tmax_prune) return 0;
     return 1;
 }
 
 static int closest_bvh(const orc_scene* s, const float o[3], const float d[3],
                        float* t_out, int32_t* id_out, int* front_out) {
     double od[3], inv[3];
+    double omax = 0.0;
     for (int c = 0; c < 3; ++c) {
         od[c] = o[c];
         inv[c] = (d[c] == 0.0f) ? INFINITY : 1.0 / (double)d[c];
+        if (fabs(od[c]) > omax) omax = fabs(od[c]);
     }
+    int kz = 0;                                   /* dominant axis, as in orc_intersect */
+    if (fabsf(d[1]) > fabsf(d[kz])) kz = 1;
+    if (fabsf(d[2]) > fabsf(d[kz])) kz = 2;
+    const double pad = ldexp(s->radius + omax, -18);
     int found = 0;
     float best = INFINITY;
     int32_t best_id = -1;
     int best_front = 0;
     int32_t stack[256];
     int sp = 0;
-    double te;
-    if (!slab(&s->nodes[0], od, inv, INFINITY, &te)) return 0;
     stack[sp++] = 0;
     while (sp > 0) {
         const obvh_node* nd = &s->nodes[stack[--sp]];
-        double prune = found ? (double)best * (1.0 + 1e-6) + 1e-12 : INFINITY;
-        if (!slab(nd, od, inv, prune, &te)) continue;
+        double prune = found ? (double)best * (1.0 + 1e-5) : INFINITY;
+        if (!slab(nd, od, inv, pad, kz, prune)) continue;
         if (nd->count > 0) {
             for (int32_t k = nd->first; k < nd->first + nd->count; ++k) {
                 int32_t id = s->order[k];

@@ -646,6 +646,9 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     s->dev.nodes = s->nodes;
     s->dev.tris = s->tris;
     s->dev.shade = s->shade;
+    float radius = 0.0f;
+    for (size_t i = 0; i < 3 * (size_t)desc->n_verts && n > 0; ++i) radius = fmaxf(radius, fabsf(desc->verts[i]));
+    s->dev.radius = radius;
     s->dev.n_nodes = n_nodes;
     s->dev.n_tris = n;
     s->dev.top_count = top_count;

@@ -59,6 +59,7 @@ struct DevScene {
     uint32_t n_tris;
     uint32_t top_count;
     uint32_t max_depth;
+    float radius;      // largest |coordinate| of any vertex
     float bg[3];
 };
 

@@ -190,18 +190,31 @@ struct Stack {
     }
 };
 
+// Box tests never decide a result, they only prune, so they are built to
+// never reject a box that holds the closest hit of the watertight test:
+//  - the watertight test accepts rays passing within about 4 ulp of
+//    (|v| + |o|) of a triangle, so every box is widened by
+//    2^-18 (R + max|o|) on each side (R: largest |coordinate| in the scene),
+//    folded into one origin per slab side;
+//  - the test against the best hit so far uses only the slab of the ray's
+//    dominant axis kz: the watertight t is a weighted mean of the vertices'
+//    kz distances, so it is never below that slab's entry, whatever the ray's
+//    angle to the triangle (the full box entry is not such a bound for
+//    grazing rays);
+//  - zero direction components use a large finite reciprocal (no inf * 0).
 template <bool STATS>
 __device__ inline void traverse(const DevScene& sc, const float4* __restrict__ top, const float o[3],
                                 const float d[3], Stack& st, Hit& h, uint32_t& n_nodes, uint32_t& n_tris) {
     const RayW rw = ray_setup(o, d);
     float inv[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float da = fabsf(d[a]) > 1e-20f ? d[a] : copysignf(1e-20f, d[a]);
-        inv[a] = 1.0f / da;
-    }
-    const float ox = o[0], oy = o[1], oz = o[2];
+    for (int a = 0; a < 3; ++a) inv[a] = fabsf(d[a]) > 1e-30f ? 1.0f / d[a] : copysignf(1e30f, d[a]);
+    const float pad = (sc.radius + fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]))) * 3.814697265625e-6f;
+    const float lx = o[0] + pad, hx = o[0] - pad;    // origin used against lo / hi planes
+    const float ly = o[1] + pad, hy = o[1] - pad;
+    const float lz = o[2] + pad, hz = o[2] - pad;
     const float ix = inv[0], iy = inv[1], iz = inv[2];
+    const int kz = rw.kz;
     int32_t node = 0;
     st.sp = 0;
     st.lo = 0;
@@ -227,19 +240,23 @@ __device__ inline void traverse(const DevScene& sc, const float4* __restrict__ t
             if (STATS) ++n_nodes;
             const float lim = h.t * kSlack;
             // child 0
-            const float a0 = (n0.x - ox) * ix, a1 = (n0.y - ox) * ix;
-            const float a2 = (n0.z - oy) * iy, a3 = (n0.w - oy) * iy;
-            const float a4 = (n2.x - oz) * iz, a5 = (n2.y - oz) * iz;
-            const float tmin0 = fmaxf(fmaxf(fminf(a0, a1), fminf(a2, a3)), fmaxf(fminf(a4, a5), 0.0f));
+            const float a0 = (n0.x - lx) * ix, a1 = (n0.y - hx) * ix;
+            const float a2 = (n0.z - ly) * iy, a3 = (n0.w - hy) * iy;
+            const float a4 = (n2.x - lz) * iz, a5 = (n2.y - hz) * iz;
+            const float ex0 = fminf(a0, a1), ey0 = fminf(a2, a3), ez0 = fminf(a4, a5);
+            const float tmin0 = fmaxf(fmaxf(ex0, ey0), fmaxf(ez0, 0.0f));
             const float tmax0 = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
+            const float near0 = kz == 0 ? ex0 : (kz == 1 ? ey0 : ez0);
             // child 1
-            const float b0 = (n1.x - ox) * ix, b1 = (n1.y - ox) * ix;
-            const float b2 = (n1.z - oy) * iy, b3 = (n1.w - oy) * iy;
-            const float b4 = (n2.z - oz) * iz, b5 = (n2.w - oz) * iz;
-            const float tmin1 = fmaxf(fmaxf(fminf(b0, b1), fminf(b2, b3)), fmaxf(fminf(b4, b5), 0.0f));
+            const float b0 = (n1.x - lx) * ix, b1 = (n1.y - hx) * ix;
+            const float b2 = (n1.z - ly) * iy, b3 = (n1.w - hy) * iy;
+            const float b4 = (n2.z - lz) * iz, b5 = (n2.w - hz) * iz;
+            const float ex1 = fminf(b0, b1), ey1 = fminf(b2, b3), ez1 = fminf(b4, b5);
+            const float tmin1 = fmaxf(fmaxf(ex1, ey1), fmaxf(ez1, 0.0f));
             const float tmax1 = fminf(fminf(fmaxf(b0, b1), fmaxf(b2, b3)), fmaxf(b4, b5)) * kSlack;
-            const bool hit0 = tmin0 <= tmax0 && tmin0 <= lim;
-            const bool hit1 = tmin1 <= tmax1 && tmin1 <= lim;
+            const float near1 = kz == 0 ? ex1 : (kz == 1 ? ey1 : ez1);
+            const bool hit0 = tmin0 <= tmax0 && near0 <= lim;
+            const bool hit1 = tmin1 <= tmax1 && near1 <= lim;
             const int32_t c0 = __float_as_int(n3.x);
             const int32_t c1 = __float_as_int(n3.y);
             if (hit0 && hit1) {

@@ -1,0 +1,169 @@
+"""GPU BVH build: structural invariants of the packed tree and the radix sort."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from paper_2312_12392_amd import rcp
+
+pytestmark = pytest.mark.gpu
+
+LEAF = 0x80000000
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.set_device(0)
+    rcp.load()
+
+
+def tri_boxes(scene):
+    v = scene.verts[scene.idx.astype(np.int64)]          # [n, 3, 3]
+    return v.min(1), v.max(1)
+
+
+def node_boxes(nodes):
+    """Child boxes [n][2][2][3] (child, lo/hi, axis) and links [n][2]."""
+    f = nodes.view(np.float32)
+    lo = np.stack([f[:, [0, 2, 8]], f[:, [4, 6, 10]]], axis=1)
+    hi = np.stack([f[:, [1, 3, 9]], f[:, [5, 7, 11]]], axis=1)
+    return lo, hi, nodes[:, 12:14].astype(np.int64)
+
+
+def check_bvh(scene, info, nodes, tri_ids):
+    n = scene.n_tris
+    assert info["n_tris"] == n
+    # packed triangle slots hold a permutation of the triangles
+    assert np.array_equal(np.sort(tri_ids), np.arange(n))
+    if n == 0:
+        assert info["n_nodes"] == 0
+        return
+    nn = info["n_nodes"]
+    lo, hi, links = node_boxes(nodes)
+    lo_t, hi_t = tri_boxes(scene)
+    lo_t, hi_t = lo_t[tri_ids], hi_t[tri_ids]
+    is_leaf = (links & LEAF) != 0
+    # leaves: range inside the triangles, size within the bound, boxes contain them
+    lf = links[is_leaf]
+    first = (lf >> 3) & 0x0FFFFFFF
+    cnt = (lf & 7) + 1
+    assert (first + cnt <= n).all()
+    assert (cnt <= info["max_leaf"]).all() or nn == 1
+    owner_lo = np.repeat(lo[is_leaf], cnt, axis=0)
+    owner_hi = np.repeat(hi[is_leaf], cnt, axis=0)
+    slots = np.concatenate([np.arange(a, a + c) for a, c in zip(first, cnt)])
+    assert (lo_t[slots] >= owner_lo).all() and (hi_t[slots] <= owner_hi).all()
+    covered = np.bincount(slots, minlength=n)
+    if nn == 1 and links[0, 0] == links[0, 1]:
+        assert (covered == 2).all()                   # one leaf referenced by both children
+    else:
+        assert (covered == 1).all()                   # every triangle in exactly one leaf
+        assert int(is_leaf.sum()) == info["n_leaves"]
+    # inner children: valid index, one parent each, box contains the child's boxes
+    inner = links[~is_leaf]
+    assert ((inner > 0) & (inner < nn)).all()
+    parents = np.bincount(inner, minlength=nn)
+    assert parents[0] == 0 and (parents[1:] == 1).all()
+    par_lo = lo[~is_leaf]
+    par_hi = hi[~is_leaf]
+    assert (lo[inner].min(axis=1) >= par_lo).all() and (hi[inner].max(axis=1) <= par_hi).all()
+    # acyclic: a breadth-first sweep from the root reaches every node
+    depth = np.full(nn, -1)
+    depth[0] = 0
+    frontier = np.array([0])
+    d = 0
+    while frontier.size:
+        ch = links[frontier].reshape(-1)
+        ch = ch[(ch & LEAF) == 0]
+        d += 1
+        depth[ch] = d
+        frontier = ch
+    assert (depth >= 0).all()
+    assert info["max_depth"] == depth.max() + 1
+    assert info["top_count"] <= nn
+
+
+@pytest.mark.parametrize("name,scene_fn", [
+    ("empty", scenegen.empty_scene),
+    ("one", lambda: scenegen.soup_scene(1, 1)),
+    ("three", lambda: scenegen.soup_scene(1, 3)),
+    ("nine", lambda: scenegen.soup_scene(1, 9)),
+    ("soup256", lambda: scenegen.soup_scene(0, 256)),
+    ("adversarial", scenegen.adversarial_scene),
+    ("patch", lambda: scenegen.terrain_patch(11, 24, 8)),
+    ("duplicates", lambda: scenegen.Scene(verts=np.tile(scenegen.soup_scene(5, 1).verts, (1, 1)),
+                                          idx=np.zeros((700, 3), np.uint32) + np.array([0, 1, 2], np.uint32),
+                                          rgb=np.full((700, 3), 0.3, np.float32))),
+    ("terrain1m", lambda: scenegen.workload("terrain1m").scene),
+])
+def test_bvh_invariants(name, scene_fn):
+    say("bvh", name)
+    sc = scene_fn()
+    s = rcp.Scene(sc)
+    info = s.info()
+    nodes, tri_ids = rcp.rcp_export_bvh(s.handle)
+    check_bvh(sc, info, nodes, tri_ids)
+    s.close()
+
+
+@pytest.mark.parametrize("top_levels", [0, 1, 5, 9])
+def test_top_levels_are_breadth_first_prefix(top_levels):
+    say("top levels", top_levels)
+    sc = scenegen.terrain_patch(12, 40, 20)
+    s = rcp.Scene(sc, rcp.build_options(top_levels=top_levels))
+    info = s.info()
+    nodes, _ = rcp.rcp_export_bvh(s.handle)
+    # breadth-first depths of inner nodes, from the root
+    depth = {0: 0}
+    order = [0]
+    for ni in order:
+        for c in range(2):
+            link = int(nodes[ni, 12 + c])
+            if not link & LEAF:
+                depth[link] = depth[ni] + 1
+                order.append(link)
+    top = sorted(i for i, d in depth.items() if d < top_levels)
+    assert info["top_count"] == len(top)
+    assert top == list(range(len(top)))              # they occupy the first slots
+    for i in range(1, len(top)):
+        assert depth[i] >= depth[i - 1]              # in breadth-first order
+    assert info["max_depth"] == max(depth.values()) + 1
+    s.close()
+
+
+@pytest.mark.parametrize("n,bits,seed", [(2, 64, 0), (1000, 64, 1), (2049, 8, 2), (4096, 20, 3), (100003, 64, 4),
+                                         (1 << 20, 63, 5)])
+def test_radix_sort_is_a_stable_sort(n, bits, seed):
+    say("radix sort", n, bits)
+    rng = np.random.default_rng(seed)
+    keys = rng.integers(0, 2 ** 63 - 1, size=n, dtype=np.int64).astype(np.uint64)
+    if bits < 64:
+        keys &= np.uint64((1 << bits) - 1)
+    keys[::3] = keys[0]                              # many duplicates
+    vals = np.arange(n, dtype=np.uint32)
+    tk = torch.from_numpy(keys.view(np.int64)).cuda()
+    tv = torch.from_numpy(vals.view(np.int32)).cuda()
+    rcp.rcp_radix_sort_u64(tk, tv, n)
+    torch.cuda.synchronize()
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(tk.cpu().numpy().view(np.uint64), keys[order])
+    assert np.array_equal(tv.cpu().numpy().view(np.uint32), vals[order])
+
+
+def test_sah_cost_reported_and_leaf_bound():
+    say("sah")
+    sc = scenegen.terrain_patch(12, 40, 20)
+    costs = []
+    for ml in (1, 4, 8):
+        s = rcp.Scene(sc, rcp.build_options(max_leaf=ml))
+        info = s.info()
+        assert info["max_leaf"] == ml and info["sah_cost"] > 0
+        costs.append(info["sah_cost"])
+        s.close()
+    # a larger leaf bound only adds options to the collapse: never worse
+    assert costs[1] <= costs[0] * (1 + 1e-5) and costs[2] <= costs[1] * (1 + 1e-5)

@@ -505,3 +505,16 @@ def test_displaced_passes_differ_and_stay_ldr(oracle_lib, patch):
     d = [float(np.mean(np.abs(img[k] - img[0]))) for k in range(6)]
     assert d[0] == 0.0 and min(d[1:]) > 0.0
     assert img.min() >= 0.0 and img.max() <= 1.0
+
+
+@pytest.mark.parametrize("W,H,eye", [(67, 45, [0, 0.5, -1.4]), (33, 33, [0, 0.3, -2.0]), (64, 48, [0.25, 0.6, -1.2])])
+def test_bvh_equals_bruteforce_on_grid_plane_rays(oracle_lib, W, H, eye):
+    """Camera rays whose direction has an exactly zero component and that lie
+    in a grid plane of the terrain (odd W: the centre column is the plane
+    x = 0) hit two triangles at the same t; the lower index must win through
+    the BVH exactly as in the brute-force scan."""
+    sc = scenegen.terrain_patch(11, 24, 8)
+    cam = scenegen.camera_look_at(eye, [eye[0], 0.05, 0], [0, 1, 0], 60.0)
+    a, ia = oracle.OracleScene(sc, use_bvh=True).render(cam, W, H, 3, 0.0, 0.05)
+    b, ib = oracle.OracleScene(sc, use_bvh=False).render(cam, W, H, 3, 0.0, 0.05)
+    assert np.array_equal(a, b) and np.array_equal(ia, ib)
