@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--workload", default="terrain1m")
     ap.add_argument("--literal-eye", action="store_true", help="displace the eye as well (lambda_eye = lambda)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-leaf", type=int, default=None, help="BVH leaf size bound (build option)")
+    ap.add_argument("--top-levels", type=int, default=None, help="BVH levels staged in LDS (build option)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -106,7 +108,11 @@ def main():
     stream = torch.cuda.current_stream()
     w = scenegen.workload(args.workload, literal_eye=args.literal_eye)
     log(f"workload {w.name}: {w.width}x{w.height} K={w.passes} tris={w.scene.n_tris}")
-    scene = rcp.Scene(w.scene)
+    opts = None
+    if args.max_leaf is not None or args.top_levels is not None:
+        opts = rcp.build_options(max_leaf=args.max_leaf or 4,
+                                 top_levels=6 if args.top_levels is None else args.top_levels)
+    scene = rcp.Scene(w.scene, opts)
     info = scene.info()
     log(f"scene built: {info}")
     K, W, H = w.passes, w.width, w.height

@@ -106,7 +106,7 @@ typedef struct {
 
 /* Build options (NULL = defaults).  max_leaf: most triangles per BVH leaf
  * (1..8, default 4); top_levels: BVH levels staged in LDS by the traversal
- * (0..9, default 8); c_trav, c_isect: SAH costs of a node visit and a
+ * (0..9, default 6); c_trav, c_isect: SAH costs of a node visit and a
  * triangle test (defaults 1, 1). */
 typedef struct {
     int32_t max_leaf;

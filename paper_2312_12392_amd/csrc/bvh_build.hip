@@ -480,7 +480,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                        rcp_scene** out) {
     const uint32_t n = desc->n_tris;
     const int max_leaf = opts ? opts->max_leaf : 4;
-    const int top_levels = opts ? opts->top_levels : 8;
+    const int top_levels = opts ? opts->top_levels : 6;
     const float c_trav = opts ? opts->c_trav : 1.0f;
     const float c_isect = opts ? opts->c_isect : 1.0f;
 

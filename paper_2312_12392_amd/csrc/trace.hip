@@ -23,6 +23,7 @@
 // correctly rounded division and square root.  The box tests only prune and
 // are widened so that they never reject a box the exact test would accept.
 #include <climits>
+#include <cstdlib>
 
 #include "rcp_internal.hpp"
 
@@ -39,6 +40,7 @@ struct PassArgs {
     int W, H, K, k;
     float le, ld;
     uint32_t n_items0;              // pass-0 items (8x8 tiles * 64)
+    int refill_min;                 // idle lanes that trigger a refill (1..64)
     int tiles_x;
     const float4* state_in;         // pass > 0: {pix bits, r, g, b}
     const float* prev_img;          // pass 0: previous image or NULL (grey seed)
@@ -202,76 +204,99 @@ struct Stack {
 //    angle to the triangle (the full box entry is not such a bound for
 //    grazing rays);
 //  - zero direction components use a large finite reciprocal (no inf * 0).
-template <bool STATS>
-__device__ inline void traverse(const DevScene& sc, const float4* __restrict__ top, const float o[3],
-                                const float d[3], Stack& st, Hit& h, uint32_t& n_nodes, uint32_t& n_tris) {
-    const RayW rw = ray_setup(o, d);
+//
+// The traversal state of one ray lives in registers (plus its stack), so a
+// lane can advance its ray one step at a time and take a new ray as soon as
+// the current one is finished.
+struct Trav {
+    RayW rw;
+    float ix, iy, iz;       // reciprocal direction
+    float lx, ly, lz;       // origin used against lo planes (o + pad)
+    float hx, hy, hz;       // origin used against hi planes (o - pad)
+    int32_t node;           // >= 0 inner node, other negative: leaf link, -1: finished
+    uint32_t budget;
+    Hit h;
+};
+
+__device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3], const float d[3], Stack& st) {
+    tv.rw = ray_setup(o, d);
     float inv[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) inv[a] = fabsf(d[a]) > 1e-30f ? 1.0f / d[a] : copysignf(1e30f, d[a]);
+    tv.ix = inv[0]; tv.iy = inv[1]; tv.iz = inv[2];
     const float pad = (sc.radius + fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]))) * 3.814697265625e-6f;
-    const float lx = o[0] + pad, hx = o[0] - pad;    // origin used against lo / hi planes
-    const float ly = o[1] + pad, hy = o[1] - pad;
-    const float lz = o[2] + pad, hz = o[2] - pad;
-    const float ix = inv[0], iy = inv[1], iz = inv[2];
-    const int kz = rw.kz;
-    int32_t node = 0;
-    st.sp = 0;
-    st.lo = 0;
+    tv.lx = o[0] + pad; tv.hx = o[0] - pad;
+    tv.ly = o[1] + pad; tv.hy = o[1] - pad;
+    tv.lz = o[2] + pad; tv.hz = o[2] - pad;
+    tv.node = sc.n_nodes > 0 ? 0 : -1;
     // Every node and leaf is entered at most once per ray; the bound only
     // guarantees termination should the tree ever be malformed.
-    uint32_t budget = 2u * sc.n_nodes + 16u;
-    for (;;) {
-        while (node >= 0) {
-            if (--budget == 0u) return;
-            float4 n0, n1, n2, n3;
-            if ((uint32_t)node < sc.top_count) {
-                n0 = top[4 * node + 0];
-                n1 = top[4 * node + 1];
-                n2 = top[4 * node + 2];
-                n3 = top[4 * node + 3];
-            } else {
-                const float4* p = sc.nodes + 4 * (size_t)node;
-                n0 = p[0];
-                n1 = p[1];
-                n2 = p[2];
-                n3 = p[3];
-            }
-            if (STATS) ++n_nodes;
-            const float lim = h.t * kSlack;
-            // child 0
-            const float a0 = (n0.x - lx) * ix, a1 = (n0.y - hx) * ix;
-            const float a2 = (n0.z - ly) * iy, a3 = (n0.w - hy) * iy;
-            const float a4 = (n2.x - lz) * iz, a5 = (n2.y - hz) * iz;
-            const float ex0 = fminf(a0, a1), ey0 = fminf(a2, a3), ez0 = fminf(a4, a5);
-            const float tmin0 = fmaxf(fmaxf(ex0, ey0), fmaxf(ez0, 0.0f));
-            const float tmax0 = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
-            const float near0 = kz == 0 ? ex0 : (kz == 1 ? ey0 : ez0);
-            // child 1
-            const float b0 = (n1.x - lx) * ix, b1 = (n1.y - hx) * ix;
-            const float b2 = (n1.z - ly) * iy, b3 = (n1.w - hy) * iy;
-            const float b4 = (n2.z - lz) * iz, b5 = (n2.w - hz) * iz;
-            const float ex1 = fminf(b0, b1), ey1 = fminf(b2, b3), ez1 = fminf(b4, b5);
-            const float tmin1 = fmaxf(fmaxf(ex1, ey1), fmaxf(ez1, 0.0f));
-            const float tmax1 = fminf(fminf(fmaxf(b0, b1), fmaxf(b2, b3)), fmaxf(b4, b5)) * kSlack;
-            const float near1 = kz == 0 ? ex1 : (kz == 1 ? ey1 : ez1);
-            const bool hit0 = tmin0 <= tmax0 && near0 <= lim;
-            const bool hit1 = tmin1 <= tmax1 && near1 <= lim;
-            const int32_t c0 = __float_as_int(n3.x);
-            const int32_t c1 = __float_as_int(n3.y);
-            if (hit0 && hit1) {
-                const bool first0 = tmin0 <= tmin1;
-                st.push(first0 ? c1 : c0);
-                node = first0 ? c0 : c1;
-            } else if (hit0) {
-                node = c0;
-            } else if (hit1) {
-                node = c1;
-            } else {
-                node = st.pop();
-            }
+    tv.budget = 2u * sc.n_nodes + 16u;
+    tv.h.t = INFINITY;
+    tv.h.id = INT_MAX;
+    tv.h.slot = 0;
+    tv.h.front = false;
+    st.sp = 0;
+    st.lo = 0;
+}
+
+// One step: descend through inner nodes until a leaf (or the end), then test
+// that leaf's triangles.  Sets tv.node = -1 once the ray is finished.
+template <bool STATS>
+__device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* __restrict__ top, Stack& st,
+                                 uint32_t& n_nodes, uint32_t& n_tris) {
+    int32_t node = tv.node;
+    const int kz = tv.rw.kz;
+    while (node >= 0) {
+        if (--tv.budget == 0u) { node = -1; break; }
+        float4 n0, n1, n2, n3;
+        if ((uint32_t)node < sc.top_count) {
+            n0 = top[4 * node + 0];
+            n1 = top[4 * node + 1];
+            n2 = top[4 * node + 2];
+            n3 = top[4 * node + 3];
+        } else {
+            const float4* p = sc.nodes + 4 * (size_t)node;
+            n0 = p[0];
+            n1 = p[1];
+            n2 = p[2];
+            n3 = p[3];
         }
-        if (node == -1) break;
+        if (STATS) ++n_nodes;
+        const float lim = tv.h.t * kSlack;
+        // child 0
+        const float a0 = (n0.x - tv.lx) * tv.ix, a1 = (n0.y - tv.hx) * tv.ix;
+        const float a2 = (n0.z - tv.ly) * tv.iy, a3 = (n0.w - tv.hy) * tv.iy;
+        const float a4 = (n2.x - tv.lz) * tv.iz, a5 = (n2.y - tv.hz) * tv.iz;
+        const float ex0 = fminf(a0, a1), ey0 = fminf(a2, a3), ez0 = fminf(a4, a5);
+        const float tmin0 = fmaxf(fmaxf(ex0, ey0), fmaxf(ez0, 0.0f));
+        const float tmax0 = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
+        const float near0 = kz == 0 ? ex0 : (kz == 1 ? ey0 : ez0);
+        // child 1
+        const float b0 = (n1.x - tv.lx) * tv.ix, b1 = (n1.y - tv.hx) * tv.ix;
+        const float b2 = (n1.z - tv.ly) * tv.iy, b3 = (n1.w - tv.hy) * tv.iy;
+        const float b4 = (n2.z - tv.lz) * tv.iz, b5 = (n2.w - tv.hz) * tv.iz;
+        const float ex1 = fminf(b0, b1), ey1 = fminf(b2, b3), ez1 = fminf(b4, b5);
+        const float tmin1 = fmaxf(fmaxf(ex1, ey1), fmaxf(ez1, 0.0f));
+        const float tmax1 = fminf(fminf(fmaxf(b0, b1), fmaxf(b2, b3)), fmaxf(b4, b5)) * kSlack;
+        const float near1 = kz == 0 ? ex1 : (kz == 1 ? ey1 : ez1);
+        const bool hit0 = tmin0 <= tmax0 && near0 <= lim;
+        const bool hit1 = tmin1 <= tmax1 && near1 <= lim;
+        const int32_t c0 = __float_as_int(n3.x);
+        const int32_t c1 = __float_as_int(n3.y);
+        if (hit0 && hit1) {
+            const bool first0 = tmin0 <= tmin1;
+            st.push(first0 ? c1 : c0);
+            node = first0 ? c0 : c1;
+        } else if (hit0) {
+            node = c0;
+        } else if (hit1) {
+            node = c1;
+        } else {
+            node = st.pop();
+        }
+    }
+    if (node != -1) {
         // leaf: triangles [first, first + count)
         const uint32_t first = ((uint32_t)node >> 3) & 0x0FFFFFFFu;
         const uint32_t count = ((uint32_t)node & 7u) + 1u;
@@ -281,30 +306,36 @@ __device__ inline void traverse(const DevScene& sc, const float4* __restrict__ t
             if (STATS) ++n_tris;
             float t;
             bool front;
-            if (hit_triangle(rw, v0, v1, v2, t, front)) {
+            if (hit_triangle(tv.rw, v0, v1, v2, t, front)) {
                 const int32_t id = __float_as_int(v0.w);
-                if (t < h.t || (t == h.t && id < h.id)) {
-                    h.t = t;
-                    h.id = id;
-                    h.slot = first + j;
-                    h.front = front;
+                if (t < tv.h.t || (t == tv.h.t && id < tv.h.id)) {
+                    tv.h.t = t;
+                    tv.h.id = id;
+                    tv.h.slot = first + j;
+                    tv.h.front = front;
                 }
             }
         }
         node = st.pop();
     }
+    tv.node = node;
 }
+
+constexpr int kWaves = kBlock / 64;
+constexpr int kStage = 128;     // per-wave staging of appended entries (flushed 64 at a time)
 
 template <bool STATS>
 __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
     extern __shared__ float4 smem[];
-    float4* top = smem;                                               // top_count * 4 float4
-    int32_t* stack_area = (int32_t*)(smem + 4 * a.sc.top_count);      // kStack * kBlock ints
+    float4* top = smem;                                                 // top_count * 4
+    float4* stage_all = smem + 4 * a.sc.top_count;                      // kWaves * kStage
+    int32_t* stack_area = (int32_t*)(stage_all + kWaves * kStage);      // kStack * kBlock
 
     for (uint32_t i = threadIdx.x; i < 4 * a.sc.top_count; i += kBlock) top[i] = a.sc.nodes[i];
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
+    float4* stage = stage_all + (threadIdx.x >> 6) * kStage;
     const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
     Stack st;
     st.lds = stack_area + threadIdx.x;
@@ -317,82 +348,123 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
     float* out_k = a.out + (size_t)a.k * P * 3;
     uint32_t s_nodes = 0, s_tris = 0, s_rays = 0, s_app = 0;
 
+    bool alive = false;
+    bool drained = false;          // wave-uniform: the pass's list is used up
+    uint32_t fill = 0;             // wave-uniform: entries in this wave's stage
+    uint32_t pix = 0;
+    float pr = 0.5f, pg = 0.5f, pb = 0.5f;
+    Trav tv;
+    tv.node = -1;
+
     for (;;) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(fetch, 64u);
-        base = __shfl(base, 0);
-        if (base >= n_items) break;
-        const uint32_t item = base + lane;
-        bool valid = item < n_items;
-        uint32_t pix = 0;
-        float pr = 0.5f, pg = 0.5f, pb = 0.5f;
-        int x = 0, y = 0;
-        if (a.k == 0) {
-            const uint32_t tile = item >> 6;
-            const uint32_t l = item & 63u;
-            x = (int)((tile % (uint32_t)a.tiles_x) * 8u + (l & 7u));
-            y = (int)((tile / (uint32_t)a.tiles_x) * 8u + (l >> 3));
-            valid = valid && x < a.W && y < a.H;
-            pix = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
-            if (valid && a.prev_img) {
-                pr = a.prev_img[3 * (size_t)pix];
-                pg = a.prev_img[3 * (size_t)pix + 1];
-                pb = a.prev_img[3 * (size_t)pix + 2];
+        // ---- refill idle lanes with new work items ----------------------
+        const unsigned long long idle = __ballot(!alive);
+        const uint32_t n_idle = (uint32_t)__popcll(idle);
+        if (!drained && n_idle >= (uint32_t)a.refill_min) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(fetch, n_idle);
+            base = __shfl(base, 0);
+            if (base + n_idle >= n_items) drained = true;
+            if (!alive) {
+                const uint32_t item = base + lanes_below(idle);
+                bool valid = item < n_items;
+                int x = 0, y = 0;
+                if (a.k == 0) {
+                    const uint32_t tile = item >> 6;
+                    const uint32_t l = item & 63u;
+                    x = (int)((tile % (uint32_t)a.tiles_x) * 8u + (l & 7u));
+                    y = (int)((tile / (uint32_t)a.tiles_x) * 8u + (l >> 3));
+                    valid = valid && x < a.W && y < a.H;
+                    pix = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
+                    pr = 0.5f; pg = 0.5f; pb = 0.5f;
+                    if (valid && a.prev_img) {
+                        pr = a.prev_img[3 * (size_t)pix];
+                        pg = a.prev_img[3 * (size_t)pix + 1];
+                        pb = a.prev_img[3 * (size_t)pix + 2];
+                    }
+                } else if (valid) {
+                    const float4 sv = a.state_in[item];
+                    pix = __float_as_uint(sv.x);
+                    pr = sv.y; pg = sv.z; pb = sv.w;
+                    y = (int)(pix / (uint32_t)a.W);
+                    x = (int)(pix - (uint32_t)y * (uint32_t)a.W);
+                }
+                if (valid) {
+                    float o[3], d[3];
+                    make_ray(a.cam, a.W, a.H, x, y, pr, pg, pb, a.le, a.ld, o, d);
+                    trav_init(tv, a.sc, o, d, st);
+                    alive = true;
+                    if (STATS) ++s_rays;
+                }
             }
-        } else if (valid) {
-            const float4 s = a.state_in[item];
-            pix = __float_as_uint(s.x);
-            pr = s.y;
-            pg = s.z;
-            pb = s.w;
-            y = (int)(pix / (uint32_t)a.W);
-            x = (int)(pix - (uint32_t)y * (uint32_t)a.W);
+        }
+        if (__ballot(alive) == 0ull) {
+            if (drained) break;
+            continue;
         }
 
-        Hit h;
-        h.t = INFINITY;
-        h.id = INT_MAX;
-        h.slot = 0;
-        h.front = false;
-        float rgb[3];
-        if (valid) {
-            float o[3], d[3];
-            make_ray(a.cam, a.W, a.H, x, y, pr, pg, pb, a.le, a.ld, o, d);
-            if (a.sc.n_nodes > 0) traverse<STATS>(a.sc, top, o, d, st, h, s_nodes, s_tris);
-            if (STATS) ++s_rays;
-            if (h.id != INT_MAX) {
-                const float4 c = a.sc.shade[2 * (size_t)h.slot + (h.front ? 0 : 1)];
+        // ---- one traversal step -------------------------------------------
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, top, st, s_nodes, s_tris);
+
+        // ---- finished rays: shade, write, compact ----------------------------
+        const bool done = alive && tv.node == -1;
+        float rgb[3] = {0.0f, 0.0f, 0.0f};
+        int32_t hid = -1;
+        if (done) {
+            if (tv.h.id != INT_MAX) {
+                const float4 c = a.sc.shade[2 * (size_t)tv.h.slot + (tv.h.front ? 0 : 1)];
                 rgb[0] = c.x; rgb[1] = c.y; rgb[2] = c.z;
+                hid = tv.h.id;
             } else {
                 rgb[0] = a.sc.bg[0]; rgb[1] = a.sc.bg[1]; rgb[2] = a.sc.bg[2];
             }
-            const int32_t hid = h.id != INT_MAX ? h.id : -1;
             float* o3 = out_k + 3 * (size_t)pix;
             o3[0] = rgb[0]; o3[1] = rgb[1]; o3[2] = rgb[2];
             if (a.ids) a.ids[(size_t)a.k * P + pix] = hid;
-            h.id = hid;
         }
-
         if (a.state_out) {
-            const bool changed = valid && (__float_as_uint(rgb[0]) != __float_as_uint(pr) ||
-                                           __float_as_uint(rgb[1]) != __float_as_uint(pg) ||
-                                           __float_as_uint(rgb[2]) != __float_as_uint(pb));
+            const bool changed = done && (__float_as_uint(rgb[0]) != __float_as_uint(pr) ||
+                                          __float_as_uint(rgb[1]) != __float_as_uint(pg) ||
+                                          __float_as_uint(rgb[2]) != __float_as_uint(pb));
             const unsigned long long m = __ballot(changed);
-            uint32_t wbase = 0;
-            if (lane == 0 && m) wbase = atomicAdd(&a.counters[a.k + 1], (uint32_t)__popcll(m));
-            wbase = __shfl(wbase, 0);
-            if (changed) {
-                a.state_out[wbase + lanes_below(m)] = make_float4(__uint_as_float(pix), rgb[0], rgb[1], rgb[2]);
-                if (STATS) ++s_app;
-            } else if (valid) {
+            if (m) {
+                if (changed) stage[fill + lanes_below(m)] = make_float4(__uint_as_float(pix), rgb[0], rgb[1], rgb[2]);
+                fill += (uint32_t)__popcll(m);
+                if (STATS && changed) ++s_app;
+                if (fill >= 64u) {
+                    // flush 64 staged entries with one atomic
+                    __builtin_amdgcn_wave_barrier();
+                    uint32_t base = 0;
+                    if (lane == 0) base = atomicAdd(&a.counters[a.k + 1], 64u);
+                    base = __shfl(base, 0);
+                    a.state_out[base + lane] = stage[lane];
+                    __builtin_amdgcn_wave_barrier();
+                    float4 rest = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if ((uint32_t)lane < fill - 64u) rest = stage[64 + lane];
+                    __builtin_amdgcn_wave_barrier();
+                    if ((uint32_t)lane < fill - 64u) stage[lane] = rest;
+                    __builtin_amdgcn_wave_barrier();
+                    fill -= 64u;
+                }
+            }
+            if (done && !changed) {
                 // same colour -> same ray -> same result in every later pass
                 for (int kk = a.k + 1; kk < a.K; ++kk) {
                     float* q = a.out + ((size_t)kk * P + pix) * 3;
                     q[0] = rgb[0]; q[1] = rgb[1]; q[2] = rgb[2];
-                    if (a.ids) a.ids[(size_t)kk * P + pix] = h.id;
+                    if (a.ids) a.ids[(size_t)kk * P + pix] = hid;
                 }
             }
         }
+        alive = alive && !done;
+    }
+    // flush what is left in the stage
+    if (a.state_out && fill > 0u) {
+        __builtin_amdgcn_wave_barrier();
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&a.counters[a.k + 1], fill);
+        base = __shfl(base, 0);
+        if ((uint32_t)lane < fill) a.state_out[base + lane] = stage[lane];
     }
     if (STATS) {
         unsigned long long* sk = a.stats + 4 * a.k;
@@ -428,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
                                                         int32_t* __restrict__ spill, uint32_t stride) {
     extern __shared__ float4 smem[];
     float4* top = smem;
-    int32_t* stack_area = (int32_t*)(smem + 4 * sc.top_count);
+    int32_t* stack_area = (int32_t*)(smem + 4 * sc.top_count + kWaves * kStage);
     for (uint32_t i = threadIdx.x; i < 4 * sc.top_count; i += kBlock) top[i] = sc.nodes[i];
     __syncthreads();
     const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
@@ -439,14 +511,14 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
     for (uint32_t r = gtid; r < (uint32_t)n; r += gridDim.x * kBlock) {
         float o[3], d[3];
         for (int c = 0; c < 3; ++c) { o[c] = org[3 * (size_t)r + c]; d[c] = dir[3 * (size_t)r + c]; }
-        Hit h;
-        h.t = INFINITY; h.id = INT_MAX; h.slot = 0; h.front = false;
+        Trav tv;
+        trav_init(tv, sc, o, d, st);
         uint32_t dn = 0, dt = 0;
-        if (sc.n_nodes > 0) traverse<false>(sc, top, o, d, st, h, dn, dt);
-        const bool hit = h.id != INT_MAX;
-        out_t[r] = hit ? h.t : INFINITY;
-        out_id[r] = hit ? h.id : -1;
-        if (out_front) out_front[r] = hit && h.front ? 1 : 0;
+        while (tv.node != -1) trav_step<false>(tv, sc, top, st, dn, dt);
+        const bool hit = tv.h.id != INT_MAX;
+        out_t[r] = hit ? tv.h.t : INFINITY;
+        out_id[r] = hit ? tv.h.id : -1;
+        if (out_front) out_front[r] = hit && tv.h.front ? 1 : 0;
     }
 }
 
@@ -473,6 +545,16 @@ rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t spill_entries) 
     return RCP_OK;
 }
 
+// Idle lanes that make a wave fetch new work (RCP_REFILL_MIN, default 16).
+int refill_min() {
+    static int v = [] {
+        const char* e = getenv("RCP_REFILL_MIN");
+        int x = e ? atoi(e) : 16;
+        return x < 1 ? 1 : (x > 64 ? 64 : x);
+    }();
+    return v;
+}
+
 struct GridInfo {
     int blocks = 0;
     size_t smem = 0;
@@ -480,7 +562,7 @@ struct GridInfo {
 
 template <typename KernelT>
 rcp_status persistent_grid(KernelT kernel, const DevScene& sc, GridInfo& g) {
-    g.smem = sizeof(float4) * 4 * (size_t)sc.top_count + sizeof(int32_t) * kStack * kBlock;
+    g.smem = sizeof(float4) * (4 * (size_t)sc.top_count + kWaves * kStage) + sizeof(int32_t) * kStack * kBlock;
     int per_cu = 0;
     RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, g.smem));
     int dev = 0, cus = 0;
@@ -515,6 +597,7 @@ rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, float le
     a.W = W; a.H = H; a.K = K;
     a.le = le; a.ld = ld;
     a.n_items0 = (uint32_t)tiles_x * (uint32_t)tiles_y * 64u;
+    a.refill_min = refill_min();
     a.tiles_x = tiles_x;
     a.counters = w.counters;
     a.out = out_images;

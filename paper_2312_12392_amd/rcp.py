@@ -271,7 +271,7 @@ def rcp_radix_sort_u64(keys, vals, n: int, stream=None) -> None:
 # Convenience wrapper
 # ---------------------------------------------------------------------------
 
-def build_options(max_leaf: int = 4, top_levels: int = 8, c_trav: float = 1.0, c_isect: float = 1.0):
+def build_options(max_leaf: int = 4, top_levels: int = 6, c_trav: float = 1.0, c_isect: float = 1.0):
     o = rcp_build_options()
     o.max_leaf, o.top_levels, o.c_trav, o.c_isect = int(max_leaf), int(top_levels), float(c_trav), float(c_isect)
     return o
