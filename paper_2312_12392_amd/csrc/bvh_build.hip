@@ -3,7 +3,7 @@
 // The paper does not say how its ray tracer built its acceleration structure
 // (Section 6 used a GPU ray-tracing engine), so this is a standard GPU build:
 //   1. per-triangle boxes and the centroid bounds (wave reductions + atomics)
-//   2. 63-bit Morton codes of the box centres (21 bits per axis)
+//   2. 63-bit Morton codes of the box centres (21 bits per axis, one scale)
 //   3. stable LSD radix sort of (code, triangle) pairs
 //   4. binary radix tree over the sorted codes, one thread per inner node
 //      (Karras, "Maximizing Parallelism in the Construction of BVHs, Octrees,
@@ -107,16 +107,20 @@ __global__ __launch_bounds__(kB) void k_morton(const float4* __restrict__ tlo, c
                                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const uint32_t i = blockIdx.x * kB + threadIdx.x;
     if (i >= n) return;
-    float lo[3], ext[3];
+    // One scale for all axes (a cube around the centroid bounds): the code's
+    // bit order then splits the longest extents first, instead of giving a
+    // thin axis (a terrain's height) as many top-level splits as the others.
+    float lo[3], ext = 0.0f;
     for (int c = 0; c < 3; ++c) {
         lo[c] = o2f(bounds[c]);
-        ext[c] = o2f(bounds[3 + c]) - lo[c];
+        ext = fmaxf(ext, o2f(bounds[3 + c]) - lo[c]);
     }
+    const float scale = ext > 0.0f ? 2097152.0f / ext : 0.0f;
     float4 a = tlo[i], b = thi[i];
     float cx = 0.5f * (a.x + b.x), cy = 0.5f * (a.y + b.y), cz = 0.5f * (a.z + b.z);
-    uint32_t qx = quant21(cx, lo[0], ext[0] > 0.0f ? 2097152.0f / ext[0] : 0.0f);
-    uint32_t qy = quant21(cy, lo[1], ext[1] > 0.0f ? 2097152.0f / ext[1] : 0.0f);
-    uint32_t qz = quant21(cz, lo[2], ext[2] > 0.0f ? 2097152.0f / ext[2] : 0.0f);
+    uint32_t qx = quant21(cx, lo[0], scale);
+    uint32_t qy = quant21(cy, lo[1], scale);
+    uint32_t qz = quant21(cz, lo[2], scale);
     keys[i] = (spread21(qx) << 2) | (spread21(qy) << 1) | spread21(qz);
     vals[i] = i;
 }

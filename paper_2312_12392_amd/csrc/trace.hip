@@ -31,7 +31,10 @@ namespace rcp {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kStack = 16;                       // per-lane LDS stack entries
+#ifndef RCP_STACK
+#define RCP_STACK 8
+#endif
+constexpr int kStack = RCP_STACK;                // per-lane LDS stack entries (power of two not required)
 constexpr float kSlack = 1.0f + 1.0f / 65536.0f; // widening of box intervals
 
 struct PassArgs {
@@ -175,10 +178,10 @@ struct Stack {
 
     __device__ inline void push(int32_t v) {
         if (sp - lo == kStack) {
-            spill[(size_t)lo * stride] = lds[(lo & (kStack - 1)) * kBlock];
+            spill[(size_t)lo * stride] = lds[(lo % kStack) * kBlock];
             ++lo;
         }
-        lds[(sp & (kStack - 1)) * kBlock] = v;
+        lds[(sp % kStack) * kBlock] = v;
         ++sp;
     }
     __device__ inline int32_t pop() {
@@ -188,7 +191,7 @@ struct Stack {
             lo = sp;
             return spill[(size_t)sp * stride];
         }
-        return lds[(sp & (kStack - 1)) * kBlock];
+        return lds[(sp % kStack) * kBlock];
     }
 };
 
@@ -211,8 +214,8 @@ struct Stack {
 struct Trav {
     RayW rw;
     float ix, iy, iz;       // reciprocal direction
-    float lx, ly, lz;       // origin used against lo planes (o + pad)
-    float hx, hy, hz;       // origin used against hi planes (o - pad)
+    float lx, ly, lz;       // (o + pad) * inv: used against lo planes
+    float hx, hy, hz;       // (o - pad) * inv: used against hi planes
     int32_t node;           // >= 0 inner node, other negative: leaf link, -1: finished
     uint32_t budget;
     Hit h;
@@ -224,10 +227,13 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
 #pragma unroll
     for (int a = 0; a < 3; ++a) inv[a] = fabsf(d[a]) > 1e-30f ? 1.0f / d[a] : copysignf(1e30f, d[a]);
     tv.ix = inv[0]; tv.iy = inv[1]; tv.iz = inv[2];
+    // A plane at coordinate c is reached at t = c * inv - (o -/+ pad) * inv,
+    // one fused multiply-add per plane.  Its rounding (a few ulp of |o * inv|)
+    // is far inside the 2^-18 (R + max|o|) widening, so the bounds stay safe.
     const float pad = (sc.radius + fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]))) * 3.814697265625e-6f;
-    tv.lx = o[0] + pad; tv.hx = o[0] - pad;
-    tv.ly = o[1] + pad; tv.hy = o[1] - pad;
-    tv.lz = o[2] + pad; tv.hz = o[2] - pad;
+    tv.lx = (o[0] + pad) * inv[0]; tv.hx = (o[0] - pad) * inv[0];
+    tv.ly = (o[1] + pad) * inv[1]; tv.hy = (o[1] - pad) * inv[1];
+    tv.lz = (o[2] + pad) * inv[2]; tv.hz = (o[2] - pad) * inv[2];
     tv.node = sc.n_nodes > 0 ? 0 : -1;
     // Every node and leaf is entered at most once per ray; the bound only
     // guarantees termination should the tree ever be malformed.
@@ -265,17 +271,17 @@ __device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* __r
         if (STATS) ++n_nodes;
         const float lim = tv.h.t * kSlack;
         // child 0
-        const float a0 = (n0.x - tv.lx) * tv.ix, a1 = (n0.y - tv.hx) * tv.ix;
-        const float a2 = (n0.z - tv.ly) * tv.iy, a3 = (n0.w - tv.hy) * tv.iy;
-        const float a4 = (n2.x - tv.lz) * tv.iz, a5 = (n2.y - tv.hz) * tv.iz;
+        const float a0 = __builtin_fmaf(n0.x, tv.ix, -tv.lx), a1 = __builtin_fmaf(n0.y, tv.ix, -tv.hx);
+        const float a2 = __builtin_fmaf(n0.z, tv.iy, -tv.ly), a3 = __builtin_fmaf(n0.w, tv.iy, -tv.hy);
+        const float a4 = __builtin_fmaf(n2.x, tv.iz, -tv.lz), a5 = __builtin_fmaf(n2.y, tv.iz, -tv.hz);
         const float ex0 = fminf(a0, a1), ey0 = fminf(a2, a3), ez0 = fminf(a4, a5);
         const float tmin0 = fmaxf(fmaxf(ex0, ey0), fmaxf(ez0, 0.0f));
         const float tmax0 = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
         const float near0 = kz == 0 ? ex0 : (kz == 1 ? ey0 : ez0);
         // child 1
-        const float b0 = (n1.x - tv.lx) * tv.ix, b1 = (n1.y - tv.hx) * tv.ix;
-        const float b2 = (n1.z - tv.ly) * tv.iy, b3 = (n1.w - tv.hy) * tv.iy;
-        const float b4 = (n2.z - tv.lz) * tv.iz, b5 = (n2.w - tv.hz) * tv.iz;
+        const float b0 = __builtin_fmaf(n1.x, tv.ix, -tv.lx), b1 = __builtin_fmaf(n1.y, tv.ix, -tv.hx);
+        const float b2 = __builtin_fmaf(n1.z, tv.iy, -tv.ly), b3 = __builtin_fmaf(n1.w, tv.iy, -tv.hy);
+        const float b4 = __builtin_fmaf(n2.z, tv.iz, -tv.lz), b5 = __builtin_fmaf(n2.w, tv.iz, -tv.hz);
         const float ex1 = fminf(b0, b1), ey1 = fminf(b2, b3), ez1 = fminf(b4, b5);
         const float tmin1 = fmaxf(fmaxf(ex1, ey1), fmaxf(ez1, 0.0f));
         const float tmax1 = fminf(fminf(fmaxf(b0, b1), fmaxf(b2, b3)), fmaxf(b4, b5)) * kSlack;

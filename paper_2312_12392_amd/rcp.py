@@ -83,6 +83,14 @@ def load(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is missing: build the HIP library first (python __graft_entry__.py build)")
+    # torch ships its own HIP runtime (libamdhip64.so.7).  Loading torch first
+    # makes librcp.so bind to that same runtime instead of pulling a second
+    # copy from /opt/rocm into the process, so device pointers and streams
+    # from torch are valid in the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(p)
     P = ctypes.c_void_p
     i32 = ctypes.c_int
