@@ -246,92 +246,118 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
     st.lo = 0;
 }
 
-// One step: descend through inner nodes until a leaf (or the end), then test
-// that leaf's triangles.  Sets tv.node = -1 once the ray is finished.
+// Visit one inner node: test both child boxes, continue with the nearer hit
+// child, push the farther one, or pop when neither is hit.
+template <bool STATS>
+__device__ inline int32_t visit_inner(Trav& tv, int32_t node, const DevScene& sc, const float4* __restrict__ top,
+                                      Stack& st, uint32_t& n_nodes) {
+    const int kz = tv.rw.kz;
+    float4 n0, n1, n2, n3;
+    if ((uint32_t)node < sc.top_count) {
+        n0 = top[4 * node + 0];
+        n1 = top[4 * node + 1];
+        n2 = top[4 * node + 2];
+        n3 = top[4 * node + 3];
+    } else {
+        const float4* p = sc.nodes + 4 * (size_t)node;
+        n0 = p[0];
+        n1 = p[1];
+        n2 = p[2];
+        n3 = p[3];
+    }
+    if (STATS) ++n_nodes;
+    const float lim = tv.h.t * kSlack;
+    // child 0
+    const float a0 = __builtin_fmaf(n0.x, tv.ix, -tv.lx), a1 = __builtin_fmaf(n0.y, tv.ix, -tv.hx);
+    const float a2 = __builtin_fmaf(n0.z, tv.iy, -tv.ly), a3 = __builtin_fmaf(n0.w, tv.iy, -tv.hy);
+    const float a4 = __builtin_fmaf(n2.x, tv.iz, -tv.lz), a5 = __builtin_fmaf(n2.y, tv.iz, -tv.hz);
+    const float ex0 = fminf(a0, a1), ey0 = fminf(a2, a3), ez0 = fminf(a4, a5);
+    const float tmin0 = fmaxf(fmaxf(ex0, ey0), fmaxf(ez0, 0.0f));
+    const float tmax0 = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
+    const float near0 = kz == 0 ? ex0 : (kz == 1 ? ey0 : ez0);
+    // child 1
+    const float b0 = __builtin_fmaf(n1.x, tv.ix, -tv.lx), b1 = __builtin_fmaf(n1.y, tv.ix, -tv.hx);
+    const float b2 = __builtin_fmaf(n1.z, tv.iy, -tv.ly), b3 = __builtin_fmaf(n1.w, tv.iy, -tv.hy);
+    const float b4 = __builtin_fmaf(n2.z, tv.iz, -tv.lz), b5 = __builtin_fmaf(n2.w, tv.iz, -tv.hz);
+    const float ex1 = fminf(b0, b1), ey1 = fminf(b2, b3), ez1 = fminf(b4, b5);
+    const float tmin1 = fmaxf(fmaxf(ex1, ey1), fmaxf(ez1, 0.0f));
+    const float tmax1 = fminf(fminf(fmaxf(b0, b1), fmaxf(b2, b3)), fmaxf(b4, b5)) * kSlack;
+    const float near1 = kz == 0 ? ex1 : (kz == 1 ? ey1 : ez1);
+    const bool hit0 = tmin0 <= tmax0 && near0 <= lim;
+    const bool hit1 = tmin1 <= tmax1 && near1 <= lim;
+    const int32_t c0 = __float_as_int(n3.x);
+    const int32_t c1 = __float_as_int(n3.y);
+    if (hit0 && hit1) {
+        const bool first0 = tmin0 <= tmin1;
+        st.push(first0 ? c1 : c0);
+        node = first0 ? c0 : c1;
+    } else if (hit0) {
+        node = c0;
+    } else if (hit1) {
+        node = c1;
+    } else {
+        node = st.pop();
+    }
+    return node;
+}
+
+// Test the triangles of leaf `link` against the ray, keeping the closest hit.
+template <bool STATS>
+__device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, uint32_t& n_tris) {
+    const int32_t node = link;
+    // leaf: triangles [first, first + count)
+    const uint32_t first = ((uint32_t)node >> 3) & 0x0FFFFFFFu;
+    const uint32_t count = ((uint32_t)node & 7u) + 1u;
+    for (uint32_t j = 0; j < count; ++j) {
+        const float4* tp = sc.tris + 3 * (size_t)(first + j);
+        const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
+        if (STATS) ++n_tris;
+        float t;
+        bool front;
+        if (hit_triangle(tv.rw, v0, v1, v2, t, front)) {
+            const int32_t id = __float_as_int(v0.w);
+            if (t < tv.h.t || (t == tv.h.t && id < tv.h.id)) {
+                tv.h.t = t;
+                tv.h.id = id;
+                tv.h.slot = first + j;
+                tv.h.front = front;
+            }
+        }
+    }
+}
+
+// One step: descend through inner nodes to a leaf and test it; sets
+// tv.node = -1 once the ray is finished.  Speculation (after Aila and Laine,
+// "Understanding the Efficiency of Ray Traversal on GPUs", HPG 2009): a lane
+// that reaches a leaf keeps descending while other lanes of the wave are still
+// looking for theirs, and holds the next leaf it meets for the following
+// step, so the wave's leaf tests run together.
 template <bool STATS>
 __device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* __restrict__ top, Stack& st,
                                  uint32_t& n_nodes, uint32_t& n_tris) {
     int32_t node = tv.node;
-    const int kz = tv.rw.kz;
-    while (node >= 0) {
-        if (--tv.budget == 0u) { node = -1; break; }
-        float4 n0, n1, n2, n3;
-        if ((uint32_t)node < sc.top_count) {
-            n0 = top[4 * node + 0];
-            n1 = top[4 * node + 1];
-            n2 = top[4 * node + 2];
-            n3 = top[4 * node + 3];
-        } else {
-            const float4* p = sc.nodes + 4 * (size_t)node;
-            n0 = p[0];
-            n1 = p[1];
-            n2 = p[2];
-            n3 = p[3];
-        }
-        if (STATS) ++n_nodes;
-        const float lim = tv.h.t * kSlack;
-        // child 0
-        const float a0 = __builtin_fmaf(n0.x, tv.ix, -tv.lx), a1 = __builtin_fmaf(n0.y, tv.ix, -tv.hx);
-        const float a2 = __builtin_fmaf(n0.z, tv.iy, -tv.ly), a3 = __builtin_fmaf(n0.w, tv.iy, -tv.hy);
-        const float a4 = __builtin_fmaf(n2.x, tv.iz, -tv.lz), a5 = __builtin_fmaf(n2.y, tv.iz, -tv.hz);
-        const float ex0 = fminf(a0, a1), ey0 = fminf(a2, a3), ez0 = fminf(a4, a5);
-        const float tmin0 = fmaxf(fmaxf(ex0, ey0), fmaxf(ez0, 0.0f));
-        const float tmax0 = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
-        const float near0 = kz == 0 ? ex0 : (kz == 1 ? ey0 : ez0);
-        // child 1
-        const float b0 = __builtin_fmaf(n1.x, tv.ix, -tv.lx), b1 = __builtin_fmaf(n1.y, tv.ix, -tv.hx);
-        const float b2 = __builtin_fmaf(n1.z, tv.iy, -tv.ly), b3 = __builtin_fmaf(n1.w, tv.iy, -tv.hy);
-        const float b4 = __builtin_fmaf(n2.z, tv.iz, -tv.lz), b5 = __builtin_fmaf(n2.w, tv.iz, -tv.hz);
-        const float ex1 = fminf(b0, b1), ey1 = fminf(b2, b3), ez1 = fminf(b4, b5);
-        const float tmin1 = fmaxf(fmaxf(ex1, ey1), fmaxf(ez1, 0.0f));
-        const float tmax1 = fminf(fminf(fmaxf(b0, b1), fmaxf(b2, b3)), fmaxf(b4, b5)) * kSlack;
-        const float near1 = kz == 0 ? ex1 : (kz == 1 ? ey1 : ez1);
-        const bool hit0 = tmin0 <= tmax0 && near0 <= lim;
-        const bool hit1 = tmin1 <= tmax1 && near1 <= lim;
-        const int32_t c0 = __float_as_int(n3.x);
-        const int32_t c1 = __float_as_int(n3.y);
-        if (hit0 && hit1) {
-            const bool first0 = tmin0 <= tmin1;
-            st.push(first0 ? c1 : c0);
-            node = first0 ? c0 : c1;
-        } else if (hit0) {
-            node = c0;
-        } else if (hit1) {
-            node = c1;
-        } else {
-            node = st.pop();
+    int32_t leaf = -1;
+    for (;;) {
+        if (node < -1 && leaf == -1) { leaf = node; node = st.pop(); }
+        if (!__any(leaf == -1 && node >= 0)) break;
+        if (node >= 0) {
+            if (--tv.budget == 0u) { node = -1; leaf = -1; break; }
+            node = visit_inner<STATS>(tv, node, sc, top, st, n_nodes);
         }
     }
-    if (node != -1) {
-        // leaf: triangles [first, first + count)
-        const uint32_t first = ((uint32_t)node >> 3) & 0x0FFFFFFFu;
-        const uint32_t count = ((uint32_t)node & 7u) + 1u;
-        for (uint32_t j = 0; j < count; ++j) {
-            const float4* tp = sc.tris + 3 * (size_t)(first + j);
-            const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
-            if (STATS) ++n_tris;
-            float t;
-            bool front;
-            if (hit_triangle(tv.rw, v0, v1, v2, t, front)) {
-                const int32_t id = __float_as_int(v0.w);
-                if (t < tv.h.t || (t == tv.h.t && id < tv.h.id)) {
-                    tv.h.t = t;
-                    tv.h.id = id;
-                    tv.h.slot = first + j;
-                    tv.h.front = front;
-                }
-            }
-        }
-        node = st.pop();
-    }
+    if (leaf != -1) visit_leaf<STATS>(tv, leaf, sc, n_tris);
     tv.node = node;
 }
 
 constexpr int kWaves = kBlock / 64;
 constexpr int kStage = 128;     // per-wave staging of appended entries (flushed 64 at a time)
 
+#ifndef RCP_WAVES_PER_EU
+#define RCP_WAVES_PER_EU 1
+#endif
+
 template <bool STATS>
-__global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVES_PER_EU))) void k_pass(PassArgs a) {
     extern __shared__ float4 smem[];
     float4* top = smem;                                                 // top_count * 4
     float4* stage_all = smem + 4 * a.sc.top_count;                      // kWaves * kStage
@@ -551,11 +577,11 @@ rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t spill_entries) 
     return RCP_OK;
 }
 
-// Idle lanes that make a wave fetch new work (RCP_REFILL_MIN, default 16).
+// Idle lanes that make a wave fetch new work (RCP_REFILL_MIN, default 40).
 int refill_min() {
     static int v = [] {
         const char* e = getenv("RCP_REFILL_MIN");
-        int x = e ? atoi(e) : 16;
+        int x = e ? atoi(e) : 40;
         return x < 1 ? 1 : (x > 64 ? 64 : x);
     }();
     return v;
