@@ -51,6 +51,8 @@ class _Cam(ctypes.Structure):
                 ("tan_half_fovy", ctypes.c_float)]
 
 
+MODE_COLOR, MODE_DEPTH, MODE_NORMAL = 0, 1, 2
+
 _lib = None
 
 
@@ -71,18 +73,19 @@ def lib():
         L.orc_scene_create.argtypes = [ctypes.POINTER(_Desc), i32]
         L.orc_scene_destroy.argtypes = [P]
         L.orc_scene_stats.argtypes = [P, P]
-        L.orc_ray.argtypes = [ctypes.POINTER(_Cam), i32, i32, i32, i32, P, f32, f32, P, P]
+        L.orc_ray.argtypes = [ctypes.POINTER(_Cam), i32, i32, i32, i32, P, P, i32, f32, f32, f32, P, P]
         L.orc_intersect.restype = i32
         L.orc_intersect.argtypes = [P, P, P, P, P, P, P]
         L.orc_closest_hit.restype = i32
         L.orc_closest_hit.argtypes = [P, P, P, i32, P, P, P]
         L.orc_shade.argtypes = [P, ctypes.c_int32, i32, P]
+        L.orc_normal.argtypes = [P, ctypes.c_int32, P]
         L.orc_render_pass.restype = i32
-        L.orc_render_pass.argtypes = [P, ctypes.POINTER(_Cam), i32, i32, f32, f32, P, P, P, i32]
+        L.orc_render_pass.argtypes = [P, ctypes.POINTER(_Cam), i32, i32, i32, f32, f32, f32, P, P, P, P, P, i32]
         L.orc_render.restype = i32
-        L.orc_render.argtypes = [P, ctypes.POINTER(_Cam), i32, i32, i32, f32, f32, P, P, i32]
+        L.orc_render.argtypes = [P, ctypes.POINTER(_Cam), i32, i32, i32, i32, f32, f32, f32, P, P, i32]
         L.orc_render_pixels.restype = i32
-        L.orc_render_pixels.argtypes = [P, ctypes.POINTER(_Cam), i32, i32, i32, f32, f32, P, i32,
+        L.orc_render_pixels.argtypes = [P, ctypes.POINTER(_Cam), i32, i32, i32, i32, f32, f32, f32, P, i32,
                                         P, P, i32]
         L.orc_default_threads.restype = i32
         _lib = L
@@ -155,33 +158,43 @@ class OracleScene:
         lib().orc_shade(self.h, int(tri_id), 1 if front else 0, _ptr(out))
         return out
 
-    def render_pass(self, cam, W, H, lambda_eye, lambda_dir, prev=None, nthreads=0):
+    def normal(self, tri_id: int):
+        out = np.zeros(3, np.float32)
+        lib().orc_normal(self.h, int(tri_id), _ptr(out))
+        return out
+
+    def render_pass(self, cam, W, H, lambda_eye, lambda_dir, prev=None, prev_aux=None, mode=MODE_COLOR,
+                    z0=0.0, nthreads=0, with_aux=False):
+        """One pass; returns (image, ids) or (image, ids, aux) with with_aux."""
         out = np.zeros((H, W, 3), np.float32)
         ids = np.zeros((H, W), np.int32)
+        aux = np.zeros((H, W, 4), np.float32)
         p = None if prev is None else np.ascontiguousarray(prev, np.float32).reshape(H, W, 3)
+        pa = None if prev_aux is None else np.ascontiguousarray(prev_aux, np.float32).reshape(H, W, 4)
         c = camera_struct(cam)
-        rc = lib().orc_render_pass(self.h, ctypes.byref(c), W, H, float(lambda_eye), float(lambda_dir),
-                                   _ptr(p), _ptr(out), _ptr(ids), int(nthreads))
+        rc = lib().orc_render_pass(self.h, ctypes.byref(c), W, H, int(mode), float(z0), float(lambda_eye),
+                                   float(lambda_dir), _ptr(p), _ptr(pa), _ptr(out), _ptr(ids), _ptr(aux),
+                                   int(nthreads))
         if rc:
             raise ValueError("orc_render_pass failed")
-        return out, ids
+        return (out, ids, aux) if with_aux else (out, ids)
 
-    def render(self, cam, W, H, K, lambda_eye, lambda_dir, nthreads=0):
+    def render(self, cam, W, H, K, lambda_eye, lambda_dir, nthreads=0, mode=MODE_COLOR, z0=0.0):
         out = np.zeros((K, H, W, 3), np.float32)
         ids = np.zeros((K, H, W), np.int32)
         c = camera_struct(cam)
-        rc = lib().orc_render(self.h, ctypes.byref(c), W, H, K, float(lambda_eye), float(lambda_dir),
-                              _ptr(out), _ptr(ids), int(nthreads))
+        rc = lib().orc_render(self.h, ctypes.byref(c), W, H, K, int(mode), float(z0), float(lambda_eye),
+                              float(lambda_dir), _ptr(out), _ptr(ids), int(nthreads))
         if rc:
             raise ValueError("orc_render failed")
         return out, ids
 
-    def render_pixels(self, cam, W, H, K, lambda_eye, lambda_dir, pix, nthreads=0):
+    def render_pixels(self, cam, W, H, K, lambda_eye, lambda_dir, pix, nthreads=0, mode=MODE_COLOR, z0=0.0):
         pix = np.ascontiguousarray(pix, np.int32).reshape(-1)
         out = np.zeros((pix.shape[0], K, 3), np.float32)
         ids = np.zeros((pix.shape[0], K), np.int32)
         c = camera_struct(cam)
-        rc = lib().orc_render_pixels(self.h, ctypes.byref(c), W, H, K, float(lambda_eye),
+        rc = lib().orc_render_pixels(self.h, ctypes.byref(c), W, H, K, int(mode), float(z0), float(lambda_eye),
                                      float(lambda_dir), _ptr(pix), pix.shape[0], _ptr(out), _ptr(ids),
                                      int(nthreads))
         if rc:
@@ -189,11 +202,13 @@ class OracleScene:
         return out, ids
 
 
-def ray(cam, W, H, x, y, prev, lambda_eye, lambda_dir):
+def ray(cam, W, H, x, y, prev, lambda_eye, lambda_dir, prev_aux=None, mode=MODE_COLOR, z0=0.0):
     o = np.zeros(3, np.float32); d = np.zeros(3, np.float32)
     p = _f3(prev)
+    pa = None if prev_aux is None else np.ascontiguousarray(prev_aux, np.float32).reshape(4)
     c = camera_struct(cam)
-    lib().orc_ray(ctypes.byref(c), W, H, x, y, _ptr(p), float(lambda_eye), float(lambda_dir), _ptr(o), _ptr(d))
+    lib().orc_ray(ctypes.byref(c), W, H, x, y, _ptr(p), _ptr(pa), int(mode), float(z0), float(lambda_eye),
+                  float(lambda_dir), _ptr(o), _ptr(d))
     return o, d
 
 

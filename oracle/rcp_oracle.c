@@ -22,6 +22,10 @@
  *     its description: shear the triangle into ray space, 2-D edge functions
  *     U, V, W with an FP64 re-evaluation when one is exactly zero, reject
  *     mixed signs and det == 0, t = T / det.
+ *   - Sections 4 and 5, the depth and normal mappings: the colour vector
+ *     scaled by |z - z0| (z the view depth of the previous hit), and
+ *     lambda (C x N) (C the pixel's view direction, N the previous hit's
+ *     world normal).
  *   - Shading (the paper leaves it open): two-sided Lambert with the flat
  *     geometric normal, one directional light, clamped to [0, 1] (Section 3
  *     speaks of low-dynamic-range channels).
@@ -257,6 +261,7 @@ void orc_scene_stats(const orc_scene* s, int32_t out[3]) {
 /* ------------------------------------------------------------------------ */
 
 void orc_ray(const orc_camera* cam, int W, int H, int x, int y, const float prev[3],
+             const float prev_aux[4], int mode, float z0,
              float lambda_eye, float lambda_dir, float o[3], float d[3]) {
     /* Pixel centre in [-1, 1]^2, row 0 at the top; vertical field of view. */
     float fx = (float)(2 * x + 1) / (float)W - 1.0f;
@@ -267,12 +272,33 @@ void orc_ray(const orc_camera* cam, int W, int H, int x, int y, const float prev
     /* Undisplaced P_p - P_e: the image plane sits one unit along forward. */
     float q[3];
     for (int c = 0; c < 3; ++c) q[c] = (cam->forward[c] + s * cam->right[c]) + t * cam->up[c];
-    /* Colour mapping: (2R-1, 2G-1, 2B-1) in the camera frame (right, up, forward). */
-    float mr = 2.0f * prev[0] - 1.0f;
-    float mg = 2.0f * prev[1] - 1.0f;
-    float mb = 2.0f * prev[2] - 1.0f;
     float w[3], dp[3];
-    for (int c = 0; c < 3; ++c) w[c] = (mr * cam->right[c] + mg * cam->up[c]) + mb * cam->forward[c];
+    if (mode == ORC_MODE_NORMAL) {
+        /* Section 5: V = lambda (C x N), C the pixel's undisplaced view
+         * direction, N the world normal of the previous hit (zero after a
+         * miss and for the seed, so the first image is the pinhole one). */
+        static const float no_normal[3] = {0.0f, 0.0f, 0.0f};
+        const float* N = prev_aux ? prev_aux + 1 : no_normal;
+        float ql = sqrtf((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]);
+        float C[3];
+        for (int c = 0; c < 3; ++c) C[c] = q[c] / ql;
+        w[0] = C[1] * N[2] - C[2] * N[1];
+        w[1] = C[2] * N[0] - C[0] * N[2];
+        w[2] = C[0] * N[1] - C[1] * N[0];
+    } else {
+        /* Colour mapping: (2R-1, 2G-1, 2B-1) in the camera frame (right, up, forward). */
+        float mr = 2.0f * prev[0] - 1.0f;
+        float mg = 2.0f * prev[1] - 1.0f;
+        float mb = 2.0f * prev[2] - 1.0f;
+        for (int c = 0; c < 3; ++c) w[c] = (mr * cam->right[c] + mg * cam->up[c]) + mb * cam->forward[c];
+        if (mode == ORC_MODE_DEPTH) {
+            /* Section 4: the colour vector scaled by |z - z0|, z the view depth
+             * of the previous hit; no displacement after a miss or for the seed. */
+            float z = prev_aux ? prev_aux[0] : INFINITY;
+            float kz = (z < INFINITY) ? fabsf(z - z0) : 0.0f;
+            for (int c = 0; c < 3; ++c) w[c] = kz * w[c];
+        }
+    }
     /* P'_e = P_e + V_e and P'_p = P_p + V_p with V_e = lambda_eye w and
      * V_p = (lambda_eye + lambda_dir) w, so P'_p - P'_e = q + lambda_dir w. */
     for (int c = 0; c < 3; ++c) {
@@ -445,15 +471,20 @@ static float clamp01(float v) {
     return v;
 }
 
-void orc_shade(const orc_scene* s, int32_t id, int front, float rgb[3]) {
+void orc_normal(const orc_scene* s, int32_t id, float n[3]) {
     const float* tr = &s->tri[9 * id];
-    float e1[3], e2[3], n[3];
+    float e1[3], e2[3];
     for (int c = 0; c < 3; ++c) { e1[c] = tr[3 + c] - tr[c]; e2[c] = tr[6 + c] - tr[c]; }
     n[0] = e1[1] * e2[2] - e1[2] * e2[1];
     n[1] = e1[2] * e2[0] - e1[0] * e2[2];
     n[2] = e1[0] * e2[1] - e1[1] * e2[0];
     float len = sqrtf((n[0] * n[0] + n[1] * n[1]) + n[2] * n[2]);
     for (int c = 0; c < 3; ++c) n[c] = n[c] / len;
+}
+
+void orc_shade(const orc_scene* s, int32_t id, int front, float rgb[3]) {
+    float n[3];
+    orc_normal(s, id, n);
     if (!front) for (int c = 0; c < 3; ++c) n[c] = -n[c];
     float dot = (n[0] * s->light[0] + n[1] * s->light[1]) + n[2] * s->light[2];
     float diff = dot > 0.0f ? dot : 0.0f;
@@ -461,19 +492,30 @@ void orc_shade(const orc_scene* s, int32_t id, int front, float rgb[3]) {
     for (int c = 0; c < 3; ++c) rgb[c] = clamp01(s->rgb[3 * id + c] * shade);
 }
 
-/* One (u,v) step of F: camera from the previous colour, then render. */
+/* One (u,v) step of F: camera from the previous image/data, then render.
+ * aux receives the data the depth and normal mappings read in the next pass:
+ * the view depth of the hit along the base camera's forward axis, and the
+ * hit triangle's unit geometric normal (+inf and 0 after a miss). */
 static void pixel_step(const orc_scene* s, const orc_camera* cam, int W, int H, int x, int y,
-                       const float prev[3], float le, float ld, float rgb[3], int32_t* id_out) {
+                       const float prev[3], const float* prev_aux, int mode, float z0, float le,
+                       float ld, float rgb[3], int32_t* id_out, float aux[4]) {
     float o[3], d[3], t;
     int32_t id;
     int front;
-    orc_ray(cam, W, H, x, y, prev, le, ld, o, d);
+    orc_ray(cam, W, H, x, y, prev, prev_aux, mode, z0, le, ld, o, d);
     if (orc_closest_hit(s, o, d, 0, &t, &id, &front)) {
         orc_shade(s, id, front, rgb);
         *id_out = id;
+        float P[3];
+        for (int c = 0; c < 3; ++c) P[c] = o[c] + t * d[c];
+        aux[0] = ((P[0] - cam->eye[0]) * cam->forward[0] + (P[1] - cam->eye[1]) * cam->forward[1]) +
+                 (P[2] - cam->eye[2]) * cam->forward[2];
+        orc_normal(s, id, &aux[1]);
     } else {
         for (int c = 0; c < 3; ++c) rgb[c] = s->background[c];
         *id_out = -1;
+        aux[0] = INFINITY;
+        aux[1] = aux[2] = aux[3] = 0.0f;
     }
 }
 
@@ -490,10 +532,13 @@ typedef struct {
     const orc_scene* s;
     const orc_camera* cam;
     int W, H;
-    float le, ld;
+    int mode;
+    float z0, le, ld;
     const float* prev;
+    const float* prev_aux;
     float* out;
     int32_t* ids;
+    float* out_aux;
     atomic_int next_row;
 } pass_job;
 
@@ -506,9 +551,13 @@ static void* pass_worker(void* arg) {
         for (int x = 0; x < j->W; ++x) {
             size_t p = (size_t)y * j->W + x;
             const float* pv = j->prev ? &j->prev[3 * p] : seed;
+            const float* pa = j->prev_aux ? &j->prev_aux[4 * p] : NULL;
             int32_t id;
-            pixel_step(j->s, j->cam, j->W, j->H, x, y, pv, j->le, j->ld, &j->out[3 * p], &id);
+            float aux[4];
+            pixel_step(j->s, j->cam, j->W, j->H, x, y, pv, pa, j->mode, j->z0, j->le, j->ld, &j->out[3 * p],
+                       &id, aux);
             if (j->ids) j->ids[p] = id;
+            if (j->out_aux) memcpy(&j->out_aux[4 * p], aux, sizeof aux);
         }
     }
     return NULL;
@@ -523,29 +572,38 @@ static void run_threads(void* (*fn)(void*), void* job, int nthreads) {
     free(th);
 }
 
-int orc_render_pass(const orc_scene* s, const orc_camera* cam, int W, int H,
-                    float lambda_eye, float lambda_dir, const float* prev,
-                    float* out, int32_t* ids, int nthreads) {
-    if (!s || !cam || W < 1 || H < 1 || !out) return -1;
+int orc_render_pass(const orc_scene* s, const orc_camera* cam, int W, int H, int mode, float z0,
+                    float lambda_eye, float lambda_dir, const float* prev, const float* prev_aux,
+                    float* out, int32_t* ids, float* out_aux, int nthreads) {
+    if (!s || !cam || W < 1 || H < 1 || !out || mode < 0 || mode > 2) return -1;
     pass_job j;
-    j.s = s; j.cam = cam; j.W = W; j.H = H; j.le = lambda_eye; j.ld = lambda_dir;
-    j.prev = prev; j.out = out; j.ids = ids;
+    j.s = s; j.cam = cam; j.W = W; j.H = H; j.mode = mode; j.z0 = z0; j.le = lambda_eye; j.ld = lambda_dir;
+    j.prev = prev; j.prev_aux = prev_aux; j.out = out; j.ids = ids; j.out_aux = out_aux;
     atomic_init(&j.next_row, 0);
     run_threads(pass_worker, &j, nthreads);
     return 0;
 }
 
-int orc_render(const orc_scene* s, const orc_camera* cam, int W, int H, int K,
+int orc_render(const orc_scene* s, const orc_camera* cam, int W, int H, int K, int mode, float z0,
                float lambda_eye, float lambda_dir, float* out, int32_t* ids, int nthreads) {
-    if (!s || !cam || W < 1 || H < 1 || K < 1 || !out) return -1;
+    if (!s || !cam || W < 1 || H < 1 || K < 1 || !out || mode < 0 || mode > 2) return -1;
     size_t P = (size_t)W * H;
+    float* aux[2] = {NULL, NULL};
+    if (mode != ORC_MODE_COLOR) {
+        aux[0] = (float*)malloc(sizeof(float) * 4 * P);
+        aux[1] = (float*)malloc(sizeof(float) * 4 * P);
+    }
     /* I_0 is the grey seed; image k of the output is the paper's I_{k+1}. */
     for (int k = 0; k < K; ++k) {
         const float* prev = k == 0 ? NULL : &out[(size_t)(k - 1) * P * 3];
-        int rc = orc_render_pass(s, cam, W, H, lambda_eye, lambda_dir, prev, &out[(size_t)k * P * 3],
-                                 ids ? &ids[(size_t)k * P] : NULL, nthreads);
-        if (rc) return rc;
+        const float* prev_aux = k == 0 ? NULL : aux[(k - 1) & 1];
+        int rc = orc_render_pass(s, cam, W, H, mode, z0, lambda_eye, lambda_dir, prev, prev_aux,
+                                 &out[(size_t)k * P * 3], ids ? &ids[(size_t)k * P] : NULL, aux[k & 1],
+                                 nthreads);
+        if (rc) { free(aux[0]); free(aux[1]); return rc; }
     }
+    free(aux[0]);
+    free(aux[1]);
     return 0;
 }
 
@@ -553,7 +611,8 @@ typedef struct {
     const orc_scene* s;
     const orc_camera* cam;
     int W, H, K;
-    float le, ld;
+    int mode;
+    float z0, le, ld;
     const int32_t* pix;
     int n;
     float* out;
@@ -569,27 +628,33 @@ static void* pix_worker(void* arg) {
         int p = j->pix[i];
         int x = p % j->W, y = p / j->W;
         float prev[3] = {0.5f, 0.5f, 0.5f};
+        float aux[4], prev_aux[4];
+        int have_aux = 0;
         for (int k = 0; k < j->K; ++k) {
             float rgb[3];
             int32_t id;
-            pixel_step(j->s, j->cam, j->W, j->H, x, y, prev, j->le, j->ld, rgb, &id);
+            pixel_step(j->s, j->cam, j->W, j->H, x, y, prev, have_aux ? prev_aux : NULL, j->mode, j->z0,
+                       j->le, j->ld, rgb, &id, aux);
             memcpy(&j->out[((size_t)i * j->K + k) * 3], rgb, sizeof rgb);
             if (j->ids) j->ids[(size_t)i * j->K + k] = id;
             memcpy(prev, rgb, sizeof rgb);
+            memcpy(prev_aux, aux, sizeof aux);
+            have_aux = 1;
         }
     }
     return NULL;
 }
 
-int orc_render_pixels(const orc_scene* s, const orc_camera* cam, int W, int H, int K,
+int orc_render_pixels(const orc_scene* s, const orc_camera* cam, int W, int H, int K, int mode, float z0,
                       float lambda_eye, float lambda_dir, const int32_t* pix, int n,
                       float* out, int32_t* ids, int nthreads) {
-    if (!s || !cam || W < 1 || H < 1 || K < 1 || n < 0 || (n > 0 && (!pix || !out))) return -1;
+    if (!s || !cam || W < 1 || H < 1 || K < 1 || n < 0 || (n > 0 && (!pix || !out)) || mode < 0 || mode > 2)
+        return -1;
     for (int i = 0; i < n; ++i)
         if (pix[i] < 0 || (int64_t)pix[i] >= (int64_t)W * H) return -1;
     pix_job j;
-    j.s = s; j.cam = cam; j.W = W; j.H = H; j.K = K; j.le = lambda_eye; j.ld = lambda_dir;
-    j.pix = pix; j.n = n; j.out = out; j.ids = ids;
+    j.s = s; j.cam = cam; j.W = W; j.H = H; j.K = K; j.mode = mode; j.z0 = z0; j.le = lambda_eye;
+    j.ld = lambda_dir; j.pix = pix; j.n = n; j.out = out; j.ids = ids;
     atomic_init(&j.next, 0);
     run_threads(pix_worker, &j, nthreads);
     return 0;

@@ -46,9 +46,16 @@ void orc_scene_destroy(orc_scene* s);
 /* BVH statistics: nodes, leaves, max depth (0s for a brute-force scene). */
 void orc_scene_stats(const orc_scene* s, int32_t out[3]);
 
-/* Ray of pixel (x, y) given the previous colour prev[3] (Eq. N, Eq. D,
- * Section 3 colour mapping). */
+/* Displacement mappings: Section 3 colour, Section 4 depth, Section 5 normal. */
+#define ORC_MODE_COLOR 0
+#define ORC_MODE_DEPTH 1
+#define ORC_MODE_NORMAL 2
+
+/* Ray of pixel (x, y) given the previous colour prev[3] and the previous
+ * hit's data prev_aux[4] = (view depth, unit normal) or NULL for the seed
+ * (Eq. N, Eq. D; Sections 3, 4, 5). */
 void orc_ray(const orc_camera* cam, int W, int H, int x, int y, const float prev[3],
+             const float prev_aux[4], int mode, float z0,
              float lambda_eye, float lambda_dir, float o[3], float d[3]);
 
 /* Watertight ray/triangle test.  Returns 1 on a hit with t > 0, writing
@@ -63,20 +70,24 @@ int orc_closest_hit(const orc_scene* s, const float o[3], const float d[3], int 
 
 /* Shaded colour of triangle id seen from its front (1) or back (0) side. */
 void orc_shade(const orc_scene* s, int32_t id, int front, float rgb[3]);
+/* Unit geometric normal cross(v1-v0, v2-v0) / |...| of triangle id. */
+void orc_normal(const orc_scene* s, int32_t id, float n[3]);
 
-/* One pass: prev [H][W][3] (NULL = the grey seed) -> out [H][W][3],
- * ids [H][W] (may be NULL).  nthreads <= 0 uses every online core. */
-int orc_render_pass(const orc_scene* s, const orc_camera* cam, int W, int H,
-                    float lambda_eye, float lambda_dir, const float* prev,
-                    float* out, int32_t* ids, int nthreads);
+/* One pass: prev [H][W][3] and prev_aux [H][W][4] (NULL = the seed) ->
+ * out [H][W][3], ids [H][W], out_aux [H][W][4] (view depth of the hit along
+ * the camera's forward axis, unit normal; +inf and 0 after a miss).  ids and
+ * out_aux may be NULL.  nthreads <= 0 uses every online core. */
+int orc_render_pass(const orc_scene* s, const orc_camera* cam, int W, int H, int mode, float z0,
+                    float lambda_eye, float lambda_dir, const float* prev, const float* prev_aux,
+                    float* out, int32_t* ids, float* out_aux, int nthreads);
 
 /* K passes from the grey seed: out [K][H][W][3], ids [K][H][W] or NULL. */
-int orc_render(const orc_scene* s, const orc_camera* cam, int W, int H, int K,
+int orc_render(const orc_scene* s, const orc_camera* cam, int W, int H, int K, int mode, float z0,
                float lambda_eye, float lambda_dir, float* out, int32_t* ids, int nthreads);
 
 /* Full K-pass chains of n selected pixels (index y*W + x): out [n][K][3],
  * ids [n][K] or NULL. */
-int orc_render_pixels(const orc_scene* s, const orc_camera* cam, int W, int H, int K,
+int orc_render_pixels(const orc_scene* s, const orc_camera* cam, int W, int H, int K, int mode, float z0,
                       float lambda_eye, float lambda_dir, const int32_t* pix, int n,
                       float* out, int32_t* ids, int nthreads);
 

@@ -39,6 +39,14 @@ MUTATIONS = {
     "cumulative_displacement": ("const float* prev = k == 0 ? NULL : &out[(size_t)(k - 1) * P * 3];",
                                 "const float* prev = k < 2 ? NULL : &out[(size_t)(k - 2) * P * 3];"),
     "aspect_inverted": ("float aspect = (float)W / (float)H;", "float aspect = (float)H / (float)W;"),
+    "depth_signed_not_abs": ("float kz = (z < INFINITY) ? fabsf(z - z0) : 0.0f;",
+                             "float kz = (z < INFINITY) ? (z - z0) : 0.0f;"),
+    "depth_miss_displaced": ("float kz = (z < INFINITY) ? fabsf(z - z0) : 0.0f;",
+                             "float kz = (z < INFINITY) ? fabsf(z - z0) : 1.0f;"),
+    "cross_product_reversed": ("w[0] = C[1] * N[2] - C[2] * N[1];", "w[0] = C[2] * N[1] - C[1] * N[2];"),
+    "view_direction_unnormalised": ("for (int c = 0; c < 3; ++c) C[c] = q[c] / ql;",
+                                    "for (int c = 0; c < 3; ++c) C[c] = q[c];"),
+    "aux_depth_is_t": ("        aux[0] = ((P[0] - cam->eye[0])", "        aux[0] = t + 0.0f * ((P[0] - cam->eye[0])"),
 }
 
 
@@ -53,6 +61,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     subprocess.check_call(["gcc", *oracle.GCC_FLAGS, "-o", str(lib), str(tmp_path / "rcp_oracle.c"), "-lm"])
     env = dict(os.environ, RCP_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_modes.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins did not catch mutation {name}:\n{r.stdout[-2000:]}"
