@@ -86,15 +86,24 @@ typedef struct {
     float tan_half_fovy;
 } rcp_camera;
 
-/* Displacement mapping.  With w = (2R-1) right + (2G-1) up + (2B-1) forward
- * computed from the previous colour of the pixel (Section 3):
+/* Displacement mapping.  Every pass displaces the base camera of each pixel
+ * by a vector w computed from the previous pass at the same pixel:
+ *   RCP_MODE_COLOR  (Section 3)  w = (2R-1) right + (2G-1) up + (2B-1) forward
+ *   RCP_MODE_DEPTH  (Section 4)  w = |z - z0| (colour vector), z the view depth
+ *                   of the previous hit along the camera's forward axis
+ *                   (w = 0 after a miss)
+ *   RCP_MODE_NORMAL (Section 5)  w = C x N, C the pixel's undisplaced view
+ *                   direction, N the previous hit's unit geometric normal
+ *                   (w = 0 after a miss)
+ * and then
  *   V_e = lambda_eye w                  (eye displacement, Section 2)
  *   V_p = (lambda_eye + lambda_dir) w   (image-plane displacement)
  * so the displaced ray starts at eye + lambda_eye w with direction
- * normalize(P_p - P_e + lambda_dir w).  Section 3's colour method keeps the
- * eye fixed: (lambda_eye, lambda_dir) = (0, lambda).
- * mode: RCP_MODE_COLOR (0) is the only mode; z0 is reserved and ignored.
- * Valid ranges: finite, lambda_eye >= 0, 0 <= lambda_dir < 1. */
+ * normalize(P_p - P_e + lambda_dir w).  The paper's mappings keep the eye
+ * fixed: (lambda_eye, lambda_dir) = (0, lambda).  The grey seed of pass 1 has
+ * no hit, so pass 1 is the undisplaced render in every mode.
+ * Valid: finite values, lambda_eye >= 0, 0 <= lambda_dir < 1; z0 is used by
+ * RCP_MODE_DEPTH only. */
 typedef struct {
     float lambda_eye;
     float lambda_dir;
@@ -103,6 +112,8 @@ typedef struct {
 } rcp_displacement;
 
 #define RCP_MODE_COLOR 0
+#define RCP_MODE_DEPTH 1
+#define RCP_MODE_NORMAL 2
 
 /* Build options (NULL = defaults).  max_leaf: most triangles per BVH leaf
  * (1..8, default 4); top_levels: BVH levels staged in LDS by the traversal
@@ -170,13 +181,19 @@ rcp_status rcp_render(rcp_scene* scene, const rcp_camera* base_camera, int W, in
 
 /* One pass of F: out = F(prev) for a caller-supplied previous image.
  *   prev_rgb  device [H][W][3] float32, or NULL for the grey seed
+ *   prev_aux  device [H][W][4] float32 (view depth, unit normal) of the
+ *             previous pass's hits, as written to out_aux; NULL = the seed
+ *             (no hit).  Read by RCP_MODE_DEPTH and RCP_MODE_NORMAL only.
  *   out_rgb   device [H][W][3] float32
  *   out_ids   device [H][W] int32 or NULL
- * rcp_render's image k equals rcp_render_pass applied to image k-1.
- * Asynchronous on hip_stream. */
+ *   out_aux   device [H][W][4] float32 or NULL: view depth of the hit along
+ *             the camera's forward axis and its unit normal (+inf and 0
+ *             after a miss)
+ * rcp_render's image k equals rcp_render_pass applied to image k-1 (and its
+ * aux).  Asynchronous on hip_stream. */
 rcp_status rcp_render_pass(rcp_scene* scene, const rcp_camera* base_camera, int W, int H,
-                           const rcp_displacement* disp, const float* prev_rgb, float* out_rgb,
-                           int32_t* out_ids, void* hip_stream);
+                           const rcp_displacement* disp, const float* prev_rgb, const float* prev_aux,
+                           float* out_rgb, int32_t* out_ids, float* out_aux, void* hip_stream);
 
 /* rcp_render plus traversal counters (a separate instrumented kernel; not
  * for timing).  counts: HOST [K][4] uint64: rays traced, inner nodes
@@ -189,13 +206,14 @@ rcp_status rcp_render_stats(rcp_scene* scene, const rcp_camera* base_camera, int
 /* Single steps of the path, for testing and measurement                   */
 /* ---------------------------------------------------------------------- */
 
-/* Displaced rays of every pixel (Section 2 ray and displacement, Section 3
- * colour mapping) without tracing them.
+/* Displaced rays of every pixel (Section 2 ray and displacement; the
+ * mapping of disp->mode) without tracing them.
  *   prev_rgb  device [H][W][3] or NULL (grey seed: the pinhole rays)
+ *   prev_aux  device [H][W][4] or NULL (see rcp_render_pass)
  *   out_org, out_dir  device [H][W][3] float32
  * Asynchronous on hip_stream. */
 rcp_status rcp_generate_rays(const rcp_camera* base_camera, int W, int H,
-                             const rcp_displacement* disp, const float* prev_rgb,
+                             const rcp_displacement* disp, const float* prev_rgb, const float* prev_aux,
                              float* out_org, float* out_dir, void* hip_stream);
 
 /* Closest hit of n arbitrary rays (org, dir device [n][3]; dir need not be

@@ -69,7 +69,9 @@ rcp_status check_disp(const rcp_displacement* d) {
     if (!std::isfinite(d->lambda_eye) || !std::isfinite(d->lambda_dir)) FAIL("displacement lambda is not finite");
     if (d->lambda_eye < 0.0f) FAIL("lambda_eye must be >= 0");
     if (!(d->lambda_dir >= 0.0f && d->lambda_dir < 1.0f)) FAIL("lambda_dir must be in [0, 1)");
-    if (d->mode != RCP_MODE_COLOR) FAIL("unknown displacement mode %d", (int)d->mode);
+    if (d->mode != RCP_MODE_COLOR && d->mode != RCP_MODE_DEPTH && d->mode != RCP_MODE_NORMAL)
+        FAIL("unknown displacement mode %d", (int)d->mode);
+    if (!std::isfinite(d->z0)) FAIL("z0 is not finite");
     return RCP_OK;
 }
 
@@ -151,8 +153,10 @@ void rcp_destroy_scene(rcp_scene* s) {
     if (s->nodes) (void)hipFree(s->nodes);
     if (s->tris) (void)hipFree(s->tris);
     if (s->shade) (void)hipFree(s->shade);
+    if (s->normals) (void)hipFree(s->normals);
     Workspace& w = s->ws;
     for (int i = 0; i < 2; ++i) if (w.state[i]) (void)hipFree(w.state[i]);
+    for (int i = 0; i < 2; ++i) if (w.aux[i]) (void)hipFree(w.aux[i]);
     if (w.counters) (void)hipFree(w.counters);
     if (w.spill) (void)hipFree(w.spill);
     if (w.stats) (void)hipFree(w.stats);
@@ -168,7 +172,8 @@ rcp_status rcp_scene_info(const rcp_scene* s, rcp_scene_stats* out) {
 
 static rcp_status render_common(rcp_scene* scene, const rcp_camera* cam, int W, int H, int K,
                                 const rcp_displacement* disp, float* out_images, int32_t* out_ids,
-                                const float* prev, unsigned long long* counts, void* stream) {
+                                const float* prev, const float* prev_aux, float* out_aux,
+                                unsigned long long* counts, void* stream) {
     clear_error();
     rcp_status st = check_scene(scene);
     if (st) return st;
@@ -178,18 +183,21 @@ static rcp_status render_common(rcp_scene* scene, const rcp_camera* cam, int W, 
     if ((st = check_size(W, H))) return st;
     if (K < 1 || K > kMaxPasses) FAIL("K = %d must be in [1, %d]", K, kMaxPasses);
     if (!out_images) FAIL("out_images must not be NULL");
-    return render(scene, c, W, H, K, disp->lambda_eye, disp->lambda_dir, out_images, out_ids, prev, counts,
-                  (hipStream_t)stream);
+    Disp d{disp->lambda_eye, disp->lambda_dir, disp->z0, disp->mode};
+    return render(scene, c, W, H, K, d, out_images, out_ids, prev, prev_aux, out_aux, counts, (hipStream_t)stream);
 }
 
 rcp_status rcp_render(rcp_scene* scene, const rcp_camera* cam, int W, int H, int K, const rcp_displacement* disp,
                       float* out_images, int32_t* out_ids, void* hip_stream) {
-    return render_common(scene, cam, W, H, K, disp, out_images, out_ids, nullptr, nullptr, hip_stream);
+    return render_common(scene, cam, W, H, K, disp, out_images, out_ids, nullptr, nullptr, nullptr, nullptr,
+                         hip_stream);
 }
 
 rcp_status rcp_render_pass(rcp_scene* scene, const rcp_camera* cam, int W, int H, const rcp_displacement* disp,
-                           const float* prev_rgb, float* out_rgb, int32_t* out_ids, void* hip_stream) {
-    return render_common(scene, cam, W, H, 1, disp, out_rgb, out_ids, prev_rgb, nullptr, hip_stream);
+                           const float* prev_rgb, const float* prev_aux, float* out_rgb, int32_t* out_ids,
+                           float* out_aux, void* hip_stream) {
+    return render_common(scene, cam, W, H, 1, disp, out_rgb, out_ids, prev_rgb, prev_aux, out_aux, nullptr,
+                         hip_stream);
 }
 
 rcp_status rcp_render_stats(rcp_scene* scene, const rcp_camera* cam, int W, int H, int K,
@@ -199,12 +207,13 @@ rcp_status rcp_render_stats(rcp_scene* scene, const rcp_camera* cam, int W, int 
         clear_error();
         FAIL("counts must not be NULL");
     }
-    return render_common(scene, cam, W, H, K, disp, out_images, out_ids, nullptr,
+    return render_common(scene, cam, W, H, K, disp, out_images, out_ids, nullptr, nullptr, nullptr,
                          (unsigned long long*)counts, hip_stream);
 }
 
 rcp_status rcp_generate_rays(const rcp_camera* cam, int W, int H, const rcp_displacement* disp,
-                             const float* prev_rgb, float* out_org, float* out_dir, void* hip_stream) {
+                             const float* prev_rgb, const float* prev_aux, float* out_org, float* out_dir,
+                             void* hip_stream) {
     clear_error();
     Camera c;
     rcp_status st;
@@ -212,8 +221,8 @@ rcp_status rcp_generate_rays(const rcp_camera* cam, int W, int H, const rcp_disp
     if ((st = check_disp(disp))) return st;
     if ((st = check_size(W, H))) return st;
     if (!out_org || !out_dir) FAIL("out_org and out_dir must not be NULL");
-    return generate_rays(c, W, H, disp->lambda_eye, disp->lambda_dir, prev_rgb, out_org, out_dir,
-                         (hipStream_t)hip_stream);
+    Disp d{disp->lambda_eye, disp->lambda_dir, disp->z0, disp->mode};
+    return generate_rays(c, W, H, d, prev_rgb, prev_aux, out_org, out_dir, (hipStream_t)hip_stream);
 }
 
 rcp_status rcp_trace_rays(rcp_scene* scene, const float* org, const float* dir, int n, float* out_t,

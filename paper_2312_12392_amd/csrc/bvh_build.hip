@@ -419,7 +419,8 @@ struct ShadeParams {
 __global__ __launch_bounds__(kB) void k_pack_tris(uint32_t n, const float* __restrict__ verts,
                                                    const uint32_t* __restrict__ idx, const float* __restrict__ albedo,
                                                    const uint32_t* __restrict__ sorted, ShadeParams sp,
-                                                   float4* __restrict__ tris, float4* __restrict__ shade) {
+                                                   float4* __restrict__ tris, float4* __restrict__ shade,
+                                                   float4* __restrict__ normals) {
     const uint32_t j = blockIdx.x * kB + threadIdx.x;
     if (j >= n) return;
     const uint32_t t = sorted ? sorted[j] : j;
@@ -439,6 +440,7 @@ __global__ __launch_bounds__(kB) void k_pack_tris(uint32_t n, const float* __res
     nx = nx / len;
     ny = ny / len;
     nz = nz / len;
+    normals[j] = make_float4(nx, ny, nz, 0.0f);
     const float3 alb = ld3(albedo, t);
     for (int side = 0; side < 2; ++side) {
         const float sx = side ? -nx : nx, sy = side ? -ny : ny, sz = side ? -nz : nz;
@@ -497,6 +499,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                 if (s->nodes) (void)hipFree(s->nodes);
                 if (s->tris) (void)hipFree(s->tris);
                 if (s->shade) (void)hipFree(s->shade);
+                if (s->normals) (void)hipFree(s->normals);
                 delete s;
                 s = nullptr;
             }
@@ -632,10 +635,11 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
         }
         RCP_TRY(dalloc(&s->tris, 3 * (size_t)n));
         RCP_TRY(dalloc(&s->shade, 2 * (size_t)n));
+        RCP_TRY(dalloc(&s->normals, (size_t)n));
         ShadeParams sp{{desc->light_dir[0], desc->light_dir[1], desc->light_dir[2]}, desc->k_a, desc->k_d};
         hipLaunchKernelGGL(k_pack_tris, dim3(blocks(n)), dim3(kB), 0, stream, n, (const float*)d_verts,
                            (const uint32_t*)d_idx, (const float*)d_rgb, (const uint32_t*)sorted, sp, s->tris,
-                           s->shade);
+                           s->shade, s->normals);
         RCP_CHECK_LAUNCH();
         if (single) {
             // SAH of one leaf holding every triangle, relative to its own box
@@ -650,6 +654,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     s->dev.nodes = s->nodes;
     s->dev.tris = s->tris;
     s->dev.shade = s->shade;
+    s->dev.normals = s->normals;
     float radius = 0.0f;
     for (size_t i = 0; i < 3 * (size_t)desc->n_verts && n > 0; ++i) radius = fmaxf(radius, fabsf(desc->verts[i]));
     s->dev.radius = radius;
@@ -663,7 +668,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     s->stats.max_depth = max_depth;
     s->stats.sah_cost = sah;
     s->stats.build_ms = ms;
-    s->stats.device_bytes = 64ull * n_nodes + 48ull * n + 32ull * n;
+    s->stats.device_bytes = 64ull * n_nodes + 48ull * n + 32ull * n + 16ull * n;
     guard.ok = true;
     *out = s;
     return RCP_OK;

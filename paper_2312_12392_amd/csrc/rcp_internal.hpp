@@ -4,6 +4,7 @@
 //   nodes  float4[n_nodes][4]   BVH2 node, 64 B: both children's boxes + links
 //   tris   float4[n_tris][3]    v0.xyz + original index bits in w, v1, v2
 //   shade  float4[n_tris][2]    shaded RGB seen from the front / back side
+//   normal float4[n_tris]       unit geometric normal (read by the normal mapping)
 // The first top_count nodes are the BVH's top levels in breadth-first order;
 // the traversal stages them in LDS.  The rest follow in depth-first order.
 #pragma once
@@ -55,6 +56,7 @@ struct DevScene {
     const float4* nodes;
     const float4* tris;
     const float4* shade;
+    const float4* normals;
     uint32_t n_nodes;
     uint32_t n_tris;
     uint32_t top_count;
@@ -71,6 +73,8 @@ struct Camera {
 // Per-render workspace (grown on demand, owned by the scene).
 struct Workspace {
     float4* state[2] = {nullptr, nullptr};    // compact {pix, rgb} lists
+    float4* aux[2] = {nullptr, nullptr};      // their {view depth, normal} (depth and normal modes)
+    size_t aux_cap = 0;
     size_t state_cap = 0;                      // entries per list
     uint32_t* counters = nullptr;              // [2 * kMaxPasses + 8]
     int32_t* spill = nullptr;                  // traversal stack overflow
@@ -88,6 +92,7 @@ struct rcp_scene {
     float4* nodes = nullptr;
     float4* tris = nullptr;
     float4* shade = nullptr;
+    float4* normals = nullptr;
     rcp_scene_stats stats{};
     rcp::Workspace ws;
 };
@@ -102,12 +107,17 @@ rcp_status radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, 
 rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts, hipStream_t stream,
                        rcp_scene** out);
 
-rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, float lambda_eye,
-                  float lambda_dir, float* out_images, int32_t* out_ids, const float* prev_rgb,
+struct Disp {
+    float le, ld, z0;
+    int mode;
+};
+
+rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& disp, float* out_images,
+                  int32_t* out_ids, const float* prev_rgb, const float* prev_aux, float* out_aux,
                   unsigned long long* host_counts, hipStream_t stream);
 
-rcp_status generate_rays(const Camera& cam, int W, int H, float lambda_eye, float lambda_dir,
-                         const float* prev_rgb, float* org, float* dir, hipStream_t stream);
+rcp_status generate_rays(const Camera& cam, int W, int H, const Disp& disp, const float* prev_rgb,
+                         const float* prev_aux, float* org, float* dir, hipStream_t stream);
 
 rcp_status trace_rays(rcp_scene* s, const float* org, const float* dir, int n, float* out_t,
                       int32_t* out_id, int32_t* out_front, hipStream_t stream);

@@ -41,16 +41,20 @@ struct PassArgs {
     DevScene sc;
     Camera cam;
     int W, H, K, k;
-    float le, ld;
+    float le, ld, z0;
     uint32_t n_items0;              // pass-0 items (8x8 tiles * 64)
     int refill_min;                 // idle lanes that trigger a refill (1..64)
     int tiles_x;
     const float4* state_in;         // pass > 0: {pix bits, r, g, b}
+    const float4* aux_in;           // pass > 0, depth/normal modes: {view depth, normal}
     const float* prev_img;          // pass 0: previous image or NULL (grey seed)
+    const float* prev_aux;          // pass 0: previous [H][W][4] hit data or NULL (seed)
     float4* state_out;              // NULL: no following pass
+    float4* aux_out;
     uint32_t* counters;             // [kMaxPasses] list sizes, [kMaxPasses..] fetch
     float* out;                     // [K][H][W][3]
     int32_t* ids;                   // [K][H][W] or NULL
+    float* out_aux;                 // [H][W][4] of image k or NULL (single passes)
     int32_t* spill;
     uint32_t spill_stride;          // threads in the grid
     unsigned long long* stats;      // [kMaxPasses][4] or NULL
@@ -64,25 +68,44 @@ __device__ inline uint32_t lanes_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Ray of pixel (x, y): P'_e = P_e + V_e, N = normalize(P'_p - P'_e) with the
-// colour mapping w = (2R-1) right + (2G-1) up + (2B-1) forward.
+// Ray of pixel (x, y): P'_e = P_e + V_e, N = normalize(P'_p - P'_e), with
+// w from the pixel's previous colour and hit data `aux` (view depth, unit
+// normal): the colour vector (2R-1) right + (2G-1) up + (2B-1) forward
+// (Section 3), that vector times |z - z0| (Section 4, none after a miss), or
+// C x N with C the undisplaced view direction (Section 5).
+template <int MODE>
 __device__ inline void make_ray(const Camera& c, int W, int H, int x, int y, float pr, float pg, float pb,
-                                float le, float ld, float o[3], float d[3]) {
+                                const float aux[4], float z0, float le, float ld, float o[3], float d[3]) {
     const float fx = (float)(2 * x + 1) / (float)W - 1.0f;
     const float fy = 1.0f - (float)(2 * y + 1) / (float)H;
     const float aspect = (float)W / (float)H;
     const float s = fx * (c.th * aspect);
     const float t = fy * c.th;
-    const float mr = 2.0f * pr - 1.0f;
-    const float mg = 2.0f * pg - 1.0f;
-    const float mb = 2.0f * pb - 1.0f;
-    float dp[3];
+    float q[3], w[3], dp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[a] = (c.forward[a] + s * c.right[a]) + t * c.up[a];
+    if (MODE == RCP_MODE_NORMAL) {
+        const float ql = sqrtf((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]);
+        const float C0 = q[0] / ql, C1 = q[1] / ql, C2 = q[2] / ql;
+        w[0] = C1 * aux[3] - C2 * aux[2];
+        w[1] = C2 * aux[1] - C0 * aux[3];
+        w[2] = C0 * aux[2] - C1 * aux[1];
+    } else {
+        const float mr = 2.0f * pr - 1.0f;
+        const float mg = 2.0f * pg - 1.0f;
+        const float mb = 2.0f * pb - 1.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) w[a] = (mr * c.right[a] + mg * c.up[a]) + mb * c.forward[a];
+        if (MODE == RCP_MODE_DEPTH) {
+            const float kz = (aux[0] < INFINITY) ? fabsf(aux[0] - z0) : 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) w[a] = kz * w[a];
+        }
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float q = (c.forward[a] + s * c.right[a]) + t * c.up[a];
-        const float w = (mr * c.right[a] + mg * c.up[a]) + mb * c.forward[a];
-        o[a] = c.eye[a] + le * w;
-        dp[a] = q + ld * w;
+        o[a] = c.eye[a] + le * w[a];
+        dp[a] = q[a] + ld * w[a];
     }
     const float len = sqrtf((dp[0] * dp[0] + dp[1] * dp[1]) + dp[2] * dp[2]);
 #pragma unroll
@@ -356,18 +379,20 @@ constexpr int kStage = 128;     // per-wave staging of appended entries (flushed
 #define RCP_WAVES_PER_EU 1
 #endif
 
-template <bool STATS>
+template <bool STATS, int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVES_PER_EU))) void k_pass(PassArgs a) {
+    constexpr bool AUX = MODE != RCP_MODE_COLOR;
     extern __shared__ float4 smem[];
     float4* top = smem;                                                 // top_count * 4
-    float4* stage_all = smem + 4 * a.sc.top_count;                      // kWaves * kStage
-    int32_t* stack_area = (int32_t*)(stage_all + kWaves * kStage);      // kStack * kBlock
+    float4* stage_all = smem + 4 * a.sc.top_count;                      // kWaves * kStage (x2 with aux)
+    int32_t* stack_area = (int32_t*)(stage_all + (AUX ? 2 : 1) * kWaves * kStage);   // kStack * kBlock
 
     for (uint32_t i = threadIdx.x; i < 4 * a.sc.top_count; i += kBlock) top[i] = a.sc.nodes[i];
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     float4* stage = stage_all + (threadIdx.x >> 6) * kStage;
+    float4* stage_aux = stage_all + kWaves * kStage + (threadIdx.x >> 6) * kStage;
     const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
     Stack st;
     st.lds = stack_area + threadIdx.x;
@@ -385,6 +410,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
     uint32_t fill = 0;             // wave-uniform: entries in this wave's stage
     uint32_t pix = 0;
     float pr = 0.5f, pg = 0.5f, pb = 0.5f;
+    float pa[4] = {INFINITY, 0.0f, 0.0f, 0.0f};   // previous hit data (depth, normal)
     Trav tv;
     tv.node = -1;
 
@@ -414,17 +440,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
                         pg = a.prev_img[3 * (size_t)pix + 1];
                         pb = a.prev_img[3 * (size_t)pix + 2];
                     }
+                    if (AUX) {
+                        pa[0] = INFINITY; pa[1] = 0.0f; pa[2] = 0.0f; pa[3] = 0.0f;
+                        if (valid && a.prev_aux) {
+                            const float4 v = *(const float4*)&a.prev_aux[4 * (size_t)pix];
+                            pa[0] = v.x; pa[1] = v.y; pa[2] = v.z; pa[3] = v.w;
+                        }
+                    }
                 } else if (valid) {
                     const float4 sv = a.state_in[item];
                     pix = __float_as_uint(sv.x);
                     pr = sv.y; pg = sv.z; pb = sv.w;
+                    if (AUX) {
+                        const float4 v = a.aux_in[item];
+                        pa[0] = v.x; pa[1] = v.y; pa[2] = v.z; pa[3] = v.w;
+                    }
                     y = (int)(pix / (uint32_t)a.W);
                     x = (int)(pix - (uint32_t)y * (uint32_t)a.W);
                 }
                 if (valid) {
-                    float o[3], d[3];
-                    make_ray(a.cam, a.W, a.H, x, y, pr, pg, pb, a.le, a.ld, o, d);
-                    trav_init(tv, a.sc, o, d, st);
+                    float ro[3], rd[3];
+                    make_ray<MODE>(a.cam, a.W, a.H, x, y, pr, pg, pb, pa, a.z0, a.le, a.ld, ro, rd);
+                    trav_init(tv, a.sc, ro, rd, st);
                     alive = true;
                     if (STATS) ++s_rays;
                 }
@@ -441,26 +478,53 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
         // ---- finished rays: shade, write, compact ----------------------------
         const bool done = alive && tv.node == -1;
         float rgb[3] = {0.0f, 0.0f, 0.0f};
+        float na[4] = {INFINITY, 0.0f, 0.0f, 0.0f};   // this pass's hit data
         int32_t hid = -1;
         if (done) {
             if (tv.h.id != INT_MAX) {
                 const float4 c = a.sc.shade[2 * (size_t)tv.h.slot + (tv.h.front ? 0 : 1)];
                 rgb[0] = c.x; rgb[1] = c.y; rgb[2] = c.z;
                 hid = tv.h.id;
+                if (AUX || a.out_aux) {
+                    // view depth of P = o + t d along the camera's forward axis; the
+                    // ray is rebuilt (bit-identical) rather than kept in registers
+                    const int y = (int)(pix / (uint32_t)a.W);
+                    const int x = (int)(pix - (uint32_t)y * (uint32_t)a.W);
+                    float ro[3], rd[3];
+                    make_ray<MODE>(a.cam, a.W, a.H, x, y, pr, pg, pb, pa, a.z0, a.le, a.ld, ro, rd);
+                    float P3[3];
+#pragma unroll
+                    for (int c3 = 0; c3 < 3; ++c3) P3[c3] = ro[c3] + tv.h.t * rd[c3];
+                    na[0] = ((P3[0] - a.cam.eye[0]) * a.cam.forward[0] + (P3[1] - a.cam.eye[1]) * a.cam.forward[1]) +
+                            (P3[2] - a.cam.eye[2]) * a.cam.forward[2];
+                    const float4 nv = a.sc.normals[tv.h.slot];
+                    na[1] = nv.x; na[2] = nv.y; na[3] = nv.z;
+                }
             } else {
                 rgb[0] = a.sc.bg[0]; rgb[1] = a.sc.bg[1]; rgb[2] = a.sc.bg[2];
             }
             float* o3 = out_k + 3 * (size_t)pix;
             o3[0] = rgb[0]; o3[1] = rgb[1]; o3[2] = rgb[2];
             if (a.ids) a.ids[(size_t)a.k * P + pix] = hid;
+            if (a.out_aux) *(float4*)&a.out_aux[4 * (size_t)pix] = make_float4(na[0], na[1], na[2], na[3]);
         }
         if (a.state_out) {
-            const bool changed = done && (__float_as_uint(rgb[0]) != __float_as_uint(pr) ||
-                                          __float_as_uint(rgb[1]) != __float_as_uint(pg) ||
-                                          __float_as_uint(rgb[2]) != __float_as_uint(pb));
+            // the next ray is a function of the colour (and, in the depth and
+            // normal modes, of the hit data): unchanged inputs, unchanged result
+            bool changed = done && (__float_as_uint(rgb[0]) != __float_as_uint(pr) ||
+                                    __float_as_uint(rgb[1]) != __float_as_uint(pg) ||
+                                    __float_as_uint(rgb[2]) != __float_as_uint(pb));
+            if (AUX)
+                changed = changed || (done && (__float_as_uint(na[0]) != __float_as_uint(pa[0]) ||
+                                               __float_as_uint(na[1]) != __float_as_uint(pa[1]) ||
+                                               __float_as_uint(na[2]) != __float_as_uint(pa[2]) ||
+                                               __float_as_uint(na[3]) != __float_as_uint(pa[3])));
             const unsigned long long m = __ballot(changed);
             if (m) {
-                if (changed) stage[fill + lanes_below(m)] = make_float4(__uint_as_float(pix), rgb[0], rgb[1], rgb[2]);
+                if (changed) {
+                    stage[fill + lanes_below(m)] = make_float4(__uint_as_float(pix), rgb[0], rgb[1], rgb[2]);
+                    if (AUX) stage_aux[fill + lanes_below(m)] = make_float4(na[0], na[1], na[2], na[3]);
+                }
                 fill += (uint32_t)__popcll(m);
                 if (STATS && changed) ++s_app;
                 if (fill >= 64u) {
@@ -470,17 +534,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
                     if (lane == 0) base = atomicAdd(&a.counters[a.k + 1], 64u);
                     base = __shfl(base, 0);
                     a.state_out[base + lane] = stage[lane];
+                    if (AUX) a.aux_out[base + lane] = stage_aux[lane];
                     __builtin_amdgcn_wave_barrier();
-                    float4 rest = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    if ((uint32_t)lane < fill - 64u) rest = stage[64 + lane];
+                    float4 rest = make_float4(0.0f, 0.0f, 0.0f, 0.0f), rest_aux = rest;
+                    if ((uint32_t)lane < fill - 64u) {
+                        rest = stage[64 + lane];
+                        if (AUX) rest_aux = stage_aux[64 + lane];
+                    }
                     __builtin_amdgcn_wave_barrier();
-                    if ((uint32_t)lane < fill - 64u) stage[lane] = rest;
+                    if ((uint32_t)lane < fill - 64u) {
+                        stage[lane] = rest;
+                        if (AUX) stage_aux[lane] = rest_aux;
+                    }
                     __builtin_amdgcn_wave_barrier();
                     fill -= 64u;
                 }
             }
             if (done && !changed) {
-                // same colour -> same ray -> same result in every later pass
+                // same inputs -> same ray -> same result in every later pass
                 for (int kk = a.k + 1; kk < a.K; ++kk) {
                     float* q = a.out + ((size_t)kk * P + pix) * 3;
                     q[0] = rgb[0]; q[1] = rgb[1]; q[2] = rgb[2];
@@ -496,7 +567,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(&a.counters[a.k + 1], fill);
         base = __shfl(base, 0);
-        if ((uint32_t)lane < fill) a.state_out[base + lane] = stage[lane];
+        if ((uint32_t)lane < fill) {
+            a.state_out[base + lane] = stage[lane];
+            if (AUX) a.aux_out[base + lane] = stage_aux[lane];
+        }
     }
     if (STATS) {
         unsigned long long* sk = a.stats + 4 * a.k;
@@ -513,16 +587,19 @@ __global__ void k_clear_counters(uint32_t* c, int n, unsigned long long* stats) 
         for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
 }
 
-__global__ __launch_bounds__(kBlock) void k_gen_rays(Camera cam, int W, int H, float le, float ld,
-                                                      const float* __restrict__ prev, float* __restrict__ org,
-                                                      float* __restrict__ dir) {
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_gen_rays(Camera cam, int W, int H, float le, float ld, float z0,
+                                                      const float* __restrict__ prev, const float* __restrict__ prev_aux,
+                                                      float* __restrict__ org, float* __restrict__ dir) {
     const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= (uint32_t)W * (uint32_t)H) return;
     const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * (uint32_t)W);
     float pr = 0.5f, pg = 0.5f, pb = 0.5f;
     if (prev) { pr = prev[3 * (size_t)p]; pg = prev[3 * (size_t)p + 1]; pb = prev[3 * (size_t)p + 2]; }
+    float pa[4] = {INFINITY, 0.0f, 0.0f, 0.0f};
+    if (prev_aux) for (int c = 0; c < 4; ++c) pa[c] = prev_aux[4 * (size_t)p + c];
     float o[3], d[3];
-    make_ray(cam, W, H, x, y, pr, pg, pb, le, ld, o, d);
+    make_ray<MODE>(cam, W, H, x, y, pr, pg, pb, pa, z0, le, ld, o, d);
     for (int c = 0; c < 3; ++c) { org[3 * (size_t)p + c] = o[c]; dir[3 * (size_t)p + c] = d[c]; }
 }
 
@@ -554,8 +631,16 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
     }
 }
 
-rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t spill_entries) {
+rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t n_aux, size_t spill_entries) {
     Workspace& w = s->ws;
+    if (n_aux > w.aux_cap) {
+        for (int i = 0; i < 2; ++i) {
+            if (w.aux[i]) { RCP_HIP(hipFree(w.aux[i])); w.aux[i] = nullptr; }
+        }
+        w.aux_cap = 0;
+        for (int i = 0; i < 2; ++i) RCP_HIP(hipMalloc((void**)&w.aux[i], sizeof(float4) * n_aux));
+        w.aux_cap = n_aux;
+    }
     if (!w.counters) {
         RCP_HIP(hipMalloc((void**)&w.counters, sizeof(uint32_t) * (2 * kMaxPasses + 8)));
         RCP_HIP(hipMalloc((void**)&w.stats, sizeof(unsigned long long) * 4 * kMaxPasses));
@@ -593,8 +678,9 @@ struct GridInfo {
 };
 
 template <typename KernelT>
-rcp_status persistent_grid(KernelT kernel, const DevScene& sc, GridInfo& g) {
-    g.smem = sizeof(float4) * (4 * (size_t)sc.top_count + kWaves * kStage) + sizeof(int32_t) * kStack * kBlock;
+rcp_status persistent_grid(KernelT kernel, const DevScene& sc, GridInfo& g, bool aux = false) {
+    g.smem = sizeof(float4) * (4 * (size_t)sc.top_count + (aux ? 2 : 1) * kWaves * kStage) +
+             sizeof(int32_t) * kStack * kBlock;
     int per_cu = 0;
     RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, g.smem));
     int dev = 0, cus = 0;
@@ -607,58 +693,95 @@ rcp_status persistent_grid(KernelT kernel, const DevScene& sc, GridInfo& g) {
 
 }  // namespace
 
-rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, float le, float ld, float* out_images,
-                  int32_t* out_ids, const float* prev_rgb, unsigned long long* host_counts, hipStream_t stream) {
-    const bool stats = host_counts != nullptr;
+namespace {
+template <bool STATS, int MODE>
+rcp_status launch_passes(rcp_scene* s, PassArgs& a, int K, hipStream_t stream) {
+    constexpr bool AUX = MODE != RCP_MODE_COLOR;
     GridInfo g;
-    if (stats) { rcp_status st = persistent_grid(k_pass<true>, s->dev, g); if (st) return st; }
-    else { rcp_status st = persistent_grid(k_pass<false>, s->dev, g); if (st) return st; }
+    rcp_status st = persistent_grid(k_pass<STATS, MODE>, s->dev, g, AUX);
+    if (st != RCP_OK) return st;
     const uint32_t threads = (uint32_t)g.blocks * kBlock;
-    const size_t P = (size_t)W * (size_t)H;
+    const size_t P = (size_t)a.W * (size_t)a.H;
     const size_t spill_depth = s->dev.max_depth > (uint32_t)kStack ? s->dev.max_depth - kStack + 1 : 1;
-    rcp_status st = ensure_workspace(s, K > 1 ? P : 1, spill_depth * threads);
+    st = ensure_workspace(s, K > 1 ? P : 1, (K > 1 && AUX) ? P : 0, spill_depth * threads);
     if (st != RCP_OK) return st;
     Workspace& w = s->ws;
+    a.spill = w.spill;
+    a.spill_stride = threads;
+    a.counters = w.counters;
+    a.stats = STATS ? w.stats : nullptr;
     hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(256), 0, stream, w.counters, 2 * kMaxPasses + 8,
-                       stats ? w.stats : (unsigned long long*)nullptr);
+                       STATS ? w.stats : (unsigned long long*)nullptr);
     RCP_CHECK_LAUNCH();
+    for (int k = 0; k < K; ++k) {
+        a.k = k;
+        a.state_in = k == 0 ? nullptr : w.state[(k - 1) & 1];
+        a.aux_in = (k == 0 || !AUX) ? nullptr : w.aux[(k - 1) & 1];
+        a.state_out = k + 1 < K ? w.state[k & 1] : nullptr;
+        a.aux_out = (k + 1 < K && AUX) ? w.aux[k & 1] : nullptr;
+        if (k > 0) { a.prev_img = nullptr; a.prev_aux = nullptr; }
+        hipLaunchKernelGGL((k_pass<STATS, MODE>), dim3(g.blocks), dim3(kBlock), g.smem, stream, a);
+        RCP_CHECK_LAUNCH();
+    }
+    return RCP_OK;
+}
+
+template <bool STATS>
+rcp_status launch_mode(rcp_scene* s, PassArgs& a, int K, int mode, hipStream_t stream) {
+    switch (mode) {
+        case RCP_MODE_DEPTH: return launch_passes<STATS, RCP_MODE_DEPTH>(s, a, K, stream);
+        case RCP_MODE_NORMAL: return launch_passes<STATS, RCP_MODE_NORMAL>(s, a, K, stream);
+        default: return launch_passes<STATS, RCP_MODE_COLOR>(s, a, K, stream);
+    }
+}
+}  // namespace
+
+rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& disp, float* out_images,
+                  int32_t* out_ids, const float* prev_rgb, const float* prev_aux, float* out_aux,
+                  unsigned long long* host_counts, hipStream_t stream) {
+    const bool stats = host_counts != nullptr;
     const int tiles_x = (W + 7) / 8, tiles_y = (H + 7) / 8;
     PassArgs a{};
     a.sc = s->dev;
     a.cam = cam;
     a.W = W; a.H = H; a.K = K;
-    a.le = le; a.ld = ld;
+    a.le = disp.le; a.ld = disp.ld; a.z0 = disp.z0;
     a.n_items0 = (uint32_t)tiles_x * (uint32_t)tiles_y * 64u;
     a.refill_min = refill_min();
     a.tiles_x = tiles_x;
-    a.counters = w.counters;
     a.out = out_images;
     a.ids = out_ids;
-    a.spill = w.spill;
-    a.spill_stride = threads;
-    a.stats = stats ? w.stats : nullptr;
-    for (int k = 0; k < K; ++k) {
-        a.k = k;
-        a.state_in = k == 0 ? nullptr : w.state[(k - 1) & 1];
-        a.prev_img = k == 0 ? prev_rgb : nullptr;
-        a.state_out = k + 1 < K ? w.state[k & 1] : nullptr;
-        if (stats) hipLaunchKernelGGL(k_pass<true>, dim3(g.blocks), dim3(kBlock), g.smem, stream, a);
-        else hipLaunchKernelGGL(k_pass<false>, dim3(g.blocks), dim3(kBlock), g.smem, stream, a);
-        RCP_CHECK_LAUNCH();
-    }
+    a.out_aux = out_aux;
+    a.prev_img = prev_rgb;
+    a.prev_aux = prev_aux;
+    rcp_status st = stats ? launch_mode<true>(s, a, K, disp.mode, stream)
+                          : launch_mode<false>(s, a, K, disp.mode, stream);
+    if (st != RCP_OK) return st;
     if (stats) {
-        RCP_HIP(hipMemcpyAsync(host_counts, w.stats, sizeof(unsigned long long) * 4 * K, hipMemcpyDeviceToHost,
+        RCP_HIP(hipMemcpyAsync(host_counts, s->ws.stats, sizeof(unsigned long long) * 4 * K, hipMemcpyDeviceToHost,
                                stream));
         RCP_HIP(hipStreamSynchronize(stream));
     }
     return RCP_OK;
 }
 
-rcp_status generate_rays(const Camera& cam, int W, int H, float le, float ld, const float* prev_rgb, float* org,
-                         float* dir, hipStream_t stream) {
+rcp_status generate_rays(const Camera& cam, int W, int H, const Disp& disp, const float* prev_rgb,
+                         const float* prev_aux, float* org, float* dir, hipStream_t stream) {
     const size_t P = (size_t)W * (size_t)H;
-    hipLaunchKernelGGL(k_gen_rays, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, cam, W, H,
-                       le, ld, prev_rgb, org, dir);
+    const dim3 grid((unsigned)((P + kBlock - 1) / kBlock));
+    switch (disp.mode) {
+        case RCP_MODE_DEPTH:
+            hipLaunchKernelGGL(k_gen_rays<RCP_MODE_DEPTH>, grid, dim3(kBlock), 0, stream, cam, W, H, disp.le, disp.ld,
+                               disp.z0, prev_rgb, prev_aux, org, dir);
+            break;
+        case RCP_MODE_NORMAL:
+            hipLaunchKernelGGL(k_gen_rays<RCP_MODE_NORMAL>, grid, dim3(kBlock), 0, stream, cam, W, H, disp.le,
+                               disp.ld, disp.z0, prev_rgb, prev_aux, org, dir);
+            break;
+        default:
+            hipLaunchKernelGGL(k_gen_rays<RCP_MODE_COLOR>, grid, dim3(kBlock), 0, stream, cam, W, H, disp.le, disp.ld,
+                               disp.z0, prev_rgb, prev_aux, org, dir);
+    }
     RCP_CHECK_LAUNCH();
     return RCP_OK;
 }
@@ -671,7 +794,7 @@ rcp_status trace_rays(rcp_scene* s, const float* org, const float* dir, int n, f
     if (st != RCP_OK) return st;
     const uint32_t threads = (uint32_t)g.blocks * kBlock;
     const size_t spill_depth = s->dev.max_depth > (uint32_t)kStack ? s->dev.max_depth - kStack + 1 : 1;
-    st = ensure_workspace(s, 1, spill_depth * threads);
+    st = ensure_workspace(s, 1, 0, spill_depth * threads);
     if (st != RCP_OK) return st;
     hipLaunchKernelGGL(k_trace_rays, dim3(g.blocks), dim3(kBlock), g.smem, stream, s->dev, org, dir, n, out_t,
                        out_id, out_front, s->ws.spill, threads);

@@ -27,6 +27,8 @@ RCP_ERR_NOT_READY = 4
 RCP_ERR_QUEUE_FULL = 5
 RCP_ERR_INTERNAL = 6
 RCP_MODE_COLOR = 0
+RCP_MODE_DEPTH = 1
+RCP_MODE_NORMAL = 2
 
 # Every symbol include/rcp.h declares.
 EXPORTED = [
@@ -102,11 +104,11 @@ def load(path: str | None = None):
         "rcp_scene_info": (st, [P, ctypes.POINTER(rcp_scene_stats)]),
         "rcp_render": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, i32, ctypes.POINTER(rcp_displacement), P, P, P]),
         "rcp_render_pass": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, ctypes.POINTER(rcp_displacement), P, P, P,
-                                 P]),
+                                 P, P, P]),
         "rcp_render_stats": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, i32, ctypes.POINTER(rcp_displacement), P,
                                   P, P, P]),
         "rcp_generate_rays": (st, [ctypes.POINTER(rcp_camera), i32, i32, ctypes.POINTER(rcp_displacement), P, P, P,
-                                   P]),
+                                   P, P]),
         "rcp_trace_rays": (st, [P, P, P, i32, P, P, P, P]),
         "rcp_export_bvh": (st, [P, P, P]),
         "rcp_radix_sort_u64": (st, [P, P, i32, P]),
@@ -171,12 +173,13 @@ def make_camera(cam) -> rcp_camera:
     return c
 
 
-def make_displacement(lambda_eye: float, lambda_dir: float, mode: int = RCP_MODE_COLOR) -> rcp_displacement:
+def make_displacement(lambda_eye: float, lambda_dir: float, mode: int = RCP_MODE_COLOR,
+                      z0: float = 0.0) -> rcp_displacement:
     d = rcp_displacement()
     d.lambda_eye = float(lambda_eye)
     d.lambda_dir = float(lambda_dir)
     d.mode = int(mode)
-    d.z0 = 0.0
+    d.z0 = float(z0)
     return d
 
 
@@ -227,10 +230,11 @@ def rcp_render(handle: int, cam, W: int, H: int, K: int, disp: rcp_displacement,
 
 
 def rcp_render_pass(handle: int, cam, W: int, H: int, disp: rcp_displacement, prev_rgb, out_rgb, out_ids=None,
-                    stream=None) -> None:
+                    stream=None, prev_aux=None, out_aux=None) -> None:
     c = make_camera(cam)
     st = load().rcp_render_pass(handle, ctypes.byref(c), int(W), int(H), ctypes.byref(disp), _dev_ptr(prev_rgb),
-                                _dev_ptr(out_rgb), _dev_ptr(out_ids), _stream(stream))
+                                _dev_ptr(prev_aux), _dev_ptr(out_rgb), _dev_ptr(out_ids), _dev_ptr(out_aux),
+                                _stream(stream))
     _check(st, "rcp_render_pass")
 
 
@@ -246,10 +250,11 @@ def rcp_render_stats(handle: int, cam, W: int, H: int, K: int, disp: rcp_displac
     return counts
 
 
-def rcp_generate_rays(cam, W: int, H: int, disp: rcp_displacement, prev_rgb, out_org, out_dir, stream=None) -> None:
+def rcp_generate_rays(cam, W: int, H: int, disp: rcp_displacement, prev_rgb, out_org, out_dir, stream=None,
+                      prev_aux=None) -> None:
     c = make_camera(cam)
     st = load().rcp_generate_rays(ctypes.byref(c), int(W), int(H), ctypes.byref(disp), _dev_ptr(prev_rgb),
-                                  _dev_ptr(out_org), _dev_ptr(out_dir), _stream(stream))
+                                  _dev_ptr(prev_aux), _dev_ptr(out_org), _dev_ptr(out_dir), _stream(stream))
     _check(st, "rcp_generate_rays")
 
 
@@ -305,10 +310,11 @@ class Scene:
         except Exception:
             pass
 
-    def render(self, cam, W, H, K, lambda_eye, lambda_dir, with_ids=True, stream=None):
+    def render(self, cam, W, H, K, lambda_eye, lambda_dir, with_ids=True, stream=None, mode=RCP_MODE_COLOR,
+               z0=0.0):
         """Allocate outputs with torch and render; returns (images, ids)."""
         import torch
         imgs = torch.empty((K, H, W, 3), dtype=torch.float32, device="cuda")
         ids = torch.empty((K, H, W), dtype=torch.int32, device="cuda") if with_ids else None
-        rcp_render(self.handle, cam, W, H, K, make_displacement(lambda_eye, lambda_dir), imgs, ids, stream)
+        rcp_render(self.handle, cam, W, H, K, make_displacement(lambda_eye, lambda_dir, mode, z0), imgs, ids, stream)
         return imgs, ids
