@@ -202,6 +202,26 @@ rcp_status rcp_render_stats(rcp_scene* scene, const rcp_camera* base_camera, int
                             const rcp_displacement* disp, float* out_images, int32_t* out_ids,
                             uint64_t* counts, void* hip_stream);
 
+/* Screen-space variant (Section 6).  With the eye fixed, re-rendering a
+ * pass reduces to fetching every pixel's new colour from the position its
+ * own red and green point to: right by m_r and up (towards row 0) by m_g
+ * times max_smudge pixels, with m = (2R-1, 2G-1) when centred != 0 (the
+ * Section 3 mapping) or m = (R, G) as Section 6.1 describes.  The fetch takes
+ * the pixel containing the displaced pixel centre; positions outside the
+ * image follow edge_mode (Section 6.1): RCP_EDGE_CLAMP to the border,
+ * RCP_EDGE_WRAP around, or RCP_EDGE_MIRROR about the border (the border
+ * pixel repeated: -1 -> 0).
+ *   in_rgb      device [H][W][3] float32, the image the first pass reads
+ *   out_images  device [n_passes][H][W][3] float32; pass k reads image k-1
+ *               (in_rgb for k = 0); must not overlap in_rgb
+ * Requires W, H >= 1, W * H <= 2^27, 1 <= n_passes <= 64,
+ * 0 <= max_smudge <= 1e6.  Asynchronous on hip_stream. */
+#define RCP_EDGE_CLAMP 0
+#define RCP_EDGE_WRAP 1
+#define RCP_EDGE_MIRROR 2
+rcp_status rcp_gather_passes(const float* in_rgb, int W, int H, int n_passes, float max_smudge,
+                             int edge_mode, int centred, float* out_images, void* hip_stream);
+
 /* ---------------------------------------------------------------------- */
 /* Single steps of the path, for testing and measurement                   */
 /* ---------------------------------------------------------------------- */

@@ -52,6 +52,7 @@ class _Cam(ctypes.Structure):
 
 
 MODE_COLOR, MODE_DEPTH, MODE_NORMAL = 0, 1, 2
+EDGE_CLAMP, EDGE_WRAP, EDGE_MIRROR = 0, 1, 2
 
 _lib = None
 
@@ -88,6 +89,8 @@ def lib():
         L.orc_render_pixels.argtypes = [P, ctypes.POINTER(_Cam), i32, i32, i32, i32, f32, f32, f32, P, i32,
                                         P, P, i32]
         L.orc_default_threads.restype = i32
+        L.orc_gather.restype = i32
+        L.orc_gather.argtypes = [P, i32, i32, i32, f32, i32, i32, P]
         _lib = L
     return _lib
 
@@ -221,3 +224,14 @@ def intersect(o, d, v0, v1, v2):
 
 def default_threads() -> int:
     return int(lib().orc_default_threads())
+
+
+def gather(img, n, max_smudge, edge=EDGE_MIRROR, centred=True):
+    """n screen-space passes starting from img [H][W][3]; returns [n][H][W][3]."""
+    img = np.ascontiguousarray(img, np.float32)
+    H, W = img.shape[:2]
+    out = np.zeros((n, H, W, 3), np.float32)
+    rc = lib().orc_gather(_ptr(img), W, H, int(n), float(max_smudge), int(edge), 1 if centred else 0, _ptr(out))
+    if rc:
+        raise ValueError("orc_gather failed")
+    return out

@@ -659,3 +659,48 @@ int orc_render_pixels(const orc_scene* s, const orc_camera* cam, int W, int H, i
     run_threads(pix_worker, &j, nthreads);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Screen-space variant (Section 6, edges Section 6.1)                       */
+/* ------------------------------------------------------------------------ */
+
+/* Edge rule for a source index i outside [0, n). */
+static int edge_index(int i, int n, int edge) {
+    if (edge == ORC_EDGE_CLAMP) return i < 0 ? 0 : (i >= n ? n - 1 : i);
+    if (edge == ORC_EDGE_WRAP) { int m = i % n; return m < 0 ? m + n : m; }
+    /* mirror about the image border, the border pixel repeated: -1 -> 0, n -> n-1 */
+    int p = 2 * n;
+    int m = i % p;
+    if (m < 0) m += p;
+    return m < n ? m : p - 1 - m;
+}
+
+int orc_gather_pass(const float* in, int W, int H, float max_smudge, int edge, int centred, float* out) {
+    if (!in || !out || W < 1 || H < 1 || edge < 0 || edge > 2) return -1;
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            const float* c = &in[3 * ((size_t)y * W + x)];
+            /* the pixel's own red and green choose where its new colour comes
+             * from: right for red, up for green (Section 3's axes) */
+            float mr = centred ? 2.0f * c[0] - 1.0f : c[0];
+            float mg = centred ? 2.0f * c[1] - 1.0f : c[1];
+            float px = ((float)x + 0.5f) + mr * max_smudge;
+            float py = ((float)y + 0.5f) - mg * max_smudge;
+            int sx = edge_index((int)floorf(px), W, edge);
+            int sy = edge_index((int)floorf(py), H, edge);
+            memcpy(&out[3 * ((size_t)y * W + x)], &in[3 * ((size_t)sy * W + sx)], 3 * sizeof(float));
+        }
+    }
+    return 0;
+}
+
+int orc_gather(const float* in, int W, int H, int n, float max_smudge, int edge, int centred, float* out) {
+    if (n < 1) return -1;
+    size_t P = (size_t)W * H;
+    for (int k = 0; k < n; ++k) {
+        int rc = orc_gather_pass(k == 0 ? in : &out[(size_t)(k - 1) * P * 3], W, H, max_smudge, edge, centred,
+                                 &out[(size_t)k * P * 3]);
+        if (rc) return rc;
+    }
+    return 0;
+}

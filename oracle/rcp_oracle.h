@@ -91,6 +91,18 @@ int orc_render_pixels(const orc_scene* s, const orc_camera* cam, int W, int H, i
                       float lambda_eye, float lambda_dir, const int32_t* pix, int n,
                       float* out, int32_t* ids, int nthreads);
 
+/* Screen-space variant (Section 6): with the eye fixed, re-rendering reduces
+ * to fetching each pixel's new colour from a position displaced by its own
+ * red and green, max_smudge pixels at most, with an edge rule for positions
+ * outside the image (Section 6.1: clamp, wrap, mirror).  centred != 0 uses
+ * (2R-1, 2G-1) as in Section 3, otherwise (R, G) as Section 6.1 describes.
+ * One pass in -> out ([H][W][3]); n passes in -> out [n][H][W][3]. */
+#define ORC_EDGE_CLAMP 0
+#define ORC_EDGE_WRAP 1
+#define ORC_EDGE_MIRROR 2
+int orc_gather_pass(const float* in, int W, int H, float max_smudge, int edge, int centred, float* out);
+int orc_gather(const float* in, int W, int H, int n, float max_smudge, int edge, int centred, float* out);
+
 /* Number of threads orc_* uses for nthreads <= 0. */
 int orc_default_threads(void);
 

@@ -225,6 +225,24 @@ rcp_status rcp_generate_rays(const rcp_camera* cam, int W, int H, const rcp_disp
     return generate_rays(c, W, H, d, prev_rgb, prev_aux, out_org, out_dir, (hipStream_t)hip_stream);
 }
 
+rcp_status rcp_gather_passes(const float* in_rgb, int W, int H, int n_passes, float max_smudge, int edge_mode,
+                             int centred, float* out_images, void* hip_stream) {
+    clear_error();
+    rcp_status st = check_size(W, H);
+    if (st) return st;
+    if (!in_rgb || !out_images) FAIL("in_rgb and out_images must not be NULL");
+    if (n_passes < 1 || n_passes > kMaxPasses) FAIL("n_passes = %d must be in [1, %d]", n_passes, kMaxPasses);
+    if (!std::isfinite(max_smudge) || max_smudge < 0.0f || max_smudge > 1e6f) FAIL("max_smudge must be in [0, 1e6]");
+    if (edge_mode != RCP_EDGE_CLAMP && edge_mode != RCP_EDGE_WRAP && edge_mode != RCP_EDGE_MIRROR)
+        FAIL("unknown edge mode %d", edge_mode);
+    const size_t P = (size_t)W * (size_t)H;
+    const uintptr_t a0 = (uintptr_t)in_rgb, a1 = a0 + 12 * P;
+    const uintptr_t b0 = (uintptr_t)out_images, b1 = b0 + 12 * P * (size_t)n_passes;
+    if (a0 < b1 && b0 < a1) FAIL("out_images overlaps in_rgb");
+    return gather_passes(in_rgb, W, H, n_passes, max_smudge, edge_mode, centred ? 1 : 0, out_images,
+                         (hipStream_t)hip_stream);
+}
+
 rcp_status rcp_trace_rays(rcp_scene* scene, const float* org, const float* dir, int n, float* out_t,
                           int32_t* out_id, int32_t* out_front, void* hip_stream) {
     clear_error();

@@ -119,6 +119,9 @@ rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Di
 rcp_status generate_rays(const Camera& cam, int W, int H, const Disp& disp, const float* prev_rgb,
                          const float* prev_aux, float* org, float* dir, hipStream_t stream);
 
+rcp_status gather_passes(const float* in, int W, int H, int n, float smudge, int edge, int centred, float* out,
+                         hipStream_t stream);
+
 rcp_status trace_rays(rcp_scene* s, const float* org, const float* dir, int n, float* out_t,
                       int32_t* out_id, int32_t* out_front, hipStream_t stream);
 

@@ -29,12 +29,15 @@ RCP_ERR_INTERNAL = 6
 RCP_MODE_COLOR = 0
 RCP_MODE_DEPTH = 1
 RCP_MODE_NORMAL = 2
+RCP_EDGE_CLAMP = 0
+RCP_EDGE_WRAP = 1
+RCP_EDGE_MIRROR = 2
 
 # Every symbol include/rcp.h declares.
 EXPORTED = [
     "rcp_build_scene", "rcp_destroy_scene", "rcp_scene_info", "rcp_render", "rcp_render_pass",
     "rcp_render_stats", "rcp_generate_rays", "rcp_trace_rays", "rcp_export_bvh", "rcp_radix_sort_u64",
-    "rcp_status_string", "rcp_last_error",
+    "rcp_status_string", "rcp_last_error", "rcp_gather_passes",
 ]
 
 
@@ -112,6 +115,7 @@ def load(path: str | None = None):
         "rcp_trace_rays": (st, [P, P, P, i32, P, P, P, P]),
         "rcp_export_bvh": (st, [P, P, P]),
         "rcp_radix_sort_u64": (st, [P, P, i32, P]),
+        "rcp_gather_passes": (st, [P, i32, i32, i32, ctypes.c_float, i32, i32, P, P]),
         "rcp_status_string": (ctypes.c_char_p, [st]),
         "rcp_last_error": (ctypes.c_char_p, []),
     }
@@ -273,6 +277,13 @@ def rcp_export_bvh(handle: int):
                                tri_ids.ctypes.data if tri_ids.size else None)
     _check(st, "rcp_export_bvh")
     return nodes, tri_ids
+
+
+def rcp_gather_passes(in_rgb, W: int, H: int, n_passes: int, max_smudge: float, edge_mode: int, centred: bool,
+                      out_images, stream=None) -> None:
+    st = load().rcp_gather_passes(_dev_ptr(in_rgb), int(W), int(H), int(n_passes), float(max_smudge),
+                                  int(edge_mode), 1 if centred else 0, _dev_ptr(out_images), _stream(stream))
+    _check(st, "rcp_gather_passes")
 
 
 def rcp_radix_sort_u64(keys, vals, n: int, stream=None) -> None:

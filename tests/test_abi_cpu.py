@@ -111,3 +111,16 @@ def test_binding_requires_the_built_library(tmp_path):
             mod.load(str(tmp_path / "nope.so"))
     finally:
         mod._lib = saved
+
+
+def test_gather_validation_on_host():
+    _bad(rcp.rcp_gather_passes, None, 8, 8, 1, 2.0, rcp.RCP_EDGE_MIRROR, True, 1 << 20, stream=0)
+    _bad(rcp.rcp_gather_passes, 1 << 20, 8, 8, 0, 2.0, rcp.RCP_EDGE_MIRROR, True, 1 << 30, stream=0)
+    _bad(rcp.rcp_gather_passes, 1 << 20, 8, 8, 65, 2.0, rcp.RCP_EDGE_MIRROR, True, 1 << 30, stream=0)
+    _bad(rcp.rcp_gather_passes, 1 << 20, 8, 8, 1, -1.0, rcp.RCP_EDGE_MIRROR, True, 1 << 30, stream=0)
+    _bad(rcp.rcp_gather_passes, 1 << 20, 8, 8, 1, float("nan"), rcp.RCP_EDGE_MIRROR, True, 1 << 30, stream=0)
+    _bad(rcp.rcp_gather_passes, 1 << 20, 8, 8, 1, 2.0, 3, True, 1 << 30, stream=0)
+    _bad(rcp.rcp_gather_passes, 1 << 20, 0, 8, 1, 2.0, rcp.RCP_EDGE_WRAP, True, 1 << 30, stream=0)
+    # the output planes must not overlap the input image
+    assert "overlaps" in _bad(rcp.rcp_gather_passes, 1 << 20, 8, 8, 2, 2.0, rcp.RCP_EDGE_WRAP, True,
+                              (1 << 20) + 100, stream=0)

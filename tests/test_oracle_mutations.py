@@ -47,6 +47,10 @@ MUTATIONS = {
     "view_direction_unnormalised": ("for (int c = 0; c < 3; ++c) C[c] = q[c] / ql;",
                                     "for (int c = 0; c < 3; ++c) C[c] = q[c];"),
     "aux_depth_is_t": ("        aux[0] = ((P[0] - cam->eye[0])", "        aux[0] = t + 0.0f * ((P[0] - cam->eye[0])"),
+    "gather_green_down": ("float py = ((float)y + 0.5f) - mg * max_smudge;", "float py = ((float)y + 0.5f) + mg * max_smudge;"),
+    "gather_mirror_off_by_one": ("return m < n ? m : p - 1 - m;", "return m < n ? m : p - m;"),
+    "gather_wrap_negative": ("{ int m = i % n; return m < 0 ? m + n : m; }", "{ int m = i % n; return m < 0 ? 0 : m; }"),
+    "gather_rounds_to_nearest": ("int sx = edge_index((int)floorf(px), W, edge);", "int sx = edge_index((int)roundf(px), W, edge);"),
 }
 
 
@@ -62,6 +66,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     env = dict(os.environ, RCP_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_modes.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_modes.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_gather.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins did not catch mutation {name}:\n{r.stdout[-2000:]}"
