@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_terrain1m_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2312_12392_amd", "csrc", f)
-                  for f in ("trace.hip", "rcp_internal.hpp", "bvh_build.hip")]
+                  for f in ("trace.hip", "traverse.hpp", "rcp_internal.hpp", "bvh_build.hip")]
 
 
 def log(*a):

@@ -202,6 +202,66 @@ rcp_status rcp_render_stats(rcp_scene* scene, const rcp_camera* base_camera, int
                             const rcp_displacement* disp, float* out_images, int32_t* out_ids,
                             uint64_t* counts, void* hip_stream);
 
+/* ---------------------------------------------------------------------- */
+/* Batched rendering, captured pass chains, tuning                         */
+/* ---------------------------------------------------------------------- */
+
+/* One view of a batch: its own base camera, image size, pass count and
+ * colour displacement (disp.mode must be RCP_MODE_COLOR), and its own
+ * output buffers (device [K][H][W][3] float32; ids [K][H][W] or NULL). */
+typedef struct {
+    rcp_camera camera;
+    int32_t W, H, K;
+    rcp_displacement disp;
+    float* out_images;
+    int32_t* out_ids;
+} rcp_view;
+
+/* Render n_views views of the scene in one persistent launch.  Each pixel's
+ * K passes form an independent chain (Section 2: pass n at (u,v) needs only
+ * pass n-1 at (u,v)), so a lane carries a pixel through all of its view's
+ * passes and no pass barrier is needed; every view's images equal those of
+ * rcp_render for that view alone.  1 <= n_views <= 1024, each view valid as
+ * for rcp_render, outputs must not overlap.  Asynchronous on hip_stream. */
+rcp_status rcp_render_batch(rcp_scene* scene, const rcp_view* views, int n_views, void* hip_stream);
+
+/* A K-pass rcp_render call captured once as a HIP graph and replayed with a
+ * single launch.  The graph holds the arguments given at creation (camera,
+ * sizes, displacement, output buffers); rcp_graph_update replaces camera and
+ * displacement in place.  Graph, scene and outputs are used on one stream at
+ * a time.  Creation synchronises hip_stream. */
+typedef struct rcp_graph rcp_graph;
+rcp_status rcp_graph_create(rcp_scene* scene, const rcp_camera* base_camera, int W, int H, int K,
+                            const rcp_displacement* disp, float* out_images, int32_t* out_ids,
+                            void* hip_stream, rcp_graph** out);
+rcp_status rcp_graph_update(rcp_graph* graph, const rcp_camera* base_camera, const rcp_displacement* disp);
+rcp_status rcp_graph_launch(rcp_graph* graph, void* hip_stream);
+void rcp_graph_destroy(rcp_graph* graph);
+
+/* Launch parameters of the persistent kernels, per scene.  They change only
+ * the speed, never an image.
+ *   refill_min     idle lanes (1..64) that make a wave fetch new pixels
+ *   staged_nodes   top BVH nodes copied to LDS (0..top_count of the scene)
+ *   blocks_per_cu  resident workgroups per compute unit (0 = occupancy limit)
+ *   tile_log2w     pass-0 pixel tile of 64: width 2^tile_log2w (0..6) */
+typedef struct {
+    int32_t refill_min;
+    int32_t staged_nodes;
+    int32_t blocks_per_cu;
+    int32_t tile_log2w;
+} rcp_tuning;
+
+rcp_status rcp_get_tuning(const rcp_scene* scene, rcp_tuning* out);
+rcp_status rcp_set_tuning(rcp_scene* scene, const rcp_tuning* tuning);
+
+/* Autotuner: times rcp_render of this workload (median of `repeats` runs,
+ * HIP events on hip_stream) over a grid of rcp_tuning candidates, sets the
+ * fastest on the scene and returns it with its time.  The outputs receive a
+ * valid render.  Synchronous. */
+rcp_status rcp_autotune(rcp_scene* scene, const rcp_camera* base_camera, int W, int H, int K,
+                        const rcp_displacement* disp, float* out_images, int32_t* out_ids, int repeats,
+                        rcp_tuning* best, float* best_ms, void* hip_stream);
+
 /* Screen-space variant (Section 6).  With the eye fixed, re-rendering a
  * pass reduces to fetching every pixel's new colour from the position its
  * own red and green point to: right by m_r and up (towards row 0) by m_g

@@ -2,7 +2,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "rcp_internal.hpp"
 
@@ -160,6 +163,7 @@ void rcp_destroy_scene(rcp_scene* s) {
     if (w.counters) (void)hipFree(w.counters);
     if (w.spill) (void)hipFree(w.spill);
     if (w.stats) (void)hipFree(w.stats);
+    free_batch_workspace(s->bws);
     delete s;
 }
 
@@ -223,6 +227,141 @@ rcp_status rcp_generate_rays(const rcp_camera* cam, int W, int H, const rcp_disp
     if (!out_org || !out_dir) FAIL("out_org and out_dir must not be NULL");
     Disp d{disp->lambda_eye, disp->lambda_dir, disp->z0, disp->mode};
     return generate_rays(c, W, H, d, prev_rgb, prev_aux, out_org, out_dir, (hipStream_t)hip_stream);
+}
+
+rcp_status rcp_render_batch(rcp_scene* scene, const rcp_view* views, int n_views, void* hip_stream) {
+    clear_error();
+    rcp_status st = check_scene(scene);
+    if (st) return st;
+    if (!views || n_views < 1 || n_views > 1024) FAIL("n_views = %d must be in [1, 1024] with views not NULL", n_views);
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+    for (int i = 0; i < n_views; ++i) {
+        const rcp_view& v = views[i];
+        Camera c;
+        if ((st = check_camera(&v.camera, c))) { set_error("view %d: %s", i, rcp_last_error()); return st; }
+        if ((st = check_disp(&v.disp))) { set_error("view %d: %s", i, rcp_last_error()); return st; }
+        if (v.disp.mode != RCP_MODE_COLOR) FAIL("view %d: batches use the colour mapping only", i);
+        if ((st = check_size(v.W, v.H))) { set_error("view %d: %s", i, rcp_last_error()); return st; }
+        if (v.K < 1 || v.K > kMaxPasses) FAIL("view %d: K = %d must be in [1, %d]", i, v.K, kMaxPasses);
+        if (!v.out_images) FAIL("view %d: out_images must not be NULL", i);
+        const size_t n = (size_t)v.W * (size_t)v.H * (size_t)v.K;
+        spans.push_back({(uintptr_t)v.out_images, (uintptr_t)v.out_images + 12 * n});
+        if (v.out_ids) spans.push_back({(uintptr_t)v.out_ids, (uintptr_t)v.out_ids + 4 * n});
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) FAIL("output buffers of the batch overlap");
+    return render_batch(scene, views, n_views, scene->bws, (hipStream_t)hip_stream);
+}
+
+rcp_status rcp_graph_create(rcp_scene* scene, const rcp_camera* cam, int W, int H, int K, const rcp_displacement* disp,
+                            float* out_images, int32_t* out_ids, void* hip_stream, rcp_graph** out) {
+    clear_error();
+    if (out) *out = nullptr;
+    if (!out) FAIL("out must not be NULL");
+    rcp_status st = check_scene(scene);
+    if (st) return st;
+    Camera c;
+    if ((st = check_camera(cam, c))) return st;
+    if ((st = check_disp(disp))) return st;
+    if ((st = check_size(W, H))) return st;
+    if (K < 1 || K > kMaxPasses) FAIL("K = %d must be in [1, %d]", K, kMaxPasses);
+    if (!out_images) FAIL("out_images must not be NULL");
+    // work already queued on the caller's stream must not race the capture's allocations
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) {
+        set_error("hipStreamSynchronize failed");
+        return RCP_ERR_DEVICE;
+    }
+    rcp_graph* g = new rcp_graph();
+    g->scene = scene;
+    g->cam = c;
+    g->disp = Disp{disp->lambda_eye, disp->lambda_dir, disp->z0, disp->mode};
+    g->W = W; g->H = H; g->K = K;
+    g->out = out_images;
+    g->ids = out_ids;
+    st = graph_capture(g);
+    if (st != RCP_OK) { graph_free(g); return st; }
+    *out = g;
+    return RCP_OK;
+}
+
+rcp_status rcp_graph_update(rcp_graph* g, const rcp_camera* cam, const rcp_displacement* disp) {
+    clear_error();
+    if (!g) FAIL("graph is NULL");
+    Camera c;
+    rcp_status st;
+    if ((st = check_camera(cam, c))) return st;
+    if ((st = check_disp(disp))) return st;
+    if (disp->mode != g->disp.mode) FAIL("the displacement mode of a graph is fixed");
+    g->cam = c;
+    g->disp = Disp{disp->lambda_eye, disp->lambda_dir, disp->z0, disp->mode};
+    return graph_capture(g);
+}
+
+rcp_status rcp_graph_launch(rcp_graph* g, void* hip_stream) {
+    clear_error();
+    if (!g || !g->exec) FAIL("graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_status(e, "hipGraphLaunch", __FILE__, __LINE__);
+    return RCP_OK;
+}
+
+void rcp_graph_destroy(rcp_graph* g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    graph_free(g);
+}
+
+rcp_status rcp_get_tuning(const rcp_scene* s, rcp_tuning* out) {
+    clear_error();
+    if (!s || !out) FAIL("scene and out must not be NULL");
+    const Launch l = launch_params(s);
+    out->refill_min = l.refill_min;
+    out->staged_nodes = (int32_t)l.staged_nodes;
+    out->blocks_per_cu = l.blocks_per_cu;
+    out->tile_log2w = l.tile_log2w;
+    return RCP_OK;
+}
+
+rcp_status rcp_set_tuning(rcp_scene* s, const rcp_tuning* t) {
+    clear_error();
+    if (!s || !t) FAIL("scene and tuning must not be NULL");
+    if (t->refill_min < 1 || t->refill_min > 64) FAIL("refill_min must be in [1, 64]");
+    if (t->staged_nodes < 0 || (uint32_t)t->staged_nodes > s->dev.top_count)
+        FAIL("staged_nodes must be in [0, %u]", s->dev.top_count);
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) FAIL("blocks_per_cu must be in [0, 64]");
+    if (t->tile_log2w < 0 || t->tile_log2w > 6) FAIL("tile_log2w must be in [0, 6]");
+    s->tuning.refill_min = t->refill_min;
+    s->tuning.staged_nodes = t->staged_nodes;
+    s->tuning.blocks_per_cu = t->blocks_per_cu;
+    s->tuning.tile_log2w = t->tile_log2w;
+    return RCP_OK;
+}
+
+rcp_status rcp_autotune(rcp_scene* scene, const rcp_camera* cam, int W, int H, int K, const rcp_displacement* disp,
+                        float* out_images, int32_t* out_ids, int repeats, rcp_tuning* best, float* best_ms,
+                        void* hip_stream) {
+    clear_error();
+    rcp_status st = check_scene(scene);
+    if (st) return st;
+    Camera c;
+    if ((st = check_camera(cam, c))) return st;
+    if ((st = check_disp(disp))) return st;
+    if ((st = check_size(W, H))) return st;
+    if (K < 1 || K > kMaxPasses) FAIL("K = %d must be in [1, %d]", K, kMaxPasses);
+    if (!out_images || !best) FAIL("out_images and best must not be NULL");
+    if (repeats < 1 || repeats > 100) FAIL("repeats must be in [1, 100]");
+    Tuning t;
+    float ms = 0.0f;
+    st = autotune(scene, c, W, H, K, Disp{disp->lambda_eye, disp->lambda_dir, disp->z0, disp->mode}, out_images,
+                  out_ids, repeats, t, ms, (hipStream_t)hip_stream);
+    if (st != RCP_OK) return st;
+    best->refill_min = t.refill_min;
+    best->staged_nodes = t.staged_nodes;
+    best->blocks_per_cu = t.blocks_per_cu;
+    best->tile_log2w = t.tile_log2w;
+    if (best_ms) *best_ms = ms;
+    return RCP_OK;
 }
 
 rcp_status rcp_gather_passes(const float* in_rgb, int W, int H, int n_passes, float max_smudge, int edge_mode,

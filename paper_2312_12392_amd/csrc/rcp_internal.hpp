@@ -13,6 +13,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <vector>
 
 #include "rcp.h"
 
@@ -84,6 +85,27 @@ struct Workspace {
 
 constexpr int kMaxPasses = 64;
 
+struct Disp {
+    float le, ld, z0;
+    int mode;
+};
+
+// Buffers of one in-flight batch (view table, work counter, stack overflow).
+struct BatchWorkspace {
+    void* views = nullptr;
+    size_t view_cap = 0;
+    uint32_t* fetch = nullptr;
+    int32_t* spill = nullptr;
+    size_t spill_cap = 0;
+};
+
+struct Tuning {
+    int refill_min = -1;          // < 0: the library default
+    int staged_nodes = -1;        // < 0: all top nodes of the build
+    int blocks_per_cu = 0;        // 0: occupancy limit
+    int tile_log2w = 3;           // 8x8 tiles
+};
+
 }  // namespace rcp
 
 struct rcp_scene {
@@ -95,6 +117,21 @@ struct rcp_scene {
     float4* normals = nullptr;
     rcp_scene_stats stats{};
     rcp::Workspace ws;
+    rcp::BatchWorkspace bws;
+    rcp::Tuning tuning;
+};
+
+// A K-pass render captured as a HIP graph.
+struct rcp_graph {
+    rcp_scene* scene = nullptr;
+    rcp::Camera cam{};
+    rcp::Disp disp{};
+    int W = 0, H = 0, K = 0;
+    float* out = nullptr;
+    int32_t* ids = nullptr;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace rcp {
@@ -104,13 +141,11 @@ namespace rcp {
 rcp_status radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
                             int n, int end_bit, hipStream_t stream);
 
+// Idle lanes that make a wave of a persistent kernel fetch new work.
+int refill_min();
+
 rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts, hipStream_t stream,
                        rcp_scene** out);
-
-struct Disp {
-    float le, ld, z0;
-    int mode;
-};
 
 rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& disp, float* out_images,
                   int32_t* out_ids, const float* prev_rgb, const float* prev_aux, float* out_aux,
@@ -121,6 +156,27 @@ rcp_status generate_rays(const Camera& cam, int W, int H, const Disp& disp, cons
 
 rcp_status gather_passes(const float* in, int W, int H, int n, float smudge, int edge, int centred, float* out,
                          hipStream_t stream);
+
+rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchWorkspace& ws, hipStream_t stream);
+void free_batch_workspace(BatchWorkspace& ws);
+
+// The launch parameters a render of this scene uses (tuning or defaults).
+struct Launch {
+    int refill_min;
+    uint32_t staged_nodes;
+    int blocks_per_cu;
+    int tile_log2w;
+};
+Launch launch_params(const rcp_scene* s);
+
+// Make sure the scene's render workspace fits a K-pass W x H render in
+// `mode` (no allocation happens in rcp_render afterwards for that size).
+rcp_status prepare_render(rcp_scene* s, int W, int H, int K, int mode);
+
+rcp_status graph_capture(rcp_graph* g);
+void graph_free(rcp_graph* g);
+rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids,
+                    int repeats, Tuning& best, float& best_ms, hipStream_t stream);
 
 rcp_status trace_rays(rcp_scene* s, const float* org, const float* dir, int n, float* out_t,
                       int32_t* out_id, int32_t* out_front, hipStream_t stream);

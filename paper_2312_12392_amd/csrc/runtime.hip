@@ -1,0 +1,127 @@
+// Host runtime around the kernels: HIP-graph capture of K-pass renders and
+// the autotuner of the persistent kernels' launch parameters.
+#include <algorithm>
+#include <vector>
+
+#include "rcp_internal.hpp"
+
+namespace rcp {
+
+// Record the render into a fresh graph and instantiate it, or update the
+// existing executable graph in place when only kernel arguments changed.
+rcp_status graph_capture(rcp_graph* g) {
+    rcp_status st = prepare_render(g->scene, g->W, g->H, g->K, g->disp.mode);   // allocations happen here, not in the graph
+    if (st != RCP_OK) return st;
+    if (!g->capture_stream) RCP_HIP(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
+    RCP_HIP(hipStreamBeginCapture(g->capture_stream, hipStreamCaptureModeThreadLocal));
+    st = render(g->scene, g->cam, g->W, g->H, g->K, g->disp, g->out, g->ids, nullptr, nullptr, nullptr, nullptr,
+                g->capture_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(g->capture_stream, &graph);
+    if (st != RCP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    RCP_HIP(ce);
+    if (g->exec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        if (hipGraphExecUpdate(g->exec, graph, &err_node, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(g->exec);
+            g->exec = nullptr;
+        }
+    }
+    if (!g->exec) {
+        hipError_t e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_status(e, "hipGraphInstantiate", __FILE__, __LINE__);
+        }
+    }
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->graph = graph;
+    return RCP_OK;
+}
+
+void graph_free(rcp_graph* g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->capture_stream) (void)hipStreamDestroy(g->capture_stream);
+    delete g;
+}
+
+namespace {
+
+rcp_status time_render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids,
+                       int repeats, hipStream_t stream, hipEvent_t e0, hipEvent_t e1, float& ms) {
+    rcp_status st = prepare_render(s, W, H, K, d.mode);
+    if (st != RCP_OK) return st;
+    st = render(s, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);   // warm-up
+    if (st != RCP_OK) return st;
+    std::vector<float> t;
+    for (int r = 0; r < repeats; ++r) {
+        RCP_HIP(hipEventRecord(e0, stream));
+        st = render(s, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);
+        if (st != RCP_OK) return st;
+        RCP_HIP(hipEventRecord(e1, stream));
+        RCP_HIP(hipEventSynchronize(e1));
+        float x = 0.0f;
+        RCP_HIP(hipEventElapsedTime(&x, e0, e1));
+        t.push_back(x);
+    }
+    std::sort(t.begin(), t.end());
+    ms = t[t.size() / 2];
+    return RCP_OK;
+}
+
+}  // namespace
+
+// Coordinate descent over the launch parameters: each round tries every
+// candidate of one parameter with the others fixed and keeps the fastest.
+rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids,
+                    int repeats, Tuning& best, float& best_ms, hipStream_t stream) {
+    hipEvent_t e0, e1;
+    RCP_HIP(hipEventCreate(&e0));
+    RCP_HIP(hipEventCreate(&e1));
+    struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
+    const int top = (int)s->dev.top_count;
+    std::vector<int> staged = {0};
+    for (int n = 1; n < top; n = 2 * n + 1) staged.push_back(n);
+    staged.push_back(top);
+    const std::vector<int> refill = {16, 24, 32, 40, 48, 64};
+    const std::vector<int> blocks = {0, 4, 3, 2};
+    const std::vector<int> tiles = {3, 4, 2, 5};
+    Tuning cur = s->tuning;
+    if (cur.refill_min <= 0) cur.refill_min = refill_min();
+    if (cur.staged_nodes < 0) cur.staged_nodes = top;
+    s->tuning = cur;
+    float cur_ms = 0.0f;
+    rcp_status st = time_render(s, cam, W, H, K, d, out, ids, repeats, stream, e0, e1, cur_ms);
+    if (st != RCP_OK) return st;
+    for (int round = 0; round < 2; ++round) {
+        for (int param = 0; param < 4; ++param) {
+            const std::vector<int>& cands = param == 0 ? refill : param == 1 ? staged : param == 2 ? blocks : tiles;
+            for (int c : cands) {
+                Tuning t = cur;
+                int& field = param == 0 ? t.refill_min : param == 1 ? t.staged_nodes : param == 2 ? t.blocks_per_cu
+                                                                                                   : t.tile_log2w;
+                if (field == c) continue;
+                field = c;
+                s->tuning = t;
+                float ms = 0.0f;
+                st = time_render(s, cam, W, H, K, d, out, ids, repeats, stream, e0, e1, ms);
+                if (st != RCP_OK) { s->tuning = cur; return st; }
+                if (ms < cur_ms) { cur = t; cur_ms = ms; }
+            }
+            s->tuning = cur;
+        }
+    }
+    best = cur;
+    best_ms = cur_ms;
+    s->tuning = cur;
+    // leave a render made with the chosen parameters in the outputs
+    return render(s, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);
+}
+
+}  // namespace rcp

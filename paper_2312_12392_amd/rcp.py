@@ -37,7 +37,8 @@ RCP_EDGE_MIRROR = 2
 EXPORTED = [
     "rcp_build_scene", "rcp_destroy_scene", "rcp_scene_info", "rcp_render", "rcp_render_pass",
     "rcp_render_stats", "rcp_generate_rays", "rcp_trace_rays", "rcp_export_bvh", "rcp_radix_sort_u64",
-    "rcp_status_string", "rcp_last_error", "rcp_gather_passes",
+    "rcp_status_string", "rcp_last_error", "rcp_gather_passes", "rcp_render_batch", "rcp_graph_create",
+    "rcp_graph_update", "rcp_graph_launch", "rcp_graph_destroy", "rcp_get_tuning", "rcp_set_tuning", "rcp_autotune",
 ]
 
 
@@ -66,6 +67,19 @@ class rcp_displacement(ctypes.Structure):
 class rcp_build_options(ctypes.Structure):
     _fields_ = [("max_leaf", ctypes.c_int32), ("top_levels", ctypes.c_int32), ("c_trav", ctypes.c_float),
                 ("c_isect", ctypes.c_float)]
+
+
+class rcp_view(ctypes.Structure):
+    _fields_ = [("camera", rcp_camera), ("W", ctypes.c_int32), ("H", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("disp", rcp_displacement), ("out_images", ctypes.c_void_p), ("out_ids", ctypes.c_void_p)]
+
+
+class rcp_tuning(ctypes.Structure):
+    _fields_ = [("refill_min", ctypes.c_int32), ("staged_nodes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("tile_log2w", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class rcp_scene_stats(ctypes.Structure):
@@ -116,6 +130,16 @@ def load(path: str | None = None):
         "rcp_export_bvh": (st, [P, P, P]),
         "rcp_radix_sort_u64": (st, [P, P, i32, P]),
         "rcp_gather_passes": (st, [P, i32, i32, i32, ctypes.c_float, i32, i32, P, P]),
+        "rcp_render_batch": (st, [P, ctypes.POINTER(rcp_view), i32, P]),
+        "rcp_graph_create": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, i32, ctypes.POINTER(rcp_displacement), P, P,
+                                  P, ctypes.POINTER(P)]),
+        "rcp_graph_update": (st, [P, ctypes.POINTER(rcp_camera), ctypes.POINTER(rcp_displacement)]),
+        "rcp_graph_launch": (st, [P, P]),
+        "rcp_graph_destroy": (None, [P]),
+        "rcp_get_tuning": (st, [P, ctypes.POINTER(rcp_tuning)]),
+        "rcp_set_tuning": (st, [P, ctypes.POINTER(rcp_tuning)]),
+        "rcp_autotune": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, i32, ctypes.POINTER(rcp_displacement), P, P, i32,
+                              ctypes.POINTER(rcp_tuning), ctypes.POINTER(ctypes.c_float), P]),
         "rcp_status_string": (ctypes.c_char_p, [st]),
         "rcp_last_error": (ctypes.c_char_p, []),
     }
@@ -289,6 +313,96 @@ def rcp_gather_passes(in_rgb, W: int, H: int, n_passes: int, max_smudge: float, 
 def rcp_radix_sort_u64(keys, vals, n: int, stream=None) -> None:
     st = load().rcp_radix_sort_u64(_dev_ptr(keys), _dev_ptr(vals), int(n), _stream(stream))
     _check(st, "rcp_radix_sort_u64")
+
+
+def rcp_render_batch(handle: int, views, stream=None) -> None:
+    """views: sequence of (camera, W, H, K, displacement, out_images, out_ids)."""
+    arr = (rcp_view * len(views))()
+    for i, (cam, W, H, K, disp, out, ids) in enumerate(views):
+        arr[i].camera = make_camera(cam)
+        arr[i].W, arr[i].H, arr[i].K = int(W), int(H), int(K)
+        arr[i].disp = disp
+        arr[i].out_images = _dev_ptr(out)
+        arr[i].out_ids = _dev_ptr(ids)
+    st = load().rcp_render_batch(handle, arr, len(views), _stream(stream))
+    _check(st, "rcp_render_batch")
+
+
+def rcp_graph_create(handle: int, cam, W: int, H: int, K: int, disp: rcp_displacement, out_images, out_ids=None,
+                     stream=None) -> int:
+    c = make_camera(cam)
+    out = ctypes.c_void_p()
+    st = load().rcp_graph_create(handle, ctypes.byref(c), int(W), int(H), int(K), ctypes.byref(disp),
+                                 _dev_ptr(out_images), _dev_ptr(out_ids), _stream(stream), ctypes.byref(out))
+    _check(st, "rcp_graph_create")
+    return out.value
+
+
+def rcp_graph_update(graph: int, cam, disp: rcp_displacement) -> None:
+    c = make_camera(cam)
+    _check(load().rcp_graph_update(graph, ctypes.byref(c), ctypes.byref(disp)), "rcp_graph_update")
+
+
+def rcp_graph_launch(graph: int, stream=None) -> None:
+    _check(load().rcp_graph_launch(graph, _stream(stream)), "rcp_graph_launch")
+
+
+def rcp_graph_destroy(graph: int) -> None:
+    load().rcp_graph_destroy(graph)
+
+
+def rcp_get_tuning(handle: int) -> dict:
+    t = rcp_tuning()
+    _check(load().rcp_get_tuning(handle, ctypes.byref(t)), "rcp_get_tuning")
+    return t.as_dict()
+
+
+def rcp_set_tuning(handle: int, refill_min: int, staged_nodes: int, blocks_per_cu: int, tile_log2w: int) -> None:
+    t = rcp_tuning(int(refill_min), int(staged_nodes), int(blocks_per_cu), int(tile_log2w))
+    _check(load().rcp_set_tuning(handle, ctypes.byref(t)), "rcp_set_tuning")
+
+
+def rcp_autotune(handle: int, cam, W: int, H: int, K: int, disp: rcp_displacement, out_images, out_ids=None,
+                 repeats: int = 3, stream=None):
+    """Returns (tuning dict, median ms of the chosen parameters)."""
+    c = make_camera(cam)
+    t = rcp_tuning()
+    ms = ctypes.c_float()
+    st = load().rcp_autotune(handle, ctypes.byref(c), int(W), int(H), int(K), ctypes.byref(disp),
+                             _dev_ptr(out_images), _dev_ptr(out_ids), int(repeats), ctypes.byref(t), ctypes.byref(ms),
+                             _stream(stream))
+    _check(st, "rcp_autotune")
+    return t.as_dict(), float(ms.value)
+
+
+def autotune_cached(handle: int, scene_key: str, cam, W: int, H: int, K: int, disp: rcp_displacement, out_images,
+                    out_ids=None, cache_path: str | None = None, repeats: int = 3, stream=None) -> dict:
+    """Tuning for (scene, resolution, K) from a JSON cache, or tuned and
+    stored.  The key names the scene (e.g. a digest of its arrays); the
+    device name is part of it, since the best parameters depend on the GPU."""
+    import json
+    import torch
+    path = cache_path or os.path.join(os.path.expanduser("~"), ".cache", "rcp_tuning.json")
+    key = f"{torch.cuda.get_device_name()}|{scene_key}|{W}x{H}|K{K}|mode{disp.mode}"
+    cache = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if key in cache:
+        t = cache[key]["tuning"]
+        rcp_set_tuning(handle, t["refill_min"], t["staged_nodes"], t["blocks_per_cu"], t["tile_log2w"])
+        return t
+    t, ms = rcp_autotune(handle, cam, W, H, K, disp, out_images, out_ids, repeats, stream)
+    cache[key] = {"tuning": t, "ms": ms}
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1)
+    os.replace(tmp, path)
+    return t
 
 
 # ---------------------------------------------------------------------------

@@ -423,3 +423,33 @@ def workload(name: str, literal_eye: bool = False) -> Workload:
     _SCENE_CACHE[name] = sc
     return Workload(scene=sc, camera=cam, width=w, height=h, passes=k,
                     lambda_eye=lam if literal_eye else 0.0, lambda_dir=lam, name=name)
+
+
+# --------------------------------------------------------------------------
+# View mixes for batched rendering
+# --------------------------------------------------------------------------
+
+BATCH_RESOLUTIONS = [(256, 256), (512, 512), (1280, 720), (1024, 1024)]
+
+
+def orbit_views(seed: int = 3, n: int = 64, resolutions=None, k_range=(1, 8), target=(0.0, 0.0, 0.0)):
+    """n views on a random orbit around the terrain: azimuth U[0, 2 pi),
+    radius U[1.2, 1.6], height U[0.3, 0.6], looking at the origin, vfov 60;
+    resolution uniform over ``resolutions``, K uniform in ``k_range``.
+
+    Draw order from ``default_rng(seed)``: azimuth, radius, height (n each),
+    resolution index (n), K (n).  Returns a list of (Camera, W, H, K)."""
+    rng = np.random.default_rng(seed)
+    res = list(resolutions or BATCH_RESOLUTIONS)
+    az = rng.uniform(0.0, 2.0 * math.pi, size=n)
+    rad = rng.uniform(1.2, 1.6, size=n)
+    hgt = rng.uniform(0.3, 0.6, size=n)
+    ri = rng.integers(0, len(res), size=n)
+    ks = rng.integers(k_range[0], k_range[1] + 1, size=n)
+    out = []
+    for i in range(n):
+        eye = [rad[i] * math.sin(az[i]), hgt[i], -rad[i] * math.cos(az[i])]
+        cam = camera_look_at(eye, target, [0, 1, 0], 60.0)
+        W, H = res[int(ri[i])]
+        out.append((cam, int(W), int(H), int(ks[i])))
+    return out

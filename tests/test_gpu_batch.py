@@ -1,0 +1,182 @@
+"""Batched rendering, HIP-graph replays and launch tuning.
+
+Every view of a batch must equal rcp_render of that view alone (both are
+bit-exact against the oracle, which is checked on a sample); graph replays
+must equal the eager render, also with eager work between replays; tuning
+parameters change the speed only, never an image."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from paper_2312_12392_amd import rcp
+
+pytestmark = pytest.mark.gpu
+
+PATCH_CAM = scenegen.camera_look_at([0, 0.5, -1.4], [0, 0.05, 0], [0, 1, 0], 60.0)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.set_device(0)
+    rcp.load()
+
+
+def single(s, cam, W, H, K, le, ld):
+    imgs, ids = s.render(cam, W, H, K, le, ld)
+    torch.cuda.synchronize()
+    return imgs, ids
+
+
+def test_batch_equals_single_views_and_oracle():
+    sc = scenegen.terrain_patch(12, 40, 20)
+    s = rcp.Scene(sc)
+    rng = np.random.default_rng(0)
+    specs = []
+    for i, (W, H, K) in enumerate([(67, 45, 4), (1, 1, 6), (130, 1, 3), (1, 77, 2), (64, 64, 8), (33, 21, 1),
+                                   (96, 72, 5), (40, 30, 7), (8, 8, 3), (57, 43, 6), (128, 96, 2), (20, 50, 4)]):
+        ang = rng.uniform(-0.6, 0.6)
+        cam = scenegen.camera_look_at([1.4 * np.sin(ang), rng.uniform(0.3, 0.7), -1.4 * np.cos(ang)],
+                                      [0, 0.05, 0], [0, 1, 0], float(rng.uniform(40, 80)))
+        le = 0.02 if i % 3 == 0 else 0.0
+        ld = float(rng.uniform(0.0, 0.2))
+        specs.append((cam, W, H, K, le, ld))
+    say("batch of", len(specs), "views")
+    outs = [(torch.full((K, H, W, 3), -1.0, device="cuda"), torch.full((K, H, W), -7, dtype=torch.int32, device="cuda"))
+            for (_, W, H, K, _, _) in specs]
+    views = [(cam, W, H, K, rcp.make_displacement(le, ld), o, i) for (cam, W, H, K, le, ld), (o, i) in zip(specs, outs)]
+    rcp.rcp_render_batch(s.handle, views)
+    torch.cuda.synchronize()
+    orc = oracle.OracleScene(sc, use_bvh=True)
+    for n, ((cam, W, H, K, le, ld), (o, i)) in enumerate(zip(specs, outs)):
+        ref_img, ref_ids = single(s, cam, W, H, K, le, ld)
+        assert torch.equal(o, ref_img) and torch.equal(i, ref_ids), n
+        if n % 3 == 0:
+            oi, oid = orc.render(cam, W, H, K, le, ld)
+            assert np.array_equal(o.cpu().numpy(), oi) and np.array_equal(i.cpu().numpy(), oid), n
+    s.close()
+
+
+def test_batch_orbit_mix_on_terrain1m():
+    """The 64-view orbit mix (256^2 .. 1024^2, K 1..8) of the 1M scene."""
+    w = scenegen.workload("terrain1m")
+    views = scenegen.orbit_views(3, 64)
+    say("orbit mix", len(views))
+    s = rcp.Scene(w.scene)
+    d = rcp.make_displacement(0.0, 0.01)
+    outs = [torch.empty((K, H, W, 3), device="cuda") for (_, W, H, K) in views]
+    rcp.rcp_render_batch(s.handle, [(cam, W, H, K, d, o, None) for (cam, W, H, K), o in zip(views, outs)])
+    torch.cuda.synchronize()
+    orc = oracle.OracleScene(w.scene, use_bvh=True)
+    rng = np.random.default_rng(1)
+    for n, ((cam, W, H, K), o) in enumerate(zip(views, outs)):
+        ref, _ = single(s, cam, W, H, K, 0.0, 0.01)
+        assert torch.equal(o, ref), n
+        if n % 8 == 0:
+            pix = rng.choice(W * H, size=300, replace=False).astype(np.int32)
+            oi, _ = orc.render_pixels(cam, W, H, K, 0.0, 0.01, pix)
+            g = o.reshape(K, W * H, 3)[:, torch.from_numpy(pix.astype(np.int64)).cuda()].permute(1, 0, 2).cpu().numpy()
+            assert np.array_equal(g, oi), n
+    s.close()
+
+
+def test_batch_rejects_bad_views():
+    w = scenegen.workload("soup256")
+    s = rcp.Scene(w.scene)
+    o = torch.empty((2, 8, 8, 3), device="cuda")
+    d = rcp.make_displacement(0.0, 0.02)
+    with pytest.raises(rcp.RcpError):
+        rcp.rcp_render_batch(s.handle, [(w.camera, 8, 8, 2, d, o, None), (w.camera, 8, 8, 2, d, o, None)])  # overlap
+    with pytest.raises(rcp.RcpError):
+        rcp.rcp_render_batch(s.handle, [(w.camera, 8, 8, 2, rcp.make_displacement(0.0, 0.02, rcp.RCP_MODE_DEPTH), o,
+                                         None)])
+    with pytest.raises(rcp.RcpError):
+        rcp.rcp_render_batch(s.handle, [])
+    s.close()
+
+
+def test_graph_replays_equal_eager_render():
+    w = scenegen.workload("soup256")
+    say("graph replays")
+    s = rcp.Scene(w.scene)
+    ref_img, ref_ids = single(s, w.camera, 64, 64, 6, 0.0, 0.02)
+    out = torch.empty_like(ref_img)
+    ids = torch.empty_like(ref_ids)
+    g = rcp.rcp_graph_create(s.handle, w.camera, 64, 64, 6, rcp.make_displacement(0.0, 0.02), out, ids)
+    for r in range(4):
+        out.zero_()
+        ids.zero_()
+        torch.cuda.synchronize()
+        rcp.rcp_graph_launch(g)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref_img) and torch.equal(ids, ref_ids), r
+        # eager work between replays, on the same scene and stream
+        single(s, w.camera, 40, 30, 3, 0.0, 0.05)
+    # new camera and displacement in place
+    cam2 = scenegen.camera_look_at([0.4, 0.3, -2.8], [0, 0, 0], [0, 1, 0], 55.0)
+    rcp.rcp_graph_update(g, cam2, rcp.make_displacement(0.01, 0.05))
+    ref2, ref2_ids = single(s, cam2, 64, 64, 6, 0.01, 0.05)
+    for r in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        rcp.rcp_graph_launch(g)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref2) and torch.equal(ids, ref2_ids), r
+    rcp.rcp_graph_destroy(g)
+    s.close()
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(refill_min=1, staged_nodes=0, blocks_per_cu=1, tile_log2w=0),
+    dict(refill_min=64, staged_nodes=7, blocks_per_cu=2, tile_log2w=6),
+    dict(refill_min=17, staged_nodes=31, blocks_per_cu=0, tile_log2w=4),
+    dict(refill_min=40, staged_nodes=63, blocks_per_cu=3, tile_log2w=2),
+])
+def test_tuning_does_not_change_images(tuning):
+    say("tuning", tuning)
+    sc = scenegen.terrain_patch(12, 40, 20)
+    s = rcp.Scene(sc)
+    ref_img, ref_ids = single(s, PATCH_CAM, 67, 45, 5, 0.0, 0.1)
+    t = dict(tuning)
+    t["staged_nodes"] = min(t["staged_nodes"], s.info()["top_count"])
+    rcp.rcp_set_tuning(s.handle, **t)
+    assert rcp.rcp_get_tuning(s.handle) == t
+    img, ids = single(s, PATCH_CAM, 67, 45, 5, 0.0, 0.1)
+    assert torch.equal(img, ref_img) and torch.equal(ids, ref_ids)
+    # the batch kernel follows the same parameters
+    o = torch.empty_like(img)
+    rcp.rcp_render_batch(s.handle, [(PATCH_CAM, 67, 45, 5, rcp.make_displacement(0.0, 0.1), o, None)])
+    torch.cuda.synchronize()
+    assert torch.equal(o, ref_img)
+    s.close()
+
+
+def test_autotune_and_cache(tmp_path):
+    w = scenegen.workload("soup256")
+    say("autotune")
+    s = rcp.Scene(w.scene)
+    ref_img, _ = single(s, w.camera, 64, 64, 6, 0.0, 0.02)
+    out = torch.empty_like(ref_img)
+    t, ms = rcp.rcp_autotune(s.handle, w.camera, 64, 64, 6, rcp.make_displacement(0.0, 0.02), out, None, repeats=2)
+    torch.cuda.synchronize()
+    assert ms > 0 and 1 <= t["refill_min"] <= 64
+    assert rcp.rcp_get_tuning(s.handle) == t
+    assert torch.equal(out, ref_img)
+    path = str(tmp_path / "tune.json")
+    t1 = rcp.autotune_cached(s.handle, "soup256", w.camera, 64, 64, 6, rcp.make_displacement(0.0, 0.02), out,
+                             cache_path=path, repeats=1)
+    assert os.path.exists(path) and len(json.load(open(path))) == 1
+    rcp.rcp_set_tuning(s.handle, 40, 0, 0, 3)
+    t2 = rcp.autotune_cached(s.handle, "soup256", w.camera, 64, 64, 6, rcp.make_displacement(0.0, 0.02), out,
+                             cache_path=path, repeats=1)
+    assert t2 == t1 and rcp.rcp_get_tuning(s.handle) == t1
+    s.close()
