@@ -262,6 +262,62 @@ rcp_status rcp_autotune(rcp_scene* scene, const rcp_camera* base_camera, int W, 
                         const rcp_displacement* disp, float* out_images, int32_t* out_ids, int repeats,
                         rcp_tuning* best, float* best_ms, void* hip_stream);
 
+/* ---------------------------------------------------------------------- */
+/* Continuous-batching server                                              */
+/* ---------------------------------------------------------------------- */
+
+/* A render request: base camera, image size, pass count, colour
+ * displacement (disp.mode must be RCP_MODE_COLOR); with_ids != 0 also keeps
+ * the hit-ID planes. */
+typedef struct {
+    rcp_camera camera;
+    int32_t W, H, K;
+    rcp_displacement disp;
+    int32_t with_ids;
+} rcp_request;
+
+#define RCP_REQ_QUEUED 0    /* waiting for pool space or a launch */
+#define RCP_REQ_RUNNING 1   /* in a launched batch */
+#define RCP_REQ_DONE 2      /* images ready in the pool */
+#define RCP_REQ_FAILED 3
+
+typedef struct rcp_server rcp_server;
+
+/* Create a server on the scene's device.  pool_bytes of HBM are allocated
+ * once and hold the output images of admitted requests (12 B per pixel and
+ * pass, plus 4 B with ids, each rounded up to 256 B); requests are admitted
+ * first-in first-out while they fit, and up to max_inflight (1..8) batched
+ * launches run at once, each on its own stream.  A request submitted while
+ * others run joins the next launch as soon as pool space and a launch slot
+ * are free; every request's images equal those of rcp_render alone.  At most
+ * queue_capacity requests wait for admission.  The scene must outlive the
+ * server. */
+rcp_status rcp_server_create(rcp_scene* scene, uint64_t pool_bytes, int max_inflight, int queue_capacity,
+                             rcp_server** out);
+/* Queue a request; *ticket identifies it.  RCP_ERR_QUEUE_FULL when
+ * queue_capacity requests already wait; RCP_ERR_INVALID_ARGUMENT for an
+ * invalid request or one larger than the whole pool.  Thread-safe. */
+rcp_status rcp_submit(rcp_server* server, const rcp_request* request, uint64_t* ticket);
+/* State of a request (RCP_REQ_*) and, if times != NULL, its submit, start
+ * and completion times in seconds since the server was created (host clock;
+ * completion is observed by the scheduler within ~50 us). */
+rcp_status rcp_poll(rcp_server* server, uint64_t ticket, int32_t* state, double* times);
+/* Device pointers of a finished request's images [K][H][W][3] and ids
+ * [K][H][W] (NULL without ids), valid until rcp_release.
+ * RCP_ERR_NOT_READY before RCP_REQ_DONE. */
+rcp_status rcp_result(rcp_server* server, uint64_t ticket, float** images, int32_t** ids);
+/* Copy a finished request's images / ids (either may be NULL) to caller
+ * device buffers, asynchronously on hip_stream. */
+rcp_status rcp_result_copy(rcp_server* server, uint64_t ticket, float* images, int32_t* ids, void* hip_stream);
+/* Return a finished (or failed) request's pool space; the ticket ends. */
+rcp_status rcp_release(rcp_server* server, uint64_t ticket);
+/* out[0] launches so far, out[1] requests waiting, out[2] pool bytes in
+ * use, out[3] live tickets. */
+rcp_status rcp_server_stats(rcp_server* server, uint64_t out[4]);
+/* Stop the scheduler (running launches finish; requests that cannot start
+ * fail) and free the server.  NULL is ignored. */
+void rcp_server_destroy(rcp_server* server);
+
 /* Screen-space variant (Section 6).  With the eye fixed, re-rendering a
  * pass reduces to fetching every pixel's new colour from the position its
  * own red and green point to: right by m_r and up (towards row 0) by m_g

@@ -364,6 +364,76 @@ rcp_status rcp_autotune(rcp_scene* scene, const rcp_camera* cam, int W, int H, i
     return RCP_OK;
 }
 
+rcp_status rcp_server_create(rcp_scene* scene, uint64_t pool_bytes, int max_inflight, int queue_capacity,
+                             rcp_server** out) {
+    clear_error();
+    if (out) *out = nullptr;
+    if (!out) FAIL("out must not be NULL");
+    rcp_status st = check_scene(scene);
+    if (st) return st;
+    if (pool_bytes < 4096) FAIL("pool_bytes must be at least 4096");
+    if (max_inflight < 1 || max_inflight > 8) FAIL("max_inflight must be in [1, 8]");
+    if (queue_capacity < 1) FAIL("queue_capacity must be >= 1");
+    try {
+        return server_create(scene, (size_t)pool_bytes, max_inflight, queue_capacity, out);
+    } catch (const std::exception&) {
+        set_error("host allocation or thread creation failed");
+        return RCP_ERR_OUT_OF_MEMORY;
+    }
+}
+
+rcp_status rcp_submit(rcp_server* server, const rcp_request* r, uint64_t* ticket) {
+    clear_error();
+    if (!server || !r || !ticket) FAIL("server, request and ticket must not be NULL");
+    Camera c;
+    rcp_status st;
+    if ((st = check_camera(&r->camera, c))) return st;
+    if ((st = check_disp(&r->disp))) return st;
+    if (r->disp.mode != RCP_MODE_COLOR) FAIL("served requests use the colour mapping only");
+    if ((st = check_size(r->W, r->H))) return st;
+    if (r->K < 1 || r->K > kMaxPasses) FAIL("K = %d must be in [1, %d]", r->K, kMaxPasses);
+    try {
+        return server_submit(server, *r, *ticket);
+    } catch (const std::exception&) {
+        set_error("host allocation failed");
+        return RCP_ERR_OUT_OF_MEMORY;
+    }
+}
+
+rcp_status rcp_poll(rcp_server* server, uint64_t ticket, int32_t* state, double* times) {
+    clear_error();
+    if (!server || !state) FAIL("server and state must not be NULL");
+    return server_poll(server, ticket, *state, times);
+}
+
+rcp_status rcp_result(rcp_server* server, uint64_t ticket, float** images, int32_t** ids) {
+    clear_error();
+    if (!server) FAIL("server is NULL");
+    return server_result(server, ticket, images, ids);
+}
+
+rcp_status rcp_result_copy(rcp_server* server, uint64_t ticket, float* images, int32_t* ids, void* hip_stream) {
+    clear_error();
+    if (!server) FAIL("server is NULL");
+    return server_result_copy(server, ticket, images, ids, (hipStream_t)hip_stream);
+}
+
+rcp_status rcp_release(rcp_server* server, uint64_t ticket) {
+    clear_error();
+    if (!server) FAIL("server is NULL");
+    return server_release(server, ticket);
+}
+
+rcp_status rcp_server_stats(rcp_server* server, uint64_t out[4]) {
+    clear_error();
+    if (!server || !out) FAIL("server and out must not be NULL");
+    return server_stats(server, out);
+}
+
+void rcp_server_destroy(rcp_server* server) {
+    if (server) server_destroy(server);
+}
+
 rcp_status rcp_gather_passes(const float* in_rgb, int W, int H, int n_passes, float max_smudge, int edge_mode,
                              int centred, float* out_images, void* hip_stream) {
     clear_error();

@@ -178,6 +178,16 @@ void graph_free(rcp_graph* g);
 rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids,
                     int repeats, Tuning& best, float& best_ms, hipStream_t stream);
 
+size_t request_bytes(const rcp_request& r);
+rcp_status server_create(rcp_scene* scene, size_t pool_bytes, int max_inflight, int queue_capacity, rcp_server** out);
+void server_destroy(rcp_server* s);
+rcp_status server_submit(rcp_server* s, const rcp_request& r, uint64_t& ticket);
+rcp_status server_poll(rcp_server* s, uint64_t ticket, int32_t& state, double times[3]);
+rcp_status server_result(rcp_server* s, uint64_t ticket, float** images, int32_t** ids);
+rcp_status server_result_copy(rcp_server* s, uint64_t ticket, float* images, int32_t* ids, hipStream_t stream);
+rcp_status server_release(rcp_server* s, uint64_t ticket);
+rcp_status server_stats(rcp_server* s, uint64_t out[4]);
+
 rcp_status trace_rays(rcp_scene* s, const float* org, const float* dir, int n, float* out_t,
                       int32_t* out_id, int32_t* out_front, hipStream_t stream);
 

@@ -32,6 +32,7 @@ RCP_MODE_NORMAL = 2
 RCP_EDGE_CLAMP = 0
 RCP_EDGE_WRAP = 1
 RCP_EDGE_MIRROR = 2
+RCP_REQ_QUEUED, RCP_REQ_RUNNING, RCP_REQ_DONE, RCP_REQ_FAILED = 0, 1, 2, 3
 
 # Every symbol include/rcp.h declares.
 EXPORTED = [
@@ -39,6 +40,8 @@ EXPORTED = [
     "rcp_render_stats", "rcp_generate_rays", "rcp_trace_rays", "rcp_export_bvh", "rcp_radix_sort_u64",
     "rcp_status_string", "rcp_last_error", "rcp_gather_passes", "rcp_render_batch", "rcp_graph_create",
     "rcp_graph_update", "rcp_graph_launch", "rcp_graph_destroy", "rcp_get_tuning", "rcp_set_tuning", "rcp_autotune",
+    "rcp_server_create", "rcp_submit", "rcp_poll", "rcp_result", "rcp_result_copy", "rcp_release", "rcp_server_stats",
+    "rcp_server_destroy",
 ]
 
 
@@ -80,6 +83,11 @@ class rcp_tuning(ctypes.Structure):
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class rcp_request(ctypes.Structure):
+    _fields_ = [("camera", rcp_camera), ("W", ctypes.c_int32), ("H", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("disp", rcp_displacement), ("with_ids", ctypes.c_int32)]
 
 
 class rcp_scene_stats(ctypes.Structure):
@@ -130,6 +138,14 @@ def load(path: str | None = None):
         "rcp_export_bvh": (st, [P, P, P]),
         "rcp_radix_sort_u64": (st, [P, P, i32, P]),
         "rcp_gather_passes": (st, [P, i32, i32, i32, ctypes.c_float, i32, i32, P, P]),
+        "rcp_server_create": (st, [P, ctypes.c_uint64, i32, i32, ctypes.POINTER(P)]),
+        "rcp_submit": (st, [P, ctypes.POINTER(rcp_request), ctypes.POINTER(ctypes.c_uint64)]),
+        "rcp_poll": (st, [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), P]),
+        "rcp_result": (st, [P, ctypes.c_uint64, ctypes.POINTER(P), ctypes.POINTER(P)]),
+        "rcp_result_copy": (st, [P, ctypes.c_uint64, P, P, P]),
+        "rcp_release": (st, [P, ctypes.c_uint64]),
+        "rcp_server_stats": (st, [P, P]),
+        "rcp_server_destroy": (None, [P]),
         "rcp_render_batch": (st, [P, ctypes.POINTER(rcp_view), i32, P]),
         "rcp_graph_create": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, i32, ctypes.POINTER(rcp_displacement), P, P,
                                   P, ctypes.POINTER(P)]),
@@ -403,6 +419,59 @@ def autotune_cached(handle: int, scene_key: str, cam, W: int, H: int, K: int, di
         json.dump(cache, f, indent=1)
     os.replace(tmp, path)
     return t
+
+
+def rcp_server_create(handle: int, pool_bytes: int, max_inflight: int = 2, queue_capacity: int = 1024) -> int:
+    out = ctypes.c_void_p()
+    _check(load().rcp_server_create(handle, int(pool_bytes), int(max_inflight), int(queue_capacity), ctypes.byref(out)),
+           "rcp_server_create")
+    return out.value
+
+
+def rcp_submit(server: int, cam, W: int, H: int, K: int, disp: rcp_displacement, with_ids: bool = False) -> int:
+    r = rcp_request()
+    r.camera = make_camera(cam)
+    r.W, r.H, r.K = int(W), int(H), int(K)
+    r.disp = disp
+    r.with_ids = 1 if with_ids else 0
+    t = ctypes.c_uint64()
+    _check(load().rcp_submit(server, ctypes.byref(r), ctypes.byref(t)), "rcp_submit")
+    return int(t.value)
+
+
+def rcp_poll(server: int, ticket: int):
+    """Returns (state, (t_submit, t_start, t_done))."""
+    state = ctypes.c_int32()
+    times = np.zeros(3, np.float64)
+    _check(load().rcp_poll(server, int(ticket), ctypes.byref(state), times.ctypes.data), "rcp_poll")
+    return int(state.value), tuple(float(x) for x in times)
+
+
+def rcp_result(server: int, ticket: int):
+    """Device addresses (images, ids) of a finished request."""
+    a = ctypes.c_void_p()
+    b = ctypes.c_void_p()
+    _check(load().rcp_result(server, int(ticket), ctypes.byref(a), ctypes.byref(b)), "rcp_result")
+    return a.value, b.value
+
+
+def rcp_result_copy(server: int, ticket: int, images, ids=None, stream=None) -> None:
+    _check(load().rcp_result_copy(server, int(ticket), _dev_ptr(images), _dev_ptr(ids), _stream(stream)),
+           "rcp_result_copy")
+
+
+def rcp_release(server: int, ticket: int) -> None:
+    _check(load().rcp_release(server, int(ticket)), "rcp_release")
+
+
+def rcp_server_stats(server: int) -> dict:
+    out = np.zeros(4, np.uint64)
+    _check(load().rcp_server_stats(server, out.ctypes.data), "rcp_server_stats")
+    return {"launches": int(out[0]), "waiting": int(out[1]), "pool_in_use": int(out[2]), "live": int(out[3])}
+
+
+def rcp_server_destroy(server: int) -> None:
+    load().rcp_server_destroy(server)
 
 
 # ---------------------------------------------------------------------------

@@ -124,3 +124,14 @@ def test_gather_validation_on_host():
     # the output planes must not overlap the input image
     assert "overlaps" in _bad(rcp.rcp_gather_passes, 1 << 20, 8, 8, 2, 2.0, rcp.RCP_EDGE_WRAP, True,
                               (1 << 20) + 100, stream=0)
+
+
+def test_server_validation_on_host():
+    _bad(rcp.rcp_server_create, 0, 1 << 20)
+    cam = scenegen.workload("soup256").camera
+    with pytest.raises(rcp.RcpError):
+        rcp.rcp_submit(0, cam, 8, 8, 2, rcp.make_displacement(0.0, 0.02))
+    with pytest.raises(rcp.RcpError):
+        rcp.rcp_poll(0, 1)
+    with pytest.raises(rcp.RcpError):
+        rcp.rcp_release(0, 1)

@@ -1,0 +1,153 @@
+"""Continuous-batching server: every request's images equal rcp_render of
+that request alone, whether it was submitted alone, in a burst, or while
+other requests were running; admission respects the pool budget and the
+queue capacity."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from paper_2312_12392_amd import rcp
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    torch.cuda.set_device(0)
+    rcp.load()
+
+
+@pytest.fixture(scope="module")
+def scene():
+    sc = scenegen.terrain_patch(12, 40, 20)
+    s = rcp.Scene(sc)
+    yield s
+    s.close()
+
+
+def requests(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    sizes = [(64, 64), (67, 45), (1, 1), (130, 3), (96, 72), (160, 90), (33, 21)]
+    for i in range(n):
+        ang = rng.uniform(-0.7, 0.7)
+        cam = scenegen.camera_look_at([1.4 * np.sin(ang), rng.uniform(0.3, 0.7), -1.4 * np.cos(ang)],
+                                      [0, 0.05, 0], [0, 1, 0], 60.0)
+        W, H = sizes[i % len(sizes)]
+        K = int(rng.integers(1, 9))
+        out.append((cam, W, H, K, rcp.make_displacement(0.0, float(rng.uniform(0.0, 0.1)))))
+    return out
+
+
+def wait_done(srv, tickets, timeout=60.0):
+    t0 = time.time()
+    pending = set(tickets)
+    while pending:
+        for t in list(pending):
+            st, _ = rcp.rcp_poll(srv, t)
+            assert st != rcp.RCP_REQ_FAILED, t
+            if st == rcp.RCP_REQ_DONE:
+                pending.discard(t)
+        assert time.time() - t0 < timeout, "requests did not finish"
+        time.sleep(0.001)
+
+
+def check_against_alone(scene, srv, reqs, tickets):
+    for (cam, W, H, K, d), t in zip(reqs, tickets):
+        img = torch.empty((K, H, W, 3), device="cuda")
+        ids = torch.empty((K, H, W), dtype=torch.int32, device="cuda")
+        rcp.rcp_result_copy(srv, t, img, ids)
+        ref_img = torch.empty_like(img)
+        ref_ids = torch.empty_like(ids)
+        rcp.rcp_render(scene.handle, cam, W, H, K, d, ref_img, ref_ids)
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref_img) and torch.equal(ids, ref_ids), t
+        rcp.rcp_release(srv, t)
+
+
+def test_burst_equals_alone(scene):
+    say("server burst")
+    srv = rcp.rcp_server_create(scene.handle, 256 << 20, max_inflight=2)
+    reqs = requests(24, 0)
+    tickets = [rcp.rcp_submit(srv, cam, W, H, K, d, with_ids=True) for (cam, W, H, K, d) in reqs]
+    wait_done(srv, tickets)
+    stats = rcp.rcp_server_stats(srv)
+    assert stats["launches"] < len(reqs)              # requests shared launches
+    check_against_alone(scene, srv, reqs, tickets)
+    assert rcp.rcp_server_stats(srv)["pool_in_use"] == 0
+    rcp.rcp_server_destroy(srv)
+
+
+def test_staggered_and_single_equal_alone(scene):
+    say("server staggered")
+    srv = rcp.rcp_server_create(scene.handle, 64 << 20, max_inflight=3)
+    reqs = requests(30, 1)
+    tickets = []
+    for i, (cam, W, H, K, d) in enumerate(reqs):
+        tickets.append(rcp.rcp_submit(srv, cam, W, H, K, d, with_ids=True))
+        if i % 4 == 0:
+            time.sleep(0.002)                         # arrivals while others run
+    wait_done(srv, tickets)
+    check_against_alone(scene, srv, reqs, tickets)
+    # one request alone
+    cam, W, H, K, d = reqs[4]
+    t = rcp.rcp_submit(srv, cam, W, H, K, d, with_ids=True)
+    wait_done(srv, [t])
+    st, (ts, tb, td) = rcp.rcp_poll(srv, t)
+    assert st == rcp.RCP_REQ_DONE and ts <= tb <= td
+    check_against_alone(scene, srv, [reqs[4]], [t])
+    rcp.rcp_server_destroy(srv)
+
+
+def test_budget_and_queue_limits(scene):
+    say("server budget")
+    cam, _, _, _, d = requests(1, 2)[0]
+    one = 12 * 96 * 72 * 4
+    pool = 2 * ((one + 255) // 256 * 256)             # two such requests fit
+    srv = rcp.rcp_server_create(scene.handle, pool, max_inflight=1, queue_capacity=3)
+    with pytest.raises(rcp.RcpError) as e:
+        rcp.rcp_submit(srv, cam, 512, 512, 8, d)      # larger than the whole pool
+    assert e.value.status == rcp.RCP_ERR_INVALID_ARGUMENT
+    tickets = [rcp.rcp_submit(srv, cam, 96, 72, 4, d) for _ in range(2)]
+    wait_done(srv, tickets)
+    # the pool is full of finished, unreleased requests: new ones wait
+    waiting = [rcp.rcp_submit(srv, cam, 96, 72, 4, d) for _ in range(3)]
+    with pytest.raises(rcp.RcpError) as e:
+        rcp.rcp_submit(srv, cam, 96, 72, 4, d)
+    assert e.value.status == rcp.RCP_ERR_QUEUE_FULL
+    time.sleep(0.05)
+    assert all(rcp.rcp_poll(srv, t)[0] == rcp.RCP_REQ_QUEUED for t in waiting)
+    with pytest.raises(rcp.RcpError) as e:
+        rcp.rcp_result(srv, waiting[0])
+    assert e.value.status == rcp.RCP_ERR_NOT_READY
+    with pytest.raises(rcp.RcpError):
+        rcp.rcp_release(srv, waiting[0])              # not finished yet
+    for t in tickets:
+        rcp.rcp_release(srv, t)                       # frees the space: two waiting ones run
+    wait_done(srv, waiting[:2])
+    time.sleep(0.05)
+    assert rcp.rcp_poll(srv, waiting[2])[0] == rcp.RCP_REQ_QUEUED    # the pool is full again
+    for t in waiting[:2]:
+        assert rcp.rcp_result(srv, t)[0] != 0
+        rcp.rcp_release(srv, t)
+    wait_done(srv, waiting[2:])
+    rcp.rcp_release(srv, waiting[2])
+    assert rcp.rcp_server_stats(srv)["live"] == 0
+    rcp.rcp_server_destroy(srv)
+
+
+def test_destroy_with_requests_in_flight(scene):
+    say("server destroy")
+    srv = rcp.rcp_server_create(scene.handle, 128 << 20, max_inflight=2)
+    for (cam, W, H, K, d) in requests(10, 3):
+        rcp.rcp_submit(srv, cam, W, H, K, d)
+    rcp.rcp_server_destroy(srv)                       # running launches finish, nothing leaks or hangs
+    torch.cuda.synchronize()
