@@ -85,7 +85,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="terrain1m")
+    ap.add_argument("--workload", default="terrain1m",
+                    help="terrain1m (default: the K-pass frame), batch64, served, terrain16m, gather4k")
+    ap.add_argument("--duration", type=float, default=6.0, help="served: seconds of arrivals per rate")
+    ap.add_argument("--rates", default="20,50,100,200", help="served: arrival rates, requests per second")
+    ap.add_argument("--frames", type=int, default=120, help="terrain16m: walk-through frames")
     ap.add_argument("--literal-eye", action="store_true", help="displace the eye as well (lambda_eye = lambda)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-leaf", type=int, default=None, help="BVH leaf size bound (build option)")
@@ -98,13 +102,22 @@ def main():
               "the render shards by pixels with no exchange, but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
 
+    import torch
+
+    torch.cuda.set_device(0)
+    if args.workload in EXTRA:
+        print(json.dumps(EXTRA[args.workload](args)), flush=True)
+        return
+    bench_frame(args)
+
+
+def bench_frame(args):
     import numpy as np
     import torch
 
     import scenegen
     from paper_2312_12392_amd import rcp
 
-    torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     w = scenegen.workload(args.workload, literal_eye=args.literal_eye)
     log(f"workload {w.name}: {w.width}x{w.height} K={w.passes} tris={w.scene.n_tris}")
@@ -207,6 +220,248 @@ def main():
         result["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(result), flush=True)
     scene.close()
+
+
+def _percentiles(x):
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    return {"p50": round(float(np.percentile(x, 50)), 3), "p99": round(float(np.percentile(x, 99)), 3),
+            "mean": round(float(x.mean()), 3), "max": round(float(x.max()), 3)}
+
+
+def bench_batch(args):
+    """64 views of the 1M scene (orbit; 256^2, 512^2, 720p, 1024^2; K 1..8):
+    one batched launch vs 64 sequential rcp_render calls vs 64 graph replays."""
+    import torch
+
+    import scenegen
+    from paper_2312_12392_amd import rcp
+
+    stream = torch.cuda.current_stream()
+    w = scenegen.workload("terrain1m")
+    views = scenegen.orbit_views(3, 64)
+    scene = rcp.Scene(w.scene)
+    d = rcp.make_displacement(0.0, w.lambda_dir)
+    outs = [torch.empty((K, H, W, 3), device="cuda") for (_, W, H, K) in views]
+    batch = [(cam, W, H, K, d, o, None) for (cam, W, H, K), o in zip(views, outs)]
+    rays = sum(W * H * K for (_, W, H, K) in views)
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_batch = timed(lambda: rcp.rcp_render_batch(scene.handle, batch, stream), args.steps)
+
+    def seq():
+        for (cam, W, H, K), o in zip(views, outs):
+            rcp.rcp_render(scene.handle, cam, W, H, K, d, o, None, stream)
+    ms_seq = timed(seq, max(1, args.steps // 4))
+    graphs = [rcp.rcp_graph_create(scene.handle, cam, W, H, K, d, o, None, stream)
+              for (cam, W, H, K), o in zip(views, outs)]
+
+    def replay():
+        for g in graphs:
+            rcp.rcp_graph_launch(g, stream)
+    ms_graph = timed(replay, max(1, args.steps // 4))
+    for g in graphs:
+        rcp.rcp_graph_destroy(g)
+    scene.close()
+    return {
+        "metric": "Mrays/s of a 64-view batch (1M-triangle scene, mixed resolution and K) in one launch",
+        "value": round(rays / (ms_batch * 1e-3) / 1e6, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+        "ms_per_step": round(ms_batch, 4), "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch64: 64 orbit views of terrain1m, resolutions 256^2/512^2/720p/1024^2, K 1..8, "
+                               "lambda_dir 0.01", "views": 64, "nominal_rays": rays},
+        "sequential_rcp_render_ms": round(ms_seq, 4),
+        "graph_replays_ms": round(ms_graph, 4),
+        "speedup_vs_sequential": round(ms_seq / ms_batch, 3),
+    }
+
+
+def _retire(rcp, srv, pending, late, lat):
+    still = []
+    for t in pending:
+        st, (ts, tb, td) = rcp.rcp_poll(srv, t)
+        if st == rcp.RCP_REQ_DONE:
+            lat.append((td - ts + late[t]) * 1e3)
+            rcp.rcp_release(srv, t)
+        else:
+            still.append(t)
+    return still
+
+
+def bench_served(args):
+    """Poisson arrivals on the 4M-triangle scene: the continuous-batching
+    server vs a plain first-in-first-out loop of synchronous rcp_render."""
+    import time
+
+    import torch
+
+    import scenegen
+    from paper_2312_12392_amd import rcp
+
+    stream = torch.cuda.current_stream()
+    w = scenegen.workload("terrain4m")
+    scene = rcp.Scene(w.scene)
+    d = rcp.make_displacement(0.0, w.lambda_dir)
+    rates = [float(r) for r in args.rates.split(",")]
+    per_rate = {}
+    total_rays = 0
+    for ri, rate in enumerate(rates):
+        trace = scenegen.served_trace(5 + ri, rate, args.duration)
+        rays = sum(W * H * K for (_, _, W, H, K) in trace)
+        total_rays += rays
+        # warm-up of both paths (kernels loaded, workspaces sized)
+        big = torch.empty((8, 2160, 3840, 3), device="cuda")
+        rcp.rcp_render(scene.handle, trace[0][1], 3840, 2160, 8, d, big, None, stream)
+        torch.cuda.synchronize()
+        # --- server ---
+        srv = rcp.rcp_server_create(scene.handle, 48 << 30, max_inflight=2)
+        tickets = []
+        t0 = time.perf_counter()
+        pending = []
+        lat = []
+        late = {}
+        for (arr, cam, W, H, K) in trace:
+            while time.perf_counter() - t0 < arr:
+                time.sleep(0.0002)
+            t = rcp.rcp_submit(srv, cam, W, H, K, d)
+            late[t] = time.perf_counter() - t0 - arr        # submitted this long after its arrival time
+            tickets.append(t)
+            pending.append(t)
+            if len(pending) > 16:                           # retire finished requests as we go
+                pending = _retire(rcp, srv, pending, late, lat)
+        while pending:
+            pending = _retire(rcp, srv, pending, late, lat)
+            time.sleep(0.0005)
+        t_srv = time.perf_counter() - t0
+        launches = rcp.rcp_server_stats(srv)["launches"]
+        rcp.rcp_server_destroy(srv)
+        # --- plain loop: one request at a time, in arrival order ---
+        lat_loop = []
+        t0 = time.perf_counter()
+        for (arr, cam, W, H, K) in trace:
+            now = time.perf_counter() - t0
+            if now < arr:
+                time.sleep(arr - now)
+            out = big[:K].view(-1)[:K * H * W * 3].view(K, H, W, 3)
+            rcp.rcp_render(scene.handle, cam, W, H, K, d, out, None, stream)
+            stream.synchronize()
+            lat_loop.append((time.perf_counter() - t0 - arr) * 1e3)
+        t_loop = time.perf_counter() - t0
+        del big
+        per_rate[str(int(rate))] = {
+            "requests": len(trace), "nominal_rays": rays, "launches": launches,
+            "server_latency_ms": _percentiles(lat), "loop_latency_ms": _percentiles(lat_loop),
+            "server_mrays_per_s": round(rays / t_srv / 1e6, 1), "loop_mrays_per_s": round(rays / t_loop / 1e6, 1),
+        }
+        log(f"rate {rate}: {per_rate[str(int(rate))]}")
+    scene.close()
+    top = per_rate[str(int(rates[-1]))]
+    return {
+        "metric": "served p50/p99 latency (ms) and Mrays/s vs a plain per-request loop, 4M-triangle scene",
+        "value": top["server_latency_ms"]["p99"], "unit": "ms (p99 latency at the highest rate)",
+        "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"served: terrain4m ({w.scene.n_tris} triangles), Poisson arrivals at {args.rates} "
+                               f"req/s for {args.duration} s each, 512^2/720p/1080p/4K, K 3..8, spline cameras",
+                   "rates": rates, "duration_s": args.duration},
+        "per_rate": per_rate,
+    }
+
+
+def bench_walk(args):
+    """The 16M-triangle scene: a walk-through of 4K, K=8 frames, each frame
+    restarting from the grey seed with a new camera."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2312_12392_amd import rcp
+
+    stream = torch.cuda.current_stream()
+    w = scenegen.workload("terrain16m")
+    log(f"terrain16m: {w.scene.n_tris} triangles")
+    scene = rcp.Scene(w.scene)
+    info = scene.info()
+    W, H, K = w.width, w.height, w.passes
+    imgs = torch.empty((K, H, W, 3), device="cuda")
+    d = rcp.make_displacement(0.0, w.lambda_dir)
+    pts = scenegen.spline_path(7)
+    cams = [scenegen.walk_camera(pts, i / args.frames) for i in range(args.frames)]
+    rcp.rcp_render(scene.handle, cams[0], W, H, K, d, imgs, None, stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.frames + 1)]
+    ev[0].record(stream)
+    for i, cam in enumerate(cams):
+        rcp.rcp_render(scene.handle, cam, W, H, K, d, imgs, None, stream)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.frames)])
+    rays = W * H * K * args.frames
+    scene.close()
+    return {
+        "metric": "Mrays/s of a 4K K=8 walk-through of the 16M-triangle scene; frame ms p50/p99",
+        "value": round(rays / (ms.sum() * 1e-3) / 1e6, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.frames,
+        "ms_per_step": round(float(ms.mean()), 4), "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"terrain16m: {W}x{H}, K={K}, {w.scene.n_tris} triangles, {args.frames}-frame spline "
+                               "walk-through, lambda_dir 0.01", "frames": args.frames},
+        "frame_ms": _percentiles(ms), "bvh_build_ms": round(info["build_ms"], 2),
+        "bvh": {"nodes": info["n_nodes"], "sah_cost": round(info["sah_cost"], 3), "max_depth": info["max_depth"]},
+    }
+
+
+def bench_gather(args):
+    """Screen-space variant: K-1 = 5 gather passes over a rendered 4K image."""
+    import torch
+
+    import scenegen
+    from paper_2312_12392_amd import rcp
+
+    stream = torch.cuda.current_stream()
+    w = scenegen.workload("terrain1m")
+    scene = rcp.Scene(w.scene)
+    W, H, n = 3840, 2160, 5
+    base = torch.empty((1, H, W, 3), device="cuda")
+    rcp.rcp_render(scene.handle, w.camera, W, H, 1, rcp.make_displacement(0.0, 0.0), base, None, stream)
+    out = torch.empty((n, H, W, 3), device="cuda")
+    for _ in range(3):
+        rcp.rcp_gather_passes(base, W, H, n, 6.0, rcp.RCP_EDGE_MIRROR, True, out, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        rcp.rcp_gather_passes(base, W, H, n, 6.0, rcp.RCP_EDGE_MIRROR, True, out, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    bytes_pass = 32.0 * W * H          # own R, G (8 B) + source RGB (12 B) + written RGB (12 B)
+    gbs = bytes_pass * n / (ms * 1e-3) / 1e9
+    scene.close()
+    return {
+        "metric": "screen-space variant: pixels/s of 5 gather passes over a 4K image (mirror edges)",
+        "value": round(W * H * n / (ms * 1e-3) / 1e9, 3), "unit": "Gpixel-passes/s", "n_gpus": 1,
+        "steps": args.steps, "ms_per_step": round(ms, 4), "higher_is_better": True, "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "gather4k: 3840x2160 render of terrain1m, 5 passes, max_smudge 6 px, mirror edges"},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_gather",
+                     "algorithmic_bytes_per_launch": round(bytes_pass)},
+    }
+
+
+EXTRA = {"batch64": bench_batch, "served": bench_served, "terrain16m": bench_walk, "gather4k": bench_gather}
 
 
 if __name__ == "__main__":

@@ -453,3 +453,64 @@ def orbit_views(seed: int = 3, n: int = 64, resolutions=None, k_range=(1, 8), ta
         W, H = res[int(ri[i])]
         out.append((cam, int(W), int(H), int(ks[i])))
     return out
+
+
+def _catmull_rom(P, u):
+    """Point at parameter u in [0, len(P) - 3] of the centripetal-free
+    (uniform) Catmull-Rom spline through control points P."""
+    i = int(min(max(math.floor(u), 0), len(P) - 4))
+    t = u - i
+    p0, p1, p2, p3 = (np.asarray(P[i + k], dtype=np.float64) for k in range(4))
+    return 0.5 * ((2 * p1) + (-p0 + p2) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t * t +
+                  (-p0 + 3 * p1 - 3 * p2 + p3) * t * t * t)
+
+
+def spline_path(seed: int, n_points: int = 16, height=(0.35, 0.65), extent: float = 0.8):
+    """Control points of a walk-through: (x, z) uniform in [-extent, extent]^2,
+    y in ``height`` (0.2-0.5 above the terrain's 0.15 maximum).  Draw order:
+    x, z, y (n_points each)."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-extent, extent, size=n_points)
+    z = rng.uniform(-extent, extent, size=n_points)
+    y = rng.uniform(height[0], height[1], size=n_points)
+    return [np.array([x[i], y[i], z[i]]) for i in range(n_points)]
+
+
+def walk_camera(points, s: float, vfov_deg: float = 60.0) -> Camera:
+    """Camera at fraction s in [0, 1) of the path, looking ahead and down
+    (0.15 below the point half a segment further along)."""
+    umax = len(points) - 3.0
+    u = s * (umax - 0.5)
+    p = _catmull_rom(points, u)
+    q = _catmull_rom(points, u + 0.5)
+    target = q + np.array([0.0, -0.15, 0.0])
+    return camera_look_at(p, target, [0, 1, 0], vfov_deg)
+
+
+SERVED_RESOLUTIONS = [(512, 512), (1280, 720), (1920, 1080), (3840, 2160)]
+
+
+def served_trace(seed: int, rate: float, duration: float, path_seed: int | None = None):
+    """Render requests for a served run: Poisson arrivals at ``rate`` per
+    second over ``duration`` seconds, resolution uniform over 512^2, 720p,
+    1080p, 4K, K uniform in 3..8, cameras along a walk-through spline in
+    arrival order.  Draw order: inter-arrival gaps (drawn until the duration
+    is covered), then resolution index and K per request.
+    Returns a list of (arrival_s, Camera, W, H, K)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    arrivals = []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        arrivals.append(t)
+    n = len(arrivals)
+    ri = rng.integers(0, len(SERVED_RESOLUTIONS), size=n)
+    ks = rng.integers(3, 9, size=n)
+    pts = spline_path(seed + 1 if path_seed is None else path_seed)
+    out = []
+    for i, a in enumerate(arrivals):
+        W, H = SERVED_RESOLUTIONS[int(ri[i])]
+        out.append((a, walk_camera(pts, i / max(n, 1)), W, H, int(ks[i])))
+    return out
