@@ -2,8 +2,10 @@
 
 One step = one frame: the whole hot path (per-pixel displaced ray
 generation, BVH traversal with watertight intersection, shading, the
-inter-pass compaction, chained over K passes on one stream) for the
-1920x1080, K=6 render of the 1,000,418-triangle synthetic terrain scene.
+convergence test, over all K passes on one stream) for the 1920x1080, K=6
+render of the 1,000,418-triangle synthetic terrain scene.  The default
+chain engine runs the frame as one persistent launch (k_chain); --engine
+passes runs one launch per pass with compaction in HBM (k_pass).
 The scene and BVH are built once (build time reported separately) and stay
 resident; outputs are preallocated; inputs are in HBM before timing starts.
 
@@ -22,9 +24,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_terrain1m_traffic.json")
+KERNEL_OF_ENGINE = {"chain": "k_chain", "passes": "k_pass"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2312_12392_amd", "csrc", f)
-                  for f in ("trace.hip", "traverse.hpp", "rcp_internal.hpp", "bvh_build.hip")]
+                  for f in ("chain.hip", "trace.hip", "traverse.hpp", "rcp_internal.hpp", "bvh_build.hip")]
+
+
+def traffic_file(kernel: str, workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
 
 
 def log(*a):
@@ -39,26 +45,28 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def algorithmic_bytes(counts, top_nodes_visits=None):
+def algorithmic_bytes(counts, engine="chain"):
     """Logical global-memory bytes of one frame from the traversal counters.
 
     Per pass k (counts[k] = rays traced, inner nodes visited, triangles
-    tested, rays appended):
+    tested, rays continued to pass k + 1), both engines:
       64 B per inner node visited (both child boxes + links)
       48 B per triangle tested (three vertices + index)
       16 B per traced ray: the shaded colour looked up (hit or miss constant)
       12 B + 4 B per traced ray: image k and its hit ID written
-      16 B per traced ray at k > 0: its {pixel, previous RGB} entry read
-      16 B per appended ray: its entry written for pass k + 1
       16 B per remaining image for every pixel that converged at pass k
+    and with one launch per pass ("passes"), the pass state in HBM:
+      16 B per traced ray at k > 0: its {pixel, previous RGB} entry read
+      16 B per continued ray: its entry written for pass k + 1
+    The chain engine keeps that state in registers.
     """
     K = len(counts)
     total = 0.0
     for k in range(K):
         rays, nodes, tris, app = (float(x) for x in counts[k])
-        total += 64 * nodes + 48 * tris + (16 + 12 + 4) * rays + 16 * app
-        if k > 0:
-            total += 16 * rays
+        total += 64 * nodes + 48 * tris + (16 + 12 + 4) * rays
+        if engine == "passes":
+            total += 16 * app + (16 * rays if k > 0 else 0.0)
         converged = rays - app if k + 1 < K else 0.0
         total += 16 * converged * (K - 1 - k)
     return total
@@ -91,6 +99,8 @@ def main():
     ap.add_argument("--rates", default="20,50,100,200", help="served: arrival rates, requests per second")
     ap.add_argument("--frames", type=int, default=120, help="terrain16m: walk-through frames")
     ap.add_argument("--literal-eye", action="store_true", help="displace the eye as well (lambda_eye = lambda)")
+    ap.add_argument("--engine", choices=["chain", "passes"], default="chain",
+                    help="chain: one persistent launch per frame; passes: one launch per pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-leaf", type=int, default=None, help="BVH leaf size bound (build option)")
     ap.add_argument("--top-levels", type=int, default=None, help="BVH levels staged in LDS (build option)")
@@ -126,8 +136,10 @@ def bench_frame(args):
         opts = rcp.build_options(max_leaf=args.max_leaf or 4,
                                  top_levels=6 if args.top_levels is None else args.top_levels)
     scene = rcp.Scene(w.scene, opts)
+    scene.set_engine(rcp.RCP_ENGINE_CHAIN if args.engine == "chain" else rcp.RCP_ENGINE_PASSES)
+    kernel = KERNEL_OF_ENGINE[args.engine]
     info = scene.info()
-    log(f"scene built: {info}")
+    log(f"scene built: {info}; engine {args.engine}")
     K, W, H = w.passes, w.width, w.height
     imgs = torch.empty((K, H, W, 3), dtype=torch.float32, device="cuda")
     ids = torch.empty((K, H, W), dtype=torch.int32, device="cuda")
@@ -146,8 +158,9 @@ def bench_frame(args):
     same = bool(torch.equal(imgs_s, imgs))
     del imgs_s
     traced = int(counts[:, 0].sum())
-    bytes_frame = algorithmic_bytes(counts)
-    log(f"counts per pass [rays, nodes, tris, appended]: {counts.tolist()} (stats image identical: {same})")
+    bytes_frame = algorithmic_bytes(counts, args.engine)
+    launches = 1 if args.engine == "chain" else K
+    log(f"counts per pass [rays, nodes, tris, continued]: {counts.tolist()} (stats image identical: {same})")
 
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")     # 1 GiB
@@ -169,13 +182,14 @@ def bench_frame(args):
     ms = ms_total / args.steps
     nominal = W * H * K
     value = nominal * args.steps / (ms_total * 1e-3) / 1e6
-    # the frame is K launches of the pass kernel plus one counter-clearing
-    # launch of a few microseconds; the average pass duration is ms / K
+    # the frame is one k_chain launch (or K k_pass launches) plus one setup
+    # launch of a few microseconds; the average launch lasts ms / launches
+    # and carries bytes_frame / launches, so the rate is the frame's
     achieved_gbs = bytes_frame / (ms * 1e-3) / 1e9
 
     traffic = None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(kernel, w.name)) as f:
             tr = json.load(f)
         if tr.get("kernel_source_sha256") == kernel_source_hash() and tr.get("workload") == w.name:
             traffic = tr["hbm_bytes_per_launch"]
@@ -210,8 +224,9 @@ def bench_frame(args):
             "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_pass",
-            "algorithmic_bytes_per_launch": round(bytes_frame / K),
+            "kernel": kernel,
+            "launches_per_step": launches,
+            "algorithmic_bytes_per_launch": round(bytes_frame / launches),
             "bytes_per_traced_ray": round(bytes_frame / traced, 1),
         },
     }

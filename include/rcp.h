@@ -207,8 +207,8 @@ rcp_status rcp_render_stats(rcp_scene* scene, const rcp_camera* base_camera, int
 /* ---------------------------------------------------------------------- */
 
 /* One view of a batch: its own base camera, image size, pass count and
- * colour displacement (disp.mode must be RCP_MODE_COLOR), and its own
- * output buffers (device [K][H][W][3] float32; ids [K][H][W] or NULL). */
+ * displacement (any mode), and its own output buffers (device [K][H][W][3]
+ * float32; ids [K][H][W] or NULL). */
 typedef struct {
     rcp_camera camera;
     int32_t W, H, K;
@@ -221,8 +221,11 @@ typedef struct {
  * K passes form an independent chain (Section 2: pass n at (u,v) needs only
  * pass n-1 at (u,v)), so a lane carries a pixel through all of its view's
  * passes and no pass barrier is needed; every view's images equal those of
- * rcp_render for that view alone.  1 <= n_views <= 1024, each view valid as
- * for rcp_render, outputs must not overlap.  Asynchronous on hip_stream. */
+ * rcp_render for that view alone.  Views are grouped by displacement mode,
+ * one launch per mode present.  1 <= n_views <= 1024, each view valid as for
+ * rcp_render, outputs must not overlap, and each mode's views together hold
+ * fewer than 2^32 - 2^24 pixels (64-pixel tiles, rounded up per view).
+ * Asynchronous on hip_stream. */
 rcp_status rcp_render_batch(rcp_scene* scene, const rcp_view* views, int n_views, void* hip_stream);
 
 /* A K-pass rcp_render call captured once as a HIP graph and replayed with a
@@ -243,12 +246,25 @@ void rcp_graph_destroy(rcp_graph* graph);
  *   refill_min     idle lanes (1..64) that make a wave fetch new pixels
  *   staged_nodes   top BVH nodes copied to LDS (0..top_count of the scene)
  *   blocks_per_cu  resident workgroups per compute unit (0 = occupancy limit)
- *   tile_log2w     pass-0 pixel tile of 64: width 2^tile_log2w (0..6) */
+ *   tile_log2w     pixel tile of 64: width 2^tile_log2w (0..6)
+ *   engine         how rcp_render (and rcp_render_stats, graphs, the
+ *                  autotuner) run the K passes:
+ *                  RCP_ENGINE_CHAIN  one persistent launch; each lane carries
+ *                                    a pixel through all its passes (Section
+ *                                    2: pass n at (u,v) needs only pass n-1
+ *                                    at (u,v)); no per-pass state in HBM
+ *                  RCP_ENGINE_PASSES one launch per pass; the pixels whose
+ *                                    colour changed are compacted into a list
+ *                                    in HBM for the next pass
+ *                  rcp_render_pass always runs one pass launch. */
+#define RCP_ENGINE_CHAIN 0
+#define RCP_ENGINE_PASSES 1
 typedef struct {
     int32_t refill_min;
     int32_t staged_nodes;
     int32_t blocks_per_cu;
     int32_t tile_log2w;
+    int32_t engine;
 } rcp_tuning;
 
 rcp_status rcp_get_tuning(const rcp_scene* scene, rcp_tuning* out);
@@ -266,9 +282,8 @@ rcp_status rcp_autotune(rcp_scene* scene, const rcp_camera* base_camera, int W, 
 /* Continuous-batching server                                              */
 /* ---------------------------------------------------------------------- */
 
-/* A render request: base camera, image size, pass count, colour
- * displacement (disp.mode must be RCP_MODE_COLOR); with_ids != 0 also keeps
- * the hit-ID planes. */
+/* A render request: base camera, image size, pass count, displacement (any
+ * mode); with_ids != 0 also keeps the hit-ID planes. */
 typedef struct {
     rcp_camera camera;
     int32_t W, H, K;

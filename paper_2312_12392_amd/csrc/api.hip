@@ -163,6 +163,7 @@ void rcp_destroy_scene(rcp_scene* s) {
     if (w.counters) (void)hipFree(w.counters);
     if (w.spill) (void)hipFree(w.spill);
     if (w.stats) (void)hipFree(w.stats);
+    if (w.view) (void)hipFree(w.view);
     free_batch_workspace(s->bws);
     delete s;
 }
@@ -240,7 +241,6 @@ rcp_status rcp_render_batch(rcp_scene* scene, const rcp_view* views, int n_views
         Camera c;
         if ((st = check_camera(&v.camera, c))) { set_error("view %d: %s", i, rcp_last_error()); return st; }
         if ((st = check_disp(&v.disp))) { set_error("view %d: %s", i, rcp_last_error()); return st; }
-        if (v.disp.mode != RCP_MODE_COLOR) FAIL("view %d: batches use the colour mapping only", i);
         if ((st = check_size(v.W, v.H))) { set_error("view %d: %s", i, rcp_last_error()); return st; }
         if (v.K < 1 || v.K > kMaxPasses) FAIL("view %d: K = %d must be in [1, %d]", i, v.K, kMaxPasses);
         if (!v.out_images) FAIL("view %d: out_images must not be NULL", i);
@@ -320,6 +320,7 @@ rcp_status rcp_get_tuning(const rcp_scene* s, rcp_tuning* out) {
     out->staged_nodes = (int32_t)l.staged_nodes;
     out->blocks_per_cu = l.blocks_per_cu;
     out->tile_log2w = l.tile_log2w;
+    out->engine = s->tuning.engine;
     return RCP_OK;
 }
 
@@ -331,10 +332,12 @@ rcp_status rcp_set_tuning(rcp_scene* s, const rcp_tuning* t) {
         FAIL("staged_nodes must be in [0, %u]", s->dev.top_count);
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) FAIL("blocks_per_cu must be in [0, 64]");
     if (t->tile_log2w < 0 || t->tile_log2w > 6) FAIL("tile_log2w must be in [0, 6]");
+    if (t->engine != RCP_ENGINE_CHAIN && t->engine != RCP_ENGINE_PASSES) FAIL("unknown engine %d", t->engine);
     s->tuning.refill_min = t->refill_min;
     s->tuning.staged_nodes = t->staged_nodes;
     s->tuning.blocks_per_cu = t->blocks_per_cu;
     s->tuning.tile_log2w = t->tile_log2w;
+    s->tuning.engine = t->engine;
     return RCP_OK;
 }
 
@@ -389,7 +392,6 @@ rcp_status rcp_submit(rcp_server* server, const rcp_request* r, uint64_t* ticket
     rcp_status st;
     if ((st = check_camera(&r->camera, c))) return st;
     if ((st = check_disp(&r->disp))) return st;
-    if (r->disp.mode != RCP_MODE_COLOR) FAIL("served requests use the colour mapping only");
     if ((st = check_size(r->W, r->H))) return st;
     if (r->K < 1 || r->K > kMaxPasses) FAIL("K = %d must be in [1, %d]", r->K, kMaxPasses);
     try {

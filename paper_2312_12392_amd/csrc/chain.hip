@@ -1,0 +1,458 @@
+// Chain engine: every pass of a render in a single persistent launch.
+//
+// The recursion I_n(u,v) = F(I_{n-1}(u,v), S) is pointwise (Section 2), so a
+// pixel's K passes form a chain that needs nothing from other pixels.  A work
+// item is one pixel of one view (64-pixel tiles per view, views back to
+// back); a lane carries its pixel through the view's passes -- trace, shade,
+// write image k, and, if the inputs of the next ray changed, displace the
+// camera and trace again -- and takes a new pixel as soon as the chain ends
+// (after K passes, or when the colour, and in the depth and normal modes the
+// hit data, stopped changing: the next ray would be identical, so the result
+// is written to the remaining images at once).  No pass barrier and no
+// per-pass state in HBM are needed, and views of any size, pass count and
+// mode share one launch and its tail.
+//
+// The same kernel serves rcp_render and rcp_render_batch.  Views are read
+// from a device table by each lane; a single render's one-entry table is
+// written by a setup kernel from its by-value argument, so a captured graph
+// holds the view and rcp_graph_update can change it.  (A view passed as a
+// kernel argument lets the compiler hoist its uniform float math into vector
+// registers for the whole loop, costing occupancy.)
+#include <algorithm>
+
+#include "traverse.hpp"
+
+namespace rcp {
+namespace {
+
+struct ViewDev {
+    Camera cam;
+    int W, H, K, tiles_x, tile_log2w;
+    float le, ld, z0;
+    float* out;            // [K][H][W][3]
+    int32_t* ids;          // [K][H][W] or NULL
+};
+
+static_assert(sizeof(ViewDev) + 2 * sizeof(uint32_t) + 64 <= kViewBytes, "one-entry view table");
+
+struct ChainArgs {
+    DevScene sc;
+    const ViewDev* views;     // [n_views]
+    const uint32_t* begin;    // [n_views + 1] first work item of each view
+    int n_views;
+    uint32_t n_items;         // work items of the launch
+    uint32_t* fetch;          // work counter, zero at launch
+    int refill_min;
+    int32_t* spill;
+    uint32_t spill_stride;
+    unsigned long long* stats;   // [K][4] (STATS): rays, inner nodes, triangles, rays continued
+};
+
+__device__ inline void tile_pixel(const ViewDev& vw, uint32_t local, int& x, int& y) {
+    const uint32_t tile = local >> 6, l = local & 63u;
+    const uint32_t tw = 1u << vw.tile_log2w;
+    x = (int)((tile % (uint32_t)vw.tiles_x) * tw + (l & (tw - 1u)));
+    y = (int)((tile / (uint32_t)vw.tiles_x) * (64u >> vw.tile_log2w) + (l >> vw.tile_log2w));
+}
+
+template <bool STATS, int MODE>
+__global__ __launch_bounds__(kBlock) void k_chain(ChainArgs a) {
+    constexpr bool AUX = MODE != RCP_MODE_COLOR;
+    extern __shared__ float4 smem[];
+    float4* top = smem;                                                   // top_count * 4
+    char* lds = (char*)(smem + 4 * a.sc.top_count);
+    unsigned long long* lstats = (unsigned long long*)lds;                // STATS: 4 * kMaxPasses
+    if (STATS) lds += sizeof(unsigned long long) * 4 * kMaxPasses;
+    uint32_t* vbegin = (uint32_t*)lds;                                    // n_views + 1
+    lds += sizeof(uint32_t) * (size_t)((a.n_views + 4) & ~3);
+    int32_t* stack_area = (int32_t*)lds;                                  // kStack * kBlock
+
+    for (uint32_t i = threadIdx.x; i < 4 * a.sc.top_count; i += kBlock) top[i] = a.sc.nodes[i];
+    for (int i = threadIdx.x; i <= a.n_views; i += kBlock) vbegin[i] = a.begin[i];
+    if (STATS)
+        for (int i = threadIdx.x; i < 4 * kMaxPasses; i += kBlock) lstats[i] = 0ull;
+    __syncthreads();
+
+    int v = 0;                 // the lane's view
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
+    Stack st;
+    st.lds = stack_area + threadIdx.x;
+    st.spill = a.spill + gtid;
+    st.stride = a.spill_stride;
+    const uint32_t n_items = a.n_items;
+
+    bool alive = false;
+    bool drained = false;      // wave-uniform
+    int k = 0, x = 0, y = 0;
+    float pr = 0.5f, pg = 0.5f, pb = 0.5f;              // previous colour (the seed I_0 at pass 0)
+    float pa[4] = {INFINITY, 0.0f, 0.0f, 0.0f};         // previous hit data: view depth, unit normal
+    uint32_t dn = 0, dt = 0;                            // STATS: nodes and triangles of the current ray
+    Trav tv;
+    tv.node = -1;
+
+    for (;;) {
+        // ---- refill idle lanes with new pixels ---------------------------------
+        const unsigned long long idle = __ballot(!alive);
+        const uint32_t n_idle = (uint32_t)__popcll(idle);
+        if (!drained && n_idle >= (uint32_t)a.refill_min) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(a.fetch, n_idle);
+            base = __shfl(base, 0);
+            if (base + n_idle >= n_items) drained = true;
+            if (!alive) {
+                const uint32_t item = base + lanes_below(idle);
+                if (item < n_items) {
+                    // the view holding this item: last begin <= item
+                    int lo = 0, hi = a.n_views;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (vbegin[mid] <= item) lo = mid; else hi = mid;
+                    }
+                    v = lo;
+                    const uint32_t local = item - vbegin[v];
+                    {
+                        const ViewDev& vw = a.views[v];
+                        tile_pixel(vw, local, x, y);
+                        if (x < vw.W && y < vw.H) {
+                            k = 0;
+                            pr = 0.5f; pg = 0.5f; pb = 0.5f;
+                            pa[0] = INFINITY; pa[1] = 0.0f; pa[2] = 0.0f; pa[3] = 0.0f;
+                            float o[3], d[3];
+                            make_ray<MODE>(vw.cam, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, o, d);
+                            trav_init(tv, a.sc, o, d, st);
+                            if (STATS) { dn = 0; dt = 0; }
+                            alive = true;
+                        }
+                    }
+                }
+            }
+        }
+        if (__ballot(alive) == 0ull) {
+            if (drained) break;
+            continue;
+        }
+
+        // ---- one traversal step -------------------------------------------------
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, top, st, dn, dt);
+
+        // ---- a finished pass: shade, write, then the next pass or the end -------
+        if (alive && tv.node == -1) {
+            {
+                const ViewDev& vw = a.views[v];
+                float rgb[3];
+                float na[4] = {INFINITY, 0.0f, 0.0f, 0.0f};
+                int32_t hid = -1;
+                if (tv.h.id != INT_MAX) {
+                    const float4 c = a.sc.shade[2 * (size_t)tv.h.slot + (tv.h.front ? 0 : 1)];
+                    rgb[0] = c.x; rgb[1] = c.y; rgb[2] = c.z;
+                    hid = tv.h.id;
+                    if (AUX) {
+                        // view depth of P = o + t d along the camera's forward axis; the
+                        // ray is rebuilt (bit-identical) rather than kept in registers
+                        float ro[3], rd[3];
+                        make_ray<MODE>(vw.cam, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, ro, rd);
+                        float P3[3];
+#pragma unroll
+                        for (int c3 = 0; c3 < 3; ++c3) P3[c3] = ro[c3] + tv.h.t * rd[c3];
+                        na[0] = ((P3[0] - vw.cam.eye[0]) * vw.cam.forward[0] +
+                                 (P3[1] - vw.cam.eye[1]) * vw.cam.forward[1]) +
+                                (P3[2] - vw.cam.eye[2]) * vw.cam.forward[2];
+                        const float4 nv = a.sc.normals[tv.h.slot];
+                        na[1] = nv.x; na[2] = nv.y; na[3] = nv.z;
+                    }
+                } else {
+                    rgb[0] = a.sc.bg[0]; rgb[1] = a.sc.bg[1]; rgb[2] = a.sc.bg[2];
+                }
+                const size_t P = (size_t)vw.W * (size_t)vw.H;
+                const size_t pix = (size_t)y * (size_t)vw.W + (size_t)x;
+                // the next ray is a function of the colour (and, in the depth and
+                // normal modes, of the hit data): unchanged inputs, unchanged result
+                bool changed = __float_as_uint(rgb[0]) != __float_as_uint(pr) ||
+                               __float_as_uint(rgb[1]) != __float_as_uint(pg) ||
+                               __float_as_uint(rgb[2]) != __float_as_uint(pb);
+                if (AUX)
+                    changed = changed || __float_as_uint(na[0]) != __float_as_uint(pa[0]) ||
+                              __float_as_uint(na[1]) != __float_as_uint(pa[1]) ||
+                              __float_as_uint(na[2]) != __float_as_uint(pa[2]) ||
+                              __float_as_uint(na[3]) != __float_as_uint(pa[3]);
+                // image k, and every later image when nothing changed
+                const int k_end = changed ? k + 1 : vw.K;
+                for (int kk = k; kk < k_end; ++kk) {
+                    float* q = vw.out + ((size_t)kk * P + pix) * 3;
+                    q[0] = rgb[0]; q[1] = rgb[1]; q[2] = rgb[2];
+                    if (vw.ids) vw.ids[(size_t)kk * P + pix] = hid;
+                }
+                const bool next = changed && k + 1 < vw.K;
+                if (STATS) {
+                    unsigned long long* sk = lstats + 4 * k;
+                    atomicAdd(&sk[0], 1ull);
+                    atomicAdd(&sk[1], (unsigned long long)dn);
+                    atomicAdd(&sk[2], (unsigned long long)dt);
+                    if (next) atomicAdd(&sk[3], 1ull);
+                    dn = 0; dt = 0;
+                }
+                if (next) {
+                    ++k;
+                    pr = rgb[0]; pg = rgb[1]; pb = rgb[2];
+                    if (AUX) { pa[0] = na[0]; pa[1] = na[1]; pa[2] = na[2]; pa[3] = na[3]; }
+                    float o[3], d[3];
+                    make_ray<MODE>(vw.cam, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, o, d);
+                    trav_init(tv, a.sc, o, d, st);
+                } else {
+                    alive = false;
+                }
+            }
+        }
+    }
+
+    if (STATS) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 4 * kMaxPasses; i += kBlock)
+            if (lstats[i]) atomicAdd(&a.stats[i], lstats[i]);
+    }
+}
+
+// Zero the work counters (one per launch, 16 words apart) and the stats.
+__global__ void k_clear_chain(uint32_t* fetch, int n, unsigned long long* stats) {
+    for (int i = threadIdx.x; i < 16 * n; i += blockDim.x) fetch[i] = 0u;
+    if (stats)
+        for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
+}
+
+// A single render's setup: its one-entry view table, item range, counter
+// and stats.
+__global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint32_t n_items, uint32_t* fetch,
+                               unsigned long long* stats) {
+    if (threadIdx.x == 0) {
+        *table = v;
+        begin[0] = 0u;
+        begin[1] = n_items;
+        *fetch = 0u;
+    }
+    if (stats)
+        for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
+}
+
+size_t chain_smem(const Launch& lp, bool stats, int n_views) {
+    size_t b = sizeof(float4) * 4 * (size_t)lp.staged_nodes + sizeof(int32_t) * kStack * kBlock +
+               sizeof(uint32_t) * (size_t)((n_views + 4) & ~3);
+    if (stats) b += sizeof(unsigned long long) * 4 * kMaxPasses;
+    return b;
+}
+
+template <bool STATS, int MODE>
+rcp_status chain_grid(const Launch& lp, int n_views, int& blocks, size_t& smem) {
+    smem = chain_smem(lp, STATS, n_views);
+    int per_cu = 0, dev = 0, cus = 0;
+    RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chain<STATS, MODE>, kBlock, smem));
+    RCP_HIP(hipGetDevice(&dev));
+    RCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (per_cu < 1) per_cu = 1;
+    if (lp.blocks_per_cu > 0 && lp.blocks_per_cu < per_cu) per_cu = lp.blocks_per_cu;
+    blocks = per_cu * cus;
+    return RCP_OK;
+}
+
+template <bool STATS>
+rcp_status chain_grid_mode(const Launch& lp, int n_views, int mode, int& blocks, size_t& smem) {
+    switch (mode) {
+        case RCP_MODE_DEPTH: return chain_grid<STATS, RCP_MODE_DEPTH>(lp, n_views, blocks, smem);
+        case RCP_MODE_NORMAL: return chain_grid<STATS, RCP_MODE_NORMAL>(lp, n_views, blocks, smem);
+        default: return chain_grid<STATS, RCP_MODE_COLOR>(lp, n_views, blocks, smem);
+    }
+}
+
+template <bool STATS>
+void launch_chain_mode(int mode, int blocks, size_t smem, hipStream_t stream, const ChainArgs& a) {
+    switch (mode) {
+        case RCP_MODE_DEPTH:
+            hipLaunchKernelGGL((k_chain<STATS, RCP_MODE_DEPTH>), dim3(blocks), dim3(kBlock), smem, stream, a);
+            break;
+        case RCP_MODE_NORMAL:
+            hipLaunchKernelGGL((k_chain<STATS, RCP_MODE_NORMAL>), dim3(blocks), dim3(kBlock), smem, stream, a);
+            break;
+        default:
+            hipLaunchKernelGGL((k_chain<STATS, RCP_MODE_COLOR>), dim3(blocks), dim3(kBlock), smem, stream, a);
+            break;
+    }
+}
+
+size_t spill_depth_of(const rcp_scene* s) {
+    return s->dev.max_depth > (uint32_t)kStack ? s->dev.max_depth - kStack + 1 : 1;
+}
+
+ViewDev view_of(const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids, int tile_log2w) {
+    ViewDev v{};
+    v.cam = cam;
+    v.W = W; v.H = H; v.K = K;
+    v.tile_log2w = tile_log2w;
+    v.tiles_x = (W + (1 << tile_log2w) - 1) >> tile_log2w;
+    v.le = d.le; v.ld = d.ld; v.z0 = d.z0;
+    v.out = out;
+    v.ids = ids;
+    return v;
+}
+
+uint64_t view_items(const ViewDev& v) {
+    const int th = 64 >> v.tile_log2w;
+    return (uint64_t)v.tiles_x * (uint64_t)((v.H + th - 1) / th) * 64u;
+}
+
+}  // namespace
+
+rcp_status prepare_chain(rcp_scene* s, int mode) {
+    const Launch lp = launch_params(s);
+    int b1 = 0, b2 = 0;
+    size_t m1 = 0, m2 = 0;
+    rcp_status st = chain_grid_mode<false>(lp, 1, mode, b1, m1);
+    if (st == RCP_OK) st = chain_grid_mode<true>(lp, 1, mode, b2, m2);
+    if (st != RCP_OK) return st;
+    const uint32_t threads = (uint32_t)std::max(b1, b2) * kBlock;
+    return ensure_workspace(s, 0, 0, spill_depth_of(s) * threads);
+}
+
+rcp_status render_chain(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& disp, float* out_images,
+                        int32_t* out_ids, unsigned long long* host_counts, hipStream_t stream) {
+    const bool stats = host_counts != nullptr;
+    const Launch lp = launch_params(s);
+    int blocks = 0;
+    size_t smem = 0;
+    rcp_status st = stats ? chain_grid_mode<true>(lp, 1, disp.mode, blocks, smem)
+                          : chain_grid_mode<false>(lp, 1, disp.mode, blocks, smem);
+    if (st != RCP_OK) return st;
+    const uint32_t threads = (uint32_t)blocks * kBlock;
+    st = ensure_workspace(s, 0, 0, spill_depth_of(s) * threads);
+    if (st != RCP_OK) return st;
+    Workspace& w = s->ws;
+    const ViewDev view = view_of(cam, W, H, K, disp, out_images, out_ids, lp.tile_log2w);
+    ChainArgs a{};
+    a.sc = s->dev;
+    a.sc.top_count = lp.staged_nodes;
+    a.views = (const ViewDev*)w.view;
+    a.begin = (const uint32_t*)((char*)w.view + ((sizeof(ViewDev) + 63) & ~(size_t)63));
+    a.n_views = 1;
+    a.n_items = (uint32_t)view_items(view);
+    a.fetch = w.counters;
+    a.refill_min = lp.refill_min;
+    a.spill = w.spill;
+    a.spill_stride = threads;
+    a.stats = stats ? w.stats : nullptr;
+    hipLaunchKernelGGL(k_setup_single, dim3(1), dim3(256), 0, stream, view, (ViewDev*)a.views, (uint32_t*)a.begin,
+                       a.n_items, w.counters, a.stats);
+    RCP_CHECK_LAUNCH();
+    if (stats) launch_chain_mode<true>(disp.mode, blocks, smem, stream, a);
+    else launch_chain_mode<false>(disp.mode, blocks, smem, stream, a);
+    RCP_CHECK_LAUNCH();
+    if (stats) {
+        RCP_HIP(hipMemcpyAsync(host_counts, w.stats, sizeof(unsigned long long) * 4 * K, hipMemcpyDeviceToHost,
+                               stream));
+        RCP_HIP(hipStreamSynchronize(stream));
+    }
+    return RCP_OK;
+}
+
+rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchWorkspace& ws, hipStream_t stream) {
+    const Launch lp = launch_params(s);
+    // views grouped by displacement mode, one launch per mode present
+    std::vector<int> order((size_t)n_views);
+    for (int i = 0; i < n_views; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int p, int q) { return views[p].disp.mode < views[q].disp.mode; });
+    std::vector<ViewDev> hv((size_t)n_views);
+    std::vector<uint32_t> hb((size_t)n_views + 3);   // begin arrays of the groups, back to back
+    struct Group { int mode, first, count; size_t bofs; uint32_t items; };
+    std::vector<Group> groups;
+    uint64_t items = 0;
+    size_t bofs = 0;
+    for (int j = 0; j < n_views; ++j) {
+        const rcp_view& vi = views[order[(size_t)j]];
+        if (groups.empty() || groups.back().mode != vi.disp.mode) {
+            if (!groups.empty()) {
+                hb[bofs++] = (uint32_t)items;
+                groups.back().items = (uint32_t)items;
+            }
+            groups.push_back(Group{vi.disp.mode, j, 0, bofs, 0});
+            items = 0;
+        }
+        Camera c{};
+        for (int a = 0; a < 3; ++a) {
+            c.eye[a] = vi.camera.eye[a];
+            c.right[a] = vi.camera.right[a];
+            c.up[a] = vi.camera.up[a];
+            c.forward[a] = vi.camera.forward[a];
+        }
+        c.th = vi.camera.tan_half_fovy;
+        const Disp d{vi.disp.lambda_eye, vi.disp.lambda_dir, vi.disp.z0, vi.disp.mode};
+        hv[(size_t)j] = view_of(c, vi.W, vi.H, vi.K, d, vi.out_images, vi.out_ids, lp.tile_log2w);
+        hb[bofs++] = (uint32_t)items;
+        items += view_items(hv[(size_t)j]);
+        if (items >= (1ull << 32) - (1ull << 24)) {   // headroom for fetches past the end
+            set_error("a batch of mode %d holds %llu work items (limit 2^32 - 2^24)", vi.disp.mode,
+                      (unsigned long long)items);
+            return RCP_ERR_INVALID_ARGUMENT;
+        }
+        groups.back().count++;
+    }
+    hb[bofs++] = (uint32_t)items;
+    groups.back().items = (uint32_t)items;
+
+    int max_blocks = 0;
+    std::vector<int> gblocks(groups.size());
+    std::vector<size_t> gsmem(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) {
+        rcp_status st = chain_grid_mode<false>(lp, groups[g].count, groups[g].mode, gblocks[g], gsmem[g]);
+        if (st != RCP_OK) return st;
+        max_blocks = std::max(max_blocks, gblocks[g]);
+    }
+    const size_t spill_need = spill_depth_of(s) * (size_t)max_blocks * kBlock;
+
+    if ((size_t)n_views > ws.view_cap) {
+        if (ws.views) { RCP_HIP(hipFree(ws.views)); ws.views = nullptr; }
+        ws.view_cap = 0;
+        RCP_HIP(hipMalloc(&ws.views, sizeof(ViewDev) * (size_t)n_views + sizeof(uint32_t) * (size_t)(n_views + 3) +
+                                         256));
+        ws.view_cap = (size_t)n_views;
+    }
+    if (!ws.fetch) RCP_HIP(hipMalloc((void**)&ws.fetch, sizeof(uint32_t) * 16 * 3));
+    if (spill_need > ws.spill_cap) {
+        if (ws.spill) { RCP_HIP(hipFree(ws.spill)); ws.spill = nullptr; }
+        ws.spill_cap = 0;
+        RCP_HIP(hipMalloc((void**)&ws.spill, sizeof(int32_t) * spill_need));
+        ws.spill_cap = spill_need;
+    }
+    ViewDev* d_views = (ViewDev*)ws.views;
+    uint32_t* d_begin = (uint32_t*)((char*)ws.views + ((sizeof(ViewDev) * (size_t)n_views + 255) & ~(size_t)255));
+    // pageable sources: the copies have read them when the calls return
+    RCP_HIP(hipMemcpyAsync(d_views, hv.data(), sizeof(ViewDev) * (size_t)n_views, hipMemcpyHostToDevice, stream));
+    RCP_HIP(hipMemcpyAsync(d_begin, hb.data(), sizeof(uint32_t) * bofs, hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_clear_chain, dim3(1), dim3(64), 0, stream, ws.fetch, (int)groups.size(),
+                       (unsigned long long*)nullptr);
+    RCP_CHECK_LAUNCH();
+    for (size_t g = 0; g < groups.size(); ++g) {
+        ChainArgs a{};
+        a.sc = s->dev;
+        a.sc.top_count = lp.staged_nodes;
+        a.views = d_views + groups[g].first;
+        a.begin = d_begin + groups[g].bofs;
+        a.n_views = groups[g].count;
+        a.n_items = groups[g].items;
+        a.fetch = ws.fetch + 16 * g;
+        a.refill_min = lp.refill_min;
+        a.spill = ws.spill;
+        a.spill_stride = (uint32_t)gblocks[g] * kBlock;
+        launch_chain_mode<false>(groups[g].mode, gblocks[g], gsmem[g], stream, a);
+        RCP_CHECK_LAUNCH();
+    }
+    return RCP_OK;
+}
+
+void free_batch_workspace(BatchWorkspace& ws) {
+    if (ws.views) (void)hipFree(ws.views);
+    if (ws.fetch) (void)hipFree(ws.fetch);
+    if (ws.spill) (void)hipFree(ws.spill);
+    ws = BatchWorkspace{};
+}
+
+}  // namespace rcp

@@ -81,7 +81,10 @@ struct Workspace {
     int32_t* spill = nullptr;                  // traversal stack overflow
     size_t spill_cap = 0;                      // int32 entries
     unsigned long long* stats = nullptr;       // [kMaxPasses][4]
+    void* view = nullptr;                      // chain engine: one-entry view table (kViewBytes)
 };
+
+constexpr size_t kViewBytes = 512;
 
 constexpr int kMaxPasses = 64;
 
@@ -104,6 +107,7 @@ struct Tuning {
     int staged_nodes = -1;        // < 0: all top nodes of the build
     int blocks_per_cu = 0;        // 0: occupancy limit
     int tile_log2w = 3;           // 8x8 tiles
+    int engine = RCP_ENGINE_CHAIN;
 };
 
 }  // namespace rcp
@@ -158,6 +162,10 @@ rcp_status gather_passes(const float* in, int W, int H, int n, float smudge, int
                          hipStream_t stream);
 
 rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchWorkspace& ws, hipStream_t stream);
+// The chain engine for a whole render from the seed: one launch, no pass barrier.
+rcp_status prepare_chain(rcp_scene* s, int mode);
+rcp_status render_chain(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& disp, float* out_images,
+                        int32_t* out_ids, unsigned long long* host_counts, hipStream_t stream);
 void free_batch_workspace(BatchWorkspace& ws);
 
 // The launch parameters a render of this scene uses (tuning or defaults).
@@ -172,6 +180,9 @@ Launch launch_params(const rcp_scene* s);
 // Make sure the scene's render workspace fits a K-pass W x H render in
 // `mode` (no allocation happens in rcp_render afterwards for that size).
 rcp_status prepare_render(rcp_scene* s, int W, int H, int K, int mode);
+// Grow the scene's workspace: per-pass state and aux lists of n_state / n_aux
+// entries (0 = none), the counters, and spill_entries stack overflow words.
+rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t n_aux, size_t spill_entries);
 
 rcp_status graph_capture(rcp_graph* g);
 void graph_free(rcp_graph* g);

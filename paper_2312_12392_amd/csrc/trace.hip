@@ -311,6 +311,8 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
     }
 }
 
+}  // namespace
+
 rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t n_aux, size_t spill_entries) {
     Workspace& w = s->ws;
     if (n_aux > w.aux_cap) {
@@ -325,6 +327,7 @@ rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t n_aux, size_t s
         RCP_HIP(hipMalloc((void**)&w.counters, sizeof(uint32_t) * (2 * kMaxPasses + 8)));
         RCP_HIP(hipMalloc((void**)&w.stats, sizeof(unsigned long long) * 4 * kMaxPasses));
     }
+    if (!w.view) RCP_HIP(hipMalloc(&w.view, kViewBytes));
     if (n_state > w.state_cap) {
         for (int i = 0; i < 2; ++i) {
             if (w.state[i]) { RCP_HIP(hipFree(w.state[i])); w.state[i] = nullptr; }
@@ -341,6 +344,8 @@ rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t n_aux, size_t s
     }
     return RCP_OK;
 }
+
+namespace {
 
 struct GridInfo {
     int blocks = 0;
@@ -451,6 +456,7 @@ rcp_status prepare_mode(rcp_scene* s, int W, int H, int K) {
 }  // namespace
 
 rcp_status prepare_render(rcp_scene* s, int W, int H, int K, int mode) {
+    if (s->tuning.engine == RCP_ENGINE_CHAIN) return prepare_chain(s, mode);
     switch (mode) {
         case RCP_MODE_DEPTH: return prepare_mode<RCP_MODE_DEPTH>(s, W, H, K);
         case RCP_MODE_NORMAL: return prepare_mode<RCP_MODE_NORMAL>(s, W, H, K);
@@ -461,6 +467,10 @@ rcp_status prepare_render(rcp_scene* s, int W, int H, int K, int mode) {
 rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& disp, float* out_images,
                   int32_t* out_ids, const float* prev_rgb, const float* prev_aux, float* out_aux,
                   unsigned long long* host_counts, hipStream_t stream) {
+    // whole renders from the seed take the chain engine unless the per-pass
+    // engine is selected; single passes with given inputs take the pass kernel
+    if (s->tuning.engine == RCP_ENGINE_CHAIN && !prev_rgb && !prev_aux && !out_aux)
+        return render_chain(s, cam, W, H, K, disp, out_images, out_ids, host_counts, stream);
     const bool stats = host_counts != nullptr;
     const Launch lp = launch_params(s);
     const int tw = 1 << lp.tile_log2w, th = 64 >> lp.tile_log2w;

@@ -135,3 +135,14 @@ def test_server_validation_on_host():
         rcp.rcp_poll(0, 1)
     with pytest.raises(rcp.RcpError):
         rcp.rcp_release(0, 1)
+
+
+def test_header_constants_match_the_binding():
+    import re
+    text = open(HEADER).read() if "HEADER" in globals() else open(
+        os.path.join(os.path.dirname(__file__), "..", "include", "rcp.h")).read()
+    defs = dict(re.findall(r"#define\s+(RCP_[A-Z_]+)\s+(-?\d+)", text))
+    assert defs, "no integer constants found in the header"
+    for name, value in defs.items():
+        assert hasattr(rcp, name), f"binding lacks {name}"
+        assert getattr(rcp, name) == int(value), name

@@ -66,6 +66,38 @@ def test_batch_equals_single_views_and_oracle():
     s.close()
 
 
+def test_batch_mixed_modes_equal_single_views_and_oracle():
+    """Colour, depth and normal views in one call: one launch per mode, each
+    view equal to rcp_render alone and to the oracle."""
+    sc = scenegen.terrain_patch(12, 40, 20)
+    s = rcp.Scene(sc)
+    orc = oracle.OracleScene(sc, use_bvh=True)
+    rng = np.random.default_rng(5)
+    modes = [rcp.RCP_MODE_DEPTH, rcp.RCP_MODE_COLOR, rcp.RCP_MODE_NORMAL, rcp.RCP_MODE_NORMAL, rcp.RCP_MODE_COLOR,
+             rcp.RCP_MODE_DEPTH, rcp.RCP_MODE_DEPTH, rcp.RCP_MODE_COLOR]
+    specs = []
+    for i, mode in enumerate(modes):
+        ang = rng.uniform(-0.6, 0.6)
+        cam = scenegen.camera_look_at([1.4 * np.sin(ang), rng.uniform(0.3, 0.7), -1.4 * np.cos(ang)],
+                                      [0, 0.05, 0], [0, 1, 0], 60.0)
+        W, H, K = [(67, 45, 4), (1, 1, 3), (40, 30, 6), (96, 72, 2), (33, 21, 5), (64, 64, 6), (8, 3, 2),
+                   (50, 41, 7)][i]
+        specs.append((cam, W, H, K, 0.01 * (i % 2), float(rng.uniform(0.02, 0.2)), mode, float(rng.uniform(0.5, 2))))
+    say("mixed-mode batch", len(specs))
+    outs = [(torch.empty((K, H, W, 3), device="cuda"), torch.empty((K, H, W), dtype=torch.int32, device="cuda"))
+            for (_, W, H, K, *_r) in specs]
+    rcp.rcp_render_batch(s.handle, [(cam, W, H, K, rcp.make_displacement(le, ld, mode, z0), o, i)
+                                    for (cam, W, H, K, le, ld, mode, z0), (o, i) in zip(specs, outs)])
+    torch.cuda.synchronize()
+    for n, ((cam, W, H, K, le, ld, mode, z0), (o, i)) in enumerate(zip(specs, outs)):
+        ref_img, ref_ids = s.render(cam, W, H, K, le, ld, mode=mode, z0=z0)
+        torch.cuda.synchronize()
+        assert torch.equal(o, ref_img) and torch.equal(i, ref_ids), n
+        oi, oid = orc.render(cam, W, H, K, le, ld, mode=mode, z0=z0)
+        assert np.array_equal(o.cpu().numpy(), oi) and np.array_equal(i.cpu().numpy(), oid), n
+    s.close()
+
+
 def test_batch_orbit_mix_on_terrain1m():
     """The 64-view orbit mix (256^2 .. 1024^2, K 1..8) of the 1M scene."""
     w = scenegen.workload("terrain1m")
@@ -97,17 +129,20 @@ def test_batch_rejects_bad_views():
     with pytest.raises(rcp.RcpError):
         rcp.rcp_render_batch(s.handle, [(w.camera, 8, 8, 2, d, o, None), (w.camera, 8, 8, 2, d, o, None)])  # overlap
     with pytest.raises(rcp.RcpError):
-        rcp.rcp_render_batch(s.handle, [(w.camera, 8, 8, 2, rcp.make_displacement(0.0, 0.02, rcp.RCP_MODE_DEPTH), o,
-                                         None)])
+        rcp.rcp_render_batch(s.handle, [(w.camera, 8, 8, 0, d, o, None)])                         # K = 0
+    with pytest.raises(rcp.RcpError):
+        rcp.rcp_render_batch(s.handle, [(w.camera, 8, 8, 2, rcp.make_displacement(0.0, 0.02, 7), o, None)])
     with pytest.raises(rcp.RcpError):
         rcp.rcp_render_batch(s.handle, [])
     s.close()
 
 
-def test_graph_replays_equal_eager_render():
+@pytest.mark.parametrize("engine", [rcp.RCP_ENGINE_CHAIN, rcp.RCP_ENGINE_PASSES], ids=["chain", "passes"])
+def test_graph_replays_equal_eager_render(engine):
     w = scenegen.workload("soup256")
-    say("graph replays")
+    say("graph replays engine", engine)
     s = rcp.Scene(w.scene)
+    s.set_engine(engine)
     ref_img, ref_ids = single(s, w.camera, 64, 64, 6, 0.0, 0.02)
     out = torch.empty_like(ref_img)
     ids = torch.empty_like(ref_ids)
@@ -136,10 +171,11 @@ def test_graph_replays_equal_eager_render():
 
 
 @pytest.mark.parametrize("tuning", [
-    dict(refill_min=1, staged_nodes=0, blocks_per_cu=1, tile_log2w=0),
-    dict(refill_min=64, staged_nodes=7, blocks_per_cu=2, tile_log2w=6),
-    dict(refill_min=17, staged_nodes=31, blocks_per_cu=0, tile_log2w=4),
-    dict(refill_min=40, staged_nodes=63, blocks_per_cu=3, tile_log2w=2),
+    dict(refill_min=1, staged_nodes=0, blocks_per_cu=1, tile_log2w=0, engine=0),
+    dict(refill_min=64, staged_nodes=7, blocks_per_cu=2, tile_log2w=6, engine=0),
+    dict(refill_min=17, staged_nodes=31, blocks_per_cu=0, tile_log2w=4, engine=1),
+    dict(refill_min=40, staged_nodes=63, blocks_per_cu=3, tile_log2w=2, engine=1),
+    dict(refill_min=1, staged_nodes=0, blocks_per_cu=1, tile_log2w=0, engine=1),
 ])
 def test_tuning_does_not_change_images(tuning):
     say("tuning", tuning)

@@ -74,13 +74,15 @@ RENDER_CASES = [
 ]
 
 
+@pytest.mark.parametrize("engine", [rcp.RCP_ENGINE_CHAIN, rcp.RCP_ENGINE_PASSES], ids=["chain", "passes"])
 @pytest.mark.parametrize("mode", [DEPTH, NORMAL])
 @pytest.mark.parametrize("case", RENDER_CASES, ids=[c[0] for c in RENDER_CASES])
-def test_render_modes_match_oracle(mode, case):
+def test_render_modes_match_oracle(mode, case, engine):
     name, scene_fn, cam, W, H, K, le, ld, z0 = case
-    say("render mode", mode, name)
+    say("render mode", mode, name, "engine", engine)
     sc = scene_fn()
     s = rcp.Scene(sc)
+    s.set_engine(engine)
     imgs, ids = s.render(cam, W, H, K, le, ld, mode=mode, z0=z0)
     torch.cuda.synchronize()
     g_img, g_ids = imgs.cpu().numpy(), ids.cpu().numpy()

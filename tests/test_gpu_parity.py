@@ -28,8 +28,13 @@ def _device():
     rcp.load()
 
 
-def gpu_render(scene, cam, W, H, K, le, ld, opts=None):
+ENGINES = [rcp.RCP_ENGINE_CHAIN, rcp.RCP_ENGINE_PASSES]
+ENGINE_IDS = ["chain", "passes"]
+
+
+def gpu_render(scene, cam, W, H, K, le, ld, opts=None, engine=rcp.RCP_ENGINE_CHAIN):
     s = rcp.Scene(scene, opts)
+    s.set_engine(engine)
     imgs, ids = s.render(cam, W, H, K, le, ld)
     torch.cuda.synchronize()
     out = imgs.cpu().numpy(), ids.cpu().numpy()
@@ -178,12 +183,13 @@ RENDER_CASES = [
 ]
 
 
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
 @pytest.mark.parametrize("case", RENDER_CASES, ids=[c[0] for c in RENDER_CASES])
-def test_render_matches_oracle(case):
+def test_render_matches_oracle(case, engine):
     name, scene_fn, cam, W, H, K, le, ld = case
-    say("render", name, W, H, K, le, ld)
+    say("render", name, W, H, K, le, ld, "engine", engine)
     sc = scene_fn()
-    g_img, g_ids = gpu_render(sc, cam, W, H, K, le, ld)
+    g_img, g_ids = gpu_render(sc, cam, W, H, K, le, ld, engine=engine)
     o_img, o_ids = oracle.OracleScene(sc, use_bvh=True).render(cam, W, H, K, le, ld)
     r = assert_parity(g_img, g_ids, o_img, o_ids, name)
     # the path is designed to reproduce the oracle's FP32 arithmetic exactly
@@ -256,15 +262,18 @@ def test_prefix_stability_and_determinism():
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
 
 
-def test_stats_kernel_counts_and_images():
-    say("render_stats")
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+def test_stats_kernel_counts_and_images(engine):
+    say("render_stats engine", engine)
     w = scenegen.workload("soup256")
     s = rcp.Scene(w.scene)
     imgs, ids = s.render(w.camera, 64, 64, 6, 0.0, 0.02)
+    s.set_engine(engine)
     i2 = torch.empty_like(imgs)
     d2 = torch.empty_like(ids)
     counts = rcp.rcp_render_stats(s.handle, w.camera, 64, 64, 6, rcp.make_displacement(0.0, 0.02), i2, d2)
     assert torch.equal(imgs, i2) and torch.equal(ids, d2)
+    assert np.all(counts[:, 1] > 0) == np.all(counts[:, 0] > 0) and np.all(counts[:, 2] >= 0)
     assert counts[0, 0] == 64 * 64
     for k in range(5):
         assert counts[k + 1, 0] == counts[k, 3]          # traced at k+1 = appended at k
@@ -354,4 +363,27 @@ def test_invalid_arguments_with_a_real_scene():
         rcp.rcp_render(s.handle, w.camera, 8, 8, 2, rcp.make_displacement(0.0, 1.5), out)
     with pytest.raises(rcp.RcpError):
         rcp.rcp_render(s.handle, w.camera, 8, 8, 2, d, None)
+    s.close()
+
+
+def test_engines_trace_the_same_rays():
+    """Both engines trace exactly the pixels whose inputs changed, pass by
+    pass; node and triangle counts may differ slightly, since speculative
+    traversal depends on which rays share a wave."""
+    w = scenegen.workload("terrain1m")
+    say("engines stats", w.name)
+    s = rcp.Scene(w.scene)
+    d = rcp.make_displacement(w.lambda_eye, w.lambda_dir)
+    out = {}
+    for e in ENGINES:
+        s.set_engine(e)
+        img = torch.empty((w.passes, w.height, w.width, 3), device="cuda")
+        out[e] = (rcp.rcp_render_stats(s.handle, w.camera, w.width, w.height, w.passes, d, img, None), img)
+    (c0, i0), (c1, i1) = out[ENGINES[0]], out[ENGINES[1]]
+    assert torch.equal(i0, i1)
+    assert np.array_equal(c0[:, 0], c1[:, 0]) and np.array_equal(c0[:, 3], c1[:, 3])
+    assert c0[0, 0] == w.width * w.height
+    for col in (1, 2):
+        a, b = c0[:, col].astype(np.float64), c1[:, col].astype(np.float64)
+        assert np.all(np.abs(a - b) <= 0.05 * np.maximum(a, b) + 64), (col, a, b)
     s.close()

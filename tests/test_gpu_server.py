@@ -107,6 +107,19 @@ def test_staggered_and_single_equal_alone(scene):
     rcp.rcp_server_destroy(srv)
 
 
+def test_mixed_modes_equal_alone(scene):
+    say("server mixed modes")
+    srv = rcp.rcp_server_create(scene.handle, 64 << 20, max_inflight=2)
+    reqs = []
+    for i, (cam, W, H, K, d) in enumerate(requests(18, 4)):
+        mode = [rcp.RCP_MODE_COLOR, rcp.RCP_MODE_DEPTH, rcp.RCP_MODE_NORMAL][i % 3]
+        reqs.append((cam, W, H, K, rcp.make_displacement(0.005 * (i % 2), d.lambda_dir + 0.01, mode, 1.1)))
+    tickets = [rcp.rcp_submit(srv, cam, W, H, K, d, with_ids=True) for (cam, W, H, K, d) in reqs]
+    wait_done(srv, tickets)
+    check_against_alone(scene, srv, reqs, tickets)
+    rcp.rcp_server_destroy(srv)
+
+
 def test_budget_and_queue_limits(scene):
     say("server budget")
     cam, _, _, _, d = requests(1, 2)[0]
