@@ -103,7 +103,7 @@ def main():
                     help="chain: one persistent launch per frame; passes: one launch per pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-leaf", type=int, default=None, help="BVH leaf size bound (build option)")
-    ap.add_argument("--top-levels", type=int, default=None, help="BVH levels staged in LDS (build option)")
+    ap.add_argument("--top-levels", type=int, default=None, help="BVH levels laid out breadth-first (build option)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()

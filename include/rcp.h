@@ -116,9 +116,10 @@ typedef struct {
 #define RCP_MODE_NORMAL 2
 
 /* Build options (NULL = defaults).  max_leaf: most triangles per BVH leaf
- * (1..8, default 4); top_levels: BVH levels staged in LDS by the traversal
- * (0..9, default 6); c_trav, c_isect: SAH costs of a node visit and a
- * triangle test (defaults 1, 1). */
+ * (1..8, default 4); top_levels: BVH levels laid out breadth-first at the
+ * start of the node array, the rest depth-first (0..9, default 6; memory
+ * layout only); c_trav, c_isect: SAH costs of a node visit and a triangle
+ * test (defaults 1, 1). */
 typedef struct {
     int32_t max_leaf;
     int32_t top_levels;
@@ -131,7 +132,7 @@ typedef struct {
     uint32_t n_tris;
     uint32_t n_nodes;        /* packed BVH2 nodes (64 B each) */
     uint32_t n_leaves;
-    uint32_t top_count;      /* nodes staged in LDS */
+    uint32_t top_count;      /* nodes of the breadth-first top block */
     uint32_t max_depth;      /* deepest node (root = 0) */
     uint32_t max_leaf;
     float sah_cost;          /* SAH cost of the packed tree, relative to the root box */
@@ -244,7 +245,6 @@ void rcp_graph_destroy(rcp_graph* graph);
 /* Launch parameters of the persistent kernels, per scene.  They change only
  * the speed, never an image.
  *   refill_min     idle lanes (1..64) that make a wave fetch new pixels
- *   staged_nodes   top BVH nodes copied to LDS (0..top_count of the scene)
  *   blocks_per_cu  resident workgroups per compute unit (0 = occupancy limit)
  *   tile_log2w     pixel tile of 64: width 2^tile_log2w (0..6)
  *   engine         how rcp_render (and rcp_render_stats, graphs, the
@@ -261,7 +261,6 @@ void rcp_graph_destroy(rcp_graph* graph);
 #define RCP_ENGINE_PASSES 1
 typedef struct {
     int32_t refill_min;
-    int32_t staged_nodes;
     int32_t blocks_per_cu;
     int32_t tile_log2w;
     int32_t engine;

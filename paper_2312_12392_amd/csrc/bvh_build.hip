@@ -11,8 +11,9 @@
 //   5. bottom-up refit with per-node arrival counters; each node also gets its
 //      SAH cost and is collapsed into a leaf (<= max_leaf triangles) when that
 //      is cheaper than keeping the split
-//   6. layout: the top levels in breadth-first order (staged in LDS by the
-//      traversal), then every remaining subtree in depth-first order
+//   6. layout: the top levels in breadth-first order (the nodes every ray
+//      visits first, packed together), then every remaining subtree in
+//      depth-first order
 //   7. packing into 64-byte BVH2 nodes, 48-byte triangles and a per-triangle
 //      table of the two shaded colours.
 #include <cmath>

@@ -59,15 +59,13 @@ template <bool STATS, int MODE>
 __global__ __launch_bounds__(kBlock) void k_chain(ChainArgs a) {
     constexpr bool AUX = MODE != RCP_MODE_COLOR;
     extern __shared__ float4 smem[];
-    float4* top = smem;                                                   // top_count * 4
-    char* lds = (char*)(smem + 4 * a.sc.top_count);
+    char* lds = (char*)smem;
     unsigned long long* lstats = (unsigned long long*)lds;                // STATS: 4 * kMaxPasses
     if (STATS) lds += sizeof(unsigned long long) * 4 * kMaxPasses;
     uint32_t* vbegin = (uint32_t*)lds;                                    // n_views + 1
     lds += sizeof(uint32_t) * (size_t)((a.n_views + 4) & ~3);
     int32_t* stack_area = (int32_t*)lds;                                  // kStack * kBlock
 
-    for (uint32_t i = threadIdx.x; i < 4 * a.sc.top_count; i += kBlock) top[i] = a.sc.nodes[i];
     for (int i = threadIdx.x; i <= a.n_views; i += kBlock) vbegin[i] = a.begin[i];
     if (STATS)
         for (int i = threadIdx.x; i < 4 * kMaxPasses; i += kBlock) lstats[i] = 0ull;
@@ -135,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(ChainArgs a) {
         }
 
         // ---- one traversal step -------------------------------------------------
-        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, top, st, dn, dt);
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, st, dn, dt);
 
         // ---- a finished pass: shade, write, then the next pass or the end -------
         if (alive && tv.node == -1) {
@@ -236,8 +234,7 @@ __global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint3
 }
 
 size_t chain_smem(const Launch& lp, bool stats, int n_views) {
-    size_t b = sizeof(float4) * 4 * (size_t)lp.staged_nodes + sizeof(int32_t) * kStack * kBlock +
-               sizeof(uint32_t) * (size_t)((n_views + 4) & ~3);
+    size_t b = sizeof(int32_t) * kStack * kBlock + sizeof(uint32_t) * (size_t)((n_views + 4) & ~3);
     if (stats) b += sizeof(unsigned long long) * 4 * kMaxPasses;
     return b;
 }
@@ -329,7 +326,6 @@ rcp_status render_chain(rcp_scene* s, const Camera& cam, int W, int H, int K, co
     const ViewDev view = view_of(cam, W, H, K, disp, out_images, out_ids, lp.tile_log2w);
     ChainArgs a{};
     a.sc = s->dev;
-    a.sc.top_count = lp.staged_nodes;
     a.views = (const ViewDev*)w.view;
     a.begin = (const uint32_t*)((char*)w.view + ((sizeof(ViewDev) + 63) & ~(size_t)63));
     a.n_views = 1;
@@ -433,7 +429,6 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
     for (size_t g = 0; g < groups.size(); ++g) {
         ChainArgs a{};
         a.sc = s->dev;
-        a.sc.top_count = lp.staged_nodes;
         a.views = d_views + groups[g].first;
         a.begin = d_begin + groups[g].bofs;
         a.n_views = groups[g].count;

@@ -6,7 +6,7 @@
 //   shade  float4[n_tris][2]    shaded RGB seen from the front / back side
 //   normal float4[n_tris]       unit geometric normal (read by the normal mapping)
 // The first top_count nodes are the BVH's top levels in breadth-first order;
-// the traversal stages them in LDS.  The rest follow in depth-first order.
+// the rest follow in depth-first order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -104,7 +104,6 @@ struct BatchWorkspace {
 
 struct Tuning {
     int refill_min = -1;          // < 0: the library default
-    int staged_nodes = -1;        // < 0: all top nodes of the build
     int blocks_per_cu = 0;        // 0: occupancy limit
     int tile_log2w = 3;           // 8x8 tiles
     int engine = RCP_ENGINE_CHAIN;
@@ -171,7 +170,6 @@ void free_batch_workspace(BatchWorkspace& ws);
 // The launch parameters a render of this scene uses (tuning or defaults).
 struct Launch {
     int refill_min;
-    uint32_t staged_nodes;
     int blocks_per_cu;
     int tile_log2w;
 };

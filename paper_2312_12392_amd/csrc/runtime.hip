@@ -85,34 +85,27 @@ rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const 
     RCP_HIP(hipEventCreate(&e0));
     RCP_HIP(hipEventCreate(&e1));
     struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
-    const int top = (int)s->dev.top_count;
-    std::vector<int> staged = {0};
-    for (int n = 1; n < top; n = 2 * n + 1) staged.push_back(n);
-    staged.push_back(top);
     const std::vector<int> refill = {16, 24, 32, 40, 48, 64};
     const std::vector<int> blocks = {0, 4, 3, 2};
     const std::vector<int> tiles = {3, 4, 2, 5};
     const std::vector<int> engines = {RCP_ENGINE_CHAIN, RCP_ENGINE_PASSES};
     Tuning cur = s->tuning;
     if (cur.refill_min <= 0) cur.refill_min = refill_min();
-    if (cur.staged_nodes < 0) cur.staged_nodes = top;
     s->tuning = cur;
     float cur_ms = 0.0f;
     rcp_status st = time_render(s, cam, W, H, K, d, out, ids, repeats, stream, e0, e1, cur_ms);
     if (st != RCP_OK) return st;
     for (int round = 0; round < 2; ++round) {
-        for (int param = 0; param < 5; ++param) {
+        for (int param = 0; param < 4; ++param) {
             const std::vector<int>& cands = param == 0   ? refill
-                                            : param == 1 ? staged
-                                            : param == 2 ? blocks
-                                            : param == 3 ? tiles
+                                            : param == 1 ? blocks
+                                            : param == 2 ? tiles
                                                          : engines;
             for (int c : cands) {
                 Tuning t = cur;
                 int& field = param == 0   ? t.refill_min
-                             : param == 1 ? t.staged_nodes
-                             : param == 2 ? t.blocks_per_cu
-                             : param == 3 ? t.tile_log2w
+                             : param == 1 ? t.blocks_per_cu
+                             : param == 2 ? t.tile_log2w
                                           : t.engine;
                 if (field == c) continue;
                 field = c;

@@ -7,8 +7,8 @@
 // item the lane
 //   1. builds the pixel's displaced camera ray from its previous colour
 //      (Section 2 ray and displacements, Section 3 colour mapping),
-//   2. traverses the BVH (top levels from LDS, a short per-lane stack in LDS
-//      that overflows into a per-lane global area) and runs the watertight
+//   2. traverses the BVH (a short per-lane stack in LDS that overflows into
+//      a per-lane global area) and runs the watertight
 //      ray/triangle test at the leaves, keeping the nearest hit and, at equal
 //      distance, the lowest triangle index,
 //   3. looks the shaded colour up in the per-triangle table and writes
@@ -62,12 +62,8 @@ template <bool STATS, int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVES_PER_EU))) void k_pass(PassArgs a) {
     constexpr bool AUX = MODE != RCP_MODE_COLOR;
     extern __shared__ float4 smem[];
-    float4* top = smem;                                                 // top_count * 4
-    float4* stage_all = smem + 4 * a.sc.top_count;                      // kWaves * kStage (x2 with aux)
+    float4* stage_all = smem;                                           // kWaves * kStage (x2 with aux)
     int32_t* stack_area = (int32_t*)(stage_all + (AUX ? 2 : 1) * kWaves * kStage);   // kStack * kBlock
-
-    for (uint32_t i = threadIdx.x; i < 4 * a.sc.top_count; i += kBlock) top[i] = a.sc.nodes[i];
-    __syncthreads();
 
     const int lane = threadIdx.x & 63;
     float4* stage = stage_all + (threadIdx.x >> 6) * kStage;
@@ -153,7 +149,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
         }
 
         // ---- one traversal step -------------------------------------------
-        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, top, st, s_nodes, s_tris);
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, st, s_nodes, s_tris);
 
         // ---- finished rays: shade, write, compact ----------------------------
         const bool done = alive && tv.node == -1;
@@ -287,11 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
                                                         const float* __restrict__ dir, int n, float* __restrict__ out_t,
                                                         int32_t* __restrict__ out_id, int32_t* __restrict__ out_front,
                                                         int32_t* __restrict__ spill, uint32_t stride) {
-    extern __shared__ float4 smem[];
-    float4* top = smem;
-    int32_t* stack_area = (int32_t*)(smem + 4 * sc.top_count + kWaves * kStage);
-    for (uint32_t i = threadIdx.x; i < 4 * sc.top_count; i += kBlock) top[i] = sc.nodes[i];
-    __syncthreads();
+    extern __shared__ int32_t stack_area[];                             // kStack * kBlock
     const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
     Stack st;
     st.lds = stack_area + threadIdx.x;
@@ -303,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
         Trav tv;
         trav_init(tv, sc, o, d, st);
         uint32_t dn = 0, dt = 0;
-        while (tv.node != -1) trav_step<false>(tv, sc, top, st, dn, dt);
+        while (tv.node != -1) trav_step<false>(tv, sc, st, dn, dt);
         const bool hit = tv.h.id != INT_MAX;
         out_t[r] = hit ? tv.h.t : INFINITY;
         out_id[r] = hit ? tv.h.id : -1;
@@ -354,8 +346,7 @@ struct GridInfo {
 
 template <typename KernelT>
 rcp_status persistent_grid(KernelT kernel, const DevScene& sc, GridInfo& g, bool aux, int blocks_per_cu) {
-    g.smem = sizeof(float4) * (4 * (size_t)sc.top_count + (aux ? 2 : 1) * kWaves * kStage) +
-             sizeof(int32_t) * kStack * kBlock;
+    g.smem = sizeof(float4) * (aux ? 2 : 1) * kWaves * kStage + sizeof(int32_t) * kStack * kBlock;
     int per_cu = 0;
     RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, g.smem));
     int dev = 0, cus = 0;
@@ -382,9 +373,6 @@ int refill_min() {
 Launch launch_params(const rcp_scene* s) {
     Launch l;
     l.refill_min = s->tuning.refill_min > 0 ? s->tuning.refill_min : refill_min();
-    l.staged_nodes = s->tuning.staged_nodes >= 0 && (uint32_t)s->tuning.staged_nodes < s->dev.top_count
-                         ? (uint32_t)s->tuning.staged_nodes
-                         : s->dev.top_count;
     l.blocks_per_cu = s->tuning.blocks_per_cu;
     l.tile_log2w = s->tuning.tile_log2w;
     return l;
@@ -393,9 +381,7 @@ Launch launch_params(const rcp_scene* s) {
 namespace {
 template <bool STATS, int MODE>
 rcp_status pass_grid(rcp_scene* s, const Launch& lp, GridInfo& g) {
-    DevScene sc = s->dev;
-    sc.top_count = lp.staged_nodes;
-    return persistent_grid(k_pass<STATS, MODE>, sc, g, MODE != RCP_MODE_COLOR, lp.blocks_per_cu);
+    return persistent_grid(k_pass<STATS, MODE>, s->dev, g, MODE != RCP_MODE_COLOR, lp.blocks_per_cu);
 }
 
 template <bool STATS, int MODE>
@@ -477,7 +463,6 @@ rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Di
     const int tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
     PassArgs a{};
     a.sc = s->dev;
-    a.sc.top_count = lp.staged_nodes;
     a.cam = cam;
     a.W = W; a.H = H; a.K = K;
     a.le = disp.le; a.ld = disp.ld; a.z0 = disp.z0;

@@ -147,6 +147,8 @@ __device__ inline bool hit_triangle(const RayW& r, const float4& v0, const float
     return true;
 }
 
+typedef __attribute__((address_space(3))) int32_t LdsI32;
+
 struct Hit {
     float t;
     int32_t id;        // original triangle index, INT_MAX when none
@@ -157,28 +159,33 @@ struct Hit {
 // Per-lane traversal stack: the newest kStack entries live in LDS (column
 // `lane_col` of the block's stack area), older ones in the lane's global
 // overflow area.
+static_assert((kStack & (kStack - 1)) == 0, "the LDS stack ring is indexed with a mask");
+
 struct Stack {
     int32_t* lds;       // &stack_area[tid]; entry e at lds[(e % kStack) * kBlock]
     int32_t* spill;     // &spill[gtid]; entry e at spill[e * stride]
     uint32_t stride;
-    int sp, lo;         // entries [0, lo) spilled, [lo, sp) in LDS
+    uint32_t sp, lo;    // entries [0, lo) spilled, [lo, sp) in LDS
 
+    __device__ inline LdsI32* ring(uint32_t e) const {
+        return (LdsI32*)lds + (e & (uint32_t)(kStack - 1)) * kBlock;
+    }
     __device__ inline void push(int32_t v) {
-        if (sp - lo == kStack) {
-            spill[(size_t)lo * stride] = lds[(lo % kStack) * kBlock];
+        if (sp - lo == (uint32_t)kStack) {
+            spill[(size_t)lo * stride] = *ring(lo);
             ++lo;
         }
-        lds[(sp % kStack) * kBlock] = v;
+        *ring(sp) = v;
         ++sp;
     }
     __device__ inline int32_t pop() {
-        if (sp == 0) return -1;
+        if (sp == 0u) return -1;
         --sp;
         if (sp < lo) {       // the LDS part is empty: take the newest spilled entry
             lo = sp;
             return spill[(size_t)sp * stride];
         }
-        return lds[(sp % kStack) * kBlock];
+        return *ring(sp);
     }
 };
 
@@ -236,16 +243,12 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
 // Visit one inner node: test both child boxes, continue with the nearer hit
 // child, push the farther one, or pop when neither is hit.
 template <bool STATS>
-__device__ inline int32_t visit_inner(Trav& tv, int32_t node, const DevScene& sc, const float4* __restrict__ top,
-                                      Stack& st, uint32_t& n_nodes) {
+__device__ inline int32_t visit_inner(Trav& tv, int32_t node, const DevScene& sc, Stack& st, uint32_t& n_nodes) {
     const int kz = tv.rw.kz;
     float4 n0, n1, n2, n3;
-    if ((uint32_t)node < sc.top_count) {
-        n0 = top[4 * node + 0];
-        n1 = top[4 * node + 1];
-        n2 = top[4 * node + 2];
-        n3 = top[4 * node + 3];
-    } else {
+    // Every node comes from global memory (L2 / Infinity Cache); staging the
+    // top levels in LDS was measured to gain nothing on gfx950.
+    {
         const float4* p = sc.nodes + 4 * (size_t)node;
         n0 = p[0];
         n1 = p[1];
@@ -320,7 +323,7 @@ __device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, ui
 // looking for theirs, and holds the next leaf it meets for the following
 // step, so the wave's leaf tests run together.
 template <bool STATS>
-__device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* __restrict__ top, Stack& st,
+__device__ inline void trav_step(Trav& tv, const DevScene& sc, Stack& st,
                                  uint32_t& n_nodes, uint32_t& n_tris) {
     int32_t node = tv.node;
     int32_t leaf = -1;
@@ -329,7 +332,7 @@ __device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* __r
         if (!__any(leaf == -1 && node >= 0)) break;
         if (node >= 0) {
             if (--tv.budget == 0u) { node = -1; leaf = -1; break; }
-            node = visit_inner<STATS>(tv, node, sc, top, st, n_nodes);
+            node = visit_inner<STATS>(tv, node, sc, st, n_nodes);
         }
     }
     if (leaf != -1) visit_leaf<STATS>(tv, leaf, sc, n_tris);

@@ -81,7 +81,7 @@ class rcp_view(ctypes.Structure):
 
 
 class rcp_tuning(ctypes.Structure):
-    _fields_ = [("refill_min", ctypes.c_int32), ("staged_nodes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+    _fields_ = [("refill_min", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("tile_log2w", ctypes.c_int32), ("engine", ctypes.c_int32)]
 
     def as_dict(self):
@@ -376,12 +376,12 @@ def rcp_get_tuning(handle: int) -> dict:
     return t.as_dict()
 
 
-def rcp_set_tuning(handle: int, refill_min: int, staged_nodes: int, blocks_per_cu: int, tile_log2w: int,
+def rcp_set_tuning(handle: int, refill_min: int, blocks_per_cu: int, tile_log2w: int,
                    engine: int | None = None) -> None:
     """engine None keeps the scene's current engine."""
     if engine is None:
         engine = rcp_get_tuning(handle)["engine"]
-    t = rcp_tuning(int(refill_min), int(staged_nodes), int(blocks_per_cu), int(tile_log2w), int(engine))
+    t = rcp_tuning(int(refill_min), int(blocks_per_cu), int(tile_log2w), int(engine))
     _check(load().rcp_set_tuning(handle, ctypes.byref(t)), "rcp_set_tuning")
 
 
@@ -416,7 +416,7 @@ def autotune_cached(handle: int, scene_key: str, cam, W: int, H: int, K: int, di
             cache = {}
     if key in cache:
         t = cache[key]["tuning"]
-        rcp_set_tuning(handle, t["refill_min"], t["staged_nodes"], t["blocks_per_cu"], t["tile_log2w"],
+        rcp_set_tuning(handle, t["refill_min"], t["blocks_per_cu"], t["tile_log2w"],
                        t.get("engine", ENGINE_CHAIN))
         return t
     t, ms = rcp_autotune(handle, cam, W, H, K, disp, out_images, out_ids, repeats, stream)
@@ -516,7 +516,7 @@ class Scene:
         """RCP_ENGINE_CHAIN or RCP_ENGINE_PASSES for rcp_render; the other
         launch parameters stay as they are."""
         t = rcp_get_tuning(self.handle)
-        rcp_set_tuning(self.handle, t["refill_min"], t["staged_nodes"], t["blocks_per_cu"], t["tile_log2w"], engine)
+        rcp_set_tuning(self.handle, t["refill_min"], t["blocks_per_cu"], t["tile_log2w"], engine)
 
     def render(self, cam, W, H, K, lambda_eye, lambda_dir, with_ids=True, stream=None, mode=RCP_MODE_COLOR,
                z0=0.0):

@@ -171,11 +171,11 @@ def test_graph_replays_equal_eager_render(engine):
 
 
 @pytest.mark.parametrize("tuning", [
-    dict(refill_min=1, staged_nodes=0, blocks_per_cu=1, tile_log2w=0, engine=0),
-    dict(refill_min=64, staged_nodes=7, blocks_per_cu=2, tile_log2w=6, engine=0),
-    dict(refill_min=17, staged_nodes=31, blocks_per_cu=0, tile_log2w=4, engine=1),
-    dict(refill_min=40, staged_nodes=63, blocks_per_cu=3, tile_log2w=2, engine=1),
-    dict(refill_min=1, staged_nodes=0, blocks_per_cu=1, tile_log2w=0, engine=1),
+    dict(refill_min=1, blocks_per_cu=1, tile_log2w=0, engine=0),
+    dict(refill_min=64, blocks_per_cu=2, tile_log2w=6, engine=0),
+    dict(refill_min=17, blocks_per_cu=0, tile_log2w=4, engine=1),
+    dict(refill_min=40, blocks_per_cu=3, tile_log2w=2, engine=1),
+    dict(refill_min=1, blocks_per_cu=1, tile_log2w=0, engine=1),
 ])
 def test_tuning_does_not_change_images(tuning):
     say("tuning", tuning)
@@ -183,7 +183,6 @@ def test_tuning_does_not_change_images(tuning):
     s = rcp.Scene(sc)
     ref_img, ref_ids = single(s, PATCH_CAM, 67, 45, 5, 0.0, 0.1)
     t = dict(tuning)
-    t["staged_nodes"] = min(t["staged_nodes"], s.info()["top_count"])
     rcp.rcp_set_tuning(s.handle, **t)
     assert rcp.rcp_get_tuning(s.handle) == t
     img, ids = single(s, PATCH_CAM, 67, 45, 5, 0.0, 0.1)
@@ -211,7 +210,7 @@ def test_autotune_and_cache(tmp_path):
     t1 = rcp.autotune_cached(s.handle, "soup256", w.camera, 64, 64, 6, rcp.make_displacement(0.0, 0.02), out,
                              cache_path=path, repeats=1)
     assert os.path.exists(path) and len(json.load(open(path))) == 1
-    rcp.rcp_set_tuning(s.handle, 40, 0, 0, 3)
+    rcp.rcp_set_tuning(s.handle, 40, 0, 3)
     t2 = rcp.autotune_cached(s.handle, "soup256", w.camera, 64, 64, 6, rcp.make_displacement(0.0, 0.02), out,
                              cache_path=path, repeats=1)
     assert t2 == t1 and rcp.rcp_get_tuning(s.handle) == t1
