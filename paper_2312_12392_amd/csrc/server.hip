@@ -1,7 +1,7 @@
 // Continuous-batching render server.
 //
-// Requests (a camera, image size, pass count and colour displacement) enter
-// a FIFO queue.  A scheduler thread admits them in order while their output
+// Requests (a camera, image size, pass count and displacement, any mode)
+// enter a FIFO queue.  A scheduler thread admits them in order while their output
 // images fit in a device pool of fixed size (the HBM budget), packs every
 // admitted request that is not yet running into one batched launch
 // (rcp_render_batch's kernel: each pixel's pass chain is independent, so
