@@ -170,16 +170,17 @@ def bench_frame(args):
         torch.cuda.synchronize()
         del a, b
 
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    # one event between consecutive frames: the total and the per-frame times
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
+    ev[0].record(stream)
+    for i in range(args.steps):
         step()
-    e1.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
-    ms_total = e0.elapsed_time(e1)
+    ms_total = ev[0].elapsed_time(ev[-1])
     ms = ms_total / args.steps
+    per_frame = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     nominal = W * H * K
     value = nominal * args.steps / (ms_total * 1e-3) / 1e6
     # the frame is one k_chain launch (or K k_pass launches) plus one setup
@@ -204,6 +205,9 @@ def bench_frame(args):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "ms_median": round(float(np.median(per_frame)), 4),
+        "ms_min": round(float(per_frame.min()), 4),
+        "ms_p90": round(float(np.percentile(per_frame, 90)), 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

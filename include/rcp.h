@@ -244,7 +244,10 @@ void rcp_graph_destroy(rcp_graph* graph);
 
 /* Launch parameters of the persistent kernels, per scene.  They change only
  * the speed, never an image.
- *   refill_min     idle lanes (1..64) that make a wave fetch new pixels
+ *   refill_min     lanes (1..64) needing a ray that make a wave run a setup
+ *                  round (new pixels, and pixels moving to their next pass)
+ *   exit_lanes     a wave's descent to the leaves ends once no more than this
+ *                  many lanes (0..64, default 4) are still looking for one
  *   blocks_per_cu  resident workgroups per compute unit (0 = occupancy limit)
  *   tile_log2w     pixel tile of 64: width 2^tile_log2w (0..6)
  *   engine         how rcp_render (and rcp_render_stats, graphs, the
@@ -261,6 +264,7 @@ void rcp_graph_destroy(rcp_graph* graph);
 #define RCP_ENGINE_PASSES 1
 typedef struct {
     int32_t refill_min;
+    int32_t exit_lanes;
     int32_t blocks_per_cu;
     int32_t tile_log2w;
     int32_t engine;

@@ -317,6 +317,7 @@ rcp_status rcp_get_tuning(const rcp_scene* s, rcp_tuning* out) {
     if (!s || !out) FAIL("scene and out must not be NULL");
     const Launch l = launch_params(s);
     out->refill_min = l.refill_min;
+    out->exit_lanes = l.exit_lanes;
     out->blocks_per_cu = l.blocks_per_cu;
     out->tile_log2w = l.tile_log2w;
     out->engine = s->tuning.engine;
@@ -327,10 +328,12 @@ rcp_status rcp_set_tuning(rcp_scene* s, const rcp_tuning* t) {
     clear_error();
     if (!s || !t) FAIL("scene and tuning must not be NULL");
     if (t->refill_min < 1 || t->refill_min > 64) FAIL("refill_min must be in [1, 64]");
+    if (t->exit_lanes < 0 || t->exit_lanes > 64) FAIL("exit_lanes must be in [0, 64]");
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) FAIL("blocks_per_cu must be in [0, 64]");
     if (t->tile_log2w < 0 || t->tile_log2w > 6) FAIL("tile_log2w must be in [0, 6]");
     if (t->engine != RCP_ENGINE_CHAIN && t->engine != RCP_ENGINE_PASSES) FAIL("unknown engine %d", t->engine);
     s->tuning.refill_min = t->refill_min;
+    s->tuning.exit_lanes = t->exit_lanes;
     s->tuning.blocks_per_cu = t->blocks_per_cu;
     s->tuning.tile_log2w = t->tile_log2w;
     s->tuning.engine = t->engine;
@@ -356,8 +359,10 @@ rcp_status rcp_autotune(rcp_scene* scene, const rcp_camera* cam, int W, int H, i
                   out_ids, repeats, t, ms, (hipStream_t)hip_stream);
     if (st != RCP_OK) return st;
     best->refill_min = t.refill_min;
+    best->exit_lanes = t.exit_lanes;
     best->blocks_per_cu = t.blocks_per_cu;
     best->tile_log2w = t.tile_log2w;
+    best->engine = t.engine;
     if (best_ms) *best_ms = ms;
     return RCP_OK;
 }

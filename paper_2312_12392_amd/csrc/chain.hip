@@ -22,6 +22,8 @@
 
 #include "traverse.hpp"
 
+
+
 namespace rcp {
 namespace {
 
@@ -43,6 +45,7 @@ struct ChainArgs {
     uint32_t n_items;         // work items of the launch
     uint32_t* fetch;          // work counter, zero at launch
     int refill_min;
+    uint32_t exit_lanes;
     int32_t* spill;
     uint32_t spill_stride;
     unsigned long long* stats;   // [K][4] (STATS): rays, inner nodes, triangles, rays continued
@@ -81,7 +84,8 @@ __global__ __launch_bounds__(kBlock) void k_chain(ChainArgs a) {
     st.stride = a.spill_stride;
     const uint32_t n_items = a.n_items;
 
-    bool alive = false;
+    bool alive = false;        // tracing a ray
+    bool pending = false;      // holds the inputs of its next pass, waiting for a setup round
     bool drained = false;      // wave-uniform
     int k = 0, x = 0, y = 0;
     float pr = 0.5f, pg = 0.5f, pb = 0.5f;              // previous colour (the seed I_0 at pass 0)
@@ -91,15 +95,22 @@ __global__ __launch_bounds__(kBlock) void k_chain(ChainArgs a) {
     tv.node = -1;
 
     for (;;) {
-        // ---- refill idle lanes with new pixels ---------------------------------
-        const unsigned long long idle = __ballot(!alive);
-        const uint32_t n_idle = (uint32_t)__popcll(idle);
-        if (!drained && n_idle >= (uint32_t)a.refill_min) {
+        // ---- setup round: new pixels for idle lanes, rays for every lane that
+        // needs one (new pixels and lanes moving to their next pass together)
+        const unsigned long long need = __ballot(!alive);
+        const unsigned long long pend = __ballot(pending);
+        const unsigned long long idle = need & ~pend;
+        if ((uint32_t)__popcll(need) >= (uint32_t)a.refill_min || (drained && pend != 0ull)) {
+            const uint32_t n_idle = (uint32_t)__popcll(idle);
             uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(a.fetch, n_idle);
-            base = __shfl(base, 0);
-            if (base + n_idle >= n_items) drained = true;
-            if (!alive) {
+            const bool fetch = !drained && n_idle > 0u;
+            if (fetch) {
+                if (lane == 0) base = atomicAdd(a.fetch, n_idle);
+                base = __shfl(base, 0);
+                if (base + n_idle >= n_items) drained = true;
+            }
+            bool init = pending;
+            if (fetch && !alive && !pending) {
                 const uint32_t item = base + lanes_below(idle);
                 if (item < n_items) {
                     // the view holding this item: last begin <= item
@@ -117,23 +128,28 @@ __global__ __launch_bounds__(kBlock) void k_chain(ChainArgs a) {
                             k = 0;
                             pr = 0.5f; pg = 0.5f; pb = 0.5f;
                             pa[0] = INFINITY; pa[1] = 0.0f; pa[2] = 0.0f; pa[3] = 0.0f;
-                            float o[3], d[3];
-                            make_ray<MODE>(vw.cam, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, o, d);
-                            trav_init(tv, a.sc, o, d, st);
-                            if (STATS) { dn = 0; dt = 0; }
-                            alive = true;
+                            init = true;
                         }
                     }
                 }
             }
+            if (init) {
+                const ViewDev& vw = a.views[v];
+                float o[3], d[3];
+                make_ray<MODE>(vw.cam, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, o, d);
+                trav_init(tv, a.sc, o, d, st);
+                if (STATS) { dn = 0; dt = 0; }
+                alive = true;
+                pending = false;
+            }
         }
         if (__ballot(alive) == 0ull) {
-            if (drained) break;
+            if (drained && __ballot(pending) == 0ull) break;
             continue;
         }
 
         // ---- one traversal step -------------------------------------------------
-        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, st, dn, dt);
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, st, a.exit_lanes, dn, dt);
 
         // ---- a finished pass: shade, write, then the next pass or the end -------
         if (alive && tv.node == -1) {
@@ -195,9 +211,10 @@ __global__ __launch_bounds__(kBlock) void k_chain(ChainArgs a) {
                     ++k;
                     pr = rgb[0]; pg = rgb[1]; pb = rgb[2];
                     if (AUX) { pa[0] = na[0]; pa[1] = na[1]; pa[2] = na[2]; pa[3] = na[3]; }
-                    float o[3], d[3];
-                    make_ray<MODE>(vw.cam, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, o, d);
-                    trav_init(tv, a.sc, o, d, st);
+                    // the ray is set up in the next setup round, together with
+                    // other lanes (a setup run by a few lanes alone wastes the wave)
+                    alive = false;
+                    pending = true;
                 } else {
                     alive = false;
                 }
@@ -332,6 +349,7 @@ rcp_status render_chain(rcp_scene* s, const Camera& cam, int W, int H, int K, co
     a.n_items = (uint32_t)view_items(view);
     a.fetch = w.counters;
     a.refill_min = lp.refill_min;
+    a.exit_lanes = (uint32_t)lp.exit_lanes;
     a.spill = w.spill;
     a.spill_stride = threads;
     a.stats = stats ? w.stats : nullptr;
@@ -435,6 +453,7 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
         a.n_items = groups[g].items;
         a.fetch = ws.fetch + 16 * g;
         a.refill_min = lp.refill_min;
+        a.exit_lanes = (uint32_t)lp.exit_lanes;
         a.spill = ws.spill;
         a.spill_stride = (uint32_t)gblocks[g] * kBlock;
         launch_chain_mode<false>(groups[g].mode, gblocks[g], gsmem[g], stream, a);

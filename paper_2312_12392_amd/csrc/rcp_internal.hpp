@@ -87,6 +87,7 @@ struct Workspace {
 constexpr size_t kViewBytes = 512;
 
 constexpr int kMaxPasses = 64;
+constexpr int kDefaultExitLanes = 4;
 
 struct Disp {
     float le, ld, z0;
@@ -104,6 +105,7 @@ struct BatchWorkspace {
 
 struct Tuning {
     int refill_min = -1;          // < 0: the library default
+    int exit_lanes = kDefaultExitLanes;
     int blocks_per_cu = 0;        // 0: occupancy limit
     int tile_log2w = 3;           // 8x8 tiles
     int engine = RCP_ENGINE_CHAIN;
@@ -170,6 +172,7 @@ void free_batch_workspace(BatchWorkspace& ws);
 // The launch parameters a render of this scene uses (tuning or defaults).
 struct Launch {
     int refill_min;
+    int exit_lanes;
     int blocks_per_cu;
     int tile_log2w;
 };

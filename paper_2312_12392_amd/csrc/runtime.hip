@@ -86,6 +86,7 @@ rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const 
     RCP_HIP(hipEventCreate(&e1));
     struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
     const std::vector<int> refill = {16, 24, 32, 40, 48, 64};
+    const std::vector<int> exits = {0, 2, 4, 8, 16};
     const std::vector<int> blocks = {0, 4, 3, 2};
     const std::vector<int> tiles = {3, 4, 2, 5};
     const std::vector<int> engines = {RCP_ENGINE_CHAIN, RCP_ENGINE_PASSES};
@@ -96,16 +97,18 @@ rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const 
     rcp_status st = time_render(s, cam, W, H, K, d, out, ids, repeats, stream, e0, e1, cur_ms);
     if (st != RCP_OK) return st;
     for (int round = 0; round < 2; ++round) {
-        for (int param = 0; param < 4; ++param) {
+        for (int param = 0; param < 5; ++param) {
             const std::vector<int>& cands = param == 0   ? refill
-                                            : param == 1 ? blocks
-                                            : param == 2 ? tiles
+                                            : param == 1 ? exits
+                                            : param == 2 ? blocks
+                                            : param == 3 ? tiles
                                                          : engines;
             for (int c : cands) {
                 Tuning t = cur;
                 int& field = param == 0   ? t.refill_min
-                             : param == 1 ? t.blocks_per_cu
-                             : param == 2 ? t.tile_log2w
+                             : param == 1 ? t.exit_lanes
+                             : param == 2 ? t.blocks_per_cu
+                             : param == 3 ? t.tile_log2w
                                           : t.engine;
                 if (field == c) continue;
                 field = c;

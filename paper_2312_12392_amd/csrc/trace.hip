@@ -34,6 +34,7 @@ struct PassArgs {
     float le, ld, z0;
     uint32_t n_items0;              // pass-0 items (8x8 tiles * 64)
     int refill_min;                 // idle lanes that trigger a refill (1..64)
+    uint32_t exit_lanes;            // searching lanes that end a traversal step early
     int tiles_x;
     int tile_log2w;                 // pass-0 tiles of 64 pixels, 2^tile_log2w wide
     const float4* state_in;         // pass > 0: {pix bits, r, g, b}
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
         }
 
         // ---- one traversal step -------------------------------------------
-        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, st, s_nodes, s_tris);
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, st, a.exit_lanes, s_nodes, s_tris);
 
         // ---- finished rays: shade, write, compact ----------------------------
         const bool done = alive && tv.node == -1;
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
         Trav tv;
         trav_init(tv, sc, o, d, st);
         uint32_t dn = 0, dt = 0;
-        while (tv.node != -1) trav_step<false>(tv, sc, st, dn, dt);
+        while (tv.node != -1) trav_step<false>(tv, sc, st, 0u, dn, dt);
         const bool hit = tv.h.id != INT_MAX;
         out_t[r] = hit ? tv.h.t : INFINITY;
         out_id[r] = hit ? tv.h.id : -1;
@@ -373,6 +374,7 @@ int refill_min() {
 Launch launch_params(const rcp_scene* s) {
     Launch l;
     l.refill_min = s->tuning.refill_min > 0 ? s->tuning.refill_min : refill_min();
+    l.exit_lanes = s->tuning.exit_lanes;
     l.blocks_per_cu = s->tuning.blocks_per_cu;
     l.tile_log2w = s->tuning.tile_log2w;
     return l;
@@ -468,6 +470,7 @@ rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Di
     a.le = disp.le; a.ld = disp.ld; a.z0 = disp.z0;
     a.n_items0 = (uint32_t)tiles_x * (uint32_t)tiles_y * 64u;
     a.refill_min = lp.refill_min;
+    a.exit_lanes = (uint32_t)lp.exit_lanes;
     a.tiles_x = tiles_x;
     a.tile_log2w = lp.tile_log2w;
     a.out = out_images;

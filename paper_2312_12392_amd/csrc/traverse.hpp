@@ -321,15 +321,22 @@ __device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, ui
 // "Understanding the Efficiency of Ray Traversal on GPUs", HPG 2009): a lane
 // that reaches a leaf keeps descending while other lanes of the wave are still
 // looking for theirs, and holds the next leaf it meets for the following
-// step, so the wave's leaf tests run together.
+// step, so the wave's leaf tests run together.  The descent ends early, after
+// at least one node per searching lane, once no more than `exit_lanes` lanes
+// are still looking for a leaf: a few deep searches would otherwise keep the
+// rest of the wave idle.  Those lanes resume where they were next step.
 template <bool STATS>
-__device__ inline void trav_step(Trav& tv, const DevScene& sc, Stack& st,
+__device__ inline void trav_step(Trav& tv, const DevScene& sc, Stack& st, uint32_t exit_lanes,
                                  uint32_t& n_nodes, uint32_t& n_tris) {
     int32_t node = tv.node;
     int32_t leaf = -1;
-    for (;;) {
+    for (int it = 0;; ++it) {
         if (node < -1 && leaf == -1) { leaf = node; node = st.pop(); }
-        if (!__any(leaf == -1 && node >= 0)) break;
+        const unsigned long long searching = __ballot(leaf == -1 && node >= 0);
+        if (searching == 0ull) break;
+        // only a few lanes still looking for a leaf: let the others test
+        // theirs (every searching lane has advanced one node this step)
+        if (it > 0 && (uint32_t)__popcll(searching) <= exit_lanes) break;
         if (node >= 0) {
             if (--tv.budget == 0u) { node = -1; leaf = -1; break; }
             node = visit_inner<STATS>(tv, node, sc, st, n_nodes);

@@ -81,7 +81,7 @@ class rcp_view(ctypes.Structure):
 
 
 class rcp_tuning(ctypes.Structure):
-    _fields_ = [("refill_min", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+    _fields_ = [("refill_min", ctypes.c_int32), ("exit_lanes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("tile_log2w", ctypes.c_int32), ("engine", ctypes.c_int32)]
 
     def as_dict(self):
@@ -377,11 +377,14 @@ def rcp_get_tuning(handle: int) -> dict:
 
 
 def rcp_set_tuning(handle: int, refill_min: int, blocks_per_cu: int, tile_log2w: int,
-                   engine: int | None = None) -> None:
-    """engine None keeps the scene's current engine."""
-    if engine is None:
-        engine = rcp_get_tuning(handle)["engine"]
-    t = rcp_tuning(int(refill_min), int(blocks_per_cu), int(tile_log2w), int(engine))
+                   engine: int | None = None, exit_lanes: int | None = None) -> None:
+    """engine / exit_lanes None keep the scene's current values."""
+    if engine is None or exit_lanes is None:
+        cur = rcp_get_tuning(handle)
+        engine = cur["engine"] if engine is None else engine
+        exit_lanes = cur["exit_lanes"] if exit_lanes is None else exit_lanes
+    t = rcp_tuning(refill_min=int(refill_min), exit_lanes=int(exit_lanes), blocks_per_cu=int(blocks_per_cu),
+                   tile_log2w=int(tile_log2w), engine=int(engine))
     _check(load().rcp_set_tuning(handle, ctypes.byref(t)), "rcp_set_tuning")
 
 
@@ -417,7 +420,7 @@ def autotune_cached(handle: int, scene_key: str, cam, W: int, H: int, K: int, di
     if key in cache:
         t = cache[key]["tuning"]
         rcp_set_tuning(handle, t["refill_min"], t["blocks_per_cu"], t["tile_log2w"],
-                       t.get("engine", ENGINE_CHAIN))
+                       t.get("engine", ENGINE_CHAIN), t.get("exit_lanes", 4))
         return t
     t, ms = rcp_autotune(handle, cam, W, H, K, disp, out_images, out_ids, repeats, stream)
     cache[key] = {"tuning": t, "ms": ms}

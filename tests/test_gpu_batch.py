@@ -171,11 +171,12 @@ def test_graph_replays_equal_eager_render(engine):
 
 
 @pytest.mark.parametrize("tuning", [
-    dict(refill_min=1, blocks_per_cu=1, tile_log2w=0, engine=0),
-    dict(refill_min=64, blocks_per_cu=2, tile_log2w=6, engine=0),
-    dict(refill_min=17, blocks_per_cu=0, tile_log2w=4, engine=1),
-    dict(refill_min=40, blocks_per_cu=3, tile_log2w=2, engine=1),
-    dict(refill_min=1, blocks_per_cu=1, tile_log2w=0, engine=1),
+    dict(refill_min=1, blocks_per_cu=1, tile_log2w=0, engine=0, exit_lanes=0),
+    dict(refill_min=64, blocks_per_cu=2, tile_log2w=6, engine=0, exit_lanes=64),
+    dict(refill_min=17, blocks_per_cu=0, tile_log2w=4, engine=1, exit_lanes=3),
+    dict(refill_min=40, blocks_per_cu=3, tile_log2w=2, engine=1, exit_lanes=64),
+    dict(refill_min=1, blocks_per_cu=1, tile_log2w=0, engine=1, exit_lanes=1),
+    dict(refill_min=64, blocks_per_cu=0, tile_log2w=3, engine=0, exit_lanes=1),
 ])
 def test_tuning_does_not_change_images(tuning):
     say("tuning", tuning)
