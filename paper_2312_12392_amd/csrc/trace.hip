@@ -361,19 +361,9 @@ rcp_status persistent_grid(KernelT kernel, const DevScene& sc, GridInfo& g, bool
 
 }  // namespace
 
-// Idle lanes that make a wave fetch new work (RCP_REFILL_MIN, default 40).
-int refill_min() {
-    static int v = [] {
-        const char* e = getenv("RCP_REFILL_MIN");
-        int x = e ? atoi(e) : 40;
-        return x < 1 ? 1 : (x > 64 ? 64 : x);
-    }();
-    return v;
-}
-
 Launch launch_params(const rcp_scene* s) {
     Launch l;
-    l.refill_min = s->tuning.refill_min > 0 ? s->tuning.refill_min : refill_min();
+    l.refill_min = s->tuning.refill_min > 0 ? s->tuning.refill_min : kDefaultRefill;
     l.exit_lanes = s->tuning.exit_lanes;
     l.blocks_per_cu = s->tuning.blocks_per_cu;
     l.tile_log2w = s->tuning.tile_log2w;
