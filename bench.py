@@ -50,7 +50,7 @@ def algorithmic_bytes(counts, engine="chain"):
 
     Per pass k (counts[k] = rays traced, inner nodes visited, triangles
     tested, rays continued to pass k + 1), both engines:
-      64 B per inner node visited (both child boxes + links)
+      112 B per 4-wide node visited (four child boxes + four links)
       48 B per triangle tested (three vertices + index)
       16 B per traced ray: the shaded colour looked up (hit or miss constant)
       12 B + 4 B per traced ray: image k and its hit ID written
@@ -64,7 +64,7 @@ def algorithmic_bytes(counts, engine="chain"):
     total = 0.0
     for k in range(K):
         rays, nodes, tris, app = (float(x) for x in counts[k])
-        total += 64 * nodes + 48 * tris + (16 + 12 + 4) * rays
+        total += 112 * nodes + 48 * tris + (16 + 12 + 4) * rays
         if engine == "passes":
             total += 16 * app + (16 * rays if k > 0 else 0.0)
         converged = rays - app if k + 1 < K else 0.0
@@ -103,7 +103,6 @@ def main():
                     help="chain: one persistent launch per frame; passes: one launch per pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-leaf", type=int, default=None, help="BVH leaf size bound (build option)")
-    ap.add_argument("--top-levels", type=int, default=None, help="BVH levels laid out breadth-first (build option)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -132,9 +131,8 @@ def bench_frame(args):
     w = scenegen.workload(args.workload, literal_eye=args.literal_eye)
     log(f"workload {w.name}: {w.width}x{w.height} K={w.passes} tris={w.scene.n_tris}")
     opts = None
-    if args.max_leaf is not None or args.top_levels is not None:
-        opts = rcp.build_options(max_leaf=args.max_leaf or 4,
-                                 top_levels=6 if args.top_levels is None else args.top_levels)
+    if args.max_leaf is not None:
+        opts = rcp.build_options(max_leaf=args.max_leaf)
     scene = rcp.Scene(w.scene, opts)
     scene.set_engine(rcp.RCP_ENGINE_CHAIN if args.engine == "chain" else rcp.RCP_ENGINE_PASSES)
     kernel = KERNEL_OF_ENGINE[args.engine]

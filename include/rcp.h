@@ -116,13 +116,11 @@ typedef struct {
 #define RCP_MODE_NORMAL 2
 
 /* Build options (NULL = defaults).  max_leaf: most triangles per BVH leaf
- * (1..8, default 4); top_levels: BVH levels laid out breadth-first at the
- * start of the node array, the rest depth-first (0..9, default 6; memory
- * layout only); c_trav, c_isect: SAH costs of a node visit and a triangle
- * test (defaults 1, 1). */
+ * (1..8, default 4); c_trav, c_isect: SAH costs of a node visit and a
+ * triangle test (defaults 1, 1), used when leaves are formed in the binary
+ * tree that the 4-wide traversal tree is collapsed from. */
 typedef struct {
     int32_t max_leaf;
-    int32_t top_levels;
     float c_trav;
     float c_isect;
 } rcp_build_options;
@@ -130,14 +128,15 @@ typedef struct {
 /* Scene statistics filled by rcp_scene_info. */
 typedef struct {
     uint32_t n_tris;
-    uint32_t n_nodes;        /* packed BVH2 nodes (64 B each) */
-    uint32_t n_leaves;
-    uint32_t top_count;      /* nodes of the breadth-first top block */
-    uint32_t max_depth;      /* deepest node (root = 0) */
+    uint32_t n_nodes;        /* 4-wide BVH nodes (node_bytes each) */
+    uint32_t n_leaves;       /* leaf links in the tree */
+    uint32_t max_depth;      /* levels of the tree including the leaves */
     uint32_t max_leaf;
-    float sah_cost;          /* SAH cost of the packed tree, relative to the root box */
+    float sah_cost;          /* SAH cost of the binary tree before the collapse,
+                                relative to the root box */
     float build_ms;          /* device time of the build kernels */
     uint64_t device_bytes;   /* HBM held by the scene */
+    uint32_t node_bytes;     /* bytes per packed BVH node (rcp_export_bvh) */
 } rcp_scene_stats;
 
 /* ---------------------------------------------------------------------- */
@@ -380,15 +379,18 @@ rcp_status rcp_generate_rays(const rcp_camera* base_camera, int W, int H,
 rcp_status rcp_trace_rays(rcp_scene* scene, const float* org, const float* dir, int n,
                           float* out_t, int32_t* out_id, int32_t* out_front, void* hip_stream);
 
-/* Copy the packed BVH to HOST memory for inspection.
- *   nodes    [n_nodes][16] 32-bit words per node (64 B), node 0 = root:
- *            words 0-3   float child0 lo.x, hi.x, lo.y, hi.y
- *            words 4-7   float child1 lo.x, hi.x, lo.y, hi.y
- *            words 8-11  float child0 lo.z, hi.z, child1 lo.z, hi.z
- *            words 12-13 child links; 14-15 zero.
+/* Copy the packed 4-wide BVH to HOST memory for inspection.
+ *   nodes    [n_nodes][32] 32-bit words per node (node_bytes = 128 B),
+ *            node 0 = root, nodes in level order:
+ *            words 0-3 / 4-7     float lo.x / hi.x of children 0..3
+ *            words 8-11 / 12-15  float lo.y / hi.y
+ *            words 16-19 / 20-23 float lo.z / hi.z
+ *            words 24-27         child links; 28-31 zero.
  *            A link with bit 31 clear is an inner node index; with bit 31
  *            set it is a leaf: bits 3..30 = first packed triangle,
- *            bits 0..2 = triangle count - 1.
+ *            bits 0..2 = triangle count - 1; 0x7FFFFFFF marks an unused
+ *            child slot (its planes are NaN).  Boxes are slightly wider
+ *            than their contents (the traversal's conservative pruning).
  *   tri_ids  [n_tris] original triangle index of each packed slot.
  * Either pointer may be NULL.  Synchronous. */
 rcp_status rcp_export_bvh(const rcp_scene* scene, uint32_t* nodes, int32_t* tri_ids);

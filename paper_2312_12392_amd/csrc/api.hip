@@ -136,8 +136,6 @@ rcp_status rcp_build_scene(const rcp_scene_desc* desc, const rcp_build_options* 
     }
     if (opts) {
         if (opts->max_leaf < 1 || opts->max_leaf > kMaxLeaf) FAIL("max_leaf must be in [1, %d]", kMaxLeaf);
-        if (opts->top_levels < 0 || opts->top_levels > kMaxTopLevels)
-            FAIL("top_levels must be in [0, %d]", kMaxTopLevels);
         if (!(opts->c_trav > 0.0f) || !(opts->c_isect > 0.0f) || !std::isfinite(opts->c_trav) ||
             !std::isfinite(opts->c_isect))
             FAIL("SAH costs must be finite and > 0");
@@ -468,7 +466,7 @@ rcp_status rcp_export_bvh(const rcp_scene* s, uint32_t* nodes, int32_t* tri_ids)
     clear_error();
     if (!s) FAIL("scene is NULL");
     if (nodes && s->dev.n_nodes) {
-        hipError_t e = hipMemcpy(nodes, s->nodes, 64 * (size_t)s->dev.n_nodes, hipMemcpyDeviceToHost);
+        hipError_t e = hipMemcpy(nodes, s->nodes, kNodeBytes * (size_t)s->dev.n_nodes, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_status(e, "export nodes", __FILE__, __LINE__);
     }
     if (tri_ids && s->dev.n_tris) {

@@ -11,11 +11,11 @@
 //   5. bottom-up refit with per-node arrival counters; each node also gets its
 //      SAH cost and is collapsed into a leaf (<= max_leaf triangles) when that
 //      is cheaper than keeping the split
-//   6. layout: the top levels in breadth-first order (the nodes every ray
-//      visits first, packed together), then every remaining subtree in
-//      depth-first order
-//   7. packing into 64-byte BVH2 nodes, 48-byte triangles and a per-triangle
-//      table of the two shaded colours.
+//   6. packing of the binary tree into 64-byte nodes in depth-first order
+//   7. collapse into 128-byte 4-wide nodes, level by level: the tree the
+//      traversal uses
+//   8. packing of 48-byte triangles, a per-triangle table of the two shaded
+//      colours and the unit normals.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -239,8 +239,6 @@ __global__ __launch_bounds__(kB) void k_refit(int n, const int32_t* __restrict__
 struct Summary {
     int32_t root_collapsed;
     int32_t n_inner;
-    int32_t top_count;
-    int32_t max_depth;
     float root_cost;
     float root_area;
     float bbox[6];
@@ -249,8 +247,6 @@ struct Summary {
 __global__ void k_summary_root(NodeData nd, Summary* sm) {
     sm->root_collapsed = nd.collapse[0];
     sm->n_inner = nd.n_inner[0];
-    sm->top_count = 0;
-    sm->max_depth = 0;
     sm->root_cost = nd.cost[0];
     float4 a = nd.lo[0], b = nd.hi[0];
     sm->root_area = half_area(make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z));
@@ -258,91 +254,26 @@ __global__ void k_summary_root(NodeData nd, Summary* sm) {
     sm->bbox[3] = b.x; sm->bbox[4] = b.y; sm->bbox[5] = b.z;
 }
 
-// Depth-first index (among emitted inner nodes) and depth of each inner node,
-// by walking up to the root.  Nodes inside a collapsed subtree get -1.
+// Depth-first rank (among emitted inner nodes) of each inner node, by walking
+// up to the root: the binary nodes are packed in depth-first order.  Nodes
+// inside a collapsed subtree get -1.
 __global__ __launch_bounds__(kB) void k_layout_walk(int n, const int32_t* __restrict__ left,
                                                      const int32_t* __restrict__ parent, NodeData nd,
-                                                     int top_levels, int32_t* __restrict__ dfs,
-                                                     int32_t* __restrict__ depth, int32_t* __restrict__ newidx,
-                                                     uint64_t* __restrict__ top_keys, Summary* sm) {
+                                                     int32_t* __restrict__ newidx) {
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= n - 1) return;
     newidx[i] = -1;
     if (nd.collapse[i]) return;
-    int x = i, idx = 0, dep = 0;
+    int x = i, idx = 0;
     while (x != 0) {
         const int p = parent[x];
         if (nd.collapse[p]) return;
         const int32_t lp = left[p];
         idx += 1;
         if (lp != x && lp >= 0) idx += nd.n_inner[lp];
-        ++dep;
         x = p;
     }
-    dfs[i] = idx;
-    depth[i] = dep;
-    atomicMax(&sm->max_depth, dep);
-    if (dep < top_levels) {
-        int slot = atomicAdd(&sm->top_count, 1);
-        top_keys[slot] = ((uint64_t)dep << 32) | (uint32_t)idx;
-    }
-}
-
-// One block: breadth-first ranks of the top nodes (sorted by depth, then
-// depth-first index), and their depth-first indices in ascending order.
-__global__ __launch_bounds__(512) void k_top_order(const uint64_t* __restrict__ top_keys, const Summary* sm,
-                                                    uint32_t* __restrict__ top_dfs_sorted,
-                                                    uint32_t* __restrict__ top_dfs_bfs) {
-    __shared__ uint64_t a[512];
-    const int m = sm->top_count;
-    const int t = threadIdx.x;
-    a[t] = t < m ? top_keys[t] : ~0ull;
-    __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int k = 2; k <= 512; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                const int p = t ^ j;
-                if (p > t) {
-                    const bool up = (t & k) == 0;
-                    uint64_t x = a[t], y = a[p];
-                    if ((x > y) == up) { a[t] = y; a[p] = x; }
-                }
-                __syncthreads();
-            }
-        }
-        if (pass == 0) {
-            if (t < m) top_dfs_bfs[t] = (uint32_t)a[t];        // BFS rank -> dfs index
-            __syncthreads();
-            a[t] = t < m ? (uint64_t)(uint32_t)a[t] : ~0ull;
-            __syncthreads();
-        } else if (t < m) {
-            top_dfs_sorted[t] = (uint32_t)a[t];
-        }
-    }
-}
-
-__global__ __launch_bounds__(kB) void k_layout_final(int n, const int32_t* __restrict__ dfs,
-                                                      const int32_t* __restrict__ depth, int top_levels,
-                                                      const uint32_t* __restrict__ top_dfs_sorted,
-                                                      const uint32_t* __restrict__ top_dfs_bfs,
-                                                      const Summary* sm, int32_t* __restrict__ newidx) {
-    const int i = blockIdx.x * kB + threadIdx.x;
-    if (i >= n - 1 || dfs[i] < 0) return;     // inside or at a collapsed subtree
-    const int m = sm->top_count;
-    const uint32_t d = (uint32_t)dfs[i];
-    // number of top nodes with a smaller depth-first index
-    int lo = 0, hi = m;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (top_dfs_sorted[mid] < d) lo = mid + 1; else hi = mid;
-    }
-    if (depth[i] < top_levels) {
-        // breadth-first rank: position of d in top_dfs_bfs (linear scan, m <= 511)
-        for (int r = 0; r < m; ++r)
-            if (top_dfs_bfs[r] == d) { newidx[i] = r; return; }
-    } else {
-        newidx[i] = m + (int)d - lo;
-    }
+    newidx[i] = idx;
 }
 
 __device__ inline float pad_lo(float v) { return v - (fabsf(v) * 4.8e-7f + 1e-30f); }
@@ -401,6 +332,92 @@ __global__ void k_pack_single(int n, const float4* __restrict__ tlo, const float
     nodes[1] = nodes[0];
     nodes[2] = make_float4(pad_lo(lo.z), pad_hi(hi.z), pad_lo(lo.z), pad_hi(hi.z));
     nodes[3] = make_float4(__uint_as_float(link), __uint_as_float(link), 0.0f, 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// 4-wide nodes from the packed binary tree.  A wide node starts from one
+// binary node's two children and repeatedly replaces the inner child with the
+// largest box surface area by its two children, until it has four children
+// or only leaves.  Boxes are copied from the binary nodes (already widened),
+// so the wide tree prunes exactly as conservatively.  Built level by level:
+// the nodes of one level are slots [begin, end), each records the binary
+// node it expands in src[], and its inner children get slots of the next
+// level from one counter.
+// ---------------------------------------------------------------------------
+struct WideCand {
+    float lo[3], hi[3];
+    uint32_t link;
+    float area;
+};
+
+__device__ inline float half_area(const WideCand& c) {
+    const float dx = c.hi[0] - c.lo[0], dy = c.hi[1] - c.lo[1], dz = c.hi[2] - c.lo[2];
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__device__ inline void wide_children(const float4* __restrict__ n2, uint32_t node, WideCand& a, WideCand& b) {
+    const float4* p = n2 + 4 * (size_t)node;
+    const float4 c0 = p[0], c1 = p[1], z = p[2], l = p[3];
+    a.lo[0] = c0.x; a.hi[0] = c0.y; a.lo[1] = c0.z; a.hi[1] = c0.w; a.lo[2] = z.x; a.hi[2] = z.y;
+    b.lo[0] = c1.x; b.hi[0] = c1.y; b.lo[1] = c1.z; b.hi[1] = c1.w; b.lo[2] = z.z; b.hi[2] = z.w;
+    a.link = __float_as_uint(l.x);
+    b.link = __float_as_uint(l.y);
+    a.area = half_area(a);
+    b.area = half_area(b);
+}
+
+__global__ __launch_bounds__(kB) void k_collapse4(const float4* __restrict__ n2, uint32_t begin, uint32_t end,
+                                                   uint32_t* __restrict__ src, uint32_t* __restrict__ counter,
+                                                   float4* __restrict__ n4) {
+    const uint32_t slot = begin + blockIdx.x * kB + threadIdx.x;
+    if (slot >= end) return;
+    WideCand c[4];
+    int m = 2;
+    wide_children(n2, src[slot], c[0], c[1]);
+    while (m < 4) {
+        int best = -1;
+        float best_area = -1.0f;
+        for (int i = 0; i < m; ++i)
+            if (!(c[i].link & kLeafBit) && c[i].area > best_area) { best = i; best_area = c[i].area; }
+        if (best < 0) break;
+        WideCand a, b;
+        wide_children(n2, c[best].link, a, b);
+        c[best] = a;
+        c[m++] = b;
+    }
+    int n_inner = 0;
+    for (int i = 0; i < m; ++i) n_inner += (c[i].link & kLeafBit) ? 0 : 1;
+    const uint32_t base = n_inner ? atomicAdd(counter, (uint32_t)n_inner) : 0u;
+    float lo[3][4], hi[3][4];
+    uint32_t link[4];
+    int k = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (i < m) {
+            for (int a = 0; a < 3; ++a) { lo[a][i] = c[i].lo[a]; hi[a][i] = c[i].hi[a]; }
+            if (c[i].link & kLeafBit) {
+                link[i] = c[i].link;
+            } else {
+                link[i] = base + (uint32_t)k;
+                src[base + (uint32_t)k] = c[i].link;
+                ++k;
+            }
+        } else {   // empty slot: NaN planes fail every box test (and the empty link)
+            for (int a = 0; a < 3; ++a) { lo[a][i] = __int_as_float(0x7FC00000); hi[a][i] = lo[a][i]; }
+            link[i] = (uint32_t)kEmptyLink;
+        }
+    }
+    float4* o = n4 + 8 * (size_t)slot;
+    for (int a = 0; a < 3; ++a) {
+        o[2 * a] = make_float4(lo[a][0], lo[a][1], lo[a][2], lo[a][3]);
+        o[2 * a + 1] = make_float4(hi[a][0], hi[a][1], hi[a][2], hi[a][3]);
+    }
+    o[6] = make_float4(__uint_as_float(link[0]), __uint_as_float(link[1]), __uint_as_float(link[2]),
+                       __uint_as_float(link[3]));
+    o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) {
+    if (threadIdx.x == 0) *p = v;
 }
 
 __device__ inline float clamp01(float v) {
@@ -487,7 +504,6 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                        rcp_scene** out) {
     const uint32_t n = desc->n_tris;
     const int max_leaf = opts ? opts->max_leaf : 4;
-    const int top_levels = opts ? opts->top_levels : 6;
     const float c_trav = opts ? opts->c_trav : 1.0f;
     const float c_isect = opts ? opts->c_isect : 1.0f;
 
@@ -534,7 +550,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     }
     RCP_HIP(hipEventRecord(e0, stream));
 
-    uint32_t n_nodes = 0, top_count = 0, max_depth = 0;
+    uint32_t n_nodes = 0, n_leaves = 0, max_depth = 0, stack_bound = 0;
     float sah = 0.0f;
     uint32_t* sorted = nullptr;
     float4 *tlo = nullptr, *thi = nullptr;
@@ -597,28 +613,12 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                                (const float4*)thi, s->nodes);
             RCP_CHECK_LAUNCH();
             sah = 1.0f;   // filled below for the single-leaf case
-            top_count = top_levels > 0 ? 1 : 0;
-            max_depth = 1;
         } else {
             const long ni = (long)n - 1;
-            int32_t *dfs, *depth, *newidx;
-            uint64_t* top_keys;
-            uint32_t *top_sorted, *top_bfs;
-            RCP_TRY(tmp.alloc(&dfs, ni));
-            RCP_TRY(tmp.alloc(&depth, ni));
+            int32_t* newidx;
             RCP_TRY(tmp.alloc(&newidx, ni));
-            RCP_TRY(tmp.alloc(&top_keys, 512));
-            RCP_TRY(tmp.alloc(&top_sorted, 512));
-            RCP_TRY(tmp.alloc(&top_bfs, 512));
-            RCP_HIP(hipMemsetAsync(dfs, 0xFF, sizeof(int32_t) * ni, stream));
-            RCP_HIP(hipMemsetAsync(depth, 0xFF, sizeof(int32_t) * ni, stream));
             hipLaunchKernelGGL(k_layout_walk, dim3(blocks(ni)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
-                               (const int32_t*)parent, nd, top_levels, dfs, depth, newidx, top_keys, sm);
-            hipLaunchKernelGGL(k_top_order, dim3(1), dim3(512), 0, stream, (const uint64_t*)top_keys,
-                               (const Summary*)sm, top_sorted, top_bfs);
-            hipLaunchKernelGGL(k_layout_final, dim3(blocks(ni)), dim3(kB), 0, stream, (int)n,
-                               (const int32_t*)dfs, (const int32_t*)depth, top_levels,
-                               (const uint32_t*)top_sorted, (const uint32_t*)top_bfs, (const Summary*)sm, newidx);
+                               (const int32_t*)parent, nd, newidx);
             RCP_CHECK_LAUNCH();
             n_nodes = (uint32_t)hs.n_inner;
             RCP_TRY(dalloc(&s->nodes, 4 * (size_t)n_nodes));
@@ -627,12 +627,41 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                                (const float4*)tlo, (const float4*)thi, (const uint32_t*)sorted, nd,
                                (const int32_t*)newidx, s->nodes);
             RCP_CHECK_LAUNCH();
-            Summary hs2{};
-            RCP_HIP(hipMemcpyAsync(&hs2, sm, sizeof(Summary), hipMemcpyDeviceToHost, stream));
-            RCP_HIP(hipStreamSynchronize(stream));
-            top_count = (uint32_t)hs2.top_count;
-            max_depth = (uint32_t)hs2.max_depth + 1;   // leaves sit one level below the deepest inner node
             sah = hs.root_area > 0.0f ? hs.root_cost / hs.root_area : 0.0f;
+        }
+        n_leaves = n_nodes + 1;
+        {
+            // collapse into 4-wide nodes, one launch per level; the binary
+            // nodes are freed with the other temporaries
+            float4* n2 = s->nodes;
+            tmp.ptrs.push_back((void*)n2);
+            s->nodes = nullptr;
+            uint32_t *src, *counter;
+            RCP_TRY(tmp.alloc(&src, n_nodes));
+            RCP_TRY(tmp.alloc(&counter, 1));
+            RCP_TRY(dalloc(&s->nodes, 8 * (size_t)n_nodes));
+            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, stream, src, 0u);
+            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, stream, counter, 1u);
+            RCP_CHECK_LAUNCH();
+            uint32_t begin = 0, end = 1, levels = 0;
+            while (begin < end) {
+                hipLaunchKernelGGL(k_collapse4, dim3(blocks(end - begin)), dim3(kB), 0, stream, (const float4*)n2,
+                                   begin, end, src, counter, s->nodes);
+                RCP_CHECK_LAUNCH();
+                uint32_t next = 0;
+                RCP_HIP(hipMemcpyAsync(&next, counter, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+                RCP_HIP(hipStreamSynchronize(stream));
+                if (next > n_nodes || next < end) {
+                    set_error("wide BVH collapse produced %u nodes from %u binary nodes", next, n_nodes);
+                    return RCP_ERR_INTERNAL;
+                }
+                begin = end;
+                end = next;
+                ++levels;
+            }
+            n_nodes = end;
+            max_depth = levels + 1;          // leaves sit one level below the deepest wide node
+            stack_bound = 3u * levels + 1u;  // at most three pushes per level
         }
         RCP_TRY(dalloc(&s->tris, 3 * (size_t)n));
         RCP_TRY(dalloc(&s->shade, 2 * (size_t)n));
@@ -661,15 +690,15 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     s->dev.radius = radius;
     s->dev.n_nodes = n_nodes;
     s->dev.n_tris = n;
-    s->dev.top_count = top_count;
     s->dev.max_depth = max_depth;
+    s->dev.stack_bound = stack_bound;
     s->stats.n_nodes = n_nodes;
-    s->stats.n_leaves = n_nodes ? n_nodes + 1 : 0;
-    s->stats.top_count = top_count;
+    s->stats.n_leaves = n_leaves;
     s->stats.max_depth = max_depth;
     s->stats.sah_cost = sah;
     s->stats.build_ms = ms;
-    s->stats.device_bytes = 64ull * n_nodes + 48ull * n + 32ull * n + 16ull * n;
+    s->stats.node_bytes = (uint32_t)kNodeBytes;
+    s->stats.device_bytes = (uint64_t)kNodeBytes * n_nodes + 48ull * n + 32ull * n + 16ull * n;
     guard.ok = true;
     *out = s;
     return RCP_OK;

@@ -59,7 +59,7 @@ __device__ inline void tile_pixel(const ViewDev& vw, uint32_t local, int& x, int
 }
 
 template <bool STATS, int MODE>
-__global__ __launch_bounds__(kBlock) void k_chain(ChainArgs a) {
+__device__ inline void chain_body(const ChainArgs& a) {
     constexpr bool AUX = MODE != RCP_MODE_COLOR;
     extern __shared__ float4 smem[];
     char* lds = (char*)smem;
@@ -229,6 +229,19 @@ __global__ __launch_bounds__(kBlock) void k_chain(ChainArgs a) {
     }
 }
 
+// Colour mode, the default: asking for 6 waves per SIMD (at most 80 VGPRs,
+// a few bytes of spill) was measured faster than the 5 its 82 registers
+// allow.  The depth and normal modes keep the compiler's choice.
+template <bool STATS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_chain(ChainArgs a) {
+    chain_body<STATS, RCP_MODE_COLOR>(a);
+}
+
+template <bool STATS, int MODE>
+__global__ __launch_bounds__(kBlock) void k_chain_aux(ChainArgs a) {
+    chain_body<STATS, MODE>(a);
+}
+
 // Zero the work counters (one per launch, 16 words apart) and the stats.
 __global__ void k_clear_chain(uint32_t* fetch, int n, unsigned long long* stats) {
     for (int i = threadIdx.x; i < 16 * n; i += blockDim.x) fetch[i] = 0u;
@@ -257,10 +270,16 @@ size_t chain_smem(const Launch& lp, bool stats, int n_views) {
 }
 
 template <bool STATS, int MODE>
+const void* chain_kernel() {
+    if constexpr (MODE == RCP_MODE_COLOR) return (const void*)k_chain<STATS>;
+    else return (const void*)k_chain_aux<STATS, MODE>;
+}
+
+template <bool STATS, int MODE>
 rcp_status chain_grid(const Launch& lp, int n_views, int& blocks, size_t& smem) {
     smem = chain_smem(lp, STATS, n_views);
     int per_cu = 0, dev = 0, cus = 0;
-    RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_chain<STATS, MODE>, kBlock, smem));
+    RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chain_kernel<STATS, MODE>(), kBlock, smem));
     RCP_HIP(hipGetDevice(&dev));
     RCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     if (per_cu < 1) per_cu = 1;
@@ -282,19 +301,19 @@ template <bool STATS>
 void launch_chain_mode(int mode, int blocks, size_t smem, hipStream_t stream, const ChainArgs& a) {
     switch (mode) {
         case RCP_MODE_DEPTH:
-            hipLaunchKernelGGL((k_chain<STATS, RCP_MODE_DEPTH>), dim3(blocks), dim3(kBlock), smem, stream, a);
+            hipLaunchKernelGGL((k_chain_aux<STATS, RCP_MODE_DEPTH>), dim3(blocks), dim3(kBlock), smem, stream, a);
             break;
         case RCP_MODE_NORMAL:
-            hipLaunchKernelGGL((k_chain<STATS, RCP_MODE_NORMAL>), dim3(blocks), dim3(kBlock), smem, stream, a);
+            hipLaunchKernelGGL((k_chain_aux<STATS, RCP_MODE_NORMAL>), dim3(blocks), dim3(kBlock), smem, stream, a);
             break;
         default:
-            hipLaunchKernelGGL((k_chain<STATS, RCP_MODE_COLOR>), dim3(blocks), dim3(kBlock), smem, stream, a);
+            hipLaunchKernelGGL((k_chain<STATS>), dim3(blocks), dim3(kBlock), smem, stream, a);
             break;
     }
 }
 
 size_t spill_depth_of(const rcp_scene* s) {
-    return s->dev.max_depth > (uint32_t)kStack ? s->dev.max_depth - kStack + 1 : 1;
+    return spill_per_thread(s->dev);
 }
 
 ViewDev view_of(const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids, int tile_log2w) {

@@ -1,12 +1,13 @@
 // Internal declarations of the recursive camera-painting library (gfx950).
 //
 // Data in HBM for a built scene (all arrays in the BVH's leaf order):
-//   nodes  float4[n_nodes][4]   BVH2 node, 64 B: both children's boxes + links
+//   nodes  float4[n_nodes][8]   4-wide BVH node, 128 B: lo.x, hi.x, lo.y, hi.y,
+//                               lo.z, hi.z of children 0..3, their links, zero
 //   tris   float4[n_tris][3]    v0.xyz + original index bits in w, v1, v2
 //   shade  float4[n_tris][2]    shaded RGB seen from the front / back side
 //   normal float4[n_tris]       unit geometric normal (read by the normal mapping)
-// The first top_count nodes are the BVH's top levels in breadth-first order;
-// the rest follow in depth-first order.
+// Nodes are in level order from the root; the inner children of a node sit in
+// consecutive slots.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,12 +25,11 @@
 namespace rcp {
 
 // ---- link encoding of BVH children ---------------------------------------
+constexpr size_t kNodeBytes = 128;           // one 4-wide BVH node
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr int kMaxLeaf = 8;                // 3 bits of count
 constexpr uint32_t kMaxTris = 1u << 28;    // 28 bits of first triangle
-constexpr int kMaxTopLevels = 9;
-constexpr int kMaxTopNodes = (1 << kMaxTopLevels) - 1;
-constexpr int32_t kSentinel = 0x7FFFFFFF;  // "stack empty" / traversal done
+constexpr uint32_t kEmptyLink = 0x7FFFFFFFu; // unused child slot of a 4-wide node
 
 __host__ __device__ inline uint32_t leaf_link(uint32_t first, uint32_t count) {
     return kLeafBit | (first << 3) | (count - 1u);
@@ -60,8 +60,8 @@ struct DevScene {
     const float4* normals;
     uint32_t n_nodes;
     uint32_t n_tris;
-    uint32_t top_count;
     uint32_t max_depth;
+    uint32_t stack_bound;   // most entries a traversal stack can hold
     float radius;      // largest |coordinate| of any vertex
     float bg[3];
 };

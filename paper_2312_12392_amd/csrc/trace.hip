@@ -385,7 +385,7 @@ rcp_status launch_passes(rcp_scene* s, PassArgs& a, int K, hipStream_t stream) {
     if (st != RCP_OK) return st;
     const uint32_t threads = (uint32_t)g.blocks * kBlock;
     const size_t P = (size_t)a.W * (size_t)a.H;
-    const size_t spill_depth = s->dev.max_depth > (uint32_t)kStack ? s->dev.max_depth - kStack + 1 : 1;
+    const size_t spill_depth = spill_per_thread(s->dev);
     st = ensure_workspace(s, K > 1 ? P : 1, (K > 1 && AUX) ? P : 0, spill_depth * threads);
     if (st != RCP_OK) return st;
     Workspace& w = s->ws;
@@ -428,7 +428,7 @@ rcp_status prepare_mode(rcp_scene* s, int W, int H, int K) {
     if (st != RCP_OK) return st;
     const uint32_t threads = (uint32_t)(g1.blocks > g2.blocks ? g1.blocks : g2.blocks) * kBlock;
     const size_t P = (size_t)W * (size_t)H;
-    const size_t spill_depth = s->dev.max_depth > (uint32_t)kStack ? s->dev.max_depth - kStack + 1 : 1;
+    const size_t spill_depth = spill_per_thread(s->dev);
     return ensure_workspace(s, K > 1 ? P : 1, (K > 1 && MODE != RCP_MODE_COLOR) ? P : 0, spill_depth * threads);
 }
 }  // namespace
@@ -507,7 +507,7 @@ rcp_status trace_rays(rcp_scene* s, const float* org, const float* dir, int n, f
     rcp_status st = persistent_grid(k_trace_rays, s->dev, g, false, 0);
     if (st != RCP_OK) return st;
     const uint32_t threads = (uint32_t)g.blocks * kBlock;
-    const size_t spill_depth = s->dev.max_depth > (uint32_t)kStack ? s->dev.max_depth - kStack + 1 : 1;
+    const size_t spill_depth = spill_per_thread(s->dev);
     st = ensure_workspace(s, 1, 0, spill_depth * threads);
     if (st != RCP_OK) return st;
     hipLaunchKernelGGL(k_trace_rays, dim3(g.blocks), dim3(kBlock), g.smem, stream, s->dev, org, dir, n, out_t,

@@ -17,11 +17,14 @@ namespace rcp {
 namespace {
 
 constexpr int kBlock = 256;
-#ifndef RCP_STACK
-#define RCP_STACK 8
-#endif
-constexpr int kStack = RCP_STACK;                // per-lane LDS stack entries (power of two not required)
+constexpr int kStack = 16;                       // per-lane LDS stack entries (a power of two)
 constexpr float kSlack = 1.0f + 1.0f / 65536.0f; // widening of box intervals
+
+// Global overflow entries per thread: the LDS ring holds kStack entries, and
+// a 4-wide visit keeps room for three pushes in it.
+inline size_t spill_per_thread(const DevScene& d) {
+    return d.stack_bound + 3u > (uint32_t)kStack ? d.stack_bound + 3u - (uint32_t)kStack : 1u;
+}
 
 
 __device__ inline float sel3(float x, float y, float z, int k) {
@@ -170,13 +173,17 @@ struct Stack {
     __device__ inline LdsI32* ring(uint32_t e) const {
         return (LdsI32*)lds + (e & (uint32_t)(kStack - 1)) * kBlock;
     }
-    __device__ inline void push(int32_t v) {
-        if (sp - lo == (uint32_t)kStack) {
+    // Push np (0..3) entries, e0 deepest, with one check for room: three ring
+    // slots are written whatever np is (those above the new top are unused).
+    __device__ inline void push_up_to_3(int32_t e0, int32_t e1, int32_t e2, uint32_t np) {
+        while (sp + 3u - lo > (uint32_t)kStack) {
             spill[(size_t)lo * stride] = *ring(lo);
             ++lo;
         }
-        *ring(sp) = v;
-        ++sp;
+        *ring(sp) = e0;
+        *ring(sp + 1u) = e1;
+        *ring(sp + 2u) = e2;
+        sp += np;
     }
     __device__ inline int32_t pop() {
         if (sp == 0u) return -1;
@@ -240,55 +247,65 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
     st.lo = 0;
 }
 
-// Visit one inner node: test both child boxes, continue with the nearer hit
-// child, push the farther one, or pop when neither is hit.
+__device__ inline float lane_of(const float4& v, int i) {
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+__device__ inline void order2(uint32_t& ka, int32_t& va, uint32_t& kb, int32_t& vb) {
+    const bool s = kb < ka;
+    const uint32_t k0 = s ? kb : ka, k1 = s ? ka : kb;
+    const int32_t v0 = s ? vb : va, v1 = s ? va : vb;
+    ka = k0; kb = k1; va = v0; vb = v1;
+}
+
+// Visit one 4-wide node: test the four child boxes (same conservative rules
+// as above), continue with the nearest hit child and push the other hit
+// children farthest first, or pop when none is hit.  Node layout (8 float4):
+// lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of children 0..3, then their links.
 template <bool STATS>
-__device__ inline int32_t visit_inner(Trav& tv, int32_t node, const DevScene& sc, Stack& st, uint32_t& n_nodes) {
-    const int kz = tv.rw.kz;
-    float4 n0, n1, n2, n3;
-    // Every node comes from global memory (L2 / Infinity Cache); staging the
-    // top levels in LDS was measured to gain nothing on gfx950.
-    {
-        const float4* p = sc.nodes + 4 * (size_t)node;
-        n0 = p[0];
-        n1 = p[1];
-        n2 = p[2];
-        n3 = p[3];
-    }
+__device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& sc, Stack& st, uint32_t& n_nodes) {
+    const float4* p = sc.nodes + 8 * (size_t)node;
+    const float4 xl = p[0], xh = p[1], yl = p[2], yh = p[3], zl = p[4], zh = p[5], lk = p[6];
     if (STATS) ++n_nodes;
+    const int kz = tv.rw.kz;
     const float lim = tv.h.t * kSlack;
-    // child 0
-    const float a0 = __builtin_fmaf(n0.x, tv.ix, -tv.lx), a1 = __builtin_fmaf(n0.y, tv.ix, -tv.hx);
-    const float a2 = __builtin_fmaf(n0.z, tv.iy, -tv.ly), a3 = __builtin_fmaf(n0.w, tv.iy, -tv.hy);
-    const float a4 = __builtin_fmaf(n2.x, tv.iz, -tv.lz), a5 = __builtin_fmaf(n2.y, tv.iz, -tv.hz);
-    const float ex0 = fminf(a0, a1), ey0 = fminf(a2, a3), ez0 = fminf(a4, a5);
-    const float tmin0 = fmaxf(fmaxf(ex0, ey0), fmaxf(ez0, 0.0f));
-    const float tmax0 = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
-    const float near0 = kz == 0 ? ex0 : (kz == 1 ? ey0 : ez0);
-    // child 1
-    const float b0 = __builtin_fmaf(n1.x, tv.ix, -tv.lx), b1 = __builtin_fmaf(n1.y, tv.ix, -tv.hx);
-    const float b2 = __builtin_fmaf(n1.z, tv.iy, -tv.ly), b3 = __builtin_fmaf(n1.w, tv.iy, -tv.hy);
-    const float b4 = __builtin_fmaf(n2.z, tv.iz, -tv.lz), b5 = __builtin_fmaf(n2.w, tv.iz, -tv.hz);
-    const float ex1 = fminf(b0, b1), ey1 = fminf(b2, b3), ez1 = fminf(b4, b5);
-    const float tmin1 = fmaxf(fmaxf(ex1, ey1), fmaxf(ez1, 0.0f));
-    const float tmax1 = fminf(fminf(fmaxf(b0, b1), fmaxf(b2, b3)), fmaxf(b4, b5)) * kSlack;
-    const float near1 = kz == 0 ? ex1 : (kz == 1 ? ey1 : ez1);
-    const bool hit0 = tmin0 <= tmax0 && near0 <= lim;
-    const bool hit1 = tmin1 <= tmax1 && near1 <= lim;
-    const int32_t c0 = __float_as_int(n3.x);
-    const int32_t c1 = __float_as_int(n3.y);
-    if (hit0 && hit1) {
-        const bool first0 = tmin0 <= tmin1;
-        st.push(first0 ? c1 : c0);
-        node = first0 ? c0 : c1;
-    } else if (hit0) {
-        node = c0;
-    } else if (hit1) {
-        node = c1;
-    } else {
-        node = st.pop();
+    uint32_t key[4];    // entry distance bits of hit children (t >= 0), all ones for the rest
+    int32_t val[4];
+    uint32_t nh = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float a0 = __builtin_fmaf(lane_of(xl, i), tv.ix, -tv.lx);
+        const float a1 = __builtin_fmaf(lane_of(xh, i), tv.ix, -tv.hx);
+        const float a2 = __builtin_fmaf(lane_of(yl, i), tv.iy, -tv.ly);
+        const float a3 = __builtin_fmaf(lane_of(yh, i), tv.iy, -tv.hy);
+        const float a4 = __builtin_fmaf(lane_of(zl, i), tv.iz, -tv.lz);
+        const float a5 = __builtin_fmaf(lane_of(zh, i), tv.iz, -tv.hz);
+        const float ex = fminf(a0, a1), ey = fminf(a2, a3), ez = fminf(a4, a5);
+        const float tmin = fmaxf(fmaxf(ex, ey), fmaxf(ez, 0.0f));
+        const float tmax = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
+        const float near = kz == 0 ? ex : (kz == 1 ? ey : ez);
+        const uint32_t link = __float_as_uint(lane_of(lk, i));
+        // an empty slot fails on its link and, independently, on its NaN planes
+        const bool hit = link != kEmptyLink && tmin <= tmax && near <= lim;
+        key[i] = hit ? __float_as_uint(tmin) : 0xFFFFFFFFu;
+        val[i] = (int32_t)link;
+        nh += hit ? 1u : 0u;
     }
-    return node;
+    // a full sorting network: hits ascending, then the misses, so that
+    // val[0 .. nh) are exactly the hit children
+    order2(key[0], val[0], key[1], val[1]);
+    order2(key[2], val[2], key[3], val[3]);
+    order2(key[0], val[0], key[2], val[2]);
+    order2(key[1], val[1], key[3], val[3]);
+    order2(key[1], val[1], key[2], val[2]);
+    if (nh == 0u) return st.pop();
+    if (nh > 1u) {
+        const uint32_t np = nh - 1u;
+        const int32_t e0 = np == 3u ? val[3] : (np == 2u ? val[2] : val[1]);
+        const int32_t e1 = np == 3u ? val[2] : val[1];
+        st.push_up_to_3(e0, e1, val[1], np);
+    }
+    return val[0];
 }
 
 // Test the triangles of leaf `link` against the ray, keeping the closest hit.
@@ -339,7 +356,7 @@ __device__ inline void trav_step(Trav& tv, const DevScene& sc, Stack& st, uint32
         if (it > 0 && (uint32_t)__popcll(searching) <= exit_lanes) break;
         if (node >= 0) {
             if (--tv.budget == 0u) { node = -1; leaf = -1; break; }
-            node = visit_inner<STATS>(tv, node, sc, st, n_nodes);
+            node = visit_inner4<STATS>(tv, node, sc, st, n_nodes);
         }
     }
     if (leaf != -1) visit_leaf<STATS>(tv, leaf, sc, n_tris);

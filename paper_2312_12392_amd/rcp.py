@@ -71,7 +71,7 @@ class rcp_displacement(ctypes.Structure):
 
 
 class rcp_build_options(ctypes.Structure):
-    _fields_ = [("max_leaf", ctypes.c_int32), ("top_levels", ctypes.c_int32), ("c_trav", ctypes.c_float),
+    _fields_ = [("max_leaf", ctypes.c_int32), ("c_trav", ctypes.c_float),
                 ("c_isect", ctypes.c_float)]
 
 
@@ -95,8 +95,9 @@ class rcp_request(ctypes.Structure):
 
 class rcp_scene_stats(ctypes.Structure):
     _fields_ = [("n_tris", ctypes.c_uint32), ("n_nodes", ctypes.c_uint32), ("n_leaves", ctypes.c_uint32),
-                ("top_count", ctypes.c_uint32), ("max_depth", ctypes.c_uint32), ("max_leaf", ctypes.c_uint32),
-                ("sah_cost", ctypes.c_float), ("build_ms", ctypes.c_float), ("device_bytes", ctypes.c_uint64)]
+                ("max_depth", ctypes.c_uint32), ("max_leaf", ctypes.c_uint32),
+                ("sah_cost", ctypes.c_float), ("build_ms", ctypes.c_float), ("device_bytes", ctypes.c_uint64),
+                ("node_bytes", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -312,9 +313,9 @@ def rcp_trace_rays(handle: int, org, dirs, n: int, out_t, out_id, out_front=None
 
 
 def rcp_export_bvh(handle: int):
-    """Returns (nodes uint32 [n_nodes][16], tri_ids int32 [n_tris]) on the host."""
+    """Returns (nodes uint32 [n_nodes][node_bytes / 4], tri_ids int32 [n_tris]) on the host."""
     info = rcp_scene_info(handle)
-    nodes = np.zeros((info["n_nodes"], 16), dtype=np.uint32)
+    nodes = np.zeros((info["n_nodes"], info["node_bytes"] // 4), dtype=np.uint32)
     tri_ids = np.zeros(info["n_tris"], dtype=np.int32)
     st = load().rcp_export_bvh(handle, nodes.ctypes.data if nodes.size else None,
                                tri_ids.ctypes.data if tri_ids.size else None)
@@ -489,9 +490,9 @@ def rcp_server_destroy(server: int) -> None:
 # Convenience wrapper
 # ---------------------------------------------------------------------------
 
-def build_options(max_leaf: int = 4, top_levels: int = 6, c_trav: float = 1.0, c_isect: float = 1.0):
+def build_options(max_leaf: int = 4, c_trav: float = 1.0, c_isect: float = 1.0):
     o = rcp_build_options()
-    o.max_leaf, o.top_levels, o.c_trav, o.c_isect = int(max_leaf), int(top_levels), float(c_trav), float(c_isect)
+    o.max_leaf, o.c_trav, o.c_isect = int(max_leaf), float(c_trav), float(c_isect)
     return o
 
 

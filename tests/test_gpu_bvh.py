@@ -9,6 +9,7 @@ from paper_2312_12392_amd import rcp
 pytestmark = pytest.mark.gpu
 
 LEAF = 0x80000000
+EMPTY = 0x7FFFFFFF
 
 
 def say(*a):
@@ -28,11 +29,11 @@ def tri_boxes(scene):
 
 
 def node_boxes(nodes):
-    """Child boxes [n][2][2][3] (child, lo/hi, axis) and links [n][2]."""
+    """Child boxes lo, hi [n][4][3] (child, axis) and links [n][4] of 4-wide nodes."""
     f = nodes.view(np.float32)
-    lo = np.stack([f[:, [0, 2, 8]], f[:, [4, 6, 10]]], axis=1)
-    hi = np.stack([f[:, [1, 3, 9]], f[:, [5, 7, 11]]], axis=1)
-    return lo, hi, nodes[:, 12:14].astype(np.int64)
+    lo = np.stack([f[:, 0:4], f[:, 8:12], f[:, 16:20]], axis=2)
+    hi = np.stack([f[:, 4:8], f[:, 12:16], f[:, 20:24]], axis=2)
+    return lo, hi, nodes[:, 24:28].astype(np.int64)
 
 
 def check_bvh(scene, info, nodes, tri_ids):
@@ -44,48 +45,65 @@ def check_bvh(scene, info, nodes, tri_ids):
         assert info["n_nodes"] == 0
         return
     nn = info["n_nodes"]
+    assert info["node_bytes"] == 128 and nodes.shape == (nn, 32)
+    assert (nodes[:, 28:32] == 0).all()
     lo, hi, links = node_boxes(nodes)
-    lo_t, hi_t = tri_boxes(scene)
-    lo_t, hi_t = lo_t[tri_ids], hi_t[tri_ids]
-    is_leaf = (links & LEAF) != 0
+    valid = links != EMPTY
+    # used slots first, at least two per node; unused slots have NaN planes
+    assert valid[:, :2].all()
+    assert (valid[:, 1:] <= valid[:, :-1]).all()
+    assert np.isnan(lo[~valid]).all() and np.isnan(hi[~valid]).all()
+    assert not np.isnan(lo[valid]).any() and not np.isnan(hi[valid]).any()
+    is_leaf = valid & ((links & LEAF) != 0)
+    is_inner = valid & ~is_leaf
     # leaves: range inside the triangles, size within the bound, boxes contain them
     lf = links[is_leaf]
     first = (lf >> 3) & 0x0FFFFFFF
     cnt = (lf & 7) + 1
     assert (first + cnt <= n).all()
-    assert (cnt <= info["max_leaf"]).all() or nn == 1
+    single = nn == 1 and bool((links[0, :2] & LEAF).all()) and links[0, 0] == links[0, 1]
+    assert (cnt <= info["max_leaf"]).all() or single
+    lo_t, hi_t = tri_boxes(scene)
+    lo_t, hi_t = lo_t[tri_ids], hi_t[tri_ids]
     owner_lo = np.repeat(lo[is_leaf], cnt, axis=0)
     owner_hi = np.repeat(hi[is_leaf], cnt, axis=0)
     slots = np.concatenate([np.arange(a, a + c) for a, c in zip(first, cnt)])
     assert (lo_t[slots] >= owner_lo).all() and (hi_t[slots] <= owner_hi).all()
     covered = np.bincount(slots, minlength=n)
-    if nn == 1 and links[0, 0] == links[0, 1]:
+    if single:
         assert (covered == 2).all()                   # one leaf referenced by both children
     else:
         assert (covered == 1).all()                   # every triangle in exactly one leaf
-        assert int(is_leaf.sum()) == info["n_leaves"]
-    # inner children: valid index, one parent each, box contains the child's boxes
-    inner = links[~is_leaf]
+    assert int(is_leaf.sum()) == info["n_leaves"]
+    # inner children: valid index, one parent each, siblings in consecutive
+    # slots, box contains the child's children's boxes
+    inner = links[is_inner]
     assert ((inner > 0) & (inner < nn)).all()
     parents = np.bincount(inner, minlength=nn)
     assert parents[0] == 0 and (parents[1:] == 1).all()
-    par_lo = lo[~is_leaf]
-    par_hi = hi[~is_leaf]
-    assert (lo[inner].min(axis=1) >= par_lo).all() and (hi[inner].max(axis=1) <= par_hi).all()
-    # acyclic: a breadth-first sweep from the root reaches every node
+    n_in = is_inner.sum(axis=1)
+    has = n_in > 0
+    mn = np.where(is_inner, links, np.iinfo(np.int64).max).min(axis=1)
+    mx = np.where(is_inner, links, -1).max(axis=1)
+    assert (mx[has] - mn[has] + 1 == n_in[has]).all()
+    par_lo, par_hi = lo[is_inner], hi[is_inner]
+    vmask = valid[inner][..., None]
+    child_lo = np.where(vmask, lo[inner], np.inf).min(axis=1)
+    child_hi = np.where(vmask, hi[inner], -np.inf).max(axis=1)
+    assert (child_lo >= par_lo).all() and (child_hi <= par_hi).all()
+    # level order from the root: depths never decrease with the slot index
     depth = np.full(nn, -1)
     depth[0] = 0
     frontier = np.array([0])
     d = 0
     while frontier.size:
-        ch = links[frontier].reshape(-1)
-        ch = ch[(ch & LEAF) == 0]
+        ch = links[frontier][is_inner[frontier]]
         d += 1
         depth[ch] = d
         frontier = ch
     assert (depth >= 0).all()
-    assert info["max_depth"] == depth.max() + 1
-    assert info["top_count"] <= nn
+    assert (np.diff(depth) >= 0).all()
+    assert info["max_depth"] == depth.max() + 2       # wide levels plus the leaves
 
 
 @pytest.mark.parametrize("name,scene_fn", [
@@ -108,31 +126,6 @@ def test_bvh_invariants(name, scene_fn):
     info = s.info()
     nodes, tri_ids = rcp.rcp_export_bvh(s.handle)
     check_bvh(sc, info, nodes, tri_ids)
-    s.close()
-
-
-@pytest.mark.parametrize("top_levels", [0, 1, 5, 9])
-def test_top_levels_are_breadth_first_prefix(top_levels):
-    say("top levels", top_levels)
-    sc = scenegen.terrain_patch(12, 40, 20)
-    s = rcp.Scene(sc, rcp.build_options(top_levels=top_levels))
-    info = s.info()
-    nodes, _ = rcp.rcp_export_bvh(s.handle)
-    # breadth-first depths of inner nodes, from the root
-    depth = {0: 0}
-    order = [0]
-    for ni in order:
-        for c in range(2):
-            link = int(nodes[ni, 12 + c])
-            if not link & LEAF:
-                depth[link] = depth[ni] + 1
-                order.append(link)
-    top = sorted(i for i, d in depth.items() if d < top_levels)
-    assert info["top_count"] == len(top)
-    assert top == list(range(len(top)))              # they occupy the first slots
-    for i in range(1, len(top)):
-        assert depth[i] >= depth[i - 1]              # in breadth-first order
-    assert info["max_depth"] == max(depth.values()) + 1
     s.close()
 
 

@@ -197,8 +197,8 @@ def test_render_matches_oracle(case, engine):
 
 
 @pytest.mark.parametrize("opts", [
-    dict(max_leaf=1, top_levels=0), dict(max_leaf=2, top_levels=3), dict(max_leaf=8, top_levels=9),
-    dict(max_leaf=4, top_levels=8, c_trav=3.0, c_isect=0.5),
+    dict(max_leaf=1), dict(max_leaf=2), dict(max_leaf=8), dict(max_leaf=3, c_isect=2.0),
+    dict(max_leaf=4, c_trav=3.0, c_isect=0.5),
 ])
 def test_build_options_do_not_change_the_image(opts):
     say("build options", opts)
