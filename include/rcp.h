@@ -115,14 +115,23 @@ typedef struct {
 #define RCP_MODE_DEPTH 1
 #define RCP_MODE_NORMAL 2
 
-/* Build options (NULL = defaults).  max_leaf: most triangles per BVH leaf
- * (1..8, default 4); c_trav, c_isect: SAH costs of a node visit and a
- * triangle test (defaults 1, 1), used when leaves are formed in the binary
- * tree that the 4-wide traversal tree is collapsed from. */
+/* Build options (NULL = defaults).
+ *   max_leaf        most triangles per BVH leaf (1..8, default 4)
+ *   c_trav, c_isect SAH costs of a node visit and a triangle test (defaults
+ *                   1, 1), used when leaves are formed in the binary tree
+ *                   that the 4-wide traversal tree is collapsed from
+ *   builder         how that binary tree is built from the Morton-sorted
+ *                   triangles: RCP_BUILDER_PLOC (default; agglomerative
+ *                   clustering of nearest neighbours, a lower SAH cost) or
+ *                   RCP_BUILDER_LBVH (binary radix tree, faster to build).
+ * The builder changes the speed of rendering only, never an image. */
+#define RCP_BUILDER_PLOC 0
+#define RCP_BUILDER_LBVH 1
 typedef struct {
     int32_t max_leaf;
     float c_trav;
     float c_isect;
+    int32_t builder;
 } rcp_build_options;
 
 /* Scene statistics filled by rcp_scene_info. */

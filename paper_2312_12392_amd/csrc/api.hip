@@ -139,6 +139,8 @@ rcp_status rcp_build_scene(const rcp_scene_desc* desc, const rcp_build_options* 
         if (!(opts->c_trav > 0.0f) || !(opts->c_isect > 0.0f) || !std::isfinite(opts->c_trav) ||
             !std::isfinite(opts->c_isect))
             FAIL("SAH costs must be finite and > 0");
+        if (opts->builder != RCP_BUILDER_PLOC && opts->builder != RCP_BUILDER_LBVH)
+            FAIL("unknown builder %d", (int)opts->builder);
     }
     try {
         return build_scene(desc, opts, (hipStream_t)hip_stream, out);

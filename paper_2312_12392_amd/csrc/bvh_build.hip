@@ -171,6 +171,197 @@ __global__ __launch_bounds__(kB) void k_radix_tree(const uint64_t* __restrict__ 
     if (i == 0) parent[0] = -1;
 }
 
+// ---------------------------------------------------------------------------
+// PLOC: parallel locally-ordered clustering (Meister and Bittner, "Parallel
+// Locally-Ordered Clustering for Bounding Volume Hierarchy Construction",
+// IEEE TVCG 2018).  Clusters start as the triangles in Morton order.  Each
+// round every cluster finds its nearest neighbour among the kPlocRadius
+// clusters on each side -- the one whose merged box has the smallest surface
+// area --, mutual nearest neighbours merge into a new inner node, and the
+// clusters are compacted in order.  Equal areas are ordered by index
+// distance, then pairs with an even lower index first, then by the lower
+// index: a strict order on pairs, so the globally best pair is always mutual
+// and every round merges, and exact duplicates pair off (0,1), (2,3), ...
+// Inner nodes are numbered downward from n - 2, so the last merge, the root,
+// is node 0.  The tree is then renumbered so that every subtree holds a
+// contiguous range of triangles (depth-first leaf order).
+// ---------------------------------------------------------------------------
+constexpr int kPlocRadius = 16;
+
+__global__ __launch_bounds__(kB) void k_ploc_init(int n, const float4* __restrict__ tlo, const float4* __restrict__ thi,
+                                                   const uint32_t* __restrict__ sorted, int32_t* __restrict__ id,
+                                                   float4* __restrict__ lo, float4* __restrict__ hi) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= n) return;
+    id[i] = (int32_t)(kLeafBit | (uint32_t)i);
+    lo[i] = tlo[sorted[i]];
+    hi[i] = thi[sorted[i]];
+}
+
+__global__ __launch_bounds__(kB) void k_ploc_nn(int m, const float4* __restrict__ lo, const float4* __restrict__ hi,
+                                                 int32_t* __restrict__ nn) {
+    constexpr int kW = kB + 2 * kPlocRadius;
+    __shared__ float s[6][kW];
+    const int base = (int)(blockIdx.x * kB) - kPlocRadius;
+    for (int t = threadIdx.x; t < kW; t += kB) {
+        const int g = base + t;
+        if (g >= 0 && g < m) {
+            const float4 a = lo[g], b = hi[g];
+            s[0][t] = a.x; s[1][t] = a.y; s[2][t] = a.z;
+            s[3][t] = b.x; s[4][t] = b.y; s[5][t] = b.z;
+        }
+    }
+    __syncthreads();
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= m) return;
+    const int li = threadIdx.x + kPlocRadius;
+    float best = INFINITY;
+    int bj = -1, bdist = 0, bmin = 0;
+    for (int d = -kPlocRadius; d <= kPlocRadius; ++d) {
+        const int j = i + d;
+        if (d == 0 || j < 0 || j >= m) continue;
+        const int lj = li + d;
+        const float3 a = make_float3(fminf(s[0][li], s[0][lj]), fminf(s[1][li], s[1][lj]), fminf(s[2][li], s[2][lj]));
+        const float3 b = make_float3(fmaxf(s[3][li], s[3][lj]), fmaxf(s[4][li], s[4][lj]), fmaxf(s[5][li], s[5][lj]));
+        const float ar = half_area(a, b);
+        const int dist = d < 0 ? -d : d;
+        const int mn = j < i ? j : i;
+        bool take = ar < best;
+        if (!take && ar == best) {
+            if (dist != bdist) take = dist < bdist;
+            else if ((mn & 1) != (bmin & 1)) take = (mn & 1) == 0;
+            else take = mn < bmin;
+        }
+        if (take || bj < 0) { best = ar; bj = j; bdist = dist; bmin = mn; }
+    }
+    nn[i] = bj;
+}
+
+__device__ inline int node_slot(int32_t c, int n) {
+    return c < 0 ? n - 1 + (int)((uint32_t)c & ~kLeafBit) : c;
+}
+
+__global__ __launch_bounds__(kB) void k_ploc_merge(int m, int n, const int32_t* __restrict__ nn,
+                                                    const int32_t* __restrict__ id, const float4* __restrict__ lo,
+                                                    const float4* __restrict__ hi, int32_t* __restrict__ id2,
+                                                    float4* __restrict__ lo2, float4* __restrict__ hi2,
+                                                    uint32_t* __restrict__ pos, uint32_t* __restrict__ keep,
+                                                    int32_t* __restrict__ next_id, int32_t* __restrict__ left,
+                                                    int32_t* __restrict__ right, int32_t* __restrict__ parent) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= m) return;
+    const int j = nn[i];
+    uint32_t k = 1u;
+    if (j >= 0 && nn[j] == i) {
+        if (i < j) {
+            const int32_t node = atomicSub(next_id, 1);
+            const int32_t a = id[i], b = id[j];
+            left[node] = a;
+            right[node] = b;
+            parent[node_slot(a, n)] = node;
+            parent[node_slot(b, n)] = node;
+            const float4 la = lo[i], lb = lo[j], ha = hi[i], hb = hi[j];
+            id2[i] = node;
+            lo2[i] = make_float4(fminf(la.x, lb.x), fminf(la.y, lb.y), fminf(la.z, lb.z), 0.0f);
+            hi2[i] = make_float4(fmaxf(ha.x, hb.x), fmaxf(ha.y, hb.y), fmaxf(ha.z, hb.z), 0.0f);
+        } else {
+            k = 0u;   // merged into cluster j
+        }
+    } else {
+        id2[i] = id[i];
+        lo2[i] = lo[i];
+        hi2[i] = hi[i];
+    }
+    pos[i] = k;
+    keep[i] = k;
+}
+
+__global__ __launch_bounds__(kB) void k_ploc_compact(int m, const uint32_t* __restrict__ pos,
+                                                      const uint32_t* __restrict__ keep,
+                                                      const int32_t* __restrict__ id2, const float4* __restrict__ lo2,
+                                                      const float4* __restrict__ hi2, int32_t* __restrict__ id,
+                                                      float4* __restrict__ lo, float4* __restrict__ hi,
+                                                      uint32_t* __restrict__ m_out) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= m) return;
+    if (keep[i]) {
+        const uint32_t p = pos[i];
+        id[p] = id2[i];
+        lo[p] = lo2[i];
+        hi[p] = hi2[i];
+    }
+    if (i == m - 1) *m_out = pos[i] + keep[i];
+}
+
+// Leaves under every inner node, bottom-up with per-node arrival counters.
+__global__ __launch_bounds__(kB) void k_leaf_counts(int n, const int32_t* __restrict__ left,
+                                                     const int32_t* __restrict__ right,
+                                                     const int32_t* __restrict__ parent, uint32_t* __restrict__ arrivals,
+                                                     int32_t* __restrict__ cnt) {
+    const int j = blockIdx.x * kB + threadIdx.x;
+    if (j >= n) return;
+    int node = parent[n - 1 + j];
+    while (node >= 0) {
+        __threadfence();
+        if (atomicAdd(&arrivals[node], 1u) == 0u) return;   // the sibling finishes this node
+        __threadfence();
+        const int32_t l = left[node], r = right[node];
+        cnt[node] = (l < 0 ? 1 : cnt[l]) + (r < 0 ? 1 : cnt[r]);
+        node = parent[node];
+    }
+}
+
+// Depth-first rank of the first leaf under every node (inner nodes at
+// [0, n-1), leaves at [n-1, 2n-1)): the leaves of the left siblings along
+// the path to the root.
+__global__ __launch_bounds__(kB) void k_dfs_first(int n, const int32_t* __restrict__ left,
+                                                   const int32_t* __restrict__ right, const int32_t* __restrict__ parent,
+                                                   const int32_t* __restrict__ cnt, int32_t* __restrict__ first) {
+    const int x = blockIdx.x * kB + threadIdx.x;
+    if (x >= 2 * n - 1) return;
+    int32_t code = x < n - 1 ? x : (int32_t)(kLeafBit | (uint32_t)(x - (n - 1)));
+    int node = parent[x];
+    int r = 0;
+    while (node >= 0) {
+        if (right[node] == code) {
+            const int32_t l = left[node];
+            r += l < 0 ? 1 : cnt[l];
+        }
+        code = node;
+        node = parent[node];
+    }
+    first[x] = r;
+}
+
+// Renumber the triangles in depth-first leaf order: the sorted array, the
+// leaves' parents, leaf children, and each inner node's range.
+__global__ __launch_bounds__(kB) void k_dfs_renumber(int n, const int32_t* __restrict__ first,
+                                                      const int32_t* __restrict__ cnt,
+                                                      const uint32_t* __restrict__ sorted_in,
+                                                      const int32_t* __restrict__ parent_in,
+                                                      uint32_t* __restrict__ sorted_out, int32_t* __restrict__ parent_out,
+                                                      int32_t* __restrict__ left, int32_t* __restrict__ right,
+                                                      int32_t* __restrict__ rfirst, int32_t* __restrict__ rlast) {
+    const int x = blockIdx.x * kB + threadIdx.x;
+    if (x >= 2 * n - 1) return;
+    if (x >= n - 1) {
+        const int p = x - (n - 1), r = first[x];
+        sorted_out[r] = sorted_in[p];
+        parent_out[n - 1 + r] = parent_in[x];
+    } else {
+        parent_out[x] = parent_in[x];
+        const int32_t l = left[x], rr = right[x];
+        if (l < 0) left[x] = (int32_t)(kLeafBit | (uint32_t)first[n - 1 + (int)((uint32_t)l & ~kLeafBit)]);
+        if (rr < 0) right[x] = (int32_t)(kLeafBit | (uint32_t)first[n - 1 + (int)((uint32_t)rr & ~kLeafBit)]);
+        rfirst[x] = first[x];
+        rlast[x] = first[x] + cnt[x] - 1;
+    }
+}
+
+__global__ void k_set_i32(int32_t* p, int32_t v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
 struct NodeData {
     float4* lo;        // box lo, w unused
     float4* hi;
@@ -498,6 +689,89 @@ struct TempSet {
 
 inline unsigned blocks(long n) { return (unsigned)((n + kB - 1) / kB); }
 
+// PLOC tree over the Morton-sorted triangles, renumbered in depth-first leaf
+// order (sorted is permuted in place).  Returns RCP_ERR_NOT_READY when the
+// rounds do not converge within the cap; the caller then builds the radix
+// tree from the untouched sorted order instead.
+rcp_status ploc_build(int n, const float4* tlo, const float4* thi, uint32_t* sorted, int32_t* left, int32_t* right,
+                      int32_t* parent, int32_t* rfirst, int32_t* rlast, hipStream_t stream) {
+    TempSet tmp;
+    int32_t *id, *id2, *nn, *next_id, *cnt, *first, *parent_tmp;
+    float4 *lo, *hi, *lo2, *hi2;
+    uint32_t *pos, *keep, *m_out, *scratch, *arrivals, *sorted2;
+    const size_t un = (size_t)n;
+    RCP_TRY(tmp.alloc(&id, un));
+    RCP_TRY(tmp.alloc(&id2, un));
+    RCP_TRY(tmp.alloc(&nn, un));
+    RCP_TRY(tmp.alloc(&next_id, 1));
+    RCP_TRY(tmp.alloc(&cnt, un));
+    RCP_TRY(tmp.alloc(&first, 2 * un));
+    RCP_TRY(tmp.alloc(&parent_tmp, 2 * un));
+    RCP_TRY(tmp.alloc(&lo, un));
+    RCP_TRY(tmp.alloc(&hi, un));
+    RCP_TRY(tmp.alloc(&lo2, un));
+    RCP_TRY(tmp.alloc(&hi2, un));
+    RCP_TRY(tmp.alloc(&pos, un));
+    RCP_TRY(tmp.alloc(&keep, un));
+    RCP_TRY(tmp.alloc(&m_out, 1));
+    RCP_TRY(tmp.alloc(&scratch, scan_scratch_words(n)));
+    RCP_TRY(tmp.alloc(&arrivals, un));
+    RCP_TRY(tmp.alloc(&sorted2, un));
+    // every entry gets its parent from a merge; -1 until then, so that a walk
+    // to the root ends whatever happens
+    RCP_HIP(hipMemsetAsync(parent_tmp, 0xFF, sizeof(int32_t) * 2 * un, stream));
+    hipLaunchKernelGGL(k_ploc_init, dim3(blocks(n)), dim3(kB), 0, stream, n, tlo, thi, (const uint32_t*)sorted, id,
+                       lo, hi);
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, stream, next_id, (int32_t)(n - 2));
+    RCP_CHECK_LAUNCH();
+    int log2n = 0;
+    while ((1 << log2n) < n) ++log2n;
+    const int max_rounds = 64 + 16 * log2n;
+    int m = n, rounds = 0;
+    while (m > 1) {
+        if (++rounds > max_rounds) return RCP_ERR_NOT_READY;
+        hipLaunchKernelGGL(k_ploc_nn, dim3(blocks(m)), dim3(kB), 0, stream, m, (const float4*)lo, (const float4*)hi,
+                           nn);
+        hipLaunchKernelGGL(k_ploc_merge, dim3(blocks(m)), dim3(kB), 0, stream, m, n, (const int32_t*)nn,
+                           (const int32_t*)id, (const float4*)lo, (const float4*)hi, id2, lo2, hi2, pos, keep, next_id,
+                           left, right, parent_tmp);
+        RCP_CHECK_LAUNCH();
+        RCP_TRY(scan_exclusive_u32(pos, m, scratch, stream));
+        hipLaunchKernelGGL(k_ploc_compact, dim3(blocks(m)), dim3(kB), 0, stream, m, (const uint32_t*)pos,
+                           (const uint32_t*)keep, (const int32_t*)id2, (const float4*)lo2, (const float4*)hi2, id, lo,
+                           hi, m_out);
+        RCP_CHECK_LAUNCH();
+        uint32_t next = 0;
+        RCP_HIP(hipMemcpyAsync(&next, m_out, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+        RCP_HIP(hipStreamSynchronize(stream));
+        if (next < 1u || next >= (uint32_t)m) {
+            set_error("PLOC round %d went from %d to %u clusters", rounds, m, next);
+            return RCP_ERR_INTERNAL;
+        }
+        m = (int)next;
+    }
+    int32_t last = 0;
+    RCP_HIP(hipMemcpyAsync(&last, next_id, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    RCP_HIP(hipStreamSynchronize(stream));
+    if (last != -1) {
+        set_error("PLOC made %d inner nodes, expected %d", n - 2 - last, n - 1);
+        return RCP_ERR_INTERNAL;
+    }
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, stream, parent_tmp, -1);   // the root
+    RCP_HIP(hipMemsetAsync(arrivals, 0, sizeof(uint32_t) * un, stream));
+    hipLaunchKernelGGL(k_leaf_counts, dim3(blocks(n)), dim3(kB), 0, stream, n, (const int32_t*)left,
+                       (const int32_t*)right, (const int32_t*)parent_tmp, arrivals, cnt);
+    hipLaunchKernelGGL(k_dfs_first, dim3(blocks(2L * n - 1)), dim3(kB), 0, stream, n, (const int32_t*)left,
+                       (const int32_t*)right, (const int32_t*)parent_tmp, (const int32_t*)cnt, first);
+    hipLaunchKernelGGL(k_dfs_renumber, dim3(blocks(2L * n - 1)), dim3(kB), 0, stream, n, (const int32_t*)first,
+                       (const int32_t*)cnt, (const uint32_t*)sorted, (const int32_t*)parent_tmp, sorted2, parent,
+                       left, right, rfirst, rlast);
+    RCP_CHECK_LAUNCH();
+    RCP_HIP(hipMemcpyAsync(sorted, sorted2, sizeof(uint32_t) * un, hipMemcpyDeviceToDevice, stream));
+    RCP_HIP(hipStreamSynchronize(stream));
+    return RCP_OK;
+}
+
 }  // namespace
 
 rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts, hipStream_t stream,
@@ -506,6 +780,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     const int max_leaf = opts ? opts->max_leaf : 4;
     const float c_trav = opts ? opts->c_trav : 1.0f;
     const float c_isect = opts ? opts->c_isect : 1.0f;
+    const int builder = opts ? opts->builder : RCP_BUILDER_PLOC;
 
     rcp_scene* s = new rcp_scene();
     struct Guard {
@@ -593,9 +868,17 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
             RCP_TRY(tmp.alloc(&nd.cost, ni));
             RCP_TRY(tmp.alloc(&nd.n_inner, ni));
             RCP_TRY(tmp.alloc(&nd.collapse, ni));
+            rcp_status tree = RCP_ERR_NOT_READY;
+            if (builder == RCP_BUILDER_PLOC)
+                tree = ploc_build((int)n, tlo, thi, sorted, left, right, parent, rfirst, rlast, stream);
+            if (tree == RCP_ERR_NOT_READY) {   // the radix tree, or PLOC did not converge
+                hipLaunchKernelGGL(k_radix_tree, dim3(blocks(ni)), dim3(kB), 0, stream, (const uint64_t*)keys,
+                                   (int)n, left, right, parent, rfirst, rlast);
+                RCP_CHECK_LAUNCH();
+                tree = RCP_OK;
+            }
+            if (tree != RCP_OK) return tree;
             RCP_HIP(hipMemsetAsync(arrivals, 0, sizeof(uint32_t) * ni, stream));
-            hipLaunchKernelGGL(k_radix_tree, dim3(blocks(ni)), dim3(kB), 0, stream, (const uint64_t*)keys, (int)n,
-                               left, right, parent, rfirst, rlast);
             hipLaunchKernelGGL(k_refit, dim3(blocks(n)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
                                (const int32_t*)right, (const int32_t*)parent, (const int32_t*)rfirst,
                                (const int32_t*)rlast, (const float4*)tlo, (const float4*)thi,

@@ -162,6 +162,13 @@ rcp_status scan_exclusive(uint32_t* data, long n, uint32_t* scratch, hipStream_t
 
 }  // namespace
 
+size_t scan_scratch_words(long n) { return (size_t)(n / (kScanTile - 1) + 64); }
+
+rcp_status scan_exclusive_u32(uint32_t* data, long n, uint32_t* scratch, hipStream_t stream) {
+    if (n <= 0) return RCP_OK;
+    return scan_exclusive(data, n, scratch, stream);
+}
+
 rcp_status radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
                             int n, int end_bit, hipStream_t stream) {
     if (n <= 1) return RCP_OK;

@@ -145,6 +145,10 @@ namespace rcp {
 
 // Stable LSD radix sort of (u64 key, u32 value) pairs over bits [0, end_bit).
 // tmp_keys / tmp_vals: n entries each.  Result ends in keys / vals.
+// In-place exclusive prefix sum of n uint32 values on the device; scratch
+// holds scan_scratch_words(n) words.
+size_t scan_scratch_words(long n);
+rcp_status scan_exclusive_u32(uint32_t* data, long n, uint32_t* scratch, hipStream_t stream);
 rcp_status radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, uint32_t* tmp_vals,
                             int n, int end_bit, hipStream_t stream);
 

@@ -29,6 +29,8 @@ RCP_ERR_INTERNAL = 6
 RCP_MODE_COLOR = 0
 RCP_MODE_DEPTH = 1
 RCP_MODE_NORMAL = 2
+RCP_BUILDER_PLOC = 0
+RCP_BUILDER_LBVH = 1
 RCP_ENGINE_CHAIN = 0
 RCP_ENGINE_PASSES = 1
 ENGINE_CHAIN, ENGINE_PASSES = RCP_ENGINE_CHAIN, RCP_ENGINE_PASSES
@@ -72,7 +74,7 @@ class rcp_displacement(ctypes.Structure):
 
 class rcp_build_options(ctypes.Structure):
     _fields_ = [("max_leaf", ctypes.c_int32), ("c_trav", ctypes.c_float),
-                ("c_isect", ctypes.c_float)]
+                ("c_isect", ctypes.c_float), ("builder", ctypes.c_int32)]
 
 
 class rcp_view(ctypes.Structure):
@@ -490,9 +492,9 @@ def rcp_server_destroy(server: int) -> None:
 # Convenience wrapper
 # ---------------------------------------------------------------------------
 
-def build_options(max_leaf: int = 4, c_trav: float = 1.0, c_isect: float = 1.0):
+def build_options(max_leaf: int = 4, c_trav: float = 1.0, c_isect: float = 1.0, builder: int = 0):
     o = rcp_build_options()
-    o.max_leaf, o.c_trav, o.c_isect = int(max_leaf), float(c_trav), float(c_isect)
+    o.max_leaf, o.c_trav, o.c_isect, o.builder = int(max_leaf), float(c_trav), float(c_isect), int(builder)
     return o
 
 

@@ -119,10 +119,11 @@ def check_bvh(scene, info, nodes, tri_ids):
                                           rgb=np.full((700, 3), 0.3, np.float32))),
     ("terrain1m", lambda: scenegen.workload("terrain1m").scene),
 ])
-def test_bvh_invariants(name, scene_fn):
-    say("bvh", name)
+@pytest.mark.parametrize("builder", [rcp.RCP_BUILDER_PLOC, rcp.RCP_BUILDER_LBVH], ids=["ploc", "lbvh"])
+def test_bvh_invariants(name, scene_fn, builder):
+    say("bvh", name, "builder", builder)
     sc = scene_fn()
-    s = rcp.Scene(sc)
+    s = rcp.Scene(sc, rcp.build_options(builder=builder))
     info = s.info()
     nodes, tri_ids = rcp.rcp_export_bvh(s.handle)
     check_bvh(sc, info, nodes, tri_ids)
