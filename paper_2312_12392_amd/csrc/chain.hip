@@ -30,6 +30,7 @@ namespace {
 struct ViewDev {
     Camera cam;
     int W, H, K, tiles_x, tile_log2w;
+    float hw;              // half_width(cam.th, W, H)
     float le, ld, z0;
     float* out;            // [K][H][W][3]
     int32_t* ids;          // [K][H][W] or NULL
@@ -85,6 +86,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
     const uint32_t n_items = a.n_items;
 
     bool alive = false;        // tracing a ray
+    bool ended = false;        // its pass is traced, waiting for a setup round to be finished
     bool pending = false;      // holds the inputs of its next pass, waiting for a setup round
     bool drained = false;      // wave-uniform
     int k = 0, x = 0, y = 0;
@@ -95,12 +97,80 @@ __device__ inline void chain_body(const ChainArgs& a) {
     tv.node = -1;
 
     for (;;) {
-        // ---- setup round: new pixels for idle lanes, rays for every lane that
-        // needs one (new pixels and lanes moving to their next pass together)
+        // ---- setup round, when enough lanes wait: finish the traced passes,
+        // fetch new pixels for idle lanes, and set up the rays of new pixels and
+        // of next passes together (work done by a few lanes alone wastes the wave)
         const unsigned long long need = __ballot(!alive);
-        const unsigned long long pend = __ballot(pending);
-        const unsigned long long idle = need & ~pend;
-        if ((uint32_t)__popcll(need) >= (uint32_t)a.refill_min || (drained && pend != 0ull)) {
+        const unsigned long long waiting = __ballot(ended || pending);
+        if ((uint32_t)__popcll(need) >= (uint32_t)a.refill_min || (drained && waiting != 0ull)) {
+            // lanes whose pass is traced: shade, write, and keep the inputs
+            // of the next pass or end the chain
+            if (ended) {
+                {
+                    const ViewDev& vw = a.views[v];
+                    float rgb[3];
+                    float na[4] = {INFINITY, 0.0f, 0.0f, 0.0f};
+                    int32_t hid = -1;
+                    if (tv.h.id != INT_MAX) {
+                        const float4 c = a.sc.shade[2 * (size_t)tv.h.slot + (tv.h.front ? 0 : 1)];
+                        rgb[0] = c.x; rgb[1] = c.y; rgb[2] = c.z;
+                        hid = tv.h.id;
+                        if (AUX) {
+                            // view depth of P = o + t d along the camera's forward axis; the
+                            // ray is rebuilt (bit-identical) rather than kept in registers
+                            float ro[3], rd[3];
+                            make_ray<MODE>(vw.cam, vw.hw, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, ro,
+                                           rd);
+                            float P3[3];
+#pragma unroll
+                            for (int c3 = 0; c3 < 3; ++c3) P3[c3] = ro[c3] + tv.h.t * rd[c3];
+                            na[0] = ((P3[0] - vw.cam.eye[0]) * vw.cam.forward[0] +
+                                     (P3[1] - vw.cam.eye[1]) * vw.cam.forward[1]) +
+                                    (P3[2] - vw.cam.eye[2]) * vw.cam.forward[2];
+                            const float4 nv = a.sc.normals[tv.h.slot];
+                            na[1] = nv.x; na[2] = nv.y; na[3] = nv.z;
+                        }
+                    } else {
+                        rgb[0] = a.sc.bg[0]; rgb[1] = a.sc.bg[1]; rgb[2] = a.sc.bg[2];
+                    }
+                    const size_t P = (size_t)vw.W * (size_t)vw.H;
+                    const size_t pix = (size_t)y * (size_t)vw.W + (size_t)x;
+                    // the next ray is a function of the colour (and, in the depth and
+                    // normal modes, of the hit data): unchanged inputs, unchanged result
+                    bool changed = __float_as_uint(rgb[0]) != __float_as_uint(pr) ||
+                                   __float_as_uint(rgb[1]) != __float_as_uint(pg) ||
+                                   __float_as_uint(rgb[2]) != __float_as_uint(pb);
+                    if (AUX)
+                        changed = changed || __float_as_uint(na[0]) != __float_as_uint(pa[0]) ||
+                                  __float_as_uint(na[1]) != __float_as_uint(pa[1]) ||
+                                  __float_as_uint(na[2]) != __float_as_uint(pa[2]) ||
+                                  __float_as_uint(na[3]) != __float_as_uint(pa[3]);
+                    // image k, and every later image when nothing changed
+                    const int k_end = changed ? k + 1 : vw.K;
+                    for (int kk = k; kk < k_end; ++kk) {
+                        float* q = vw.out + ((size_t)kk * P + pix) * 3;
+                        q[0] = rgb[0]; q[1] = rgb[1]; q[2] = rgb[2];
+                        if (vw.ids) vw.ids[(size_t)kk * P + pix] = hid;
+                    }
+                    const bool next = changed && k + 1 < vw.K;
+                    if (STATS) {
+                        unsigned long long* sk = lstats + 4 * k;
+                        atomicAdd(&sk[0], 1ull);
+                        atomicAdd(&sk[1], (unsigned long long)dn);
+                        atomicAdd(&sk[2], (unsigned long long)dt);
+                        if (next) atomicAdd(&sk[3], 1ull);
+                        dn = 0; dt = 0;
+                    }
+                    if (next) {
+                        ++k;
+                        pr = rgb[0]; pg = rgb[1]; pb = rgb[2];
+                        if (AUX) { pa[0] = na[0]; pa[1] = na[1]; pa[2] = na[2]; pa[3] = na[3]; }
+                        pending = true;
+                    }
+                }
+                ended = false;
+            }
+            const unsigned long long idle = __ballot(!alive && !pending);
             const uint32_t n_idle = (uint32_t)__popcll(idle);
             uint32_t base = 0;
             const bool fetch = !drained && n_idle > 0u;
@@ -136,7 +206,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
             if (init) {
                 const ViewDev& vw = a.views[v];
                 float o[3], d[3];
-                make_ray<MODE>(vw.cam, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, o, d);
+                make_ray<MODE>(vw.cam, vw.hw, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, o, d);
                 trav_init(tv, a.sc, o, d, st);
                 if (STATS) { dn = 0; dt = 0; }
                 alive = true;
@@ -144,81 +214,16 @@ __device__ inline void chain_body(const ChainArgs& a) {
             }
         }
         if (__ballot(alive) == 0ull) {
-            if (drained && __ballot(pending) == 0ull) break;
+            if (drained && __ballot(pending || ended) == 0ull) break;
             continue;
         }
 
         // ---- one traversal step -------------------------------------------------
         if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, st, a.exit_lanes, dn, dt);
 
-        // ---- a finished pass: shade, write, then the next pass or the end -------
-        if (alive && tv.node == -1) {
-            {
-                const ViewDev& vw = a.views[v];
-                float rgb[3];
-                float na[4] = {INFINITY, 0.0f, 0.0f, 0.0f};
-                int32_t hid = -1;
-                if (tv.h.id != INT_MAX) {
-                    const float4 c = a.sc.shade[2 * (size_t)tv.h.slot + (tv.h.front ? 0 : 1)];
-                    rgb[0] = c.x; rgb[1] = c.y; rgb[2] = c.z;
-                    hid = tv.h.id;
-                    if (AUX) {
-                        // view depth of P = o + t d along the camera's forward axis; the
-                        // ray is rebuilt (bit-identical) rather than kept in registers
-                        float ro[3], rd[3];
-                        make_ray<MODE>(vw.cam, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, ro, rd);
-                        float P3[3];
-#pragma unroll
-                        for (int c3 = 0; c3 < 3; ++c3) P3[c3] = ro[c3] + tv.h.t * rd[c3];
-                        na[0] = ((P3[0] - vw.cam.eye[0]) * vw.cam.forward[0] +
-                                 (P3[1] - vw.cam.eye[1]) * vw.cam.forward[1]) +
-                                (P3[2] - vw.cam.eye[2]) * vw.cam.forward[2];
-                        const float4 nv = a.sc.normals[tv.h.slot];
-                        na[1] = nv.x; na[2] = nv.y; na[3] = nv.z;
-                    }
-                } else {
-                    rgb[0] = a.sc.bg[0]; rgb[1] = a.sc.bg[1]; rgb[2] = a.sc.bg[2];
-                }
-                const size_t P = (size_t)vw.W * (size_t)vw.H;
-                const size_t pix = (size_t)y * (size_t)vw.W + (size_t)x;
-                // the next ray is a function of the colour (and, in the depth and
-                // normal modes, of the hit data): unchanged inputs, unchanged result
-                bool changed = __float_as_uint(rgb[0]) != __float_as_uint(pr) ||
-                               __float_as_uint(rgb[1]) != __float_as_uint(pg) ||
-                               __float_as_uint(rgb[2]) != __float_as_uint(pb);
-                if (AUX)
-                    changed = changed || __float_as_uint(na[0]) != __float_as_uint(pa[0]) ||
-                              __float_as_uint(na[1]) != __float_as_uint(pa[1]) ||
-                              __float_as_uint(na[2]) != __float_as_uint(pa[2]) ||
-                              __float_as_uint(na[3]) != __float_as_uint(pa[3]);
-                // image k, and every later image when nothing changed
-                const int k_end = changed ? k + 1 : vw.K;
-                for (int kk = k; kk < k_end; ++kk) {
-                    float* q = vw.out + ((size_t)kk * P + pix) * 3;
-                    q[0] = rgb[0]; q[1] = rgb[1]; q[2] = rgb[2];
-                    if (vw.ids) vw.ids[(size_t)kk * P + pix] = hid;
-                }
-                const bool next = changed && k + 1 < vw.K;
-                if (STATS) {
-                    unsigned long long* sk = lstats + 4 * k;
-                    atomicAdd(&sk[0], 1ull);
-                    atomicAdd(&sk[1], (unsigned long long)dn);
-                    atomicAdd(&sk[2], (unsigned long long)dt);
-                    if (next) atomicAdd(&sk[3], 1ull);
-                    dn = 0; dt = 0;
-                }
-                if (next) {
-                    ++k;
-                    pr = rgb[0]; pg = rgb[1]; pb = rgb[2];
-                    if (AUX) { pa[0] = na[0]; pa[1] = na[1]; pa[2] = na[2]; pa[3] = na[3]; }
-                    // the ray is set up in the next setup round, together with
-                    // other lanes (a setup run by a few lanes alone wastes the wave)
-                    alive = false;
-                    pending = true;
-                } else {
-                    alive = false;
-                }
-            }
+        if (alive && tv.node == -1) {   // the pass is traced: finish it in the next round
+            alive = false;
+            ended = true;
         }
     }
 
@@ -320,6 +325,7 @@ ViewDev view_of(const Camera& cam, int W, int H, int K, const Disp& d, float* ou
     ViewDev v{};
     v.cam = cam;
     v.W = W; v.H = H; v.K = K;
+    v.hw = half_width(cam.th, W, H);
     v.tile_log2w = tile_log2w;
     v.tiles_x = (W + (1 << tile_log2w) - 1) >> tile_log2w;
     v.le = d.le; v.ld = d.ld; v.z0 = d.z0;

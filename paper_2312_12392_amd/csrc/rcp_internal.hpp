@@ -88,7 +88,7 @@ constexpr size_t kViewBytes = 512;
 
 constexpr int kMaxPasses = 64;
 // Defaults of the launch parameters, measured on the 1080p K=6 terrain frame.
-constexpr int kDefaultExitLanes = 6;
+constexpr int kDefaultExitLanes = 8;
 constexpr int kDefaultRefill = 52;
 
 struct Disp {

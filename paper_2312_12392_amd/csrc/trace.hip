@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
                 }
                 if (valid) {
                     float ro[3], rd[3];
-                    make_ray<MODE>(a.cam, a.W, a.H, x, y, pr, pg, pb, pa, a.z0, a.le, a.ld, ro, rd);
+                    make_ray<MODE>(a.cam, half_width(a.cam.th, a.W, a.H), a.W, a.H, x, y, pr, pg, pb, pa, a.z0, a.le, a.ld, ro, rd);
                     trav_init(tv, a.sc, ro, rd, st);
                     alive = true;
                     if (STATS) ++s_rays;
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
                     const int y = (int)(pix / (uint32_t)a.W);
                     const int x = (int)(pix - (uint32_t)y * (uint32_t)a.W);
                     float ro[3], rd[3];
-                    make_ray<MODE>(a.cam, a.W, a.H, x, y, pr, pg, pb, pa, a.z0, a.le, a.ld, ro, rd);
+                    make_ray<MODE>(a.cam, half_width(a.cam.th, a.W, a.H), a.W, a.H, x, y, pr, pg, pb, pa, a.z0, a.le, a.ld, ro, rd);
                     float P3[3];
 #pragma unroll
                     for (int c3 = 0; c3 < 3; ++c3) P3[c3] = ro[c3] + tv.h.t * rd[c3];
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_gen_rays(Camera cam, int W, int H, f
     float pa[4] = {INFINITY, 0.0f, 0.0f, 0.0f};
     if (prev_aux) for (int c = 0; c < 4; ++c) pa[c] = prev_aux[4 * (size_t)p + c];
     float o[3], d[3];
-    make_ray<MODE>(cam, W, H, x, y, pr, pg, pb, pa, z0, le, ld, o, d);
+    make_ray<MODE>(cam, half_width(cam.th, W, H), W, H, x, y, pr, pg, pb, pa, z0, le, ld, o, d);
     for (int c = 0; c < 3; ++c) { org[3 * (size_t)p + c] = o[c]; dir[3 * (size_t)p + c] = d[c]; }
 }
 

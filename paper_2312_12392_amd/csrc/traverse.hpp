@@ -35,18 +35,25 @@ __device__ inline uint32_t lanes_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Horizontal half extent of the image plane, tan(fovy / 2) * W / H: one value
+// per view, the same bits on the host and the device.
+__host__ __device__ inline float half_width(float th, int W, int H) {
+    const float aspect = (float)W / (float)H;
+    return th * aspect;
+}
+
 // Ray of pixel (x, y): P'_e = P_e + V_e, N = normalize(P'_p - P'_e), with
 // w from the pixel's previous colour and hit data `aux` (view depth, unit
 // normal): the colour vector (2R-1) right + (2G-1) up + (2B-1) forward
 // (Section 3), that vector times |z - z0| (Section 4, none after a miss), or
 // C x N with C the undisplaced view direction (Section 5).
+// hw is half_width(c.th, W, H).
 template <int MODE>
-__device__ inline void make_ray(const Camera& c, int W, int H, int x, int y, float pr, float pg, float pb,
+__device__ inline void make_ray(const Camera& c, float hw, int W, int H, int x, int y, float pr, float pg, float pb,
                                 const float aux[4], float z0, float le, float ld, float o[3], float d[3]) {
     const float fx = (float)(2 * x + 1) / (float)W - 1.0f;
     const float fy = 1.0f - (float)(2 * y + 1) / (float)H;
-    const float aspect = (float)W / (float)H;
-    const float s = fx * (c.th * aspect);
+    const float s = fx * hw;
     const float t = fy * c.th;
     float q[3], w[3], dp[3];
 #pragma unroll
@@ -226,7 +233,10 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
     tv.rw = ray_setup(o, d);
     float inv[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) inv[a] = fabsf(d[a]) > 1e-30f ? 1.0f / d[a] : copysignf(1e30f, d[a]);
+    // The reciprocals only prune: the hardware reciprocal (within 1 ulp) is
+    // far inside the box widening, so no correctly rounded division here.
+    for (int a = 0; a < 3; ++a)
+        inv[a] = fabsf(d[a]) > 1e-30f ? __builtin_amdgcn_rcpf(d[a]) : copysignf(1e30f, d[a]);
     tv.ix = inv[0]; tv.iy = inv[1]; tv.iz = inv[2];
     // A plane at coordinate c is reached at t = c * inv - (o -/+ pad) * inv,
     // one fused multiply-add per plane.  Its rounding (a few ulp of |o * inv|)
