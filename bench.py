@@ -82,8 +82,14 @@ def cpu_baseline(w, reps=3):
         o.render(w.camera, w.width, w.height, w.passes, w.lambda_eye, w.lambda_dir)
         times.append(time.perf_counter() - t0)
     t = float(np.median(times))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": w.nominal_rays / t / 1e6, "unit": "Mrays/s", "cores": oracle.default_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": model,
             "sample": f"full {w.width}x{w.height} K={w.passes} frame of the same scene, median of {reps} "
                       f"({t:.2f} s each; oracle BVH build not timed)"}
 
