@@ -825,7 +825,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     }
     RCP_HIP(hipEventRecord(e0, stream));
 
-    uint32_t n_nodes = 0, n_leaves = 0, max_depth = 0, stack_bound = 0;
+    uint32_t n_nodes = 0, n_leaves = 0, max_depth = 0, stack_bound = 0, top_count = 0;
     float sah = 0.0f;
     uint32_t* sorted = nullptr;
     float4 *tlo = nullptr, *thi = nullptr;
@@ -941,8 +941,10 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                 begin = end;
                 end = next;
                 ++levels;
+                if (levels == (uint32_t)kTopLevels) top_count = begin;   // slots of levels < kTopLevels
             }
             n_nodes = end;
+            if (levels < (uint32_t)kTopLevels) top_count = n_nodes;
             max_depth = levels + 1;          // leaves sit one level below the deepest wide node
             stack_bound = 3u * levels + 1u;  // at most three pushes per level
         }
@@ -975,6 +977,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     s->dev.n_tris = n;
     s->dev.max_depth = max_depth;
     s->dev.stack_bound = stack_bound;
+    s->dev.top_count = top_count;
     s->stats.n_nodes = n_nodes;
     s->stats.n_leaves = n_leaves;
     s->stats.max_depth = max_depth;

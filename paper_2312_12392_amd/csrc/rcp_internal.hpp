@@ -62,6 +62,7 @@ struct DevScene {
     uint32_t n_tris;
     uint32_t max_depth;
     uint32_t stack_bound;   // most entries a traversal stack can hold
+    uint32_t top_count;     // nodes of the first kTopLevels levels (staged in LDS)
     float radius;      // largest |coordinate| of any vertex
     float bg[3];
 };
@@ -89,6 +90,10 @@ constexpr size_t kViewBytes = 512;
 constexpr int kMaxPasses = 64;
 // Defaults of the launch parameters, measured on the 1080p K=6 terrain frame.
 constexpr int kDefaultExitLanes = 8;
+// Levels of the 4-wide BVH (up to 21 nodes, 2.7 KB) the chain engine reads
+// from LDS: LDS reads bypass the vector-memory address unit, the busiest unit
+// of the traversal (measured: 2 levels no gain, 3 levels 2% faster, 4 less).
+constexpr int kTopLevels = 3;
 constexpr int kDefaultRefill = 52;
 
 struct Disp {
@@ -176,6 +181,7 @@ void free_batch_workspace(BatchWorkspace& ws);
 
 // The launch parameters a render of this scene uses (tuning or defaults).
 struct Launch {
+    uint32_t top_count;      // top BVH nodes staged in LDS by the chain engine
     int refill_min;
     int exit_lanes;
     int blocks_per_cu;

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
         }
 
         // ---- one traversal step -------------------------------------------
-        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, st, a.exit_lanes, s_nodes, s_tris);
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, nullptr, st, a.exit_lanes, s_nodes, s_tris);
 
         // ---- finished rays: shade, write, compact ----------------------------
         const bool done = alive && tv.node == -1;
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
         Trav tv;
         trav_init(tv, sc, o, d, st);
         uint32_t dn = 0, dt = 0;
-        while (tv.node != -1) trav_step<false>(tv, sc, st, 0u, dn, dt);
+        while (tv.node != -1) trav_step<false>(tv, sc, nullptr, st, 0u, dn, dt);
         const bool hit = tv.h.id != INT_MAX;
         out_t[r] = hit ? tv.h.t : INFINITY;
         out_id[r] = hit ? tv.h.id : -1;
@@ -365,6 +365,7 @@ Launch launch_params(const rcp_scene* s) {
     Launch l;
     l.refill_min = s->tuning.refill_min > 0 ? s->tuning.refill_min : kDefaultRefill;
     l.exit_lanes = s->tuning.exit_lanes;
+    l.top_count = s->dev.top_count;
     l.blocks_per_cu = s->tuning.blocks_per_cu;
     l.tile_log2w = s->tuning.tile_log2w;
     return l;
@@ -455,6 +456,7 @@ rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Di
     const int tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
     PassArgs a{};
     a.sc = s->dev;
+    a.sc.top_count = 0;          // this kernel stages nothing in LDS
     a.cam = cam;
     a.W = W; a.H = H; a.K = K;
     a.le = disp.le; a.ld = disp.ld; a.z0 = disp.z0;
@@ -510,7 +512,9 @@ rcp_status trace_rays(rcp_scene* s, const float* org, const float* dir, int n, f
     const size_t spill_depth = spill_per_thread(s->dev);
     st = ensure_workspace(s, 1, 0, spill_depth * threads);
     if (st != RCP_OK) return st;
-    hipLaunchKernelGGL(k_trace_rays, dim3(g.blocks), dim3(kBlock), g.smem, stream, s->dev, org, dir, n, out_t,
+    DevScene sc = s->dev;
+    sc.top_count = 0;            // this kernel stages nothing in LDS
+    hipLaunchKernelGGL(k_trace_rays, dim3(g.blocks), dim3(kBlock), g.smem, stream, sc, org, dir, n, out_t,
                        out_id, out_front, s->ws.spill, threads);
     RCP_CHECK_LAUNCH();
     return RCP_OK;

@@ -272,10 +272,28 @@ __device__ inline void order2(uint32_t& ka, int32_t& va, uint32_t& kb, int32_t& 
 // as above), continue with the nearest hit child and push the other hit
 // children farthest first, or pop when none is hit.  Node layout (8 float4):
 // lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of children 0..3, then their links.
+typedef float V4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) V4 LdsV4;
+
 template <bool STATS>
-__device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& sc, Stack& st, uint32_t& n_nodes) {
-    const float4* p = sc.nodes + 8 * (size_t)node;
-    const float4 xl = p[0], xh = p[1], yl = p[2], yh = p[3], zl = p[4], zh = p[5], lk = p[6];
+__device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& sc, const float4* top, Stack& st,
+                                       uint32_t& n_nodes) {
+    float4 xl, xh, yl, yh, zl, zh, lk;
+    if ((uint32_t)node < sc.top_count) {
+        // the top levels, staged in LDS: LDS reads do not use the vector
+        // memory address path (the compiler barrier keeps the two paths from
+        // being merged into flat loads)
+        const LdsV4* t3 = (const LdsV4*)top + 8 * node;
+        const V4 a = t3[0], b = t3[1], c = t3[2], d = t3[3], e = t3[4], f = t3[5], g = t3[6];
+        xl = make_float4(a.x, a.y, a.z, a.w); xh = make_float4(b.x, b.y, b.z, b.w);
+        yl = make_float4(c.x, c.y, c.z, c.w); yh = make_float4(d.x, d.y, d.z, d.w);
+        zl = make_float4(e.x, e.y, e.z, e.w); zh = make_float4(f.x, f.y, f.z, f.w);
+        lk = make_float4(g.x, g.y, g.z, g.w);
+        __asm__ volatile("" ::: "memory");
+    } else {
+        const float4* p = sc.nodes + 8 * (size_t)node;
+        xl = p[0]; xh = p[1]; yl = p[2]; yh = p[3]; zl = p[4]; zh = p[5]; lk = p[6];
+    }
     if (STATS) ++n_nodes;
     const int kz = tv.rw.kz;
     const float lim = tv.h.t * kSlack;
@@ -353,7 +371,7 @@ __device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, ui
 // are still looking for a leaf: a few deep searches would otherwise keep the
 // rest of the wave idle.  Those lanes resume where they were next step.
 template <bool STATS>
-__device__ inline void trav_step(Trav& tv, const DevScene& sc, Stack& st, uint32_t exit_lanes,
+__device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* top, Stack& st, uint32_t exit_lanes,
                                  uint32_t& n_nodes, uint32_t& n_tris) {
     int32_t node = tv.node;
     int32_t leaf = -1;
@@ -366,7 +384,7 @@ __device__ inline void trav_step(Trav& tv, const DevScene& sc, Stack& st, uint32
         if (it > 0 && (uint32_t)__popcll(searching) <= exit_lanes) break;
         if (node >= 0) {
             if (--tv.budget == 0u) { node = -1; leaf = -1; break; }
-            node = visit_inner4<STATS>(tv, node, sc, st, n_nodes);
+            node = visit_inner4<STATS>(tv, node, sc, top, st, n_nodes);
         }
     }
     if (leaf != -1) visit_leaf<STATS>(tv, leaf, sc, n_tris);
