@@ -63,8 +63,8 @@ template <bool STATS, int MODE>
 __device__ inline void chain_body(const ChainArgs& a) {
     constexpr bool AUX = MODE != RCP_MODE_COLOR;
     extern __shared__ float4 smem[];
-    float4* top = smem;                                                   // top_count * 8
-    char* lds = (char*)(smem + 8 * a.sc.top_count);
+    float4* top = smem;                                                   // top_count * kStagedNodeF4
+    char* lds = (char*)(smem + kStagedNodeF4 * a.sc.top_count);
     unsigned long long* lstats = (unsigned long long*)lds;                // STATS: 4 * kMaxPasses
     if (STATS) lds += sizeof(unsigned long long) * 4 * kMaxPasses;
     uint32_t* vbegin = (uint32_t*)lds;                                    // n_views + 1
@@ -72,7 +72,8 @@ __device__ inline void chain_body(const ChainArgs& a) {
     int32_t* stack_area = (int32_t*)lds;                                  // kStack * kBlock
 
     for (int i = threadIdx.x; i <= a.n_views; i += kBlock) vbegin[i] = a.begin[i];
-    for (uint32_t i = threadIdx.x; i < 8 * a.sc.top_count; i += kBlock) top[i] = a.sc.nodes[i];
+    for (uint32_t i = threadIdx.x; i < kStagedNodeF4 * a.sc.top_count; i += kBlock)
+        top[i] = a.sc.nodes[8 * (i / kStagedNodeF4) + i % kStagedNodeF4];
     if (STATS)
         for (int i = threadIdx.x; i < 4 * kMaxPasses; i += kBlock) lstats[i] = 0ull;
     __syncthreads();
@@ -271,7 +272,7 @@ __global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint3
 }
 
 size_t chain_smem(const Launch& lp, bool stats, int n_views) {
-    size_t b = sizeof(float4) * 8 * (size_t)lp.top_count + sizeof(int32_t) * kStack * kBlock +
+    size_t b = sizeof(float4) * kStagedNodeF4 * (size_t)lp.top_count + sizeof(int32_t) * kStack * kBlock +
                sizeof(uint32_t) * (size_t)((n_views + 4) & ~3);
     if (stats) b += sizeof(unsigned long long) * 4 * kMaxPasses;
     return b;

@@ -90,10 +90,13 @@ constexpr size_t kViewBytes = 512;
 constexpr int kMaxPasses = 64;
 // Defaults of the launch parameters, measured on the 1080p K=6 terrain frame.
 constexpr int kDefaultExitLanes = 8;
-// Levels of the 4-wide BVH (up to 21 nodes, 2.7 KB) the chain engine reads
+// Levels of the 4-wide BVH (up to 85 nodes, 9.3 KB) the chain engine reads
 // from LDS: LDS reads bypass the vector-memory address unit, the busiest unit
-// of the traversal (measured: 2 levels no gain, 3 levels 2% faster, 4 less).
-constexpr int kTopLevels = 3;
+// of the traversal.  Measured: 2 levels no gain, 3 levels 2% faster, 4
+// levels 1% more as long as the workgroup's LDS still allows 6 per CU
+// (hence the 112-byte stride: the zero padding of a node is left out).
+constexpr int kTopLevels = 4;
+constexpr int kStagedNodeF4 = 7;
 constexpr int kDefaultRefill = 52;
 
 struct Disp {

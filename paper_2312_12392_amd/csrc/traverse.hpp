@@ -283,7 +283,7 @@ __device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& s
         // the top levels, staged in LDS: LDS reads do not use the vector
         // memory address path (the compiler barrier keeps the two paths from
         // being merged into flat loads)
-        const LdsV4* t3 = (const LdsV4*)top + 8 * node;
+        const LdsV4* t3 = (const LdsV4*)top + kStagedNodeF4 * node;
         const V4 a = t3[0], b = t3[1], c = t3[2], d = t3[3], e = t3[4], f = t3[5], g = t3[6];
         xl = make_float4(a.x, a.y, a.z, a.w); xh = make_float4(b.x, b.y, b.z, b.w);
         yl = make_float4(c.x, c.y, c.z, c.w); yh = make_float4(d.x, d.y, d.z, d.w);
