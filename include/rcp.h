@@ -397,9 +397,10 @@ rcp_status rcp_trace_rays(rcp_scene* scene, const float* org, const float* dir, 
  *            words 24-27         child links; 28-31 zero.
  *            A link with bit 31 clear is an inner node index; with bit 31
  *            set it is a leaf: bits 3..30 = first packed triangle,
- *            bits 0..2 = triangle count - 1; 0x7FFFFFFF marks an unused
- *            child slot (its planes are NaN).  Boxes are slightly wider
- *            than their contents (the traversal's conservative pruning).
+ *            bits 0..2 = triangle count - 1.  An unused child slot has NaN
+ *            planes (its link is the leaf of triangle 0, never entered).
+ *            Boxes are slightly wider than their contents (the traversal's
+ *            conservative pruning).
  *   tri_ids  [n_tris] original triangle index of each packed slot.
  * Either pointer may be NULL.  Synchronous. */
 rcp_status rcp_export_bvh(const rcp_scene* scene, uint32_t* nodes, int32_t* tri_ids);

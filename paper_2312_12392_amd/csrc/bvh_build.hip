@@ -592,9 +592,9 @@ __global__ __launch_bounds__(kB) void k_collapse4(const float4* __restrict__ n2,
                 src[base + (uint32_t)k] = c[i].link;
                 ++k;
             }
-        } else {   // empty slot: NaN planes fail every box test (and the empty link)
+        } else {   // unused slot: NaN planes fail every box test
             for (int a = 0; a < 3; ++a) { lo[a][i] = __int_as_float(0x7FC00000); hi[a][i] = lo[a][i]; }
-            link[i] = (uint32_t)kEmptyLink;
+            link[i] = leaf_link(0u, 1u);
         }
     }
     float4* o = n4 + 8 * (size_t)slot;

@@ -29,7 +29,9 @@ constexpr size_t kNodeBytes = 128;           // one 4-wide BVH node
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr int kMaxLeaf = 8;                // 3 bits of count
 constexpr uint32_t kMaxTris = 1u << 28;    // 28 bits of first triangle
-constexpr uint32_t kEmptyLink = 0x7FFFFFFFu; // unused child slot of a 4-wide node
+// Unused child slot of a 4-wide node: NaN planes, which fail every box test,
+// and a link to the one-triangle leaf of triangle 0, so that even a slot
+// that were entered could only repeat a test (never change the closest hit).
 
 __host__ __device__ inline uint32_t leaf_link(uint32_t first, uint32_t count) {
     return kLeafBit | (first << 3) | (count - 1u);

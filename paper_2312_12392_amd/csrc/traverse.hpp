@@ -313,8 +313,9 @@ __device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& s
         const float tmax = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
         const float near = kz == 0 ? ex : (kz == 1 ? ey : ez);
         const uint32_t link = __float_as_uint(lane_of(lk, i));
-        // an empty slot fails on its link and, independently, on its NaN planes
-        const bool hit = link != kEmptyLink && tmin <= tmax && near <= lim;
+        // an unused slot has NaN planes: tmax and near are NaN and both tests
+        // fail (its link, a one-triangle leaf, is never followed)
+        const bool hit = tmin <= tmax && near <= lim;
         key[i] = hit ? __float_as_uint(tmin) : 0xFFFFFFFFu;
         val[i] = (int32_t)link;
         nh += hit ? 1u : 0u;

@@ -9,7 +9,6 @@ from paper_2312_12392_amd import rcp
 pytestmark = pytest.mark.gpu
 
 LEAF = 0x80000000
-EMPTY = 0x7FFFFFFF
 
 
 def say(*a):
@@ -48,12 +47,13 @@ def check_bvh(scene, info, nodes, tri_ids):
     assert info["node_bytes"] == 128 and nodes.shape == (nn, 32)
     assert (nodes[:, 28:32] == 0).all()
     lo, hi, links = node_boxes(nodes)
-    valid = links != EMPTY
-    # used slots first, at least two per node; unused slots have NaN planes
+    # unused slots: all six planes NaN, link = the leaf of triangle 0
+    valid = ~np.isnan(lo).any(axis=2)
+    assert (np.isnan(lo[~valid]).all() and np.isnan(hi[~valid]).all() and not np.isnan(hi[valid]).any())
+    assert (links[~valid] == (LEAF | 0)).all()
+    # used slots first, at least two per node
     assert valid[:, :2].all()
     assert (valid[:, 1:] <= valid[:, :-1]).all()
-    assert np.isnan(lo[~valid]).all() and np.isnan(hi[~valid]).all()
-    assert not np.isnan(lo[valid]).any() and not np.isnan(hi[valid]).any()
     is_leaf = valid & ((links & LEAF) != 0)
     is_inner = valid & ~is_leaf
     # leaves: range inside the triangles, size within the bound, boxes contain them
