@@ -72,15 +72,18 @@ def algorithmic_bytes(counts, engine="chain"):
     return total
 
 
-def cpu_baseline(w, reps=3):
+def cpu_baseline(w, min_seconds=10.0, min_reps=3, max_reps=60):
+    """The oracle on the host cores: whole frames until at least min_seconds
+    of work (and min_reps frames) have run; the median frame is reported."""
     import numpy as np
     import oracle
     o = oracle.OracleScene(w.scene, use_bvh=True)
     times = []
-    for _ in range(reps):
+    while len(times) < min_reps or (sum(times) < min_seconds and len(times) < max_reps):
         t0 = time.perf_counter()
         o.render(w.camera, w.width, w.height, w.passes, w.lambda_eye, w.lambda_dir)
         times.append(time.perf_counter() - t0)
+    reps = len(times)
     t = float(np.median(times))
     model = "unknown"
     try:
@@ -90,8 +93,8 @@ def cpu_baseline(w, reps=3):
         pass
     return {"value": w.nominal_rays / t / 1e6, "unit": "Mrays/s", "cores": oracle.default_threads(),
             "kind": "oracle", "cpu": model,
-            "sample": f"full {w.width}x{w.height} K={w.passes} frame of the same scene, median of {reps} "
-                      f"({t:.2f} s each; oracle BVH build not timed)"}
+            "sample": f"full {w.width}x{w.height} K={w.passes} frames of the same scene, median of {reps} "
+                      f"({t:.2f} s each, {sum(times):.1f} s in all; oracle BVH build not timed)"}
 
 
 def main():
