@@ -11,7 +11,8 @@
 //   5. bottom-up refit with per-node arrival counters; each node also gets its
 //      SAH cost and is collapsed into a leaf (<= max_leaf triangles) when that
 //      is cheaper than keeping the split
-//   6. packing of the binary tree into 64-byte nodes in depth-first order
+//   6. packing of the binary tree (two children's boxes and links per
+//      node) in depth-first order
 //   7. collapse into 128-byte 4-wide nodes, level by level: the tree the
 //      traversal uses
 //   8. packing of 48-byte triangles, a per-triangle table of the two shaded

@@ -12,6 +12,11 @@
 // per-pass state in HBM are needed, and views of any size, pass count and
 // mode share one launch and its tail.
 //
+// The work that is not traversal -- finishing a traced pass (shade, write,
+// decide) and setting up rays (new pixels, next passes) -- runs in setup
+// rounds, when at least refill_min lanes of the wave wait for it, so that it
+// runs with most of the wave's lanes instead of a few at a time.
+//
 // The same kernel serves rcp_render and rcp_render_batch.  Views are read
 // from a device table by each lane; a single render's one-entry table is
 // written by a setup kernel from its by-value argument, so a captured graph
