@@ -153,12 +153,15 @@ typedef struct {
 /* ---------------------------------------------------------------------- */
 
 /* Copy the scene to the device and build its BVH (Morton codes, radix sort,
- * binary radix tree, bottom-up refit with SAH leaf collapse, packing).  The
- * call is synchronous: it returns once the scene is ready.  desc pointers
- * are host pointers (see rcp_scene_desc); opts may be NULL.
+ * PLOC or radix binary tree, bottom-up refit with SAH leaf collapse, 4-wide
+ * collapse, packing).  The call is synchronous: it returns once the scene is
+ * ready.  desc pointers are host pointers (see rcp_scene_desc); opts may be
+ * NULL.  Limits: n_tris <= 2^28 - 8, and at most 2^25 BVH nodes (4 GB of
+ * nodes, about 10^8 triangles).
  * Errors: RCP_ERR_INVALID_ARGUMENT (NULL desc/out, idx >= n_verts, a
- * non-finite vertex, light or background value, invalid options),
- * RCP_ERR_OUT_OF_MEMORY, RCP_ERR_DEVICE.  On error *out is set to NULL. */
+ * non-finite vertex, light or background value, invalid options, a scene
+ * beyond the limits), RCP_ERR_OUT_OF_MEMORY, RCP_ERR_DEVICE.  On error *out
+ * is set to NULL. */
 rcp_status rcp_build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts,
                            void* hip_stream, rcp_scene** out);
 

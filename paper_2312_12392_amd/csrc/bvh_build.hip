@@ -946,6 +946,11 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
             }
             n_nodes = end;
             if (levels < (uint32_t)kTopLevels) top_count = n_nodes;
+            if (top_count > kMaxStagedNodes) top_count = kMaxStagedNodes;
+            if (n_nodes > kMaxNodes) {
+                set_error("the scene needs %u BVH nodes, more than the %u a scene can hold", n_nodes, kMaxNodes);
+                return RCP_ERR_INVALID_ARGUMENT;
+            }
             max_depth = levels + 1;          // leaves sit one level below the deepest wide node
             stack_bound = 3u * levels + 1u;  // at most three pushes per level
         }

@@ -57,28 +57,38 @@ struct ChainArgs {
     unsigned long long* stats;   // [K][4] (STATS): rays, inner nodes, triangles, rays continued
 };
 
-__device__ inline void tile_pixel(const ViewDev& vw, uint32_t local, int& x, int& y) {
+template <class View>
+__device__ inline void tile_pixel(const View& vw, uint32_t local, int& x, int& y) {
     const uint32_t tile = local >> 6, l = local & 63u;
     const uint32_t tw = 1u << vw.tile_log2w;
     x = (int)((tile % (uint32_t)vw.tiles_x) * tw + (l & (tw - 1u)));
     y = (int)((tile / (uint32_t)vw.tiles_x) * (64u >> vw.tile_log2w) + (l >> vw.tile_log2w));
 }
 
-template <bool STATS, int MODE>
+// ONE: the launch holds a single view.  Its entry is then read with scalar
+// loads (the table is constant during the launch), not per lane through the
+// vector-memory path, which the traversal keeps busy.
+typedef __attribute__((address_space(4))) ViewDev ConstView;
+
+template <bool STATS, int MODE, bool ONE>
 __device__ inline void chain_body(const ChainArgs& a) {
     constexpr bool AUX = MODE != RCP_MODE_COLOR;
+    // the staged top levels sit at a fixed LDS address, so node offsets need
+    // no base added
     extern __shared__ float4 smem[];
-    float4* top = smem;                                                   // top_count * kStagedNodeF4
-    char* lds = (char*)(smem + kStagedNodeF4 * a.sc.top_count);
+    float4* top = smem;
+    char* lds = (char*)(smem + 8 * (size_t)a.sc.top_count);
     unsigned long long* lstats = (unsigned long long*)lds;                // STATS: 4 * kMaxPasses
     if (STATS) lds += sizeof(unsigned long long) * 4 * kMaxPasses;
     uint32_t* vbegin = (uint32_t*)lds;                                    // n_views + 1
     lds += sizeof(uint32_t) * (size_t)((a.n_views + 4) & ~3);
     int32_t* stack_area = (int32_t*)lds;                                  // kStack * kBlock
 
-    for (int i = threadIdx.x; i <= a.n_views; i += kBlock) vbegin[i] = a.begin[i];
-    for (uint32_t i = threadIdx.x; i < kStagedNodeF4 * a.sc.top_count; i += kBlock)
-        top[i] = a.sc.nodes[8 * (i / kStagedNodeF4) + i % kStagedNodeF4];
+    const ConstView* views = (const ConstView*)a.views;
+    if (!ONE)
+        for (int i = threadIdx.x; i <= a.n_views; i += kBlock) vbegin[i] = a.begin[i];
+    for (uint32_t i = threadIdx.x; i < 8u * a.sc.top_count; i += kBlock)
+        if ((i & 7u) != 7u) top[i] = a.sc.nodes[i];   // the zero padding is never read
     if (STATS)
         for (int i = threadIdx.x; i < 4 * kMaxPasses; i += kBlock) lstats[i] = 0ull;
     __syncthreads();
@@ -115,7 +125,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
             // of the next pass or end the chain
             if (ended) {
                 {
-                    const ViewDev& vw = a.views[v];
+                    const ConstView& vw = views[ONE ? 0 : v];
                     float rgb[3];
                     float na[4] = {INFINITY, 0.0f, 0.0f, 0.0f};
                     int32_t hid = -1;
@@ -192,15 +202,17 @@ __device__ inline void chain_body(const ChainArgs& a) {
                 const uint32_t item = base + lanes_below(idle);
                 if (item < n_items) {
                     // the view holding this item: last begin <= item
-                    int lo = 0, hi = a.n_views;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (vbegin[mid] <= item) lo = mid; else hi = mid;
+                    if (!ONE) {
+                        int lo = 0, hi = a.n_views;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (vbegin[mid] <= item) lo = mid; else hi = mid;
+                        }
+                        v = lo;
                     }
-                    v = lo;
-                    const uint32_t local = item - vbegin[v];
+                    const uint32_t local = ONE ? item : item - vbegin[v];
                     {
-                        const ViewDev& vw = a.views[v];
+                        const ConstView& vw = views[ONE ? 0 : v];
                         tile_pixel(vw, local, x, y);
                         if (x < vw.W && y < vw.H) {
                             k = 0;
@@ -212,7 +224,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
                 }
             }
             if (init) {
-                const ViewDev& vw = a.views[v];
+                const ConstView& vw = views[ONE ? 0 : v];
                 float o[3], d[3];
                 make_ray<MODE>(vw.cam, vw.hw, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, o, d);
                 trav_init(tv, a.sc, o, d, st);
@@ -245,14 +257,14 @@ __device__ inline void chain_body(const ChainArgs& a) {
 // Colour mode, the default: asking for 6 waves per SIMD (at most 80 VGPRs,
 // a few bytes of spill) was measured faster than the 5 its 82 registers
 // allow.  The depth and normal modes keep the compiler's choice.
-template <bool STATS>
+template <bool STATS, bool ONE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_chain(ChainArgs a) {
-    chain_body<STATS, RCP_MODE_COLOR>(a);
+    chain_body<STATS, RCP_MODE_COLOR, ONE>(a);
 }
 
-template <bool STATS, int MODE>
+template <bool STATS, int MODE, bool ONE>
 __global__ __launch_bounds__(kBlock) void k_chain_aux(ChainArgs a) {
-    chain_body<STATS, MODE>(a);
+    chain_body<STATS, MODE, ONE>(a);
 }
 
 // Zero the work counters (one per launch, 16 words apart) and the stats.
@@ -277,23 +289,24 @@ __global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint3
 }
 
 size_t chain_smem(const Launch& lp, bool stats, int n_views) {
-    size_t b = sizeof(float4) * kStagedNodeF4 * (size_t)lp.top_count + sizeof(int32_t) * kStack * kBlock +
+    // dynamic part only: the staged top levels are a static array
+    size_t b = kNodeBytes * (size_t)lp.top_count + sizeof(int32_t) * kStack * kBlock +
                sizeof(uint32_t) * (size_t)((n_views + 4) & ~3);
     if (stats) b += sizeof(unsigned long long) * 4 * kMaxPasses;
     return b;
 }
 
-template <bool STATS, int MODE>
+template <bool STATS, int MODE, bool ONE>
 const void* chain_kernel() {
-    if constexpr (MODE == RCP_MODE_COLOR) return (const void*)k_chain<STATS>;
-    else return (const void*)k_chain_aux<STATS, MODE>;
+    if constexpr (MODE == RCP_MODE_COLOR) return (const void*)k_chain<STATS, ONE>;
+    else return (const void*)k_chain_aux<STATS, MODE, ONE>;
 }
 
-template <bool STATS, int MODE>
+template <bool STATS, int MODE, bool ONE>
 rcp_status chain_grid(const Launch& lp, int n_views, int& blocks, size_t& smem) {
     smem = chain_smem(lp, STATS, n_views);
     int per_cu = 0, dev = 0, cus = 0;
-    RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chain_kernel<STATS, MODE>(), kBlock, smem));
+    RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chain_kernel<STATS, MODE, ONE>(), kBlock, smem));
     RCP_HIP(hipGetDevice(&dev));
     RCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     if (per_cu < 1) per_cu = 1;
@@ -302,28 +315,44 @@ rcp_status chain_grid(const Launch& lp, int n_views, int& blocks, size_t& smem) 
     return RCP_OK;
 }
 
+template <bool STATS, bool ONE>
+rcp_status chain_grid_mode1(const Launch& lp, int n_views, int mode, int& blocks, size_t& smem) {
+    switch (mode) {
+        case RCP_MODE_DEPTH: return chain_grid<STATS, RCP_MODE_DEPTH, ONE>(lp, n_views, blocks, smem);
+        case RCP_MODE_NORMAL: return chain_grid<STATS, RCP_MODE_NORMAL, ONE>(lp, n_views, blocks, smem);
+        default: return chain_grid<STATS, RCP_MODE_COLOR, ONE>(lp, n_views, blocks, smem);
+    }
+}
+
+// Grid of a launch over n_views views in `mode` (the single-view kernels
+// when n_views == 1).
 template <bool STATS>
 rcp_status chain_grid_mode(const Launch& lp, int n_views, int mode, int& blocks, size_t& smem) {
+    return n_views == 1 ? chain_grid_mode1<STATS, true>(lp, n_views, mode, blocks, smem)
+                        : chain_grid_mode1<STATS, false>(lp, n_views, mode, blocks, smem);
+}
+
+template <bool STATS, bool ONE>
+void launch_chain_mode1(int mode, int blocks, size_t smem, hipStream_t stream, const ChainArgs& a) {
     switch (mode) {
-        case RCP_MODE_DEPTH: return chain_grid<STATS, RCP_MODE_DEPTH>(lp, n_views, blocks, smem);
-        case RCP_MODE_NORMAL: return chain_grid<STATS, RCP_MODE_NORMAL>(lp, n_views, blocks, smem);
-        default: return chain_grid<STATS, RCP_MODE_COLOR>(lp, n_views, blocks, smem);
+        case RCP_MODE_DEPTH:
+            hipLaunchKernelGGL((k_chain_aux<STATS, RCP_MODE_DEPTH, ONE>), dim3(blocks), dim3(kBlock), smem, stream,
+                               a);
+            break;
+        case RCP_MODE_NORMAL:
+            hipLaunchKernelGGL((k_chain_aux<STATS, RCP_MODE_NORMAL, ONE>), dim3(blocks), dim3(kBlock), smem, stream,
+                               a);
+            break;
+        default:
+            hipLaunchKernelGGL((k_chain<STATS, ONE>), dim3(blocks), dim3(kBlock), smem, stream, a);
+            break;
     }
 }
 
 template <bool STATS>
 void launch_chain_mode(int mode, int blocks, size_t smem, hipStream_t stream, const ChainArgs& a) {
-    switch (mode) {
-        case RCP_MODE_DEPTH:
-            hipLaunchKernelGGL((k_chain_aux<STATS, RCP_MODE_DEPTH>), dim3(blocks), dim3(kBlock), smem, stream, a);
-            break;
-        case RCP_MODE_NORMAL:
-            hipLaunchKernelGGL((k_chain_aux<STATS, RCP_MODE_NORMAL>), dim3(blocks), dim3(kBlock), smem, stream, a);
-            break;
-        default:
-            hipLaunchKernelGGL((k_chain<STATS>), dim3(blocks), dim3(kBlock), smem, stream, a);
-            break;
-    }
+    if (a.n_views == 1) launch_chain_mode1<STATS, true>(mode, blocks, smem, stream, a);
+    else launch_chain_mode1<STATS, false>(mode, blocks, smem, stream, a);
 }
 
 size_t spill_depth_of(const rcp_scene* s) {

@@ -64,7 +64,7 @@ struct DevScene {
     uint32_t n_tris;
     uint32_t max_depth;
     uint32_t stack_bound;   // most entries a traversal stack can hold
-    uint32_t top_count;     // nodes of the first kTopLevels levels (staged in LDS)
+    uint32_t top_count;     // nodes of the first kTopLevels levels, at most kMaxStagedNodes (staged in LDS)
     float radius;      // largest |coordinate| of any vertex
     float bg[3];
 };
@@ -92,13 +92,16 @@ constexpr size_t kViewBytes = 512;
 constexpr int kMaxPasses = 64;
 // Defaults of the launch parameters, measured on the 1080p K=6 terrain frame.
 constexpr int kDefaultExitLanes = 8;
-// Levels of the 4-wide BVH (up to 85 nodes, 9.3 KB) the chain engine reads
-// from LDS: LDS reads bypass the vector-memory address unit, the busiest unit
-// of the traversal.  Measured: 2 levels no gain, 3 levels 2% faster, 4
-// levels 1% more as long as the workgroup's LDS still allows 6 per CU
-// (hence the 112-byte stride: the zero padding of a node is left out).
+// Levels of the 4-wide BVH the chain engine reads from LDS: LDS reads bypass
+// the vector-memory address unit, the busiest unit of the traversal.
+// Measured: 2 levels no gain, 3 levels 2% faster, 4 levels 1% more as long as
+// the workgroup's LDS still allows 6 per CU.  Staged nodes keep their
+// 128-byte layout, so at most kMaxStagedNodes of the 85 nodes of 4 levels
+// (10 KB next to the 16 KB stack area).
 constexpr int kTopLevels = 4;
-constexpr int kStagedNodeF4 = 7;
+constexpr uint32_t kMaxStagedNodes = 80;
+// The node array is addressed with 32-bit byte offsets.
+constexpr uint32_t kMaxNodes = 1u << 25;
 constexpr int kDefaultRefill = 52;
 
 struct Disp {

@@ -47,9 +47,9 @@ __host__ __device__ inline float half_width(float th, int W, int H) {
 // normal): the colour vector (2R-1) right + (2G-1) up + (2B-1) forward
 // (Section 3), that vector times |z - z0| (Section 4, none after a miss), or
 // C x N with C the undisplaced view direction (Section 5).
-// hw is half_width(c.th, W, H).
-template <int MODE>
-__device__ inline void make_ray(const Camera& c, float hw, int W, int H, int x, int y, float pr, float pg, float pb,
+// hw is half_width(c.th, W, H).  Cam is Camera, in any address space.
+template <int MODE, class Cam>
+__device__ inline void make_ray(const Cam& c, float hw, int W, int H, int x, int y, float pr, float pg, float pb,
                                 const float aux[4], float z0, float le, float ld, float o[3], float d[3]) {
     const float fx = (float)(2 * x + 1) / (float)W - 1.0f;
     const float fy = 1.0f - (float)(2 * y + 1) / (float)H;
@@ -221,9 +221,17 @@ struct Stack {
 // the current one is finished.
 struct Trav {
     RayW rw;
-    float ix, iy, iz;       // reciprocal direction
-    float lx, ly, lz;       // (o + pad) * inv: used against lo planes
-    float hx, hy, hz;       // (o - pad) * inv: used against hi planes
+    // Box test constants per axis, in the order kx, ky, kz of the watertight
+    // test, so that the dominant axis is always the third.  For each axis the
+    // ray enters a slab through the plane facing it (lo when the direction
+    // component is positive, hi otherwise) and leaves through the other, so
+    // the lane loads the entry and exit planes directly and needs no min/max
+    // per slab.
+    float inv[3];           // reciprocal direction component
+    float ent[3];           // (o -/+ pad) * inv for the entry plane (lo: o + pad, hi: o - pad)
+    float ext[3];           // the same for the exit plane
+    uint32_t off[3];        // byte offset of the entry plane in a node: 32 * axis + 16 * (inv < 0);
+                            // the exit plane is at off ^ 16
     int32_t node;           // >= 0 inner node, other negative: leaf link, -1: finished
     uint32_t budget;
     Hit h;
@@ -237,14 +245,25 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
     // far inside the box widening, so no correctly rounded division here.
     for (int a = 0; a < 3; ++a)
         inv[a] = fabsf(d[a]) > 1e-30f ? __builtin_amdgcn_rcpf(d[a]) : copysignf(1e30f, d[a]);
-    tv.ix = inv[0]; tv.iy = inv[1]; tv.iz = inv[2];
     // A plane at coordinate c is reached at t = c * inv - (o -/+ pad) * inv,
     // one fused multiply-add per plane.  Its rounding (a few ulp of |o * inv|)
     // is far inside the 2^-18 (R + max|o|) widening, so the bounds stay safe.
+    // Rounding is monotonic, so the entry plane's t is never above the exit
+    // plane's: the same values a min/max over the two planes would give.
     const float pad = (sc.radius + fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]))) * 3.814697265625e-6f;
-    tv.lx = (o[0] + pad) * inv[0]; tv.hx = (o[0] - pad) * inv[0];
-    tv.ly = (o[1] + pad) * inv[1]; tv.hy = (o[1] - pad) * inv[1];
-    tv.lz = (o[2] + pad) * inv[2]; tv.hz = (o[2] - pad) * inv[2];
+    const int ax[3] = {tv.rw.kx, tv.rw.ky, tv.rw.kz};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float iv = sel3(inv[0], inv[1], inv[2], ax[j]);
+        const float oa = sel3(o[0], o[1], o[2], ax[j]);
+        const float lo_term = (oa + pad) * iv;   // against lo planes
+        const float hi_term = (oa - pad) * iv;   // against hi planes
+        const bool neg = iv < 0.0f;
+        tv.inv[j] = iv;
+        tv.ent[j] = neg ? hi_term : lo_term;
+        tv.ext[j] = neg ? lo_term : hi_term;
+        tv.off[j] = 32u * (uint32_t)ax[j] + (neg ? 16u : 0u);
+    }
     tv.node = sc.n_nodes > 0 ? 0 : -1;
     // Every node and leaf is entered at most once per ray; the bound only
     // guarantees termination should the tree ever be malformed.
@@ -270,52 +289,60 @@ __device__ inline void order2(uint32_t& ka, int32_t& va, uint32_t& kb, int32_t& 
 
 // Visit one 4-wide node: test the four child boxes (same conservative rules
 // as above), continue with the nearest hit child and push the other hit
-// children farthest first, or pop when none is hit.  Node layout (8 float4):
-// lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of children 0..3, then their links.
+// children farthest first, or pop when none is hit.  Node layout (8 float4,
+// 128 bytes): lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of children 0..3, then their
+// links.  The top levels staged in LDS keep the same 128-byte layout, so one
+// set of offsets serves both.
 typedef float V4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) V4 LdsV4;
+
+__device__ inline float4 f4(V4 v) { return make_float4(v.x, v.y, v.z, v.w); }
 
 template <bool STATS>
 __device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& sc, const float4* top, Stack& st,
                                        uint32_t& n_nodes) {
-    float4 xl, xh, yl, yh, zl, zh, lk;
+    // byte offsets of the entry and exit planes of the three axes (the
+    // node array is limited to 4 GB, so offsets fit 32 bits)
+    const uint32_t base = (uint32_t)node << 7;
+    const uint32_t e0 = base + tv.off[0], e1 = base + tv.off[1], e2 = base + tv.off[2];
+    float4 n0, x0, n1, x1, n2, x2, lk;
     if ((uint32_t)node < sc.top_count) {
         // the top levels, staged in LDS: LDS reads do not use the vector
         // memory address path (the compiler barrier keeps the two paths from
         // being merged into flat loads)
-        const LdsV4* t3 = (const LdsV4*)top + kStagedNodeF4 * node;
-        const V4 a = t3[0], b = t3[1], c = t3[2], d = t3[3], e = t3[4], f = t3[5], g = t3[6];
-        xl = make_float4(a.x, a.y, a.z, a.w); xh = make_float4(b.x, b.y, b.z, b.w);
-        yl = make_float4(c.x, c.y, c.z, c.w); yh = make_float4(d.x, d.y, d.z, d.w);
-        zl = make_float4(e.x, e.y, e.z, e.w); zh = make_float4(f.x, f.y, f.z, f.w);
-        lk = make_float4(g.x, g.y, g.z, g.w);
+        const char __attribute__((address_space(3)))* t = (const char __attribute__((address_space(3)))*)top;
+        n0 = f4(*(const LdsV4*)(t + e0)); x0 = f4(*(const LdsV4*)(t + (e0 ^ 16u)));
+        n1 = f4(*(const LdsV4*)(t + e1)); x1 = f4(*(const LdsV4*)(t + (e1 ^ 16u)));
+        n2 = f4(*(const LdsV4*)(t + e2)); x2 = f4(*(const LdsV4*)(t + (e2 ^ 16u)));
+        lk = f4(*(const LdsV4*)(t + base + 96u));
         __asm__ volatile("" ::: "memory");
     } else {
-        const float4* p = sc.nodes + 8 * (size_t)node;
-        xl = p[0]; xh = p[1]; yl = p[2]; yh = p[3]; zl = p[4]; zh = p[5]; lk = p[6];
+        const char* g = (const char*)sc.nodes;
+        n0 = *(const float4*)(g + e0); x0 = *(const float4*)(g + (e0 ^ 16u));
+        n1 = *(const float4*)(g + e1); x1 = *(const float4*)(g + (e1 ^ 16u));
+        n2 = *(const float4*)(g + e2); x2 = *(const float4*)(g + (e2 ^ 16u));
+        lk = *(const float4*)(g + base + 96u);
     }
     if (STATS) ++n_nodes;
-    const int kz = tv.rw.kz;
     const float lim = tv.h.t * kSlack;
     uint32_t key[4];    // entry distance bits of hit children (t >= 0), all ones for the rest
     int32_t val[4];
     uint32_t nh = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const float a0 = __builtin_fmaf(lane_of(xl, i), tv.ix, -tv.lx);
-        const float a1 = __builtin_fmaf(lane_of(xh, i), tv.ix, -tv.hx);
-        const float a2 = __builtin_fmaf(lane_of(yl, i), tv.iy, -tv.ly);
-        const float a3 = __builtin_fmaf(lane_of(yh, i), tv.iy, -tv.hy);
-        const float a4 = __builtin_fmaf(lane_of(zl, i), tv.iz, -tv.lz);
-        const float a5 = __builtin_fmaf(lane_of(zh, i), tv.iz, -tv.hz);
-        const float ex = fminf(a0, a1), ey = fminf(a2, a3), ez = fminf(a4, a5);
-        const float tmin = fmaxf(fmaxf(ex, ey), fmaxf(ez, 0.0f));
-        const float tmax = fminf(fminf(fmaxf(a0, a1), fmaxf(a2, a3)), fmaxf(a4, a5)) * kSlack;
-        const float near = kz == 0 ? ex : (kz == 1 ? ey : ez);
+        const float a0 = __builtin_fmaf(lane_of(n0, i), tv.inv[0], -tv.ent[0]);
+        const float b0 = __builtin_fmaf(lane_of(x0, i), tv.inv[0], -tv.ext[0]);
+        const float a1 = __builtin_fmaf(lane_of(n1, i), tv.inv[1], -tv.ent[1]);
+        const float b1 = __builtin_fmaf(lane_of(x1, i), tv.inv[1], -tv.ext[1]);
+        const float a2 = __builtin_fmaf(lane_of(n2, i), tv.inv[2], -tv.ent[2]);
+        const float b2 = __builtin_fmaf(lane_of(x2, i), tv.inv[2], -tv.ext[2]);
+        const float tmin = fmaxf(fmaxf(a0, a1), fmaxf(a2, 0.0f));
+        const float tmax = fminf(fminf(b0, b1), b2) * kSlack;
         const uint32_t link = __float_as_uint(lane_of(lk, i));
-        // an unused slot has NaN planes: tmax and near are NaN and both tests
-        // fail (its link, a one-triangle leaf, is never followed)
-        const bool hit = tmin <= tmax && near <= lim;
+        // a2 is the entry of the dominant axis's slab (see above).  An unused
+        // slot has NaN planes: tmax and a2 are NaN and both tests fail (its
+        // link, a one-triangle leaf, is never followed)
+        const bool hit = tmin <= tmax && a2 <= lim;
         key[i] = hit ? __float_as_uint(tmin) : 0xFFFFFFFFu;
         val[i] = (int32_t)link;
         nh += hit ? 1u : 0u;
