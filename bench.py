@@ -117,7 +117,10 @@ def main():
     ap.add_argument("--engine", choices=["chain", "passes"], default="chain",
                     help="chain: one persistent launch per frame; passes: one launch per pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--max-leaf", type=int, default=None, help="BVH leaf size bound (build option)")
+    ap.add_argument("--max-leaf", type=int, default=4, help="BVH leaf size bound (build option)")
+    ap.add_argument("--collapse", choices=["sah", "greedy"], default="sah",
+                    help="how the 4-wide tree is formed from the binary tree (build option)")
+    ap.add_argument("--builder", choices=["ploc", "lbvh"], default="ploc", help="binary tree builder (build option)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -135,6 +138,14 @@ def main():
     bench_frame(args)
 
 
+def build_options(args):
+    """The BVH build options named on the command line."""
+    from paper_2312_12392_amd import rcp
+    return rcp.build_options(max_leaf=args.max_leaf,
+                             builder=rcp.RCP_BUILDER_PLOC if args.builder == "ploc" else rcp.RCP_BUILDER_LBVH,
+                             collapse=rcp.RCP_COLLAPSE_SAH if args.collapse == "sah" else rcp.RCP_COLLAPSE_GREEDY)
+
+
 def bench_frame(args):
     import numpy as np
     import torch
@@ -145,10 +156,7 @@ def bench_frame(args):
     stream = torch.cuda.current_stream()
     w = scenegen.workload(args.workload, literal_eye=args.literal_eye)
     log(f"workload {w.name}: {w.width}x{w.height} K={w.passes} tris={w.scene.n_tris}")
-    opts = None
-    if args.max_leaf is not None:
-        opts = rcp.build_options(max_leaf=args.max_leaf)
-    scene = rcp.Scene(w.scene, opts)
+    scene = rcp.Scene(w.scene, build_options(args))
     scene.set_engine(rcp.RCP_ENGINE_CHAIN if args.engine == "chain" else rcp.RCP_ENGINE_PASSES)
     kernel = KERNEL_OF_ENGINE[args.engine]
     info = scene.info()
@@ -233,7 +241,8 @@ def bench_frame(args):
         "traced_rays_per_frame": traced,
         "active_per_pass": [int(c) for c in counts[:, 0]],
         "bvh_build_ms": round(info["build_ms"], 3),
-        "bvh": {"nodes": info["n_nodes"], "sah_cost": round(info["sah_cost"], 3), "max_depth": info["max_depth"]},
+        "bvh": {"nodes": info["n_nodes"], "sah_cost": round(info["sah_cost"], 3), "max_depth": info["max_depth"],
+                "builder": args.builder, "collapse": args.collapse, "max_leaf": args.max_leaf},
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved_gbs, 1),
@@ -272,7 +281,7 @@ def bench_batch(args):
     stream = torch.cuda.current_stream()
     w = scenegen.workload("terrain1m")
     views = scenegen.orbit_views(3, 64)
-    scene = rcp.Scene(w.scene)
+    scene = rcp.Scene(w.scene, build_options(args))
     d = rcp.make_displacement(0.0, w.lambda_dir)
     outs = [torch.empty((K, H, W, 3), device="cuda") for (_, W, H, K) in views]
     batch = [(cam, W, H, K, d, o, None) for (cam, W, H, K), o in zip(views, outs)]
@@ -344,7 +353,7 @@ def bench_served(args):
 
     stream = torch.cuda.current_stream()
     w = scenegen.workload("terrain4m")
-    scene = rcp.Scene(w.scene)
+    scene = rcp.Scene(w.scene, build_options(args))
     d = rcp.make_displacement(0.0, w.lambda_dir)
     rates = [float(r) for r in args.rates.split(",")]
     per_rate = {}
@@ -423,7 +432,7 @@ def bench_walk(args):
     stream = torch.cuda.current_stream()
     w = scenegen.workload("terrain16m")
     log(f"terrain16m: {w.scene.n_tris} triangles")
-    scene = rcp.Scene(w.scene)
+    scene = rcp.Scene(w.scene, build_options(args))
     info = scene.info()
     W, H, K = w.width, w.height, w.passes
     imgs = torch.empty((K, H, W, 3), device="cuda")
@@ -449,7 +458,8 @@ def bench_walk(args):
         "config": {"workload": f"terrain16m: {W}x{H}, K={K}, {w.scene.n_tris} triangles, {args.frames}-frame spline "
                                "walk-through, lambda_dir 0.01", "frames": args.frames},
         "frame_ms": _percentiles(ms), "bvh_build_ms": round(info["build_ms"], 2),
-        "bvh": {"nodes": info["n_nodes"], "sah_cost": round(info["sah_cost"], 3), "max_depth": info["max_depth"]},
+        "bvh": {"nodes": info["n_nodes"], "sah_cost": round(info["sah_cost"], 3), "max_depth": info["max_depth"],
+                "builder": args.builder, "collapse": args.collapse, "max_leaf": args.max_leaf},
     }
 
 
@@ -462,7 +472,7 @@ def bench_gather(args):
 
     stream = torch.cuda.current_stream()
     w = scenegen.workload("terrain1m")
-    scene = rcp.Scene(w.scene)
+    scene = rcp.Scene(w.scene, build_options(args))
     W, H, n = 3840, 2160, 5
     base = torch.empty((1, H, W, 3), device="cuda")
     rcp.rcp_render(scene.handle, w.camera, W, H, 1, rcp.make_displacement(0.0, 0.0), base, None, stream)

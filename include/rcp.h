@@ -118,20 +118,30 @@ typedef struct {
 /* Build options (NULL = defaults).
  *   max_leaf        most triangles per BVH leaf (1..8, default 4)
  *   c_trav, c_isect SAH costs of a node visit and a triangle test (defaults
- *                   1, 1), used when leaves are formed in the binary tree
- *                   that the 4-wide traversal tree is collapsed from
+ *                   1, 1), used when the 4-wide traversal tree is formed
+ *                   from the binary tree (the SAH collapse also charges
+ *                   2 * c_trav for entering a leaf)
  *   builder         how that binary tree is built from the Morton-sorted
  *                   triangles: RCP_BUILDER_PLOC (default; agglomerative
  *                   clustering of nearest neighbours, a lower SAH cost) or
  *                   RCP_BUILDER_LBVH (binary radix tree, faster to build).
- * The builder changes the speed of rendering only, never an image. */
+ *   collapse        how the binary tree becomes the 4-wide traversal tree:
+ *                   RCP_COLLAPSE_SAH (default; the wide tree of least SAH
+ *                   cost over all ways to form leaves and 4-wide nodes from
+ *                   the binary tree's subtrees, by dynamic programming) or
+ *                   RCP_COLLAPSE_GREEDY (leaves formed in the binary tree,
+ *                   then each wide node opens its children of largest area).
+ * Builder and collapse change the speed of rendering only, never an image. */
 #define RCP_BUILDER_PLOC 0
 #define RCP_BUILDER_LBVH 1
+#define RCP_COLLAPSE_SAH 0
+#define RCP_COLLAPSE_GREEDY 1
 typedef struct {
     int32_t max_leaf;
     float c_trav;
     float c_isect;
     int32_t builder;
+    int32_t collapse;
 } rcp_build_options;
 
 /* Scene statistics filled by rcp_scene_info. */
@@ -141,8 +151,9 @@ typedef struct {
     uint32_t n_leaves;       /* leaf links in the tree */
     uint32_t max_depth;      /* levels of the tree including the leaves */
     uint32_t max_leaf;
-    float sah_cost;          /* SAH cost of the binary tree before the collapse,
-                                relative to the root box */
+    float sah_cost;          /* SAH cost of the 4-wide tree (c_trav per node
+                                visit, 2 * c_trav per leaf entered, c_isect
+                                per triangle test), relative to the root box */
     float build_ms;          /* device time of the build kernels */
     uint64_t device_bytes;   /* HBM held by the scene */
     uint32_t node_bytes;     /* bytes per packed BVH node (rcp_export_bvh) */

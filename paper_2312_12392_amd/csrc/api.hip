@@ -141,6 +141,8 @@ rcp_status rcp_build_scene(const rcp_scene_desc* desc, const rcp_build_options* 
             FAIL("SAH costs must be finite and > 0");
         if (opts->builder != RCP_BUILDER_PLOC && opts->builder != RCP_BUILDER_LBVH)
             FAIL("unknown builder %d", (int)opts->builder);
+        if (opts->collapse != RCP_COLLAPSE_SAH && opts->collapse != RCP_COLLAPSE_GREEDY)
+            FAIL("unknown collapse %d", (int)opts->collapse);
     }
     try {
         return build_scene(desc, opts, (hipStream_t)hip_stream, out);

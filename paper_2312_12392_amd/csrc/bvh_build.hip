@@ -8,14 +8,15 @@
 //   4. binary radix tree over the sorted codes, one thread per inner node
 //      (Karras, "Maximizing Parallelism in the Construction of BVHs, Octrees,
 //      and k-d Trees", HPG 2012), duplicate codes split by index
-//   5. bottom-up refit with per-node arrival counters; each node also gets its
-//      SAH cost and is collapsed into a leaf (<= max_leaf triangles) when that
-//      is cheaper than keeping the split
-//   6. packing of the binary tree (two children's boxes and links per
-//      node) in depth-first order
-//   7. collapse into 128-byte 4-wide nodes, level by level: the tree the
-//      traversal uses
-//   8. packing of 48-byte triangles, a per-triangle table of the two shaded
+//      (or, by default, PLOC: agglomerative clustering of Morton neighbours)
+//   5. the 4-wide tree the traversal uses, 128-byte nodes, by default from
+//      an SAH-optimal collapse of the binary tree: a bottom-up dynamic
+//      programme over the subtrees (arrival counters), then emission level by
+//      level.  The greedy alternative: a bottom-up refit that collapses
+//      subtrees into leaves (<= max_leaf triangles) where the binary SAH says
+//      so, packing of the binary tree in depth-first order, and wide nodes
+//      that open their children of largest area
+//   6. packing of 48-byte triangles, a per-triangle table of the two shaded
 //      colours and the unit normals.
 #include <cmath>
 #include <cstring>
@@ -27,6 +28,16 @@ namespace rcp {
 namespace {
 
 constexpr int kB = 256;
+
+// Entering a leaf costs the traversal a step of its own (the lane holds the
+// leaf, and its triangles are tested after the descent), so the cost model
+// charges a leaf kLeafEntry * c_trav on top of its triangle tests (the SAH
+// collapse optimises it, and the reported SAH cost includes it).  Measured
+// on the terrain frames against the greedy collapse: 0 (plain SAH) split
+// two-triangle cells into one-triangle leaves and was 4% slower, 1 was 3%
+// slower, 2 equal at 1M triangles and 1% faster at 16M (20% fewer nodes), 3
+// 4% slower again.
+constexpr float kLeafEntry = 2.0f;
 
 __device__ inline uint32_t f2o(float f) {
     uint32_t u = __float_as_uint(f);
@@ -536,6 +547,20 @@ __global__ void k_pack_single(int n, const float4* __restrict__ tlo, const float
 // node it expands in src[], and its inner children get slots of the next
 // level from one counter.
 // ---------------------------------------------------------------------------
+// Statistics of the emitted wide tree, accumulated exactly: leaf links, and
+// the SAH cost relative to the root box in 2^-32 fixed point.
+struct WideStats {
+    unsigned long long leaves;
+    unsigned long long sah_fx;
+};
+
+__device__ inline void wide_stat(WideStats* ws, float node_area, float leaf_cost, uint32_t n_leaves, float c_trav,
+                                 float inv_root_area) {
+    const float rel = (c_trav * node_area + leaf_cost) * inv_root_area;
+    atomicAdd(&ws->sah_fx, (unsigned long long)((double)rel * 4294967296.0 + 0.5));
+    if (n_leaves) atomicAdd(&ws->leaves, (unsigned long long)n_leaves);
+}
+
 struct WideCand {
     float lo[3], hi[3];
     uint32_t link;
@@ -560,7 +585,8 @@ __device__ inline void wide_children(const float4* __restrict__ n2, uint32_t nod
 
 __global__ __launch_bounds__(kB) void k_collapse4(const float4* __restrict__ n2, uint32_t begin, uint32_t end,
                                                    uint32_t* __restrict__ src, uint32_t* __restrict__ counter,
-                                                   float4* __restrict__ n4) {
+                                                   float4* __restrict__ n4, WideStats* stats, float c_trav,
+                                                   float c_isect, float inv_root_area) {
     const uint32_t slot = begin + blockIdx.x * kB + threadIdx.x;
     if (slot >= end) return;
     WideCand c[4];
@@ -606,6 +632,238 @@ __global__ __launch_bounds__(kB) void k_collapse4(const float4* __restrict__ n2,
     o[6] = make_float4(__uint_as_float(link[0]), __uint_as_float(link[1]), __uint_as_float(link[2]),
                        __uint_as_float(link[3]));
     o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    WideCand u = c[0];
+    float leaf_cost = 0.0f;
+    uint32_t n_leaves = 0;
+    for (int i = 0; i < m; ++i) {
+        for (int a = 0; a < 3; ++a) { u.lo[a] = fminf(u.lo[a], c[i].lo[a]); u.hi[a] = fmaxf(u.hi[a], c[i].hi[a]); }
+        if (c[i].link & kLeafBit) {
+            leaf_cost += (c_isect * (float)((c[i].link & 7u) + 1u) + kLeafEntry * c_trav) * c[i].area;
+            ++n_leaves;
+        }
+    }
+    wide_stat(stats, half_area(u), leaf_cost, n_leaves, c_trav, inv_root_area);
+}
+
+// ---------------------------------------------------------------------------
+// SAH-optimal collapse into 4-wide nodes (after Ylitie, Karras and Laine,
+// "Efficient Incoherent Ray Traversal on GPUs Through Compressed Wide BVHs",
+// HPG 2017, here for 4 children).  C(i, j) is the least SAH cost of the
+// binary subtree i when it may fill j (1..4) child slots of its wide parent:
+//   C(i, 1)  = min(leaf: (c_isect * count + c_leaf) * A(i) if count <= max_leaf,
+//                  wide node: c_trav * A(i) + min_k C(l, k) + C(r, 4 - k))
+//   C(i, j)  = min(C(i, j - 1), min_k C(l, k) + C(r, j - k))
+// with A the box surface area and c_leaf = kLeafEntry * c_trav; a single
+// triangle costs (c_isect + c_leaf) * A(tri) whatever j.  One bottom-up pass (arrival counters, as the refit) computes
+// the costs, the decisions and the number of wide nodes each choice makes;
+// the wide nodes are then emitted level by level from the decisions.
+// Decision word of inner node i: bit 0 leaf at j = 1; bits 1-2 the left
+// child's slots k of the wide node rooted at i; bits 2j-1..2j the left
+// child's slots for j = 2, 3, 4 (0: j - 1 slots of i itself suffice).
+// ---------------------------------------------------------------------------
+
+struct WideDP {
+    float4* cost;      // C(i, 1..4)
+    int4* count;       // wide nodes of each choice
+    uint32_t* dec;
+};
+
+__device__ inline void dp_child(int32_t c, const float4* __restrict__ tlo, const float4* __restrict__ thi,
+                                const uint32_t* __restrict__ sorted, NodeData nd, WideDP wd, float c_isect,
+                                float c_entry, float3& lo, float3& hi, float C[5], int W[5]) {
+    if (c < 0) {
+        const uint32_t t = sorted[(uint32_t)c & ~kLeafBit];
+        const float4 a = tlo[t], b = thi[t];
+        lo = make_float3(a.x, a.y, a.z);
+        hi = make_float3(b.x, b.y, b.z);
+        const float ct = (c_isect + c_entry) * half_area(lo, hi);
+        for (int j = 1; j <= 4; ++j) { C[j] = ct; W[j] = 0; }
+    } else {
+        // written by the sibling's thread before its release fence
+        const float4 a = nd.lo[c], b = nd.hi[c];
+        lo = make_float3(a.x, a.y, a.z);
+        hi = make_float3(b.x, b.y, b.z);
+        const float4 cc = wd.cost[c];
+        const int4 ww = wd.count[c];
+        C[1] = cc.x; C[2] = cc.y; C[3] = cc.z; C[4] = cc.w;
+        W[1] = ww.x; W[2] = ww.y; W[3] = ww.z; W[4] = ww.w;
+    }
+}
+
+__global__ __launch_bounds__(kB) void k_wide_dp(int n, const int32_t* __restrict__ left,
+                                                 const int32_t* __restrict__ right, const int32_t* __restrict__ parent,
+                                                 const int32_t* __restrict__ rfirst, const int32_t* __restrict__ rlast,
+                                                 const float4* __restrict__ tlo, const float4* __restrict__ thi,
+                                                 const uint32_t* __restrict__ sorted, uint32_t* __restrict__ arrivals,
+                                                 NodeData nd, WideDP wd, int max_leaf, float c_trav, float c_isect) {
+    const int j0 = blockIdx.x * kB + threadIdx.x;
+    if (j0 >= n) return;
+    const float c_entry = kLeafEntry * c_trav;
+    int node = parent[n - 1 + j0];
+    while (node >= 0) {
+        __threadfence();
+        if (atomicAdd(&arrivals[node], 1u) == 0u) return;   // the sibling finishes this node
+        __threadfence();
+        float3 llo, lhi, rlo, rhi;
+        float Cl[5], Cr[5];
+        int Wl[5], Wr[5];
+        dp_child(left[node], tlo, thi, sorted, nd, wd, c_isect, c_entry, llo, lhi, Cl, Wl);
+        dp_child(right[node], tlo, thi, sorted, nd, wd, c_isect, c_entry, rlo, rhi, Cr, Wr);
+        const float3 lo = make_float3(fminf(llo.x, rlo.x), fminf(llo.y, rlo.y), fminf(llo.z, rlo.z));
+        const float3 hi = make_float3(fmaxf(lhi.x, rhi.x), fmaxf(lhi.y, rhi.y), fmaxf(lhi.z, rhi.z));
+        const float a = half_area(lo, hi);
+        const int cnt = rlast[node] - rfirst[node] + 1;
+        // the wide node rooted here: its four slots split between the children
+        int kint = 1;
+        float best4 = Cl[1] + Cr[3];
+        for (int k = 2; k <= 3; ++k) {
+            const float c = Cl[k] + Cr[4 - k];
+            if (c < best4) { best4 = c; kint = k; }
+        }
+        const float c_int = c_trav * a + best4;
+        const float c_leaf = cnt <= max_leaf ? (c_isect * (float)cnt + c_entry) * a : INFINITY;
+        const bool leaf = c_leaf <= c_int;
+        float C[5];
+        int W[5];
+        C[1] = leaf ? c_leaf : c_int;
+        W[1] = leaf ? 0 : 1 + Wl[kint] + Wr[4 - kint];
+        uint32_t dec = (leaf ? 1u : 0u) | ((uint32_t)kint << 1);
+        for (int j = 2; j <= 4; ++j) {
+            float best = C[j - 1];
+            int d = 0;
+            for (int k = 1; k < j; ++k) {
+                const float c = Cl[k] + Cr[j - k];
+                if (c < best) { best = c; d = k; }
+            }
+            C[j] = best;
+            W[j] = d ? Wl[d] + Wr[j - d] : W[j - 1];
+            dec |= (uint32_t)d << (2 * j - 1);
+        }
+        nd.lo[node] = make_float4(lo.x, lo.y, lo.z, 0.0f);
+        nd.hi[node] = make_float4(hi.x, hi.y, hi.z, 0.0f);
+        wd.cost[node] = make_float4(C[1], C[2], C[3], C[4]);
+        wd.count[node] = make_int4(W[1], W[2], W[3], W[4]);
+        wd.dec[node] = dec;
+        node = parent[node];
+    }
+}
+
+// Wide nodes of the whole tree (the root is always a wide node) and the root box.
+struct WideSummary {
+    int32_t n_wide;
+    float bbox[6];
+};
+
+__global__ void k_wide_summary(const int32_t* __restrict__ left, const int32_t* __restrict__ right, NodeData nd,
+                               WideDP wd, WideSummary* sm) {
+    const int kint = (int)((wd.dec[0] >> 1) & 3u);
+    const int32_t l = left[0], r = right[0];
+    const int wl = l < 0 ? 0 : (&wd.count[l].x)[kint - 1];
+    const int wr = r < 0 ? 0 : (&wd.count[r].x)[4 - kint - 1];
+    sm->n_wide = 1 + wl + wr;
+    const float4 a = nd.lo[0], b = nd.hi[0];
+    sm->bbox[0] = a.x; sm->bbox[1] = a.y; sm->bbox[2] = a.z;
+    sm->bbox[3] = b.x; sm->bbox[4] = b.y; sm->bbox[5] = b.z;
+}
+
+// One level of the optimal collapse: slot s expands binary node src[s].
+__global__ __launch_bounds__(kB) void k_emit4(const int32_t* __restrict__ left, const int32_t* __restrict__ right,
+                                               const int32_t* __restrict__ rfirst, const int32_t* __restrict__ rlast,
+                                               const float4* __restrict__ tlo, const float4* __restrict__ thi,
+                                               const uint32_t* __restrict__ sorted, NodeData nd, WideDP wd,
+                                               uint32_t begin, uint32_t end, uint32_t* __restrict__ src,
+                                               uint32_t* __restrict__ counter, float4* __restrict__ n4,
+                                               WideStats* stats, float c_trav, float c_isect, float inv_root_area,
+                                               uint32_t cap, uint32_t* __restrict__ error) {
+    const uint32_t slot = begin + blockIdx.x * kB + threadIdx.x;
+    if (slot >= end) return;
+    const int32_t x = (int32_t)src[slot];
+    const int kint = (int)((wd.dec[x] >> 1) & 3u);
+    // work list of (binary child, slots it may fill); the slots of its
+    // entries never sum to more than 4, so it holds at most 4 entries
+    int32_t wn[4];
+    int wj[4];
+    int sp = 0;
+    wn[sp] = right[x]; wj[sp++] = 4 - kint;
+    wn[sp] = left[x]; wj[sp++] = kint;
+    float lo[3][4], hi[3][4];
+    uint32_t link[4];
+    int32_t inner[4];
+    int m = 0;
+    float leaf_cost = 0.0f;
+    uint32_t n_leaves = 0;
+    for (int guard = 0; sp > 0 && guard < 256; ++guard) {
+        const int32_t c = wn[--sp];
+        const int j = wj[sp];
+        if (c >= 0 && j > 1) {
+            const int d = (int)((wd.dec[c] >> (2 * j - 1)) & 3u);
+            if (sp + 2 > 4 || d >= j) { atomicOr(error, 1u); return; }
+            if (d == 0) {
+                wn[sp] = c; wj[sp++] = j - 1;
+            } else {
+                wn[sp] = right[c]; wj[sp++] = j - d;
+                wn[sp] = left[c]; wj[sp++] = d;
+            }
+            continue;
+        }
+        if (m >= 4) { atomicOr(error, 1u); return; }
+        float4 a, b;
+        if (c < 0) {   // one triangle
+            const uint32_t pos = (uint32_t)c & ~kLeafBit;
+            const uint32_t t = sorted[pos];
+            a = tlo[t]; b = thi[t];
+            link[m] = leaf_link(pos, 1u);
+            inner[m] = -1;
+        } else {
+            a = nd.lo[c]; b = nd.hi[c];
+            if (wd.dec[c] & 1u) {
+                link[m] = leaf_link((uint32_t)rfirst[c], (uint32_t)(rlast[c] - rfirst[c] + 1));
+                inner[m] = -1;
+            } else {
+                link[m] = 0u;
+                inner[m] = c;
+            }
+        }
+        if (inner[m] < 0) {
+            const uint32_t cnt = (link[m] & 7u) + 1u;
+            leaf_cost += (c_isect * (float)cnt + kLeafEntry * c_trav) *
+                         half_area(make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z));
+            ++n_leaves;
+        }
+        lo[0][m] = pad_lo(a.x); hi[0][m] = pad_hi(b.x);
+        lo[1][m] = pad_lo(a.y); hi[1][m] = pad_hi(b.y);
+        lo[2][m] = pad_lo(a.z); hi[2][m] = pad_hi(b.z);
+        ++m;
+    }
+    if (sp > 0 || m < 2) { atomicOr(error, 1u); return; }
+    int n_inner = 0;
+    for (int i = 0; i < m; ++i) n_inner += inner[i] >= 0 ? 1 : 0;
+    const uint32_t base = n_inner ? atomicAdd(counter, (uint32_t)n_inner) : 0u;
+    if (base + (uint32_t)n_inner > cap) { atomicOr(error, 2u); return; }   // more nodes than counted
+    int k = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (i < m) {
+            if (inner[i] >= 0) {
+                link[i] = base + (uint32_t)k;
+                src[base + (uint32_t)k] = (uint32_t)inner[i];
+                ++k;
+            }
+        } else {   // unused slot: NaN planes fail every box test
+            for (int a = 0; a < 3; ++a) { lo[a][i] = __int_as_float(0x7FC00000); hi[a][i] = lo[a][i]; }
+            link[i] = leaf_link(0u, 1u);
+        }
+    }
+    float4* o = n4 + 8 * (size_t)slot;
+    for (int a = 0; a < 3; ++a) {
+        o[2 * a] = make_float4(lo[a][0], lo[a][1], lo[a][2], lo[a][3]);
+        o[2 * a + 1] = make_float4(hi[a][0], hi[a][1], hi[a][2], hi[a][3]);
+    }
+    o[6] = make_float4(__uint_as_float(link[0]), __uint_as_float(link[1]), __uint_as_float(link[2]),
+                       __uint_as_float(link[3]));
+    o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float4 xa = nd.lo[x], xb = nd.hi[x];
+    wide_stat(stats, half_area(make_float3(xa.x, xa.y, xa.z), make_float3(xb.x, xb.y, xb.z)), leaf_cost, n_leaves,
+              c_trav, inv_root_area);
 }
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) {
@@ -782,6 +1040,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     const float c_trav = opts ? opts->c_trav : 1.0f;
     const float c_isect = opts ? opts->c_isect : 1.0f;
     const int builder = opts ? opts->builder : RCP_BUILDER_PLOC;
+    const int collapse = opts ? opts->collapse : RCP_COLLAPSE_SAH;
 
     rcp_scene* s = new rcp_scene();
     struct Guard {
@@ -850,11 +1109,22 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
         RCP_TRY(radix_sort_pairs(keys, sorted, keys2, vals2, (int)n, 64, stream));
 
         Summary* sm;
+        WideSummary* wsm;
+        WideStats* wst;
+        uint32_t* err;
         RCP_TRY(tmp.alloc(&sm, 1));
+        RCP_TRY(tmp.alloc(&wsm, 1));
+        RCP_TRY(tmp.alloc(&wst, 1));
+        RCP_TRY(tmp.alloc(&err, 1));
+        RCP_HIP(hipMemsetAsync(wst, 0, sizeof(WideStats), stream));
+        RCP_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), stream));
         Summary hs{};
+        WideSummary hw{};
         bool single = n <= 1;
         int32_t *left = nullptr, *right = nullptr, *parent = nullptr, *rfirst = nullptr, *rlast = nullptr;
         NodeData nd{};
+        WideDP wd{};
+        float bbox[6] = {0, 0, 0, 0, 0, 0};
         if (!single) {
             const long ni = (long)n - 1;
             uint32_t* arrivals;
@@ -866,9 +1136,6 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
             RCP_TRY(tmp.alloc(&arrivals, ni));
             RCP_TRY(tmp.alloc(&nd.lo, ni));
             RCP_TRY(tmp.alloc(&nd.hi, ni));
-            RCP_TRY(tmp.alloc(&nd.cost, ni));
-            RCP_TRY(tmp.alloc(&nd.n_inner, ni));
-            RCP_TRY(tmp.alloc(&nd.collapse, ni));
             rcp_status tree = RCP_ERR_NOT_READY;
             if (builder == RCP_BUILDER_PLOC)
                 tree = ploc_build((int)n, tlo, thi, sorted, left, right, parent, rfirst, rlast, stream);
@@ -880,43 +1147,105 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
             }
             if (tree != RCP_OK) return tree;
             RCP_HIP(hipMemsetAsync(arrivals, 0, sizeof(uint32_t) * ni, stream));
-            hipLaunchKernelGGL(k_refit, dim3(blocks(n)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
-                               (const int32_t*)right, (const int32_t*)parent, (const int32_t*)rfirst,
-                               (const int32_t*)rlast, (const float4*)tlo, (const float4*)thi,
-                               (const uint32_t*)sorted, arrivals, nd, max_leaf, c_trav, c_isect);
-            hipLaunchKernelGGL(k_summary_root, dim3(1), dim3(1), 0, stream, nd, sm);
-            RCP_CHECK_LAUNCH();
-            RCP_HIP(hipMemcpyAsync(&hs, sm, sizeof(Summary), hipMemcpyDeviceToHost, stream));
-            RCP_HIP(hipStreamSynchronize(stream));
-            single = hs.root_collapsed != 0;
+            if (collapse == RCP_COLLAPSE_SAH) {
+                RCP_TRY(tmp.alloc(&wd.cost, ni));
+                RCP_TRY(tmp.alloc(&wd.count, ni));
+                RCP_TRY(tmp.alloc(&wd.dec, ni));
+                hipLaunchKernelGGL(k_wide_dp, dim3(blocks(n)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
+                                   (const int32_t*)right, (const int32_t*)parent, (const int32_t*)rfirst,
+                                   (const int32_t*)rlast, (const float4*)tlo, (const float4*)thi,
+                                   (const uint32_t*)sorted, arrivals, nd, wd, max_leaf, c_trav, c_isect);
+                hipLaunchKernelGGL(k_wide_summary, dim3(1), dim3(1), 0, stream, (const int32_t*)left,
+                                   (const int32_t*)right, nd, wd, wsm);
+                RCP_CHECK_LAUNCH();
+                RCP_HIP(hipMemcpyAsync(&hw, wsm, sizeof(WideSummary), hipMemcpyDeviceToHost, stream));
+                RCP_HIP(hipStreamSynchronize(stream));
+                memcpy(bbox, hw.bbox, sizeof(bbox));
+                if (hw.n_wide < 1 || (uint32_t)hw.n_wide > (uint32_t)ni) {
+                    set_error("optimal collapse counted %d wide nodes for %ld binary nodes", hw.n_wide, ni);
+                    return RCP_ERR_INTERNAL;
+                }
+            } else {
+                RCP_TRY(tmp.alloc(&nd.cost, ni));
+                RCP_TRY(tmp.alloc(&nd.n_inner, ni));
+                RCP_TRY(tmp.alloc(&nd.collapse, ni));
+                hipLaunchKernelGGL(k_refit, dim3(blocks(n)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
+                                   (const int32_t*)right, (const int32_t*)parent, (const int32_t*)rfirst,
+                                   (const int32_t*)rlast, (const float4*)tlo, (const float4*)thi,
+                                   (const uint32_t*)sorted, arrivals, nd, max_leaf, c_trav, c_isect);
+                hipLaunchKernelGGL(k_summary_root, dim3(1), dim3(1), 0, stream, nd, sm);
+                RCP_CHECK_LAUNCH();
+                RCP_HIP(hipMemcpyAsync(&hs, sm, sizeof(Summary), hipMemcpyDeviceToHost, stream));
+                RCP_HIP(hipStreamSynchronize(stream));
+                memcpy(bbox, hs.bbox, sizeof(bbox));
+                single = hs.root_collapsed != 0;
+            }
         }
-        if (single) {
-            n_nodes = 1;
-            RCP_TRY(dalloc(&s->nodes, 4));
-            hipLaunchKernelGGL(k_pack_single, dim3(1), dim3(1), 0, stream, (int)n, (const float4*)tlo,
-                               (const float4*)thi, s->nodes);
+        const float root_area = (bbox[3] - bbox[0]) * (bbox[4] - bbox[1]) + (bbox[4] - bbox[1]) * (bbox[5] - bbox[2]) +
+                                (bbox[5] - bbox[2]) * (bbox[3] - bbox[0]);
+        const float inv_root_area = root_area > 0.0f ? 1.0f / root_area : 0.0f;
+        uint32_t levels = 0;
+        if (!single && collapse == RCP_COLLAPSE_SAH) {
+            // the optimal collapse, one launch per level of wide nodes
+            n_nodes = (uint32_t)hw.n_wide;
+            uint32_t *src, *counter;
+            RCP_TRY(tmp.alloc(&src, n_nodes));
+            RCP_TRY(tmp.alloc(&counter, 1));
+            RCP_TRY(dalloc(&s->nodes, 8 * (size_t)n_nodes));
+            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, stream, src, 0u);
+            hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, stream, counter, 1u);
             RCP_CHECK_LAUNCH();
-            sah = 1.0f;   // filled below for the single-leaf case
+            uint32_t begin = 0, end = 1;
+            while (begin < end) {
+                hipLaunchKernelGGL(k_emit4, dim3(blocks(end - begin)), dim3(kB), 0, stream, (const int32_t*)left,
+                                   (const int32_t*)right, (const int32_t*)rfirst, (const int32_t*)rlast,
+                                   (const float4*)tlo, (const float4*)thi, (const uint32_t*)sorted, nd, wd, begin,
+                                   end, src, counter, s->nodes, wst, c_trav, c_isect, inv_root_area, n_nodes,
+                                   err);
+                RCP_CHECK_LAUNCH();
+                uint32_t next = 0, bad = 0;
+                RCP_HIP(hipMemcpyAsync(&next, counter, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+                RCP_HIP(hipMemcpyAsync(&bad, err, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+                RCP_HIP(hipStreamSynchronize(stream));
+                if (bad || next > n_nodes || next < end) {
+                    set_error("optimal collapse: level %u ended at %u of %u nodes (error %u)", levels, next, n_nodes,
+                              bad);
+                    return RCP_ERR_INTERNAL;
+                }
+                begin = end;
+                end = next;
+                ++levels;
+                if (levels == (uint32_t)kTopLevels) top_count = begin;   // slots of levels < kTopLevels
+            }
+            if (end != n_nodes) {
+                set_error("optimal collapse emitted %u of %u wide nodes", end, n_nodes);
+                return RCP_ERR_INTERNAL;
+            }
         } else {
-            const long ni = (long)n - 1;
-            int32_t* newidx;
-            RCP_TRY(tmp.alloc(&newidx, ni));
-            hipLaunchKernelGGL(k_layout_walk, dim3(blocks(ni)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
-                               (const int32_t*)parent, nd, newidx);
-            RCP_CHECK_LAUNCH();
-            n_nodes = (uint32_t)hs.n_inner;
-            RCP_TRY(dalloc(&s->nodes, 4 * (size_t)n_nodes));
-            hipLaunchKernelGGL(k_pack_nodes, dim3(blocks(ni)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
-                               (const int32_t*)right, (const int32_t*)rfirst, (const int32_t*)rlast,
-                               (const float4*)tlo, (const float4*)thi, (const uint32_t*)sorted, nd,
-                               (const int32_t*)newidx, s->nodes);
-            RCP_CHECK_LAUNCH();
-            sah = hs.root_area > 0.0f ? hs.root_cost / hs.root_area : 0.0f;
-        }
-        n_leaves = n_nodes + 1;
-        {
-            // collapse into 4-wide nodes, one launch per level; the binary
-            // nodes are freed with the other temporaries
+            if (single) {
+                n_nodes = 1;
+                RCP_TRY(dalloc(&s->nodes, 4));
+                hipLaunchKernelGGL(k_pack_single, dim3(1), dim3(1), 0, stream, (int)n, (const float4*)tlo,
+                                   (const float4*)thi, s->nodes);
+                RCP_CHECK_LAUNCH();
+            } else {
+                const long ni = (long)n - 1;
+                int32_t* newidx;
+                RCP_TRY(tmp.alloc(&newidx, ni));
+                hipLaunchKernelGGL(k_layout_walk, dim3(blocks(ni)), dim3(kB), 0, stream, (int)n,
+                                   (const int32_t*)left, (const int32_t*)parent, nd, newidx);
+                RCP_CHECK_LAUNCH();
+                n_nodes = (uint32_t)hs.n_inner;
+                RCP_TRY(dalloc(&s->nodes, 4 * (size_t)n_nodes));
+                hipLaunchKernelGGL(k_pack_nodes, dim3(blocks(ni)), dim3(kB), 0, stream, (int)n,
+                                   (const int32_t*)left, (const int32_t*)right, (const int32_t*)rfirst,
+                                   (const int32_t*)rlast, (const float4*)tlo, (const float4*)thi,
+                                   (const uint32_t*)sorted, nd, (const int32_t*)newidx, s->nodes);
+                RCP_CHECK_LAUNCH();
+            }
+            // greedy collapse of the packed binary tree into 4-wide nodes, one
+            // launch per level; the binary nodes are freed with the other
+            // temporaries
             float4* n2 = s->nodes;
             tmp.ptrs.push_back((void*)n2);
             s->nodes = nullptr;
@@ -927,10 +1256,10 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
             hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, stream, src, 0u);
             hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, stream, counter, 1u);
             RCP_CHECK_LAUNCH();
-            uint32_t begin = 0, end = 1, levels = 0;
+            uint32_t begin = 0, end = 1;
             while (begin < end) {
                 hipLaunchKernelGGL(k_collapse4, dim3(blocks(end - begin)), dim3(kB), 0, stream, (const float4*)n2,
-                                   begin, end, src, counter, s->nodes);
+                                   begin, end, src, counter, s->nodes, wst, c_trav, c_isect, inv_root_area);
                 RCP_CHECK_LAUNCH();
                 uint32_t next = 0;
                 RCP_HIP(hipMemcpyAsync(&next, counter, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
@@ -945,14 +1274,22 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                 if (levels == (uint32_t)kTopLevels) top_count = begin;   // slots of levels < kTopLevels
             }
             n_nodes = end;
-            if (levels < (uint32_t)kTopLevels) top_count = n_nodes;
-            if (top_count > kMaxStagedNodes) top_count = kMaxStagedNodes;
-            if (n_nodes > kMaxNodes) {
-                set_error("the scene needs %u BVH nodes, more than the %u a scene can hold", n_nodes, kMaxNodes);
-                return RCP_ERR_INVALID_ARGUMENT;
-            }
-            max_depth = levels + 1;          // leaves sit one level below the deepest wide node
-            stack_bound = 3u * levels + 1u;  // at most three pushes per level
+        }
+        if (levels < (uint32_t)kTopLevels) top_count = n_nodes;
+        if (top_count > kMaxStagedNodes) top_count = kMaxStagedNodes;
+        if (n_nodes > kMaxNodes) {
+            set_error("the scene needs %u BVH nodes, more than the %u a scene can hold", n_nodes, kMaxNodes);
+            return RCP_ERR_INVALID_ARGUMENT;
+        }
+        max_depth = levels + 1;          // leaves sit one level below the deepest wide node
+        stack_bound = 3u * levels + 1u;  // at most three pushes per level
+        {
+            WideStats hst{};
+            RCP_HIP(hipMemcpyAsync(&hst, wst, sizeof(WideStats), hipMemcpyDeviceToHost, stream));
+            RCP_HIP(hipStreamSynchronize(stream));
+            n_leaves = (uint32_t)hst.leaves;
+            sah = (float)((double)hst.sah_fx / 4294967296.0);
+            if (single) sah = c_isect * (float)n;   // one leaf of every triangle, relative to its own box
         }
         RCP_TRY(dalloc(&s->tris, 3 * (size_t)n));
         RCP_TRY(dalloc(&s->shade, 2 * (size_t)n));
@@ -962,10 +1299,6 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                            (const uint32_t*)d_idx, (const float*)d_rgb, (const uint32_t*)sorted, sp, s->tris,
                            s->shade, s->normals);
         RCP_CHECK_LAUNCH();
-        if (single) {
-            // SAH of one leaf holding every triangle, relative to its own box
-            sah = c_isect * (float)n;
-        }
     }
     RCP_HIP(hipEventRecord(e1, stream));
     RCP_HIP(hipStreamSynchronize(stream));

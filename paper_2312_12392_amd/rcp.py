@@ -31,6 +31,8 @@ RCP_MODE_DEPTH = 1
 RCP_MODE_NORMAL = 2
 RCP_BUILDER_PLOC = 0
 RCP_BUILDER_LBVH = 1
+RCP_COLLAPSE_SAH = 0
+RCP_COLLAPSE_GREEDY = 1
 RCP_ENGINE_CHAIN = 0
 RCP_ENGINE_PASSES = 1
 ENGINE_CHAIN, ENGINE_PASSES = RCP_ENGINE_CHAIN, RCP_ENGINE_PASSES
@@ -74,7 +76,7 @@ class rcp_displacement(ctypes.Structure):
 
 class rcp_build_options(ctypes.Structure):
     _fields_ = [("max_leaf", ctypes.c_int32), ("c_trav", ctypes.c_float),
-                ("c_isect", ctypes.c_float), ("builder", ctypes.c_int32)]
+                ("c_isect", ctypes.c_float), ("builder", ctypes.c_int32), ("collapse", ctypes.c_int32)]
 
 
 class rcp_view(ctypes.Structure):
@@ -492,9 +494,11 @@ def rcp_server_destroy(server: int) -> None:
 # Convenience wrapper
 # ---------------------------------------------------------------------------
 
-def build_options(max_leaf: int = 4, c_trav: float = 1.0, c_isect: float = 1.0, builder: int = 0):
+def build_options(max_leaf: int = 4, c_trav: float = 1.0, c_isect: float = 1.0, builder: int = 0,
+                  collapse: int = 0):
     o = rcp_build_options()
     o.max_leaf, o.c_trav, o.c_isect, o.builder = int(max_leaf), float(c_trav), float(c_isect), int(builder)
+    o.collapse = int(collapse)
     return o
 
 

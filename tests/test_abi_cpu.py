@@ -80,7 +80,7 @@ def test_build_argument_validation_on_host():
     _bad(rcp.rcp_build_scene, nbg, stream=0)
     for opts in [rcp.build_options(max_leaf=0), rcp.build_options(max_leaf=9), rcp.build_options(c_trav=-1.0),
                  rcp.build_options(c_trav=0.0), rcp.build_options(c_isect=np.nan), rcp.build_options(builder=2),
-                 rcp.build_options(builder=-1)]:
+                 rcp.build_options(builder=-1), rcp.build_options(collapse=2), rcp.build_options(collapse=-1)]:
         _bad(rcp.rcp_build_scene, sc, opts, stream=0)
 
 

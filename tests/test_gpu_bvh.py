@@ -120,10 +120,11 @@ def check_bvh(scene, info, nodes, tri_ids):
     ("terrain1m", lambda: scenegen.workload("terrain1m").scene),
 ])
 @pytest.mark.parametrize("builder", [rcp.RCP_BUILDER_PLOC, rcp.RCP_BUILDER_LBVH], ids=["ploc", "lbvh"])
-def test_bvh_invariants(name, scene_fn, builder):
-    say("bvh", name, "builder", builder)
+@pytest.mark.parametrize("collapse", [rcp.RCP_COLLAPSE_SAH, rcp.RCP_COLLAPSE_GREEDY], ids=["sah", "greedy"])
+def test_bvh_invariants(name, scene_fn, builder, collapse):
+    say("bvh", name, "builder", builder, "collapse", collapse)
     sc = scene_fn()
-    s = rcp.Scene(sc, rcp.build_options(builder=builder))
+    s = rcp.Scene(sc, rcp.build_options(builder=builder, collapse=collapse))
     info = s.info()
     nodes, tri_ids = rcp.rcp_export_bvh(s.handle)
     check_bvh(sc, info, nodes, tri_ids)
@@ -161,3 +162,18 @@ def test_sah_cost_reported_and_leaf_bound():
         s.close()
     # a larger leaf bound only adds options to the collapse: never worse
     assert costs[1] <= costs[0] * (1 + 1e-5) and costs[2] <= costs[1] * (1 + 1e-5)
+
+
+@pytest.mark.parametrize("builder", [rcp.RCP_BUILDER_PLOC, rcp.RCP_BUILDER_LBVH], ids=["ploc", "lbvh"])
+def test_optimal_collapse_is_never_worse_than_greedy(builder):
+    # both collapses choose among ways to cut the same binary tree into leaves
+    # and 4-wide nodes; the dynamic programme takes the cheapest, so its SAH
+    # cost (measured on the emitted tree) is at most the greedy one's
+    say("collapse sah", builder)
+    for sc in (scenegen.terrain_patch(12, 40, 20), scenegen.soup_scene(3, 500), scenegen.adversarial_scene()):
+        cost = {}
+        for collapse in (rcp.RCP_COLLAPSE_SAH, rcp.RCP_COLLAPSE_GREEDY):
+            s = rcp.Scene(sc, rcp.build_options(builder=builder, collapse=collapse))
+            cost[collapse] = s.info()["sah_cost"]
+            s.close()
+        assert cost[rcp.RCP_COLLAPSE_SAH] <= cost[rcp.RCP_COLLAPSE_GREEDY] * (1 + 1e-5), cost

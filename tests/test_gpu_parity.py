@@ -199,6 +199,7 @@ def test_render_matches_oracle(case, engine):
 @pytest.mark.parametrize("opts", [
     dict(max_leaf=1), dict(max_leaf=2), dict(max_leaf=8), dict(max_leaf=3, c_isect=2.0),
     dict(max_leaf=4, c_trav=3.0, c_isect=0.5), dict(builder=1), dict(builder=1, max_leaf=1),
+    dict(collapse=1), dict(collapse=1, builder=1, max_leaf=2), dict(collapse=0, c_trav=4.0, max_leaf=8),
 ])
 def test_build_options_do_not_change_the_image(opts):
     say("build options", opts)
