@@ -43,13 +43,29 @@ struct ViewDev {
 
 static_assert(sizeof(ViewDev) + 2 * sizeof(uint32_t) + 64 <= kViewBytes, "one-entry view table");
 
+// The work items are split into kFetchParts contiguous ranges (bands of
+// tiles), one per XCD, each with its own counter.  Workgroups are dispatched
+// to the XCDs round robin, so the waves of one XCD start on their own band:
+// neighbouring pixels trace through the same parts of the tree, and each
+// XCD's L2 holds the nodes of its band.  A wave whose band is used up takes
+// work from the next band, so the split never leaves work undone.
+constexpr uint32_t kFetchParts = 8;
+constexpr uint32_t kFetchStride = 16;     // words between counters (64 bytes)
+
+// a single render's counters live in the scene's per-pass counter array
+static_assert(kFetchParts * kFetchStride <= 2 * kMaxPasses + 8, "band counters of a single render");
+
+__device__ inline uint32_t part_begin(uint32_t n_items, uint32_t p) {
+    return p >= kFetchParts ? n_items : (uint32_t)(((uint64_t)n_items * p / kFetchParts) & ~63ull);
+}
+
 struct ChainArgs {
     DevScene sc;
     const ViewDev* views;     // [n_views]
     const uint32_t* begin;    // [n_views + 1] first work item of each view
     int n_views;
     uint32_t n_items;         // work items of the launch
-    uint32_t* fetch;          // work counter, zero at launch
+    uint32_t* fetch;          // kFetchParts work counters kFetchStride words apart, zero at launch
     int refill_min;
     uint32_t exit_lanes;
     int32_t* spill;
@@ -107,6 +123,8 @@ __device__ inline void chain_body(const ChainArgs& a) {
     bool ended = false;        // its pass is traced, waiting for a setup round to be finished
     bool pending = false;      // holds the inputs of its next pass, waiting for a setup round
     bool drained = false;      // wave-uniform
+    uint32_t part = blockIdx.x % kFetchParts;   // wave-uniform: the band fetched from
+    uint32_t parts_done = 0;                    // wave-uniform: bands found used up
     int k = 0, x = 0, y = 0;
     float pr = 0.5f, pg = 0.5f, pb = 0.5f;              // previous colour (the seed I_0 at pass 0)
     float pa[4] = {INFINITY, 0.0f, 0.0f, 0.0f};         // previous hit data: view depth, unit normal
@@ -190,17 +208,35 @@ __device__ inline void chain_body(const ChainArgs& a) {
             }
             const unsigned long long idle = __ballot(!alive && !pending);
             const uint32_t n_idle = (uint32_t)__popcll(idle);
-            uint32_t base = 0;
+            uint32_t base = 0, lim = 0;
             const bool fetch = !drained && n_idle > 0u;
             if (fetch) {
-                if (lane == 0) base = atomicAdd(a.fetch, n_idle);
-                base = __shfl(base, 0);
-                if (base + n_idle >= n_items) drained = true;
+                // own band first, then the next ones; every attempt either
+                // takes items or retires a band, so the loop ends
+                if (lane == 0) {
+                    for (;;) {
+                        const uint32_t lo = part_begin(n_items, part), hi = part_begin(n_items, part + 1u);
+                        const uint32_t got = lo < hi ? atomicAdd(&a.fetch[kFetchStride * part], n_idle) : hi - lo;
+                        if (got < hi - lo) { base = lo + got; lim = hi; break; }
+                        part = (part + 1u) % kFetchParts;
+                        if (++parts_done >= kFetchParts) { base = lim = n_items; break; }
+                    }
+                }
+                // lane 0 is the first active lane (the whole wave is here)
+                base = __builtin_amdgcn_readfirstlane(base);
+                lim = __builtin_amdgcn_readfirstlane(lim);
+                part = __builtin_amdgcn_readfirstlane(part);
+                parts_done = __builtin_amdgcn_readfirstlane(parts_done);
+                if (base + n_idle >= lim) {   // this band is used up now
+                    part = (part + 1u) % kFetchParts;
+                    ++parts_done;
+                }
+                if (parts_done >= kFetchParts) drained = true;
             }
             bool init = pending;
             if (fetch && !alive && !pending) {
                 const uint32_t item = base + lanes_below(idle);
-                if (item < n_items) {
+                if (item < lim) {
                     // the view holding this item: last begin <= item
                     if (!ONE) {
                         int lo = 0, hi = a.n_views;
@@ -267,9 +303,9 @@ __global__ __launch_bounds__(kBlock) void k_chain_aux(ChainArgs a) {
     chain_body<STATS, MODE, ONE>(a);
 }
 
-// Zero the work counters (one per launch, 16 words apart) and the stats.
+// Zero the work counters (kFetchParts per launch) and the stats.
 __global__ void k_clear_chain(uint32_t* fetch, int n, unsigned long long* stats) {
-    for (int i = threadIdx.x; i < 16 * n; i += blockDim.x) fetch[i] = 0u;
+    for (int i = threadIdx.x; i < (int)(kFetchParts * kFetchStride) * n; i += blockDim.x) fetch[i] = 0u;
     if (stats)
         for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
 }
@@ -282,7 +318,7 @@ __global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint3
         *table = v;
         begin[0] = 0u;
         begin[1] = n_items;
-        *fetch = 0u;
+        for (uint32_t p = 0; p < kFetchParts; ++p) fetch[kFetchStride * p] = 0u;
     }
     if (stats)
         for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
@@ -492,7 +528,7 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
                                          256));
         ws.view_cap = (size_t)n_views;
     }
-    if (!ws.fetch) RCP_HIP(hipMalloc((void**)&ws.fetch, sizeof(uint32_t) * 16 * 3));
+    if (!ws.fetch) RCP_HIP(hipMalloc((void**)&ws.fetch, sizeof(uint32_t) * kFetchParts * kFetchStride * 3));
     if (spill_need > ws.spill_cap) {
         if (ws.spill) { RCP_HIP(hipFree(ws.spill)); ws.spill = nullptr; }
         ws.spill_cap = 0;
@@ -514,7 +550,7 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
         a.begin = d_begin + groups[g].bofs;
         a.n_views = groups[g].count;
         a.n_items = groups[g].items;
-        a.fetch = ws.fetch + 16 * g;
+        a.fetch = ws.fetch + kFetchParts * kFetchStride * g;
         a.refill_min = lp.refill_min;
         a.exit_lanes = (uint32_t)lp.exit_lanes;
         a.spill = ws.spill;
