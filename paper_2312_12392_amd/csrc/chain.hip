@@ -35,6 +35,7 @@ namespace {
 struct ViewDev {
     Camera cam;
     int W, H, K, tiles_x, tile_log2w;
+    int super_log2;        // log2 of the super-tile side in tiles (0: plain tile rows)
     float hw;              // half_width(cam.th, W, H)
     float le, ld, z0;
     float* out;            // [K][H][W][3]
@@ -73,12 +74,27 @@ struct ChainArgs {
     unsigned long long* stats;   // [K][4] (STATS): rays, inner nodes, triangles, rays continued
 };
 
+// Work item -> pixel.  Items come in 64-pixel tiles; tiles are ordered by
+// super-tiles of 16 x 16 tiles, row by row, so that the pixels in flight on
+// one XCD form a compact patch of the screen (their rays share more of the
+// tree than a thin strip of whole tile rows does).  The super-tile grid
+// covers the image, so the items of its tiles beyond the image edges are
+// skipped; views smaller than a super-tile keep plain tile rows.  (Measured
+// on the terrain frame: 8 x 8 tiles 1.8% faster than plain tile rows,
+// 16 x 16 3.5%; super-tiles clipped to the image instead of padded were 2%
+// slower than padded ones.)
+constexpr int kSuperLog2 = 4;
+
 template <class View>
 __device__ inline void tile_pixel(const View& vw, uint32_t local, int& x, int& y) {
     const uint32_t tile = local >> 6, l = local & 63u;
     const uint32_t tw = 1u << vw.tile_log2w;
-    x = (int)((tile % (uint32_t)vw.tiles_x) * tw + (l & (tw - 1u)));
-    y = (int)((tile / (uint32_t)vw.tiles_x) * (64u >> vw.tile_log2w) + (l >> vw.tile_log2w));
+    const uint32_t sl = (uint32_t)vw.super_log2, sm = (1u << sl) - 1u;
+    const uint32_t st = tile >> (2u * sl), w = tile & ((1u << (2u * sl)) - 1u);
+    const uint32_t sx = ((uint32_t)vw.tiles_x + sm) >> sl;   // super-tiles per row
+    const uint32_t tx = ((st % sx) << sl) + (w & sm), ty = ((st / sx) << sl) + (w >> sl);
+    x = (int)(tx * tw + (l & (tw - 1u)));
+    y = (int)(ty * (64u >> vw.tile_log2w) + (l >> vw.tile_log2w));
 }
 
 // ONE: the launch holds a single view.  Its entry is then read with scalar
@@ -136,8 +152,8 @@ __device__ inline void chain_body(const ChainArgs& a) {
         // ---- setup round, when enough lanes wait: finish the traced passes,
         // fetch new pixels for idle lanes, and set up the rays of new pixels and
         // of next passes together (work done by a few lanes alone wastes the wave)
-        const unsigned long long need = __ballot(!alive);
-        const unsigned long long waiting = __ballot(ended || pending);
+        const unsigned long long need = wave_ballot(!alive);
+        const unsigned long long waiting = wave_ballot(ended || pending);
         if ((uint32_t)__popcll(need) >= (uint32_t)a.refill_min || (drained && waiting != 0ull)) {
             // lanes whose pass is traced: shade, write, and keep the inputs
             // of the next pass or end the chain
@@ -206,7 +222,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
                 }
                 ended = false;
             }
-            const unsigned long long idle = __ballot(!alive && !pending);
+            const unsigned long long idle = wave_ballot(!alive && !pending);
             const uint32_t n_idle = (uint32_t)__popcll(idle);
             uint32_t base = 0, lim = 0;
             const bool fetch = !drained && n_idle > 0u;
@@ -269,8 +285,8 @@ __device__ inline void chain_body(const ChainArgs& a) {
                 pending = false;
             }
         }
-        if (__ballot(alive) == 0ull) {
-            if (drained && __ballot(pending || ended) == 0ull) break;
+        if (wave_ballot(alive) == 0ull) {
+            if (drained && wave_ballot(pending || ended) == 0ull) break;
             continue;
         }
 
@@ -402,6 +418,8 @@ ViewDev view_of(const Camera& cam, int W, int H, int K, const Disp& d, float* ou
     v.hw = half_width(cam.th, W, H);
     v.tile_log2w = tile_log2w;
     v.tiles_x = (W + (1 << tile_log2w) - 1) >> tile_log2w;
+    const int tiles_y = (H + (64 >> tile_log2w) - 1) / (64 >> tile_log2w);
+    v.super_log2 = (v.tiles_x >= (1 << kSuperLog2) && tiles_y >= (1 << kSuperLog2)) ? kSuperLog2 : 0;
     v.le = d.le; v.ld = d.ld; v.z0 = d.z0;
     v.out = out;
     v.ids = ids;
@@ -409,8 +427,10 @@ ViewDev view_of(const Camera& cam, int W, int H, int K, const Disp& d, float* ou
 }
 
 uint64_t view_items(const ViewDev& v) {
-    const int th = 64 >> v.tile_log2w;
-    return (uint64_t)v.tiles_x * (uint64_t)((v.H + th - 1) / th) * 64u;
+    const uint64_t th = 64u >> v.tile_log2w, side = 1ull << v.super_log2;
+    const uint64_t sx = ((uint64_t)v.tiles_x + side - 1u) / side;
+    const uint64_t sy = (((uint64_t)v.H + th - 1u) / th + side - 1u) / side;
+    return sx * sy * side * side * 64u;
 }
 
 }  // namespace

@@ -31,6 +31,9 @@ __device__ inline float sel3(float x, float y, float z, int k) {
     return k == 0 ? x : (k == 1 ? y : z);
 }
 
+// Mask of the wave's lanes where p holds (straight to a scalar register).
+__device__ inline unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 __device__ inline uint32_t lanes_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
@@ -265,9 +268,10 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
         tv.off[j] = 32u * (uint32_t)ax[j] + (neg ? 16u : 0u);
     }
     tv.node = sc.n_nodes > 0 ? 0 : -1;
-    // Every node and leaf is entered at most once per ray; the bound only
+    // Every step of a ray enters a node or a leaf, each at most once per ray
+    // (a wide node has at most 4 children); the bound on steps only
     // guarantees termination should the tree ever be malformed.
-    tv.budget = 2u * sc.n_nodes + 16u;
+    tv.budget = 5u * sc.n_nodes + 16u;
     tv.h.t = INFINITY;
     tv.h.id = INT_MAX;
     tv.h.slot = 0;
@@ -398,22 +402,22 @@ __device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, ui
 // at least one node per searching lane, once no more than `exit_lanes` lanes
 // are still looking for a leaf: a few deep searches would otherwise keep the
 // rest of the wave idle.  Those lanes resume where they were next step.
+constexpr int kMaxDescent = 256;   // node visits of one step (the step ends, the ray goes on)
+
 template <bool STATS>
 __device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* top, Stack& st, uint32_t exit_lanes,
                                  uint32_t& n_nodes, uint32_t& n_tris) {
+    if (--tv.budget == 0u) { tv.node = -1; return; }
     int32_t node = tv.node;
     int32_t leaf = -1;
-    for (int it = 0;; ++it) {
+    for (int it = 0; it < kMaxDescent; ++it) {
         if (node < -1 && leaf == -1) { leaf = node; node = st.pop(); }
-        const unsigned long long searching = __ballot(leaf == -1 && node >= 0);
+        const unsigned long long searching = wave_ballot(leaf == -1 && node >= 0);
         if (searching == 0ull) break;
         // only a few lanes still looking for a leaf: let the others test
         // theirs (every searching lane has advanced one node this step)
         if (it > 0 && (uint32_t)__popcll(searching) <= exit_lanes) break;
-        if (node >= 0) {
-            if (--tv.budget == 0u) { node = -1; leaf = -1; break; }
-            node = visit_inner4<STATS>(tv, node, sc, top, st, n_nodes);
-        }
+        if (node >= 0) node = visit_inner4<STATS>(tv, node, sc, top, st, n_nodes);
     }
     if (leaf != -1) visit_leaf<STATS>(tv, leaf, sc, n_tris);
     tv.node = node;
