@@ -44,21 +44,8 @@ struct ViewDev {
 
 static_assert(sizeof(ViewDev) + 2 * sizeof(uint32_t) + 64 <= kViewBytes, "one-entry view table");
 
-// The work items are split into kFetchParts contiguous ranges (bands of
-// tiles), one per XCD, each with its own counter.  Workgroups are dispatched
-// to the XCDs round robin, so the waves of one XCD start on their own band:
-// neighbouring pixels trace through the same parts of the tree, and each
-// XCD's L2 holds the nodes of its band.  A wave whose band is used up takes
-// work from the next band, so the split never leaves work undone.
-constexpr uint32_t kFetchParts = 8;
-constexpr uint32_t kFetchStride = 16;     // words between counters (64 bytes)
-
-// a single render's counters live in the scene's per-pass counter array
-static_assert(kFetchParts * kFetchStride <= 2 * kMaxPasses + 8, "band counters of a single render");
-
-__device__ inline uint32_t part_begin(uint32_t n_items, uint32_t p) {
-    return p >= kFetchParts ? n_items : (uint32_t)(((uint64_t)n_items * p / kFetchParts) & ~63ull);
-}
+// a single render's band counters live in the scene's counter array
+static_assert(kFetchWords <= 2 * kMaxPasses + 8, "band counters of a single render");
 
 struct ChainArgs {
     DevScene sc;
@@ -74,28 +61,6 @@ struct ChainArgs {
     unsigned long long* stats;   // [K][4] (STATS): rays, inner nodes, triangles, rays continued
 };
 
-// Work item -> pixel.  Items come in 64-pixel tiles; tiles are ordered by
-// super-tiles of 16 x 16 tiles, row by row, so that the pixels in flight on
-// one XCD form a compact patch of the screen (their rays share more of the
-// tree than a thin strip of whole tile rows does).  The super-tile grid
-// covers the image, so the items of its tiles beyond the image edges are
-// skipped; views smaller than a super-tile keep plain tile rows.  (Measured
-// on the terrain frame: 8 x 8 tiles 1.8% faster than plain tile rows,
-// 16 x 16 3.5%; super-tiles clipped to the image instead of padded were 2%
-// slower than padded ones.)
-constexpr int kSuperLog2 = 4;
-
-template <class View>
-__device__ inline void tile_pixel(const View& vw, uint32_t local, int& x, int& y) {
-    const uint32_t tile = local >> 6, l = local & 63u;
-    const uint32_t tw = 1u << vw.tile_log2w;
-    const uint32_t sl = (uint32_t)vw.super_log2, sm = (1u << sl) - 1u;
-    const uint32_t st = tile >> (2u * sl), w = tile & ((1u << (2u * sl)) - 1u);
-    const uint32_t sx = ((uint32_t)vw.tiles_x + sm) >> sl;   // super-tiles per row
-    const uint32_t tx = ((st % sx) << sl) + (w & sm), ty = ((st / sx) << sl) + (w >> sl);
-    x = (int)(tx * tw + (l & (tw - 1u)));
-    y = (int)(ty * (64u >> vw.tile_log2w) + (l >> vw.tile_log2w));
-}
 
 // ONE: the launch holds a single view.  Its entry is then read with scalar
 // loads (the table is constant during the launch), not per lane through the
@@ -226,29 +191,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
             const uint32_t n_idle = (uint32_t)__popcll(idle);
             uint32_t base = 0, lim = 0;
             const bool fetch = !drained && n_idle > 0u;
-            if (fetch) {
-                // own band first, then the next ones; every attempt either
-                // takes items or retires a band, so the loop ends
-                if (lane == 0) {
-                    for (;;) {
-                        const uint32_t lo = part_begin(n_items, part), hi = part_begin(n_items, part + 1u);
-                        const uint32_t got = lo < hi ? atomicAdd(&a.fetch[kFetchStride * part], n_idle) : hi - lo;
-                        if (got < hi - lo) { base = lo + got; lim = hi; break; }
-                        part = (part + 1u) % kFetchParts;
-                        if (++parts_done >= kFetchParts) { base = lim = n_items; break; }
-                    }
-                }
-                // lane 0 is the first active lane (the whole wave is here)
-                base = __builtin_amdgcn_readfirstlane(base);
-                lim = __builtin_amdgcn_readfirstlane(lim);
-                part = __builtin_amdgcn_readfirstlane(part);
-                parts_done = __builtin_amdgcn_readfirstlane(parts_done);
-                if (base + n_idle >= lim) {   // this band is used up now
-                    part = (part + 1u) % kFetchParts;
-                    ++parts_done;
-                }
-                if (parts_done >= kFetchParts) drained = true;
-            }
+            if (fetch) wave_fetch(a.fetch, n_items, n_idle, part, parts_done, drained, base, lim);
             bool init = pending;
             if (fetch && !alive && !pending) {
                 const uint32_t item = base + lanes_below(idle);
@@ -265,7 +208,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
                     const uint32_t local = ONE ? item : item - vbegin[v];
                     {
                         const ConstView& vw = views[ONE ? 0 : v];
-                        tile_pixel(vw, local, x, y);
+                        tile_pixel(local, (uint32_t)vw.tiles_x, (uint32_t)vw.tile_log2w, (uint32_t)vw.super_log2, x, y);
                         if (x < vw.W && y < vw.H) {
                             k = 0;
                             pr = 0.5f; pg = 0.5f; pb = 0.5f;
@@ -321,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_aux(ChainArgs a) {
 
 // Zero the work counters (kFetchParts per launch) and the stats.
 __global__ void k_clear_chain(uint32_t* fetch, int n, unsigned long long* stats) {
-    for (int i = threadIdx.x; i < (int)(kFetchParts * kFetchStride) * n; i += blockDim.x) fetch[i] = 0u;
+    for (int i = threadIdx.x; i < (int)kFetchWords * n; i += blockDim.x) fetch[i] = 0u;
     if (stats)
         for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
 }
@@ -418,8 +361,7 @@ ViewDev view_of(const Camera& cam, int W, int H, int K, const Disp& d, float* ou
     v.hw = half_width(cam.th, W, H);
     v.tile_log2w = tile_log2w;
     v.tiles_x = (W + (1 << tile_log2w) - 1) >> tile_log2w;
-    const int tiles_y = (H + (64 >> tile_log2w) - 1) / (64 >> tile_log2w);
-    v.super_log2 = (v.tiles_x >= (1 << kSuperLog2) && tiles_y >= (1 << kSuperLog2)) ? kSuperLog2 : 0;
+    v.super_log2 = super_log2_for(W, H, tile_log2w);
     v.le = d.le; v.ld = d.ld; v.z0 = d.z0;
     v.out = out;
     v.ids = ids;
@@ -427,10 +369,7 @@ ViewDev view_of(const Camera& cam, int W, int H, int K, const Disp& d, float* ou
 }
 
 uint64_t view_items(const ViewDev& v) {
-    const uint64_t th = 64u >> v.tile_log2w, side = 1ull << v.super_log2;
-    const uint64_t sx = ((uint64_t)v.tiles_x + side - 1u) / side;
-    const uint64_t sy = (((uint64_t)v.H + th - 1u) / th + side - 1u) / side;
-    return sx * sy * side * side * 64u;
+    return view_tile_items(v.W, v.H, v.tile_log2w, v.super_log2);
 }
 
 }  // namespace
@@ -548,7 +487,7 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
                                          256));
         ws.view_cap = (size_t)n_views;
     }
-    if (!ws.fetch) RCP_HIP(hipMalloc((void**)&ws.fetch, sizeof(uint32_t) * kFetchParts * kFetchStride * 3));
+    if (!ws.fetch) RCP_HIP(hipMalloc((void**)&ws.fetch, sizeof(uint32_t) * kFetchWords * 3));
     if (spill_need > ws.spill_cap) {
         if (ws.spill) { RCP_HIP(hipFree(ws.spill)); ws.spill = nullptr; }
         ws.spill_cap = 0;
@@ -570,7 +509,7 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
         a.begin = d_begin + groups[g].bofs;
         a.n_views = groups[g].count;
         a.n_items = groups[g].items;
-        a.fetch = ws.fetch + kFetchParts * kFetchStride * g;
+        a.fetch = ws.fetch + kFetchWords * g;
         a.refill_min = lp.refill_min;
         a.exit_lanes = (uint32_t)lp.exit_lanes;
         a.spill = ws.spill;

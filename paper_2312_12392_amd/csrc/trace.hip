@@ -37,13 +37,15 @@ struct PassArgs {
     uint32_t exit_lanes;            // searching lanes that end a traversal step early
     int tiles_x;
     int tile_log2w;                 // pass-0 tiles of 64 pixels, 2^tile_log2w wide
+    int super_log2;                 // pass-0 super-tiles of 2^super_log2 tiles a side
     const float4* state_in;         // pass > 0: {pix bits, r, g, b}
     const float4* aux_in;           // pass > 0, depth/normal modes: {view depth, normal}
     const float* prev_img;          // pass 0: previous image or NULL (grey seed)
     const float* prev_aux;          // pass 0: previous [H][W][4] hit data or NULL (seed)
     float4* state_out;              // NULL: no following pass
     float4* aux_out;
-    uint32_t* counters;             // [kMaxPasses] list sizes, [kMaxPasses..] fetch
+    uint32_t* counters;             // [kMaxPasses] list sizes, then per pass kFetchWords band counters
+                                    // at kPassFetch
     float* out;                     // [K][H][W][3]
     int32_t* ids;                   // [K][H][W] or NULL
     float* out_aux;                 // [H][W][4] of image k or NULL (single passes)
@@ -51,6 +53,11 @@ struct PassArgs {
     uint32_t spill_stride;          // threads in the grid
     unsigned long long* stats;      // [kMaxPasses][4] or NULL
 };
+
+// The scene's counter array: list sizes, then the band counters of each pass
+// (a single chain render uses the first kFetchWords words).
+constexpr size_t kPassFetch = 2 * kMaxPasses + 8;
+constexpr size_t kCounterWords = kPassFetch + (size_t)kMaxPasses * kFetchWords;
 
 constexpr int kWaves = kBlock / 64;
 constexpr int kStage = 128;     // per-wave staging of appended entries (flushed 64 at a time)
@@ -77,12 +84,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
 
     const uint32_t P = (uint32_t)a.W * (uint32_t)a.H;
     const uint32_t n_items = a.k == 0 ? a.n_items0 : a.counters[a.k];
-    uint32_t* fetch = &a.counters[kMaxPasses + a.k];
+    uint32_t* fetch = a.counters + kPassFetch + (size_t)a.k * kFetchWords;
     float* out_k = a.out + (size_t)a.k * P * 3;
     uint32_t s_nodes = 0, s_tris = 0, s_rays = 0, s_app = 0;
 
     bool alive = false;
     bool drained = false;          // wave-uniform: the pass's list is used up
+    uint32_t part = blockIdx.x % kFetchParts;   // wave-uniform: the band fetched from
+    uint32_t parts_done = 0;                    // wave-uniform: bands found used up
     uint32_t fill = 0;             // wave-uniform: entries in this wave's stage
     uint32_t pix = 0;
     float pr = 0.5f, pg = 0.5f, pb = 0.5f;
@@ -95,20 +104,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
         const unsigned long long idle = __ballot(!alive);
         const uint32_t n_idle = (uint32_t)__popcll(idle);
         if (!drained && n_idle >= (uint32_t)a.refill_min) {
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(fetch, n_idle);
-            base = __shfl(base, 0);
-            if (base + n_idle >= n_items) drained = true;
+            uint32_t base = 0, lim = 0;
+            wave_fetch(fetch, n_items, n_idle, part, parts_done, drained, base, lim);
             if (!alive) {
                 const uint32_t item = base + lanes_below(idle);
-                bool valid = item < n_items;
+                bool valid = item < lim;
                 int x = 0, y = 0;
                 if (a.k == 0) {
-                    const uint32_t tile = item >> 6;
-                    const uint32_t l = item & 63u;
-                    const uint32_t tw = 1u << a.tile_log2w;
-                    x = (int)((tile % (uint32_t)a.tiles_x) * tw + (l & (tw - 1u)));
-                    y = (int)((tile / (uint32_t)a.tiles_x) * (64u >> a.tile_log2w) + (l >> a.tile_log2w));
+                    tile_pixel(item, (uint32_t)a.tiles_x, (uint32_t)a.tile_log2w, (uint32_t)a.super_log2, x, y);
                     valid = valid && x < a.W && y < a.H;
                     pix = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
                     pr = 0.5f; pg = 0.5f; pb = 0.5f;
@@ -317,7 +320,7 @@ rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t n_aux, size_t s
         w.aux_cap = n_aux;
     }
     if (!w.counters) {
-        RCP_HIP(hipMalloc((void**)&w.counters, sizeof(uint32_t) * (2 * kMaxPasses + 8)));
+        RCP_HIP(hipMalloc((void**)&w.counters, sizeof(uint32_t) * kCounterWords));
         RCP_HIP(hipMalloc((void**)&w.stats, sizeof(unsigned long long) * 4 * kMaxPasses));
     }
     if (!w.view) RCP_HIP(hipMalloc(&w.view, kViewBytes));
@@ -394,7 +397,7 @@ rcp_status launch_passes(rcp_scene* s, PassArgs& a, int K, hipStream_t stream) {
     a.spill_stride = threads;
     a.counters = w.counters;
     a.stats = STATS ? w.stats : nullptr;
-    hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(256), 0, stream, w.counters, 2 * kMaxPasses + 8,
+    hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(256), 0, stream, w.counters, (int)kCounterWords,
                        STATS ? w.stats : (unsigned long long*)nullptr);
     RCP_CHECK_LAUNCH();
     for (int k = 0; k < K; ++k) {
@@ -452,19 +455,21 @@ rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Di
         return render_chain(s, cam, W, H, K, disp, out_images, out_ids, host_counts, stream);
     const bool stats = host_counts != nullptr;
     const Launch lp = launch_params(s);
-    const int tw = 1 << lp.tile_log2w, th = 64 >> lp.tile_log2w;
-    const int tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
+    const int tw = 1 << lp.tile_log2w;
+    const int tiles_x = (W + tw - 1) / tw;
+    const int super_log2 = super_log2_for(W, H, lp.tile_log2w);
     PassArgs a{};
     a.sc = s->dev;
     a.sc.top_count = 0;          // this kernel stages nothing in LDS
     a.cam = cam;
     a.W = W; a.H = H; a.K = K;
     a.le = disp.le; a.ld = disp.ld; a.z0 = disp.z0;
-    a.n_items0 = (uint32_t)tiles_x * (uint32_t)tiles_y * 64u;
+    a.n_items0 = (uint32_t)view_tile_items(W, H, lp.tile_log2w, super_log2);
     a.refill_min = lp.refill_min;
     a.exit_lanes = (uint32_t)lp.exit_lanes;
     a.tiles_x = tiles_x;
     a.tile_log2w = lp.tile_log2w;
+    a.super_log2 = super_log2;
     a.out = out_images;
     a.ids = out_ids;
     a.out_aux = out_aux;

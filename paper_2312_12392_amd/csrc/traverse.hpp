@@ -38,6 +38,87 @@ __device__ inline uint32_t lanes_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// ---- work distribution ------------------------------------------------------
+// A launch's work items are split into kFetchParts contiguous ranges (bands),
+// one per XCD, each with its own counter (kFetchStride words apart).
+// Workgroups are dispatched to the XCDs round robin, so the waves of one XCD
+// start on their own band: neighbouring pixels trace through the same parts
+// of the tree, and each XCD's L2 holds the nodes of its band.  A wave whose
+// band is used up takes work from the next band, so no work is left undone.
+constexpr uint32_t kFetchParts = 8;
+constexpr uint32_t kFetchStride = 16;     // words between counters (64 bytes)
+constexpr uint32_t kFetchWords = kFetchParts * kFetchStride;
+
+__device__ inline uint32_t part_begin(uint32_t n_items, uint32_t p) {
+    return p >= kFetchParts ? n_items : (uint32_t)(((uint64_t)n_items * p / kFetchParts) & ~63ull);
+}
+
+// Items [base, lim) for the wave's n_idle idle lanes (the lanes below lim
+// get one each).  part and parts_done are wave-uniform (start: the
+// workgroup's XCD, 0); drained is set once every band is used up.  Called by
+// the whole wave.
+__device__ inline void wave_fetch(uint32_t* ctr, uint32_t n_items, uint32_t n_idle, uint32_t& part,
+                                  uint32_t& parts_done, bool& drained, uint32_t& base, uint32_t& lim) {
+    // own band first, then the next ones; every attempt either takes items
+    // or retires a band, so the loop ends
+    if ((threadIdx.x & 63) == 0) {
+        for (;;) {
+            const uint32_t lo = part_begin(n_items, part), hi = part_begin(n_items, part + 1u);
+            const uint32_t got = lo < hi ? atomicAdd(&ctr[kFetchStride * part], n_idle) : hi - lo;
+            if (got < hi - lo) { base = lo + got; lim = hi; break; }
+            part = (part + 1u) % kFetchParts;
+            if (++parts_done >= kFetchParts) { base = lim = n_items; break; }
+        }
+    }
+    // lane 0 is the first active lane (the whole wave is here)
+    base = __builtin_amdgcn_readfirstlane(base);
+    lim = __builtin_amdgcn_readfirstlane(lim);
+    part = __builtin_amdgcn_readfirstlane(part);
+    parts_done = __builtin_amdgcn_readfirstlane(parts_done);
+    if (base + n_idle >= lim) {   // this band is used up now
+        part = (part + 1u) % kFetchParts;
+        ++parts_done;
+    }
+    if (parts_done >= kFetchParts) drained = true;
+}
+
+// Work item -> pixel.  Items come in 64-pixel tiles 2^tile_log2w wide;
+// tiles are ordered by super-tiles of 2^super_log2 x 2^super_log2 tiles, row
+// by row, so that the pixels in flight on one XCD form a compact patch of the
+// screen (their rays share more of the tree than a thin strip of whole tile
+// rows does).  The super-tile grid covers the image, so the items of its
+// tiles beyond the image edges are skipped; views smaller than a super-tile
+// keep plain tile rows (super_log2 = 0).  (Measured on the terrain frame:
+// 8 x 8 tiles 1.8% faster than plain tile rows, 16 x 16 3.5%; super-tiles
+// clipped to the image instead of padded were 2% slower than padded ones.)
+constexpr int kSuperLog2 = 4;
+
+inline int super_log2_for(int W, int H, int tile_log2w) {
+    const int tiles_x = (W + (1 << tile_log2w) - 1) >> tile_log2w;
+    const int tiles_y = (H + (64 >> tile_log2w) - 1) / (64 >> tile_log2w);
+    return (tiles_x >= (1 << kSuperLog2) && tiles_y >= (1 << kSuperLog2)) ? kSuperLog2 : 0;
+}
+
+// Work items of a W x H view (a whole number of super-tiles).
+inline uint64_t view_tile_items(int W, int H, int tile_log2w, int super_log2) {
+    const uint64_t tw = 1ull << tile_log2w, th = 64u >> tile_log2w, side = 1ull << super_log2;
+    const uint64_t sx = (((uint64_t)W + tw - 1u) / tw + side - 1u) / side;
+    const uint64_t sy = (((uint64_t)H + th - 1u) / th + side - 1u) / side;
+    return sx * sy * side * side * 64u;
+}
+
+__device__ inline void tile_pixel(uint32_t local, uint32_t tiles_x, uint32_t tile_log2w, uint32_t super_log2, int& x,
+                                  int& y) {
+    const uint32_t tile = local >> 6, l = local & 63u;
+    const uint32_t tw = 1u << tile_log2w;
+    const uint32_t sl = super_log2, sm = (1u << sl) - 1u;
+    const uint32_t st = tile >> (2u * sl), w = tile & ((1u << (2u * sl)) - 1u);
+    const uint32_t sx = (tiles_x + sm) >> sl;   // super-tiles per row
+    const uint32_t tx = ((st % sx) << sl) + (w & sm), ty = ((st / sx) << sl) + (w >> sl);
+    x = (int)(tx * tw + (l & (tw - 1u)));
+    y = (int)(ty * (64u >> tile_log2w) + (l >> tile_log2w));
+}
+
 // Horizontal half extent of the image plane, tan(fovy / 2) * W / H: one value
 // per view, the same bits on the host and the device.
 __host__ __device__ inline float half_width(float th, int W, int H) {
