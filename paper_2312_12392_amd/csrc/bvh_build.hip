@@ -18,6 +18,7 @@
 //      that open their children of largest area
 //   6. packing of 48-byte triangles, a per-triangle table of the two shaded
 //      colours and the unit normals.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -77,10 +78,11 @@ __global__ void k_init_bounds(uint32_t* bounds) {
 __global__ __launch_bounds__(kB) void k_tri_prep(const float* __restrict__ verts, const uint32_t* __restrict__ idx,
                                                   uint32_t n, float4* __restrict__ tlo, float4* __restrict__ thi,
                                                   uint32_t* __restrict__ bounds) {
-    const uint32_t i = blockIdx.x * kB + threadIdx.x;
-    float3 c = make_float3(INFINITY, INFINITY, INFINITY);
+    // grid-stride over the triangles; the centroid bounds are reduced per
+    // thread, per wave and per workgroup before six atomics per workgroup
+    float3 cmin = make_float3(INFINITY, INFINITY, INFINITY);
     float3 cmax = make_float3(-INFINITY, -INFINITY, -INFINITY);
-    if (i < n) {
+    for (uint32_t i = blockIdx.x * kB + threadIdx.x; i < n; i += gridDim.x * kB) {
         float3 a = ld3(verts, idx[3 * (size_t)i]);
         float3 b = ld3(verts, idx[3 * (size_t)i + 1]);
         float3 d = ld3(verts, idx[3 * (size_t)i + 2]);
@@ -88,14 +90,28 @@ __global__ __launch_bounds__(kB) void k_tri_prep(const float* __restrict__ verts
         float3 hi = make_float3(fmaxf(fmaxf(a.x, b.x), d.x), fmaxf(fmaxf(a.y, b.y), d.y), fmaxf(fmaxf(a.z, b.z), d.z));
         tlo[i] = make_float4(lo.x, lo.y, lo.z, 0.0f);
         thi[i] = make_float4(hi.x, hi.y, hi.z, 0.0f);
-        c = make_float3(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z));
-        cmax = c;
+        const float3 c = make_float3(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z));
+        cmin = make_float3(fminf(cmin.x, c.x), fminf(cmin.y, c.y), fminf(cmin.z, c.z));
+        cmax = make_float3(fmaxf(cmax.x, c.x), fmaxf(cmax.y, c.y), fmaxf(cmax.z, c.z));
     }
-    float m0 = wave_min(c.x), m1 = wave_min(c.y), m2 = wave_min(c.z);
-    float x0 = wave_max(cmax.x), x1 = wave_max(cmax.y), x2 = wave_max(cmax.z);
-    if ((threadIdx.x & 63) == 0 && m0 <= x0) {
-        atomicMin(&bounds[0], f2o(m0)); atomicMin(&bounds[1], f2o(m1)); atomicMin(&bounds[2], f2o(m2));
-        atomicMax(&bounds[3], f2o(x0)); atomicMax(&bounds[4], f2o(x1)); atomicMax(&bounds[5], f2o(x2));
+    __shared__ float red[kB / 64][6];
+    const int wave = threadIdx.x >> 6;
+    const float r[6] = {wave_min(cmin.x), wave_min(cmin.y), wave_min(cmin.z),
+                        wave_max(cmax.x), wave_max(cmax.y), wave_max(cmax.z)};
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 6; ++k) red[wave][k] = r[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float v[6];
+        for (int k = 0; k < 6; ++k) v[k] = red[0][k];
+        for (int w = 1; w < kB / 64; ++w) {
+            for (int k = 0; k < 3; ++k) v[k] = fminf(v[k], red[w][k]);
+            for (int k = 3; k < 6; ++k) v[k] = fmaxf(v[k], red[w][k]);
+        }
+        if (v[0] <= v[3]) {
+            atomicMin(&bounds[0], f2o(v[0])); atomicMin(&bounds[1], f2o(v[1])); atomicMin(&bounds[2], f2o(v[2]));
+            atomicMax(&bounds[3], f2o(v[3])); atomicMax(&bounds[4], f2o(v[4])); atomicMax(&bounds[5], f2o(v[5]));
+        }
     }
 }
 
@@ -306,10 +322,21 @@ __global__ __launch_bounds__(kB) void k_ploc_compact(int m, const uint32_t* __re
 }
 
 // Leaves under every inner node, bottom-up with per-node arrival counters.
-__global__ __launch_bounds__(kB) void k_leaf_counts(int n, const int32_t* __restrict__ left,
-                                                     const int32_t* __restrict__ right,
-                                                     const int32_t* __restrict__ parent, uint32_t* __restrict__ arrivals,
-                                                     int32_t* __restrict__ cnt) {
+// ---- bottom-up passes -----------------------------------------------------
+// A pass computes each inner node from its two children.  It runs either one
+// launch per tree level, deepest first (the nodes sorted by depth; kernel
+// boundaries order the levels, no fences), or, for trees too deep for that,
+// as one launch of walks up from the leaves with per-node arrival counters
+// (the second thread to arrive computes the node, after device-scope fences).
+template <class Body>
+__global__ __launch_bounds__(kB) void k_level(const int32_t* __restrict__ ids, uint32_t count, Body body) {
+    const uint32_t i = blockIdx.x * kB + threadIdx.x;
+    if (i < count) body(ids[i]);
+}
+
+template <class Body>
+__global__ __launch_bounds__(kB) void k_walk_up(int n, const int32_t* __restrict__ parent,
+                                                 uint32_t* __restrict__ arrivals, Body body) {
     const int j = blockIdx.x * kB + threadIdx.x;
     if (j >= n) return;
     int node = parent[n - 1 + j];
@@ -317,15 +344,43 @@ __global__ __launch_bounds__(kB) void k_leaf_counts(int n, const int32_t* __rest
         __threadfence();
         if (atomicAdd(&arrivals[node], 1u) == 0u) return;   // the sibling finishes this node
         __threadfence();
-        const int32_t l = left[node], r = right[node];
-        cnt[node] = (l < 0 ? 1 : cnt[l]) + (r < 0 ? 1 : cnt[r]);
+        body(node);
         node = parent[node];
     }
 }
 
-// Depth-first rank of the first leaf under every node (inner nodes at
-// [0, n-1), leaves at [n-1, 2n-1)): the leaves of the left siblings along
-// the path to the root.
+// Depth of every inner node (walk up to the root), as a sort key.
+__global__ __launch_bounds__(kB) void k_node_depth(int n, const int32_t* __restrict__ parent,
+                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ ids,
+                                                    uint32_t* __restrict__ max_depth) {
+    const int x = blockIdx.x * kB + threadIdx.x;
+    uint32_t d = 0;
+    if (x < n - 1) {
+        for (int p = parent[x]; p >= 0 && d < (uint32_t)n; p = parent[p]) ++d;
+        keys[x] = d;
+        ids[x] = (uint32_t)x;
+    }
+    for (int o = 32; o > 0; o >>= 1) d = max(d, (uint32_t)__shfl_xor((int)d, o));
+    if ((threadIdx.x & 63) == 0 && x < n - 1 + 64) atomicMax(max_depth, d);
+}
+
+// First position of each depth in the depth-sorted order.
+__global__ __launch_bounds__(kB) void k_level_starts(int m, const uint64_t* __restrict__ keys,
+                                                      uint32_t* __restrict__ starts) {
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i < m && (i == 0 || keys[i] != keys[i - 1])) starts[keys[i]] = (uint32_t)i;
+}
+
+struct LeafCountBody {
+    const int32_t* left;
+    const int32_t* right;
+    int32_t* cnt;
+    __device__ void operator()(int node) const {
+        const int32_t l = left[node], r = right[node];
+        cnt[node] = (l < 0 ? 1 : cnt[l]) + (r < 0 ? 1 : cnt[r]);
+    }
+};
+
 __global__ __launch_bounds__(kB) void k_dfs_first(int n, const int32_t* __restrict__ left,
                                                    const int32_t* __restrict__ right, const int32_t* __restrict__ parent,
                                                    const int32_t* __restrict__ cnt, int32_t* __restrict__ first) {
@@ -393,7 +448,7 @@ __device__ inline void child_info(int32_t c, const float4* __restrict__ tlo, con
         cost = c_isect * half_area(lo, hi);
         ninner = 0;
     } else {
-        // written by the sibling's thread before its release fence
+        // computed earlier in the pass (a deeper level, or the sibling's walk)
         float4 a = nd.lo[c];
         float4 b = nd.hi[c];
         lo = make_float3(a.x, a.y, a.z);
@@ -403,19 +458,18 @@ __device__ inline void child_info(int32_t c, const float4* __restrict__ tlo, con
     }
 }
 
-__global__ __launch_bounds__(kB) void k_refit(int n, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
-                                               const int32_t* __restrict__ parent, const int32_t* __restrict__ rfirst,
-                                               const int32_t* __restrict__ rlast, const float4* __restrict__ tlo,
-                                               const float4* __restrict__ thi, const uint32_t* __restrict__ sorted,
-                                               uint32_t* __restrict__ arrivals, NodeData nd, int max_leaf,
-                                               float c_trav, float c_isect) {
-    const int j = blockIdx.x * kB + threadIdx.x;
-    if (j >= n) return;
-    int node = parent[n - 1 + j];
-    while (node >= 0) {
-        __threadfence();
-        if (atomicAdd(&arrivals[node], 1u) == 0u) return;   // the sibling finishes this node
-        __threadfence();
+struct RefitBody {
+    const int32_t* left;
+    const int32_t* right;
+    const int32_t* rfirst;
+    const int32_t* rlast;
+    const float4* tlo;
+    const float4* thi;
+    const uint32_t* sorted;
+    NodeData nd;
+    int max_leaf;
+    float c_trav, c_isect;
+    __device__ void operator()(int node) const {
         float3 llo, lhi, rlo, rhi;
         float cl, cr;
         int nl, nr;
@@ -433,9 +487,8 @@ __global__ __launch_bounds__(kB) void k_refit(int n, const int32_t* __restrict__
         nd.cost[node] = col ? leaf_cost : split_cost;
         nd.n_inner[node] = col ? 0 : 1 + nl + nr;
         nd.collapse[node] = col ? 1 : 0;
-        node = parent[node];
     }
-}
+};
 
 // Summary read back by the host: [0] collapse(root), [1] n_inner(root),
 // [2] top count, [3] max depth of inner nodes; floats follow.
@@ -654,7 +707,7 @@ __global__ __launch_bounds__(kB) void k_collapse4(const float4* __restrict__ n2,
 //                  wide node: c_trav * A(i) + min_k C(l, k) + C(r, 4 - k))
 //   C(i, j)  = min(C(i, j - 1), min_k C(l, k) + C(r, j - k))
 // with A the box surface area and c_leaf = kLeafEntry * c_trav; a single
-// triangle costs (c_isect + c_leaf) * A(tri) whatever j.  One bottom-up pass (arrival counters, as the refit) computes
+// triangle costs (c_isect + c_leaf) * A(tri) whatever j.  One bottom-up pass computes
 // the costs, the decisions and the number of wide nodes each choice makes;
 // the wide nodes are then emitted level by level from the decisions.
 // Decision word of inner node i: bit 0 leaf at j = 1; bits 1-2 the left
@@ -679,7 +732,7 @@ __device__ inline void dp_child(int32_t c, const float4* __restrict__ tlo, const
         const float ct = (c_isect + c_entry) * half_area(lo, hi);
         for (int j = 1; j <= 4; ++j) { C[j] = ct; W[j] = 0; }
     } else {
-        // written by the sibling's thread before its release fence
+        // computed earlier in the pass (a deeper level, or the sibling's walk)
         const float4 a = nd.lo[c], b = nd.hi[c];
         lo = make_float3(a.x, a.y, a.z);
         hi = make_float3(b.x, b.y, b.z);
@@ -690,20 +743,20 @@ __device__ inline void dp_child(int32_t c, const float4* __restrict__ tlo, const
     }
 }
 
-__global__ __launch_bounds__(kB) void k_wide_dp(int n, const int32_t* __restrict__ left,
-                                                 const int32_t* __restrict__ right, const int32_t* __restrict__ parent,
-                                                 const int32_t* __restrict__ rfirst, const int32_t* __restrict__ rlast,
-                                                 const float4* __restrict__ tlo, const float4* __restrict__ thi,
-                                                 const uint32_t* __restrict__ sorted, uint32_t* __restrict__ arrivals,
-                                                 NodeData nd, WideDP wd, int max_leaf, float c_trav, float c_isect) {
-    const int j0 = blockIdx.x * kB + threadIdx.x;
-    if (j0 >= n) return;
-    const float c_entry = kLeafEntry * c_trav;
-    int node = parent[n - 1 + j0];
-    while (node >= 0) {
-        __threadfence();
-        if (atomicAdd(&arrivals[node], 1u) == 0u) return;   // the sibling finishes this node
-        __threadfence();
+struct WideDPBody {
+    const int32_t* left;
+    const int32_t* right;
+    const int32_t* rfirst;
+    const int32_t* rlast;
+    const float4* tlo;
+    const float4* thi;
+    const uint32_t* sorted;
+    NodeData nd;
+    WideDP wd;
+    int max_leaf;
+    float c_trav, c_isect;
+    __device__ void operator()(int node) const {
+        const float c_entry = kLeafEntry * c_trav;
         float3 llo, lhi, rlo, rhi;
         float Cl[5], Cr[5];
         int Wl[5], Wr[5];
@@ -744,9 +797,8 @@ __global__ __launch_bounds__(kB) void k_wide_dp(int n, const int32_t* __restrict
         wd.cost[node] = make_float4(C[1], C[2], C[3], C[4]);
         wd.count[node] = make_int4(W[1], W[2], W[3], W[4]);
         wd.dec[node] = dec;
-        node = parent[node];
     }
-}
+};
 
 // Wide nodes of the whole tree (the root is always a wide node) and the root box.
 struct WideSummary {
@@ -948,12 +1000,74 @@ struct TempSet {
 
 inline unsigned blocks(long n) { return (unsigned)((n + kB - 1) / kB); }
 
+// Inner nodes sorted by depth, and where each depth starts (host copy), for
+// the per-level form of the bottom-up passes.  ids stays NULL for trees
+// deeper than kMaxLevels: the passes then take the walk-up form.
+constexpr uint32_t kMaxLevels = 1024;
+
+struct LevelOrder {
+    int32_t* ids = nullptr;
+    std::vector<uint32_t> starts;   // depth d: ids[starts[d] .. starts[d + 1])
+};
+
+rcp_status level_order(int n, const int32_t* parent, TempSet& tmp, LevelOrder& lo, hipStream_t stream) {
+    const int m = n - 1;
+    uint64_t *keys, *keys2;
+    uint32_t *ids, *ids2, *max_depth, *starts;
+    RCP_TRY(tmp.alloc(&keys, (size_t)m));
+    RCP_TRY(tmp.alloc(&keys2, (size_t)m));
+    RCP_TRY(tmp.alloc(&ids, (size_t)m));
+    RCP_TRY(tmp.alloc(&ids2, (size_t)m));
+    RCP_TRY(tmp.alloc(&max_depth, 1));
+    RCP_TRY(tmp.alloc(&starts, kMaxLevels + 1));
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, stream, max_depth, 0u);
+    hipLaunchKernelGGL(k_node_depth, dim3(blocks(m)), dim3(kB), 0, stream, n, parent, keys, ids, max_depth);
+    RCP_CHECK_LAUNCH();
+    uint32_t depth = 0;
+    RCP_HIP(hipMemcpyAsync(&depth, max_depth, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    RCP_HIP(hipStreamSynchronize(stream));
+    lo.ids = nullptr;
+    lo.starts.clear();
+    if (depth + 1 > kMaxLevels) return RCP_OK;
+    int bits = 8;
+    while ((1u << bits) <= depth) bits += 8;
+    RCP_TRY(radix_sort_pairs(keys, ids, keys2, ids2, m, bits, stream));
+    hipLaunchKernelGGL(k_level_starts, dim3(blocks(m)), dim3(kB), 0, stream, m, (const uint64_t*)keys, starts);
+    RCP_CHECK_LAUNCH();
+    lo.starts.resize(depth + 2);
+    RCP_HIP(hipMemcpyAsync(lo.starts.data(), starts, sizeof(uint32_t) * (depth + 1), hipMemcpyDeviceToHost, stream));
+    RCP_HIP(hipStreamSynchronize(stream));
+    lo.starts[depth + 1] = (uint32_t)m;
+    lo.ids = (int32_t*)ids;
+    return RCP_OK;
+}
+
+// Run a bottom-up pass over the tree (see k_level / k_walk_up).
+template <class Body>
+rcp_status bottom_up(int n, const int32_t* parent, uint32_t* arrivals, const LevelOrder& lo, const Body& body,
+                     hipStream_t stream) {
+    if (lo.ids) {
+        for (int d = (int)lo.starts.size() - 2; d >= 0; --d) {
+            const uint32_t c = lo.starts[(size_t)d + 1] - lo.starts[(size_t)d];
+            if (c == 0) continue;
+            hipLaunchKernelGGL(k_level<Body>, dim3(blocks(c)), dim3(kB), 0, stream,
+                               (const int32_t*)lo.ids + lo.starts[(size_t)d], c, body);
+        }
+    } else {
+        RCP_HIP(hipMemsetAsync(arrivals, 0, sizeof(uint32_t) * (size_t)(n - 1), stream));
+        hipLaunchKernelGGL(k_walk_up<Body>, dim3(blocks(n)), dim3(kB), 0, stream, n, parent, arrivals, body);
+    }
+    RCP_CHECK_LAUNCH();
+    return RCP_OK;
+}
+
 // PLOC tree over the Morton-sorted triangles, renumbered in depth-first leaf
 // order (sorted is permuted in place).  Returns RCP_ERR_NOT_READY when the
 // rounds do not converge within the cap; the caller then builds the radix
 // tree from the untouched sorted order instead.
 rcp_status ploc_build(int n, const float4* tlo, const float4* thi, uint32_t* sorted, int32_t* left, int32_t* right,
-                      int32_t* parent, int32_t* rfirst, int32_t* rlast, hipStream_t stream) {
+                      int32_t* parent, int32_t* rfirst, int32_t* rlast, TempSet& outer, LevelOrder& levels,
+                      hipStream_t stream) {
     TempSet tmp;
     int32_t *id, *id2, *nn, *next_id, *cnt, *first, *parent_tmp;
     float4 *lo, *hi, *lo2, *hi2;
@@ -1017,9 +1131,11 @@ rcp_status ploc_build(int n, const float4* tlo, const float4* thi, uint32_t* sor
         return RCP_ERR_INTERNAL;
     }
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, stream, parent_tmp, -1);   // the root
-    RCP_HIP(hipMemsetAsync(arrivals, 0, sizeof(uint32_t) * un, stream));
-    hipLaunchKernelGGL(k_leaf_counts, dim3(blocks(n)), dim3(kB), 0, stream, n, (const int32_t*)left,
-                       (const int32_t*)right, (const int32_t*)parent_tmp, arrivals, cnt);
+    RCP_CHECK_LAUNCH();
+    // the depth order of the inner nodes holds for the renumbered tree too
+    // (inner nodes keep their numbers)
+    RCP_TRY(level_order(n, parent_tmp, outer, levels, stream));
+    RCP_TRY(bottom_up(n, parent_tmp, arrivals, levels, LeafCountBody{left, right, cnt}, stream));
     hipLaunchKernelGGL(k_dfs_first, dim3(blocks(2L * n - 1)), dim3(kB), 0, stream, n, (const int32_t*)left,
                        (const int32_t*)right, (const int32_t*)parent_tmp, (const int32_t*)cnt, first);
     hipLaunchKernelGGL(k_dfs_renumber, dim3(blocks(2L * n - 1)), dim3(kB), 0, stream, n, (const int32_t*)first,
@@ -1101,7 +1217,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
         RCP_TRY(tmp.alloc(&sorted, n));
         RCP_TRY(tmp.alloc(&vals2, n));
         hipLaunchKernelGGL(k_init_bounds, dim3(1), dim3(64), 0, stream, bounds);
-        hipLaunchKernelGGL(k_tri_prep, dim3(blocks(n)), dim3(kB), 0, stream, (const float*)d_verts,
+        hipLaunchKernelGGL(k_tri_prep, dim3(std::min(blocks(n), 2048u)), dim3(kB), 0, stream, (const float*)d_verts,
                            (const uint32_t*)d_idx, n, tlo, thi, bounds);
         hipLaunchKernelGGL(k_morton, dim3(blocks(n)), dim3(kB), 0, stream, (const float4*)tlo,
                            (const float4*)thi, n, (const uint32_t*)bounds, keys, sorted);
@@ -1137,24 +1253,24 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
             RCP_TRY(tmp.alloc(&nd.lo, ni));
             RCP_TRY(tmp.alloc(&nd.hi, ni));
             rcp_status tree = RCP_ERR_NOT_READY;
+            LevelOrder levels;
             if (builder == RCP_BUILDER_PLOC)
-                tree = ploc_build((int)n, tlo, thi, sorted, left, right, parent, rfirst, rlast, stream);
+                tree = ploc_build((int)n, tlo, thi, sorted, left, right, parent, rfirst, rlast, tmp, levels, stream);
             if (tree == RCP_ERR_NOT_READY) {   // the radix tree, or PLOC did not converge
                 hipLaunchKernelGGL(k_radix_tree, dim3(blocks(ni)), dim3(kB), 0, stream, (const uint64_t*)keys,
                                    (int)n, left, right, parent, rfirst, rlast);
                 RCP_CHECK_LAUNCH();
-                tree = RCP_OK;
+                tree = level_order((int)n, parent, tmp, levels, stream);
             }
             if (tree != RCP_OK) return tree;
-            RCP_HIP(hipMemsetAsync(arrivals, 0, sizeof(uint32_t) * ni, stream));
             if (collapse == RCP_COLLAPSE_SAH) {
                 RCP_TRY(tmp.alloc(&wd.cost, ni));
                 RCP_TRY(tmp.alloc(&wd.count, ni));
                 RCP_TRY(tmp.alloc(&wd.dec, ni));
-                hipLaunchKernelGGL(k_wide_dp, dim3(blocks(n)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
-                                   (const int32_t*)right, (const int32_t*)parent, (const int32_t*)rfirst,
-                                   (const int32_t*)rlast, (const float4*)tlo, (const float4*)thi,
-                                   (const uint32_t*)sorted, arrivals, nd, wd, max_leaf, c_trav, c_isect);
+                RCP_TRY(bottom_up((int)n, parent, arrivals, levels,
+                                  WideDPBody{left, right, rfirst, rlast, tlo, thi, sorted, nd, wd, max_leaf, c_trav,
+                                             c_isect},
+                                  stream));
                 hipLaunchKernelGGL(k_wide_summary, dim3(1), dim3(1), 0, stream, (const int32_t*)left,
                                    (const int32_t*)right, nd, wd, wsm);
                 RCP_CHECK_LAUNCH();
@@ -1169,10 +1285,9 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                 RCP_TRY(tmp.alloc(&nd.cost, ni));
                 RCP_TRY(tmp.alloc(&nd.n_inner, ni));
                 RCP_TRY(tmp.alloc(&nd.collapse, ni));
-                hipLaunchKernelGGL(k_refit, dim3(blocks(n)), dim3(kB), 0, stream, (int)n, (const int32_t*)left,
-                                   (const int32_t*)right, (const int32_t*)parent, (const int32_t*)rfirst,
-                                   (const int32_t*)rlast, (const float4*)tlo, (const float4*)thi,
-                                   (const uint32_t*)sorted, arrivals, nd, max_leaf, c_trav, c_isect);
+                RCP_TRY(bottom_up((int)n, parent, arrivals, levels,
+                                  RefitBody{left, right, rfirst, rlast, tlo, thi, sorted, nd, max_leaf, c_trav, c_isect},
+                                  stream));
                 hipLaunchKernelGGL(k_summary_root, dim3(1), dim3(1), 0, stream, nd, sm);
                 RCP_CHECK_LAUNCH();
                 RCP_HIP(hipMemcpyAsync(&hs, sm, sizeof(Summary), hipMemcpyDeviceToHost, stream));

@@ -92,7 +92,6 @@ __device__ inline void chain_body(const ChainArgs& a) {
 
     int v = 0;                 // the lane's view
 
-    const int lane = threadIdx.x & 63;
     const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
     Stack st;
     st.lds = stack_area + threadIdx.x;
