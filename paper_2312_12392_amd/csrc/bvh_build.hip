@@ -11,8 +11,8 @@
 //      (or, by default, PLOC: agglomerative clustering of Morton neighbours)
 //   5. the 4-wide tree the traversal uses, 128-byte nodes, by default from
 //      an SAH-optimal collapse of the binary tree: a bottom-up dynamic
-//      programme over the subtrees (arrival counters), then emission level by
-//      level.  The greedy alternative: a bottom-up refit that collapses
+//      programme over the subtrees (one launch per tree level), then
+//      emission level by level.  The greedy alternative: a bottom-up refit that collapses
 //      subtrees into leaves (<= max_leaf triangles) where the binary SAH says
 //      so, packing of the binary tree in depth-first order, and wide nodes
 //      that open their children of largest area
@@ -321,32 +321,17 @@ __global__ __launch_bounds__(kB) void k_ploc_compact(int m, const uint32_t* __re
     if (i == m - 1) *m_out = pos[i] + keep[i];
 }
 
-// Leaves under every inner node, bottom-up with per-node arrival counters.
 // ---- bottom-up passes -----------------------------------------------------
-// A pass computes each inner node from its two children.  It runs either one
-// launch per tree level, deepest first (the nodes sorted by depth; kernel
-// boundaries order the levels, no fences), or, for trees too deep for that,
-// as one launch of walks up from the leaves with per-node arrival counters
-// (the second thread to arrive computes the node, after device-scope fences).
+// A pass computes each inner node from its two children, one launch per tree
+// level, deepest first: the inner nodes are sorted by depth, and kernel
+// boundaries order the levels, so no fences are needed.  (Walks up from the
+// leaves, where the second thread to reach a node computes it, need
+// device-scope fences around every arrival counter; on 8 XCDs with their own
+// L2s those cost 5-7 ms per pass at 1M triangles, the levels 0.3 ms.)
 template <class Body>
 __global__ __launch_bounds__(kB) void k_level(const int32_t* __restrict__ ids, uint32_t count, Body body) {
     const uint32_t i = blockIdx.x * kB + threadIdx.x;
     if (i < count) body(ids[i]);
-}
-
-template <class Body>
-__global__ __launch_bounds__(kB) void k_walk_up(int n, const int32_t* __restrict__ parent,
-                                                 uint32_t* __restrict__ arrivals, Body body) {
-    const int j = blockIdx.x * kB + threadIdx.x;
-    if (j >= n) return;
-    int node = parent[n - 1 + j];
-    while (node >= 0) {
-        __threadfence();
-        if (atomicAdd(&arrivals[node], 1u) == 0u) return;   // the sibling finishes this node
-        __threadfence();
-        body(node);
-        node = parent[node];
-    }
 }
 
 // Depth of every inner node (walk up to the root), as a sort key.
@@ -371,6 +356,7 @@ __global__ __launch_bounds__(kB) void k_level_starts(int m, const uint64_t* __re
     if (i < m && (i == 0 || keys[i] != keys[i - 1])) starts[keys[i]] = (uint32_t)i;
 }
 
+// Leaves under every inner node.
 struct LeafCountBody {
     const int32_t* left;
     const int32_t* right;
@@ -1001,8 +987,9 @@ struct TempSet {
 inline unsigned blocks(long n) { return (unsigned)((n + kB - 1) / kB); }
 
 // Inner nodes sorted by depth, and where each depth starts (host copy), for
-// the per-level form of the bottom-up passes.  ids stays NULL for trees
-// deeper than kMaxLevels: the passes then take the walk-up form.
+// the bottom-up passes.  A PLOC tree is at most as deep as its rounds (at
+// most 64 + 16 log2 n <= 512), a radix tree at most 64 key bits plus log2 n
+// for equal keys, so kMaxLevels is never reached by a tree built here.
 constexpr uint32_t kMaxLevels = 1024;
 
 struct LevelOrder {
@@ -1028,7 +1015,10 @@ rcp_status level_order(int n, const int32_t* parent, TempSet& tmp, LevelOrder& l
     RCP_HIP(hipStreamSynchronize(stream));
     lo.ids = nullptr;
     lo.starts.clear();
-    if (depth + 1 > kMaxLevels) return RCP_OK;
+    if (depth + 1 > kMaxLevels) {
+        set_error("binary tree of depth %u (limit %u)", depth, kMaxLevels - 1);
+        return RCP_ERR_INTERNAL;
+    }
     int bits = 8;
     while ((1u << bits) <= depth) bits += 8;
     RCP_TRY(radix_sort_pairs(keys, ids, keys2, ids2, m, bits, stream));
@@ -1042,20 +1032,14 @@ rcp_status level_order(int n, const int32_t* parent, TempSet& tmp, LevelOrder& l
     return RCP_OK;
 }
 
-// Run a bottom-up pass over the tree (see k_level / k_walk_up).
+// Run a bottom-up pass over the tree, deepest level first.
 template <class Body>
-rcp_status bottom_up(int n, const int32_t* parent, uint32_t* arrivals, const LevelOrder& lo, const Body& body,
-                     hipStream_t stream) {
-    if (lo.ids) {
-        for (int d = (int)lo.starts.size() - 2; d >= 0; --d) {
-            const uint32_t c = lo.starts[(size_t)d + 1] - lo.starts[(size_t)d];
-            if (c == 0) continue;
-            hipLaunchKernelGGL(k_level<Body>, dim3(blocks(c)), dim3(kB), 0, stream,
-                               (const int32_t*)lo.ids + lo.starts[(size_t)d], c, body);
-        }
-    } else {
-        RCP_HIP(hipMemsetAsync(arrivals, 0, sizeof(uint32_t) * (size_t)(n - 1), stream));
-        hipLaunchKernelGGL(k_walk_up<Body>, dim3(blocks(n)), dim3(kB), 0, stream, n, parent, arrivals, body);
+rcp_status bottom_up(const LevelOrder& lo, const Body& body, hipStream_t stream) {
+    for (int d = (int)lo.starts.size() - 2; d >= 0; --d) {
+        const uint32_t c = lo.starts[(size_t)d + 1] - lo.starts[(size_t)d];
+        if (c == 0) continue;
+        hipLaunchKernelGGL(k_level<Body>, dim3(blocks(c)), dim3(kB), 0, stream,
+                           (const int32_t*)lo.ids + lo.starts[(size_t)d], c, body);
     }
     RCP_CHECK_LAUNCH();
     return RCP_OK;
@@ -1071,7 +1055,7 @@ rcp_status ploc_build(int n, const float4* tlo, const float4* thi, uint32_t* sor
     TempSet tmp;
     int32_t *id, *id2, *nn, *next_id, *cnt, *first, *parent_tmp;
     float4 *lo, *hi, *lo2, *hi2;
-    uint32_t *pos, *keep, *m_out, *scratch, *arrivals, *sorted2;
+    uint32_t *pos, *keep, *m_out, *scratch, *sorted2;
     const size_t un = (size_t)n;
     RCP_TRY(tmp.alloc(&id, un));
     RCP_TRY(tmp.alloc(&id2, un));
@@ -1088,7 +1072,6 @@ rcp_status ploc_build(int n, const float4* tlo, const float4* thi, uint32_t* sor
     RCP_TRY(tmp.alloc(&keep, un));
     RCP_TRY(tmp.alloc(&m_out, 1));
     RCP_TRY(tmp.alloc(&scratch, scan_scratch_words(n)));
-    RCP_TRY(tmp.alloc(&arrivals, un));
     RCP_TRY(tmp.alloc(&sorted2, un));
     // every entry gets its parent from a merge; -1 until then, so that a walk
     // to the root ends whatever happens
@@ -1135,7 +1118,7 @@ rcp_status ploc_build(int n, const float4* tlo, const float4* thi, uint32_t* sor
     // the depth order of the inner nodes holds for the renumbered tree too
     // (inner nodes keep their numbers)
     RCP_TRY(level_order(n, parent_tmp, outer, levels, stream));
-    RCP_TRY(bottom_up(n, parent_tmp, arrivals, levels, LeafCountBody{left, right, cnt}, stream));
+    RCP_TRY(bottom_up(levels, LeafCountBody{left, right, cnt}, stream));
     hipLaunchKernelGGL(k_dfs_first, dim3(blocks(2L * n - 1)), dim3(kB), 0, stream, n, (const int32_t*)left,
                        (const int32_t*)right, (const int32_t*)parent_tmp, (const int32_t*)cnt, first);
     hipLaunchKernelGGL(k_dfs_renumber, dim3(blocks(2L * n - 1)), dim3(kB), 0, stream, n, (const int32_t*)first,
@@ -1243,13 +1226,11 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
         float bbox[6] = {0, 0, 0, 0, 0, 0};
         if (!single) {
             const long ni = (long)n - 1;
-            uint32_t* arrivals;
             RCP_TRY(tmp.alloc(&left, ni));
             RCP_TRY(tmp.alloc(&right, ni));
             RCP_TRY(tmp.alloc(&parent, 2 * (size_t)n - 1));
             RCP_TRY(tmp.alloc(&rfirst, ni));
             RCP_TRY(tmp.alloc(&rlast, ni));
-            RCP_TRY(tmp.alloc(&arrivals, ni));
             RCP_TRY(tmp.alloc(&nd.lo, ni));
             RCP_TRY(tmp.alloc(&nd.hi, ni));
             rcp_status tree = RCP_ERR_NOT_READY;
@@ -1267,7 +1248,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                 RCP_TRY(tmp.alloc(&wd.cost, ni));
                 RCP_TRY(tmp.alloc(&wd.count, ni));
                 RCP_TRY(tmp.alloc(&wd.dec, ni));
-                RCP_TRY(bottom_up((int)n, parent, arrivals, levels,
+                RCP_TRY(bottom_up(levels,
                                   WideDPBody{left, right, rfirst, rlast, tlo, thi, sorted, nd, wd, max_leaf, c_trav,
                                              c_isect},
                                   stream));
@@ -1285,7 +1266,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                 RCP_TRY(tmp.alloc(&nd.cost, ni));
                 RCP_TRY(tmp.alloc(&nd.n_inner, ni));
                 RCP_TRY(tmp.alloc(&nd.collapse, ni));
-                RCP_TRY(bottom_up((int)n, parent, arrivals, levels,
+                RCP_TRY(bottom_up(levels,
                                   RefitBody{left, right, rfirst, rlast, tlo, thi, sorted, nd, max_leaf, c_trav, c_isect},
                                   stream));
                 hipLaunchKernelGGL(k_summary_root, dim3(1), dim3(1), 0, stream, nd, sm);
