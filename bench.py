@@ -138,6 +138,27 @@ def main():
     bench_frame(args)
 
 
+def copy_bandwidth_gbs(stream, reps: int = 3) -> float:
+    """Best of `reps` 1 GiB device-to-device copies on `stream`, in GB/s of
+    bytes read plus written."""
+    import torch
+
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.copy_(a)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    moved = 2 * a.numel() * a.element_size()
+    del a, b
+    return moved / (best * 1e-3) / 1e9
+
+
 def build_options(args):
     """The BVH build options named on the command line."""
     from paper_2312_12392_amd import rcp
@@ -209,6 +230,8 @@ def bench_frame(args):
     # and carries bytes_frame / launches, so the rate is the frame's
     achieved_gbs = bytes_frame / (ms * 1e-3) / 1e9
 
+    copy_gbs = copy_bandwidth_gbs(stream)
+
     traffic = None
     try:
         with open(traffic_file(kernel, w.name)) as f:
@@ -254,6 +277,10 @@ def bench_frame(args):
             "launches_per_step": launches,
             "algorithmic_bytes_per_launch": round(bytes_frame / launches),
             "bytes_per_traced_ray": round(bytes_frame / traced, 1),
+            # HBM-side rate of the measured traffic, and what a plain device
+            # copy reaches on the same GPU (read + write bytes / time)
+            "traffic_gbs": None if traffic is None else round(traffic / (ms * 1e-3) / 1e9, 1),
+            "copy_gbs": round(copy_gbs, 1),
         },
     }
     if not args.no_cpu_baseline:
