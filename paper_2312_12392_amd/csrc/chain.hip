@@ -24,6 +24,9 @@
 // kernel argument lets the compiler hoist its uniform float math into vector
 // registers for the whole loop, costing occupancy.)
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "traverse.hpp"
 
@@ -296,13 +299,37 @@ const void* chain_kernel() {
     else return (const void*)k_chain_aux<STATS, MODE, ONE>;
 }
 
+// Resident workgroups per CU and CU count of a kernel at an LDS size, on the
+// current device.  The runtime's answers are cached: they cannot change in a
+// process, and asking costs more than a launch.
+rcp_status occupancy(const void* kernel, size_t smem, int& per_cu, int& cus) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void*, size_t, int>, std::pair<int, int>> cache;
+    int dev = 0;
+    RCP_HIP(hipGetDevice(&dev));
+    const auto key = std::make_tuple(kernel, smem, dev);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        const auto it = cache.find(key);
+        if (it != cache.end()) {
+            per_cu = it->second.first;
+            cus = it->second.second;
+            return RCP_OK;
+        }
+    }
+    RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, smem));
+    RCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = std::make_pair(per_cu, cus);
+    return RCP_OK;
+}
+
 template <bool STATS, int MODE, bool ONE>
 rcp_status chain_grid(const Launch& lp, int n_views, int& blocks, size_t& smem) {
     smem = chain_smem(lp, STATS, n_views);
-    int per_cu = 0, dev = 0, cus = 0;
-    RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, chain_kernel<STATS, MODE, ONE>(), kBlock, smem));
-    RCP_HIP(hipGetDevice(&dev));
-    RCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu = 0, cus = 0;
+    const rcp_status st = occupancy(chain_kernel<STATS, MODE, ONE>(), smem, per_cu, cus);
+    if (st != RCP_OK) return st;
     if (per_cu < 1) per_cu = 1;
     if (lp.blocks_per_cu > 0 && lp.blocks_per_cu < per_cu) per_cu = lp.blocks_per_cu;
     blocks = per_cu * cus;
@@ -495,11 +522,19 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
     }
     ViewDev* d_views = (ViewDev*)ws.views;
     uint32_t* d_begin = (uint32_t*)((char*)ws.views + ((sizeof(ViewDev) * (size_t)n_views + 255) & ~(size_t)255));
-    // pageable sources: the copies have read them when the calls return
-    RCP_HIP(hipMemcpyAsync(d_views, hv.data(), sizeof(ViewDev) * (size_t)n_views, hipMemcpyHostToDevice, stream));
-    RCP_HIP(hipMemcpyAsync(d_begin, hb.data(), sizeof(uint32_t) * bofs, hipMemcpyHostToDevice, stream));
-    hipLaunchKernelGGL(k_clear_chain, dim3(1), dim3(64), 0, stream, ws.fetch, (int)groups.size(),
-                       (unsigned long long*)nullptr);
+    if (n_views == 1) {
+        // one view (a lone request of a server, say): the setup kernel writes
+        // its table from the by-value argument, with no host copy
+        hipLaunchKernelGGL(k_setup_single, dim3(1), dim3(256), 0, stream, hv[0], d_views, d_begin,
+                           groups[0].items, ws.fetch, (unsigned long long*)nullptr);
+    } else {
+        // pageable sources: the copies have read them when the calls return
+        RCP_HIP(hipMemcpyAsync(d_views, hv.data(), sizeof(ViewDev) * (size_t)n_views, hipMemcpyHostToDevice,
+                               stream));
+        RCP_HIP(hipMemcpyAsync(d_begin, hb.data(), sizeof(uint32_t) * bofs, hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(k_clear_chain, dim3(1), dim3(64), 0, stream, ws.fetch, (int)groups.size(),
+                           (unsigned long long*)nullptr);
+    }
     RCP_CHECK_LAUNCH();
     for (size_t g = 0; g < groups.size(); ++g) {
         ChainArgs a{};
