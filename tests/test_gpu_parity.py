@@ -180,6 +180,11 @@ RENDER_CASES = [
     ("empty_scene", lambda: scenegen.empty_scene(), AXIS_CAM, 23, 19, 4, 0.0, 0.02),
     ("one_triangle", lambda: scenegen.soup_scene(7, 1, extent=1.2), AXIS_CAM, 40, 40, 4, 0.0, 0.1),
     ("many_passes", lambda: scenegen.soup_scene(2, 300), AXIS_CAM, 48, 40, 20, 0.0, 0.05),
+    # views of 16 or more tiles a side take their work in super-tiles of
+    # 16 x 16 tiles, padded at the right and bottom edges
+    ("supertiles_padded", lambda: scenegen.terrain_patch(11, 24, 8), PATCH_CAM, 200, 150, 4, 0.0, 0.05),
+    ("supertiles_exact", lambda: scenegen.terrain_patch(12, 40, 20), PATCH_CAM, 256, 128, 3, 0.0, 0.05),
+    ("supertiles_edges", lambda: scenegen.soup_scene(9, 1500), OBLIQUE_CAM, 129, 257, 3, 0.01, 0.05),
 ]
 
 
@@ -209,12 +214,13 @@ def test_build_options_do_not_change_the_image(opts):
     assert np.array_equal(base[0], other[0]) and np.array_equal(base[1], other[1])
 
 
-def test_render_pass_chain_equals_render():
+@pytest.mark.parametrize("W,H", [(61, 47), (200, 150)])
+def test_render_pass_chain_equals_render(W, H):
     """rcp_render_pass applied to image k-1 gives image k (each pass starts
     from the base camera; only the image carries state)."""
-    say("render_pass chain")
+    say("render_pass chain", W, H)
     sc = scenegen.terrain_patch(11, 24, 8)
-    W, H, K = 61, 47, 5
+    K = 5
     s = rcp.Scene(sc)
     imgs, ids = s.render(PATCH_CAM, W, H, K, 0.01, 0.05)
     d = rcp.make_displacement(0.01, 0.05)
