@@ -2,8 +2,9 @@
 //
 // The recursion I_n(u,v) = F(I_{n-1}(u,v), S) is pointwise (Section 2), so a
 // pixel's K passes form a chain that needs nothing from other pixels.  A work
-// item is one pixel of one view (64-pixel tiles per view, views back to
-// back); a lane carries its pixel through the view's passes -- trace, shade,
+// item is one pixel of one view (64-pixel tiles in super-tiles per view,
+// views back to back, taken through one band of items per XCD); a lane
+// carries its pixel through the view's passes -- trace, shade,
 // write image k, and, if the inputs of the next ray changed, displace the
 // camera and trace again -- and takes a new pixel as soon as the chain ends
 // (after K passes, or when the colour, and in the depth and normal modes the
@@ -18,19 +19,18 @@
 // runs with most of the wave's lanes instead of a few at a time.
 //
 // The same kernel serves rcp_render and rcp_render_batch.  Views are read
-// from a device table by each lane; a single render's one-entry table is
-// written by a setup kernel from its by-value argument, so a captured graph
-// holds the view and rcp_graph_update can change it.  (A view passed as a
-// kernel argument lets the compiler hoist its uniform float math into vector
-// registers for the whole loop, costing occupancy.)
+// from a device table, by each lane, or with scalar loads when the launch
+// holds one view; a single render's one-entry table is written by a setup
+// kernel from its by-value argument, so a captured graph holds the view and
+// rcp_graph_update can change it.  (A view passed as a kernel argument lets
+// the compiler hoist its uniform float math into vector registers for the
+// whole loop, costing occupancy.)
 #include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
 
 #include "traverse.hpp"
-
-
 
 namespace rcp {
 namespace {
@@ -73,8 +73,8 @@ typedef __attribute__((address_space(4))) ViewDev ConstView;
 template <bool STATS, int MODE, bool ONE>
 __device__ inline void chain_body(const ChainArgs& a) {
     constexpr bool AUX = MODE != RCP_MODE_COLOR;
-    // the staged top levels sit at a fixed LDS address, so node offsets need
-    // no base added
+    // LDS: the staged top levels (128-byte nodes, as in HBM, so the same
+    // plane offsets serve both), then the stats, view starts and stack area
     extern __shared__ float4 smem[];
     float4* top = smem;
     char* lds = (char*)(smem + 8 * (size_t)a.sc.top_count);
@@ -251,9 +251,10 @@ __device__ inline void chain_body(const ChainArgs& a) {
     }
 }
 
-// Colour mode, the default: asking for 6 waves per SIMD (at most 80 VGPRs,
-// a few bytes of spill) was measured faster than the 5 its 82 registers
-// allow.  The depth and normal modes keep the compiler's choice.
+// Colour mode, the default: asking for 6 waves per SIMD (at most 80 VGPRs)
+// was measured faster than the 5 the compiler picks alone; 7 and 8 spill and
+// are slower.  The depth and normal modes keep the compiler's choice (6
+// spills there and measured 1% slower).
 template <bool STATS, bool ONE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_chain(ChainArgs a) {
     chain_body<STATS, RCP_MODE_COLOR, ONE>(a);
@@ -271,8 +272,8 @@ __global__ void k_clear_chain(uint32_t* fetch, int n, unsigned long long* stats)
         for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
 }
 
-// A single render's setup: its one-entry view table, item range, counter
-// and stats.
+// Setup of a one-view launch (a single render, or a batch of one view): its
+// one-entry view table, item range, band counters and stats.
 __global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint32_t n_items, uint32_t* fetch,
                                unsigned long long* stats) {
     if (threadIdx.x == 0) {
@@ -285,8 +286,9 @@ __global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint3
         for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
 }
 
+// LDS of a workgroup: the staged top levels, the stack area and the view
+// starts (and the stats).
 size_t chain_smem(const Launch& lp, bool stats, int n_views) {
-    // dynamic part only: the staged top levels are a static array
     size_t b = kNodeBytes * (size_t)lp.top_count + sizeof(int32_t) * kStack * kBlock +
                sizeof(uint32_t) * (size_t)((n_views + 4) & ~3);
     if (stats) b += sizeof(unsigned long long) * 4 * kMaxPasses;
