@@ -1,10 +1,11 @@
 // The K-pass render: one persistent kernel launch per pass.
 //
-// Per pass, every wave repeatedly takes 64 work items from a pass counter.
-// A work item is a pixel still being painted: at pass 0 the pixels in 8x8
-// tiles (with the grey seed, or a caller-supplied previous image), later the
-// compact list {pixel, previous RGB} appended by the pass before.  For each
-// item the lane
+// Per pass, every wave repeatedly takes work items for its idle lanes from
+// the pass's band counters (one band per XCD, see wave_fetch).  A work item
+// is a pixel still being painted: at pass 0 the pixels in 64-pixel tiles
+// ordered by super-tiles (with the grey seed, or a caller-supplied previous
+// image), later the compact list {pixel, previous RGB} appended by the pass
+// before.  For each item the lane
 //   1. builds the pixel's displaced camera ray from its previous colour
 //      (Section 2 ray and displacements, Section 3 colour mapping),
 //   2. traverses the BVH (a short per-lane stack in LDS that overflows into
@@ -32,7 +33,7 @@ struct PassArgs {
     Camera cam;
     int W, H, K, k;
     float le, ld, z0;
-    uint32_t n_items0;              // pass-0 items (8x8 tiles * 64)
+    uint32_t n_items0;              // pass-0 items (whole super-tiles of 64-pixel tiles)
     int refill_min;                 // idle lanes that trigger a refill (1..64)
     uint32_t exit_lanes;            // searching lanes that end a traversal step early
     int tiles_x;
