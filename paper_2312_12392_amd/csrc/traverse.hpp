@@ -18,7 +18,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kStack = 16;                       // per-lane LDS stack entries (a power of two)
-constexpr float kSlack = 1.0f + 1.0f / 65536.0f; // widening of box intervals
+constexpr float kSlack = 1.0f + 1.0f / 65536.0f; // relative widening of the best-hit bound
 
 // Global overflow entries per thread: the LDS ring holds kStack entries, and
 // a 4-wide visit keeps room for three pushes in it.
@@ -293,11 +293,18 @@ struct Stack {
 //    (|v| + |o|) of a triangle, so every box is widened by
 //    2^-18 (R + max|o|) on each side (R: largest |coordinate| in the scene),
 //    folded into one origin per slab side;
+//  - the overlap test tmin <= tmax needs no slack: a slab's entry and exit
+//    are computed with a few ulp of (R + max|o|) |inv| of rounding (the
+//    reciprocal within 1 ulp, one rounding per product and fused
+//    multiply-add), far below the widening of 2^-18 (R + max|o|) |inv| they
+//    move each plane by, so a ray through the exact box at t gets every
+//    computed entry below t and every exit above it;
 //  - the test against the best hit so far uses only the slab of the ray's
 //    dominant axis kz: the watertight t is a weighted mean of the vertices'
 //    kz distances, so it is never below that slab's entry, whatever the ray's
 //    angle to the triangle (the full box entry is not such a bound for
-//    grazing rays);
+//    grazing rays); the best hit is widened by a relative 2^-16 there, which
+//    covers the rounding of both sides;
 //  - zero direction components use a large finite reciprocal (no inf * 0).
 //
 // The traversal state of one ray lives in registers (plus its stack), so a
@@ -422,7 +429,7 @@ __device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& s
         const float a2 = __builtin_fmaf(lane_of(n2, i), tv.inv[2], -tv.ent[2]);
         const float b2 = __builtin_fmaf(lane_of(x2, i), tv.inv[2], -tv.ext[2]);
         const float tmin = fmaxf(fmaxf(a0, a1), fmaxf(a2, 0.0f));
-        const float tmax = fminf(fminf(b0, b1), b2) * kSlack;
+        const float tmax = fminf(fminf(b0, b1), b2);
         const uint32_t link = __float_as_uint(lane_of(lk, i));
         // a2 is the entry of the dominant axis's slab (see above).  An unused
         // slot has NaN planes: tmax and a2 are NaN and both tests fail (its
