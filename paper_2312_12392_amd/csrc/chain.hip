@@ -16,7 +16,10 @@
 // The work that is not traversal -- finishing a traced pass (shade, write,
 // decide) and setting up rays (new pixels, next passes) -- runs in setup
 // rounds, when at least refill_min lanes of the wave wait for it, so that it
-// runs with most of the wave's lanes instead of a few at a time.
+// runs with most of the wave's lanes instead of a few at a time.  A setup
+// round also sets the wave's issue priority from the passes still ahead of
+// its youngest chain: longest work first, which shortens the launch's tail
+// (the last pixels handed out start chains of up to K passes).
 //
 // The same kernel serves rcp_render and rcp_render_batch.  Views are read
 // from a device table, by each lane, or with scalar loads when the launch
@@ -219,6 +222,21 @@ __device__ inline void chain_body(const ChainArgs& a) {
                         }
                     }
                 }
+            }
+            {
+                // Longest remaining work first: the wave's issue priority follows
+                // the passes still ahead of its youngest chain (at most K - k),
+                // so that the chains started last, which decide when the launch
+                // ends, are not slowed down by waves about to finish.
+                // (Measured on the terrain frame: 3.7% faster; applied only once
+                // the bands are used up, 3.0%.)
+                const int kk = views[ONE ? 0 : v].K;
+                const bool live = alive || init;
+                const int rem = kk - k;
+                if (wave_ballot(live && 3 * rem >= 2 * kk) != 0ull) __builtin_amdgcn_s_setprio(3);
+                else if (wave_ballot(live && 2 * rem >= kk) != 0ull) __builtin_amdgcn_s_setprio(2);
+                else if (wave_ballot(live && 3 * rem >= kk) != 0ull) __builtin_amdgcn_s_setprio(1);
+                else __builtin_amdgcn_s_setprio(0);
             }
             if (init) {
                 const ConstView& vw = views[ONE ? 0 : v];
