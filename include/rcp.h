@@ -270,7 +270,8 @@ void rcp_graph_destroy(rcp_graph* graph);
  *                  run a setup round (new pixels, and pixels moving to their
  *                  next pass)
  *   exit_lanes     a wave's descent to the leaves ends once no more than this
- *                  many lanes (0..64, default 8) are still looking for one
+ *                  many lanes (0..64, default 16) are still looking for one
+ *                  and at least as many hold one
  *   blocks_per_cu  resident workgroups per compute unit (0 = occupancy limit)
  *   tile_log2w     pixel tile of 64: width 2^tile_log2w (0..6)
  *   engine         how rcp_render (and rcp_render_stats, graphs, the

@@ -91,7 +91,7 @@ constexpr size_t kViewBytes = 512;
 
 constexpr int kMaxPasses = 64;
 // Defaults of the launch parameters, measured on the 1080p K=6 terrain frame.
-constexpr int kDefaultExitLanes = 8;
+constexpr int kDefaultExitLanes = 16;
 // Levels of the 4-wide BVH the chain engine reads from LDS: LDS reads bypass
 // the vector-memory address unit, the busiest unit of the traversal.
 // Measured: 2 levels no gain, 3 levels 2% faster, 4 levels 1% more as long as

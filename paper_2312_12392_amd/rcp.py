@@ -425,7 +425,7 @@ def autotune_cached(handle: int, scene_key: str, cam, W: int, H: int, K: int, di
     if key in cache:
         t = cache[key]["tuning"]
         rcp_set_tuning(handle, t["refill_min"], t["blocks_per_cu"], t["tile_log2w"],
-                       t.get("engine", ENGINE_CHAIN), t.get("exit_lanes", 8))
+                       t.get("engine", ENGINE_CHAIN), t.get("exit_lanes"))
         return t
     t, ms = rcp_autotune(handle, cam, W, H, K, disp, out_images, out_ids, repeats, stream)
     cache[key] = {"tuning": t, "ms": ms}
