@@ -266,7 +266,7 @@ void rcp_graph_destroy(rcp_graph* graph);
 
 /* Launch parameters of the persistent kernels, per scene.  They change only
  * the speed, never an image.
- *   refill_min     lanes (1..64, default 52) needing a ray that make a wave
+ *   refill_min     lanes (1..64, default 56) needing a ray that make a wave
  *                  run a setup round (new pixels, and pixels moving to their
  *                  next pass)
  *   exit_lanes     a wave's descent to the leaves ends once no more than this

@@ -102,7 +102,7 @@ constexpr int kTopLevels = 4;
 constexpr uint32_t kMaxStagedNodes = 80;
 // The node array is addressed with 32-bit byte offsets.
 constexpr uint32_t kMaxNodes = 1u << 25;
-constexpr int kDefaultRefill = 52;
+constexpr int kDefaultRefill = 56;
 
 struct Disp {
     float le, ld, z0;

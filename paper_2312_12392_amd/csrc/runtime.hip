@@ -85,7 +85,7 @@ rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const 
     RCP_HIP(hipEventCreate(&e0));
     RCP_HIP(hipEventCreate(&e1));
     struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
-    const std::vector<int> refill = {32, 40, 48, 52, 56, 64};
+    const std::vector<int> refill = {40, 48, 52, 56, 60, 64};
     const std::vector<int> exits = {4, 8, 12, 16, 24, 64};
     const std::vector<int> blocks = {0, 4, 3, 2};
     const std::vector<int> tiles = {3, 4, 2, 5};
