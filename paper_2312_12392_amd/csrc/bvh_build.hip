@@ -918,7 +918,11 @@ struct ShadeParams {
     float k_a, k_d;
 };
 
-// Triangles in leaf order plus their two shaded colours.  Shading: two-sided
+// Triangles in leaf order, in three copies (copy c, for rays whose dominant
+// axis is c, stores each vertex as (x[c+1], x[c+2], x[c]), indices mod 3: the
+// watertight test's axis order, so it needs no per-vertex selects), the
+// original index in the w word of the first vertex of each copy; plus their
+// two shaded colours.  Shading: two-sided
 // Lambert with the flat geometric normal n = cross(v1 - v0, v2 - v0) (flipped
 // for the back side), one directional light, clamped to [0, 1]; evaluated in
 // FP32 left to right without contraction.
@@ -933,9 +937,16 @@ __global__ __launch_bounds__(kB) void k_pack_tris(uint32_t n, const float* __res
     const float3 a = ld3(verts, idx[3 * (size_t)t]);
     const float3 b = ld3(verts, idx[3 * (size_t)t + 1]);
     const float3 c = ld3(verts, idx[3 * (size_t)t + 2]);
-    tris[3 * (size_t)j + 0] = make_float4(a.x, a.y, a.z, __uint_as_float(t));
-    tris[3 * (size_t)j + 1] = make_float4(b.x, b.y, b.z, 0.0f);
-    tris[3 * (size_t)j + 2] = make_float4(c.x, c.y, c.z, 0.0f);
+    const float id = __uint_as_float(t);
+    tris[3 * (size_t)j + 0] = make_float4(a.y, a.z, a.x, id);   // kz = x
+    tris[3 * (size_t)j + 1] = make_float4(b.y, b.z, b.x, 0.0f);
+    tris[3 * (size_t)j + 2] = make_float4(c.y, c.z, c.x, 0.0f);
+    tris[3 * ((size_t)n + j) + 0] = make_float4(a.z, a.x, a.y, id);   // kz = y
+    tris[3 * ((size_t)n + j) + 1] = make_float4(b.z, b.x, b.y, 0.0f);
+    tris[3 * ((size_t)n + j) + 2] = make_float4(c.z, c.x, c.y, 0.0f);
+    tris[3 * (2 * (size_t)n + j) + 0] = make_float4(a.x, a.y, a.z, id);   // kz = z
+    tris[3 * (2 * (size_t)n + j) + 1] = make_float4(b.x, b.y, b.z, 0.0f);
+    tris[3 * (2 * (size_t)n + j) + 2] = make_float4(c.x, c.y, c.z, 0.0f);
 
     const float e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
     const float e2x = c.x - a.x, e2y = c.y - a.y, e2z = c.z - a.z;
@@ -1387,7 +1398,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
             sah = (float)((double)hst.sah_fx / 4294967296.0);
             if (single) sah = c_isect * (float)n;   // one leaf of every triangle, relative to its own box
         }
-        RCP_TRY(dalloc(&s->tris, 3 * (size_t)n));
+        RCP_TRY(dalloc(&s->tris, 9 * (size_t)n));   // three rotated copies
         RCP_TRY(dalloc(&s->shade, 2 * (size_t)n));
         RCP_TRY(dalloc(&s->normals, (size_t)n));
         ShadeParams sp{{desc->light_dir[0], desc->light_dir[1], desc->light_dir[2]}, desc->k_a, desc->k_d};

@@ -3,7 +3,9 @@
 // Data in HBM for a built scene (all arrays in the BVH's leaf order):
 //   nodes  float4[n_nodes][8]   4-wide BVH node, 128 B: lo.x, hi.x, lo.y, hi.y,
 //                               lo.z, hi.z of children 0..3, their links, zero
-//   tris   float4[n_tris][3]    v0.xyz + original index bits in w, v1, v2
+//   tris   float4[3][n_tris][3] three copies, copy c with each vertex rotated to
+//                               (x[c+1], x[c+2], x[c]) (indices mod 3): v0 +
+//                               original index bits in w, v1, v2
 //   shade  float4[n_tris][2]    shaded RGB seen from the front / back side
 //   normal float4[n_tris]       unit geometric normal (read by the normal mapping)
 // Nodes are in level order from the root; the inner children of a node sit in

@@ -172,23 +172,31 @@ __device__ inline void make_ray(const Cam& c, float hw, int W, int H, int x, int
 
 // Ray constants of the watertight test (Woop, Benthin, Wald, JCGT 2013):
 // the dominant direction axis kz (first of equal magnitudes), kx and ky
-// following it cyclically and swapped when d[kz] < 0, and the shear.
+// following it cyclically, and the shear.  The test swaps kx and ky when
+// d[kz] < 0; here they stay in cyclic order and the swap is applied to the
+// result instead (see hit_triangle).
 struct RayW {
-    int kx, ky, kz;
+    uint32_t tri_base;    // kz * n_tris: the first triangle of the copy rotated to (kx, ky, kz)
+    bool swap;            // d[kz] < 0
     float Sx, Sy, Sz;
     float ox, oy, oz;     // origin components along kx, ky, kz
 };
 
-__device__ inline RayW ray_setup(const float o[3], const float d[3]) {
-    RayW r;
+// kz of a direction (first of equal magnitudes).
+__device__ inline int dominant_axis(const float d[3]) {
     int kz = 0;
     if (fabsf(d[1]) > fabsf(d[0])) kz = 1;
     if (fabsf(d[2]) > fabsf(sel3(d[0], d[1], d[2], kz))) kz = 2;
-    int kx = kz == 2 ? 0 : kz + 1;
-    int ky = kx == 2 ? 0 : kx + 1;
+    return kz;
+}
+
+__device__ inline RayW ray_setup(const float o[3], const float d[3], int kz, uint32_t n_tris) {
+    RayW r;
+    const int kx = kz == 2 ? 0 : kz + 1;
+    const int ky = kx == 2 ? 0 : kx + 1;
     const float dz = sel3(d[0], d[1], d[2], kz);
-    if (dz < 0.0f) { int t = kx; kx = ky; ky = t; }
-    r.kx = kx; r.ky = ky; r.kz = kz;
+    r.tri_base = (uint32_t)kz * n_tris;
+    r.swap = dz < 0.0f;
     r.Sx = sel3(d[0], d[1], d[2], kx) / dz;
     r.Sy = sel3(d[0], d[1], d[2], ky) / dz;
     r.Sz = 1.0f / dz;
@@ -198,20 +206,29 @@ __device__ inline RayW ray_setup(const float o[3], const float d[3]) {
     return r;
 }
 
-// Watertight test against triangle (v0, v1, v2).  On a hit with t > 0
-// returns true with t and front (det > 0: the normal cross(v1-v0, v2-v0)
-// faces against the ray).
+// Watertight test against triangle (v0, v1, v2), whose coordinates come
+// rotated to the ray's (kx, ky, kz) (the triangle array holds one copy per
+// kz).  On a hit with t > 0 returns true with t and front (det > 0 in the
+// test's own axis order: the normal cross(v1-v0, v2-v0) faces against the
+// ray).
+//
+// The test proper swaps kx and ky when d[kz] < 0.  That swap exchanges the
+// x and y terms, so it turns every edge function into the same two
+// products subtracted the other way round; rounding to nearest is symmetric,
+// so U, V, W, det and T come out exactly negated (or are zero in both
+// orders, which the test rejects either way).  t = T / det is then the same
+// number, and only the sign of det, the front flag, flips.
 __device__ inline bool hit_triangle(const RayW& r, const float4& v0, const float4& v1, const float4& v2,
                                     float& t_out, bool& front) {
-    const float Akx = sel3(v0.x, v0.y, v0.z, r.kx) - r.ox;
-    const float Aky = sel3(v0.x, v0.y, v0.z, r.ky) - r.oy;
-    const float Akz = sel3(v0.x, v0.y, v0.z, r.kz) - r.oz;
-    const float Bkx = sel3(v1.x, v1.y, v1.z, r.kx) - r.ox;
-    const float Bky = sel3(v1.x, v1.y, v1.z, r.ky) - r.oy;
-    const float Bkz = sel3(v1.x, v1.y, v1.z, r.kz) - r.oz;
-    const float Ckx = sel3(v2.x, v2.y, v2.z, r.kx) - r.ox;
-    const float Cky = sel3(v2.x, v2.y, v2.z, r.ky) - r.oy;
-    const float Ckz = sel3(v2.x, v2.y, v2.z, r.kz) - r.oz;
+    const float Akx = v0.x - r.ox;
+    const float Aky = v0.y - r.oy;
+    const float Akz = v0.z - r.oz;
+    const float Bkx = v1.x - r.ox;
+    const float Bky = v1.y - r.oy;
+    const float Bkz = v1.z - r.oz;
+    const float Ckx = v2.x - r.ox;
+    const float Cky = v2.y - r.oy;
+    const float Ckz = v2.z - r.oz;
     const float Ax = Akx - r.Sx * Akz;
     const float Ay = Aky - r.Sy * Akz;
     const float Bx = Bkx - r.Sx * Bkz;
@@ -237,7 +254,7 @@ __device__ inline bool hit_triangle(const RayW& r, const float4& v0, const float
     const float t = T / det;
     if (!(t > 0.0f)) return false;
     t_out = t;
-    front = det > 0.0f;
+    front = (det > 0.0f) != r.swap;
     return true;
 }
 
@@ -329,7 +346,8 @@ struct Trav {
 };
 
 __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3], const float d[3], Stack& st) {
-    tv.rw = ray_setup(o, d);
+    const int kz = dominant_axis(d);
+    tv.rw = ray_setup(o, d, kz, sc.n_tris);
     float inv[3];
 #pragma unroll
     // The reciprocals only prune: the hardware reciprocal (within 1 ulp) is
@@ -342,7 +360,7 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
     // Rounding is monotonic, so the entry plane's t is never above the exit
     // plane's: the same values a min/max over the two planes would give.
     const float pad = (sc.radius + fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fabsf(o[2]))) * 3.814697265625e-6f;
-    const int ax[3] = {tv.rw.kx, tv.rw.ky, tv.rw.kz};
+    const int ax[3] = {kz == 2 ? 0 : kz + 1, kz == 0 ? 2 : kz - 1, kz};   // kx, ky, kz
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const float iv = sel3(inv[0], inv[1], inv[2], ax[j]);
@@ -464,7 +482,7 @@ __device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, ui
     const uint32_t first = ((uint32_t)node >> 3) & 0x0FFFFFFFu;
     const uint32_t count = ((uint32_t)node & 7u) + 1u;
     for (uint32_t j = 0; j < count; ++j) {
-        const float4* tp = sc.tris + 3 * (size_t)(first + j);
+        const float4* tp = sc.tris + 3 * (size_t)(tv.rw.tri_base + first + j);
         const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
         if (STATS) ++n_tris;
         float t;
