@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--engine", choices=["chain", "passes"], default="chain",
                     help="chain: one persistent launch per frame; passes: one launch per pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--max-leaf", type=int, default=4, help="BVH leaf size bound (build option)")
+    ap.add_argument("--max-leaf", type=int, default=3, help="BVH leaf size bound (build option)")
     ap.add_argument("--collapse", choices=["sah", "greedy"], default="sah",
                     help="how the 4-wide tree is formed from the binary tree (build option)")
     ap.add_argument("--builder", choices=["ploc", "lbvh"], default="ploc", help="binary tree builder (build option)")

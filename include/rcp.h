@@ -116,7 +116,7 @@ typedef struct {
 #define RCP_MODE_NORMAL 2
 
 /* Build options (NULL = defaults).
- *   max_leaf        most triangles per BVH leaf (1..8, default 4)
+ *   max_leaf        most triangles per BVH leaf (1..8, default 3)
  *   c_trav, c_isect SAH costs of a node visit and a triangle test (defaults
  *                   1, 1), used when the 4-wide traversal tree is formed
  *                   from the binary tree (the SAH collapse also charges

@@ -1146,7 +1146,7 @@ rcp_status ploc_build(int n, const float4* tlo, const float4* thi, uint32_t* sor
 rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts, hipStream_t stream,
                        rcp_scene** out) {
     const uint32_t n = desc->n_tris;
-    const int max_leaf = opts ? opts->max_leaf : 4;
+    const int max_leaf = opts ? opts->max_leaf : kDefaultMaxLeaf;
     const float c_trav = opts ? opts->c_trav : 1.0f;
     const float c_isect = opts ? opts->c_isect : 1.0f;
     const int builder = opts ? opts->builder : RCP_BUILDER_PLOC;

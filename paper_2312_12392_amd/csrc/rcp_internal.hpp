@@ -105,6 +105,10 @@ constexpr uint32_t kMaxStagedNodes = 80;
 // The node array is addressed with 32-bit byte offsets.
 constexpr uint32_t kMaxNodes = 1u << 25;
 constexpr int kDefaultRefill = 56;
+// Most triangles per leaf when the caller gives no build options: 3 measured
+// 1.6-2.6% faster than 4 on the terrain frame, a 64-view batch and the 16M
+// walk-through (2 and 6 slower).
+constexpr int kDefaultMaxLeaf = 3;
 
 struct Disp {
     float le, ld, z0;

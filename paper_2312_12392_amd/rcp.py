@@ -494,7 +494,7 @@ def rcp_server_destroy(server: int) -> None:
 # Convenience wrapper
 # ---------------------------------------------------------------------------
 
-def build_options(max_leaf: int = 4, c_trav: float = 1.0, c_isect: float = 1.0, builder: int = 0,
+def build_options(max_leaf: int = 3, c_trav: float = 1.0, c_isect: float = 1.0, builder: int = 0,
                   collapse: int = 0):
     o = rcp_build_options()
     o.max_leaf, o.c_trav, o.c_isect, o.builder = int(max_leaf), float(c_trav), float(c_isect), int(builder)
