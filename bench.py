@@ -118,6 +118,8 @@ def main():
                     help="chain: one persistent launch per frame; passes: one launch per pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-leaf", type=int, default=3, help="BVH leaf size bound (build option)")
+    ap.add_argument("--c-trav", type=float, default=1.0, help="SAH cost of a node visit (build option)")
+    ap.add_argument("--c-isect", type=float, default=1.0, help="SAH cost of a triangle test (build option)")
     ap.add_argument("--collapse", choices=["sah", "greedy"], default="sah",
                     help="how the 4-wide tree is formed from the binary tree (build option)")
     ap.add_argument("--builder", choices=["ploc", "lbvh"], default="ploc", help="binary tree builder (build option)")
@@ -162,7 +164,7 @@ def copy_bandwidth_gbs(stream, reps: int = 3) -> float:
 def build_options(args):
     """The BVH build options named on the command line."""
     from paper_2312_12392_amd import rcp
-    return rcp.build_options(max_leaf=args.max_leaf,
+    return rcp.build_options(max_leaf=args.max_leaf, c_trav=args.c_trav, c_isect=args.c_isect,
                              builder=rcp.RCP_BUILDER_PLOC if args.builder == "ploc" else rcp.RCP_BUILDER_LBVH,
                              collapse=rcp.RCP_COLLAPSE_SAH if args.collapse == "sah" else rcp.RCP_COLLAPSE_GREEDY)
 
@@ -265,7 +267,8 @@ def bench_frame(args):
         "active_per_pass": [int(c) for c in counts[:, 0]],
         "bvh_build_ms": round(info["build_ms"], 3),
         "bvh": {"nodes": info["n_nodes"], "sah_cost": round(info["sah_cost"], 3), "max_depth": info["max_depth"],
-                "builder": args.builder, "collapse": args.collapse, "max_leaf": args.max_leaf},
+                "builder": args.builder, "collapse": args.collapse, "max_leaf": args.max_leaf,
+                "c_trav": args.c_trav, "c_isect": args.c_isect},
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved_gbs, 1),
@@ -486,7 +489,8 @@ def bench_walk(args):
                                "walk-through, lambda_dir 0.01", "frames": args.frames},
         "frame_ms": _percentiles(ms), "bvh_build_ms": round(info["build_ms"], 2),
         "bvh": {"nodes": info["n_nodes"], "sah_cost": round(info["sah_cost"], 3), "max_depth": info["max_depth"],
-                "builder": args.builder, "collapse": args.collapse, "max_leaf": args.max_leaf},
+                "builder": args.builder, "collapse": args.collapse, "max_leaf": args.max_leaf,
+                "c_trav": args.c_trav, "c_isect": args.c_isect},
     }
 
 
