@@ -215,9 +215,10 @@ __device__ inline RayW ray_setup(const float o[3], const float d[3], int kz, uin
 // The test proper swaps kx and ky when d[kz] < 0.  That swap exchanges the
 // x and y terms, so it turns every edge function into the same two
 // products subtracted the other way round; rounding to nearest is symmetric,
-// so U, V, W, det and T come out exactly negated (or are zero in both
-// orders, which the test rejects either way).  t = T / det is then the same
-// number, and only the sign of det, the front flag, flips.
+// so each of U, V, W, det and T comes out exactly negated, or zero in both
+// orders.  A zero edge function is neither negative nor positive to the sign
+// test, and a zero det or T (t = 0) is rejected in both orders.  t = T / det
+// is then the same number, and only the sign of det, the front flag, flips.
 __device__ inline bool hit_triangle(const RayW& r, const float4& v0, const float4& v1, const float4& v2,
                                     float& t_out, bool& front) {
     const float Akx = v0.x - r.ox;
