@@ -102,9 +102,10 @@ def _random_rays(scene, n, seed):
     tg = ctr + rng.uniform(-0.5, 0.5, size=(n, 3)) * ext
     d = tg - o
     d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
-    for a in range(3):                                                      # axis-aligned rays
+    for a in range(3):                           # axis-aligned rays, both signs on every axis
         d[a::11] = 0.0
-        d[a::11, a] = 1.0 if a != 1 else -1.0
+        d[a::22, a] = 1.0
+        d[a + 11::22, a] = -1.0
     d[5::13] *= 3.0                                                         # unnormalised directions
     return o, d
 
