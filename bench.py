@@ -127,8 +127,8 @@ def main():
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the render shards by pixels with no exchange, but no multi-GPU path is built", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the render would shard "
+              "by pixels with no exchange, but no multi-GPU path is implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
