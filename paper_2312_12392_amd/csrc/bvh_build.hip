@@ -1430,7 +1430,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     s->stats.sah_cost = sah;
     s->stats.build_ms = ms;
     s->stats.node_bytes = (uint32_t)kNodeBytes;
-    s->stats.device_bytes = (uint64_t)kNodeBytes * n_nodes + 48ull * n + 32ull * n + 16ull * n;
+    s->stats.device_bytes = (uint64_t)kNodeBytes * n_nodes + 3ull * 48ull * n + 32ull * n + 16ull * n;
     guard.ok = true;
     *out = s;
     return RCP_OK;
