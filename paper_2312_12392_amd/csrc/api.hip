@@ -3,6 +3,8 @@
 #include <cstdarg>
 #include <cstring>
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -26,6 +28,41 @@ rcp_status hip_status(hipError_t e, const char* what, const char* file, int line
     set_error("%s: %s (%s:%d)", what, hipGetErrorString(e), file, line);
     (void)hipGetLastError();
     return e == hipErrorOutOfMemory ? RCP_ERR_OUT_OF_MEMORY : RCP_ERR_DEVICE;
+}
+
+namespace {
+// The current device has memory pools (the stream-ordered allocator); asked
+// once per device.
+bool pools_supported() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    static std::mutex mu;
+    static std::map<int, bool> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int v = 0;
+    const bool ok = hipDeviceGetAttribute(&v, hipDeviceAttributeMemoryPoolsSupported, dev) == hipSuccess && v != 0;
+    cache[dev] = ok;
+    return ok;
+}
+}  // namespace
+
+rcp_status stream_alloc(void** p, size_t bytes, hipStream_t stream) {
+    *p = nullptr;
+    if (bytes == 0) return RCP_OK;
+    const hipError_t e = pools_supported() ? hipMallocAsync(p, bytes, stream) : hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_status(e, "device allocation", __FILE__, __LINE__);
+    }
+    return RCP_OK;
+}
+
+void stream_free(void* p, hipStream_t stream) {
+    if (!p) return;
+    if (pools_supported()) (void)hipFreeAsync(p, stream);
+    else (void)hipFree(p);
 }
 
 }  // namespace rcp

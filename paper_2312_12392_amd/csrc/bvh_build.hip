@@ -980,15 +980,19 @@ rcp_status dalloc(T** p, size_t count) {
     return RCP_OK;
 }
 
+// Scratch buffers of a build, released on its stream when the set goes out
+// of scope (stream-ordered, so no device-wide synchronisation).
 struct TempSet {
+    hipStream_t stream;
     std::vector<void*> ptrs;
+    explicit TempSet(hipStream_t s) : stream(s) {}
     ~TempSet() {
-        for (void* p : ptrs) if (p) (void)hipFree(p);
+        for (void* p : ptrs) stream_free(p, stream);
     }
     template <typename T>
     rcp_status alloc(T** p, size_t count) {
-        rcp_status st = dalloc(p, count);
-        if (st == RCP_OK) ptrs.push_back((void*)*p);
+        rcp_status st = stream_alloc((void**)p, sizeof(T) * count, stream);
+        if (st == RCP_OK && *p) ptrs.push_back((void*)*p);
         return st;
     }
 };
@@ -1063,7 +1067,7 @@ rcp_status bottom_up(const LevelOrder& lo, const Body& body, hipStream_t stream)
 rcp_status ploc_build(int n, const float4* tlo, const float4* thi, uint32_t* sorted, int32_t* left, int32_t* right,
                       int32_t* parent, int32_t* rfirst, int32_t* rlast, TempSet& outer, LevelOrder& levels,
                       hipStream_t stream) {
-    TempSet tmp;
+    TempSet tmp(stream);
     int32_t *id, *id2, *nn, *next_id, *cnt, *first, *parent_tmp;
     float4 *lo, *hi, *lo2, *hi2;
     uint32_t *pos, *keep, *m_out, *scratch, *sorted2;
@@ -1180,7 +1184,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     RCP_HIP(hipEventCreate(&e1));
     struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } evg{e0, e1};
 
-    TempSet tmp;
+    TempSet tmp(stream);
     float* d_verts = nullptr;
     uint32_t* d_idx = nullptr;
     float* d_rgb = nullptr;

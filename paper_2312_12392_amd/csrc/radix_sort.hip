@@ -177,7 +177,10 @@ rcp_status radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, 
     // histogram table + scan scratch (a geometric series bounded by hist_n / 2047 + levels)
     const long scratch_n = hist_n / (kScanTile - 1) + 64;
     uint32_t* hist = nullptr;
-    RCP_HIP(hipMalloc((void**)&hist, sizeof(uint32_t) * (size_t)(hist_n + scratch_n)));
+    {
+        const rcp_status ast = stream_alloc((void**)&hist, sizeof(uint32_t) * (size_t)(hist_n + scratch_n), stream);
+        if (ast != RCP_OK) return ast;
+    }
     uint64_t* ka = keys;
     uint32_t* va = vals;
     uint64_t* kb = tmp_keys;
@@ -200,14 +203,13 @@ rcp_status radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, 
             hipMemcpyAsync(vals, va, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, stream) != hipSuccess)
             st = RCP_ERR_DEVICE;
     }
+    stream_free(hist, stream);
     hipError_t se = hipStreamSynchronize(stream);
-    hipError_t fe = hipFree(hist);
     if (st == RCP_OK && se != hipSuccess) return hip_status(se, "radix sort", __FILE__, __LINE__);
     if (st != RCP_OK) {
         if (st == RCP_ERR_DEVICE) set_error("radix sort: kernel launch failed");
         return st;
     }
-    RCP_HIP(fe);
     return RCP_OK;
 }
 

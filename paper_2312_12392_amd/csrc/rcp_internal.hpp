@@ -44,6 +44,14 @@ void set_error(const char* fmt, ...);
 void clear_error();
 rcp_status hip_status(hipError_t e, const char* what, const char* file, int line);
 
+// Scratch device memory ordered on a stream: allocated for the work enqueued
+// after the call, released once the stream's earlier work is done, with no
+// device-wide synchronisation (hipMallocAsync / hipFreeAsync; plain
+// hipMalloc / hipFree on a device without memory pools).  Free on the same
+// device and stream.
+rcp_status stream_alloc(void** p, size_t bytes, hipStream_t stream);
+void stream_free(void* p, hipStream_t stream);
+
 #define RCP_HIP(call)                                                          \
     do {                                                                       \
         hipError_t e_ = (call);                                                \
