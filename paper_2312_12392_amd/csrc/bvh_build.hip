@@ -321,6 +321,103 @@ __global__ __launch_bounds__(kB) void k_ploc_compact(int m, const uint32_t* __re
     if (i == m - 1) *m_out = pos[i] + keep[i];
 }
 
+// The last rounds of PLOC, once at most kPlocSmall clusters remain, in one
+// workgroup: the same neighbour search (the same order of candidates and of
+// ties), the same merge rule and the same order-keeping compaction as the
+// per-round kernels above, so the tree is the same; the clusters stay in LDS
+// and a workgroup barrier stands in for each launch and host read.  Thread i
+// holds cluster i.  Ends with the cluster count in *m_out (1 when done; more
+// if max_rounds ran out).
+constexpr int kPlocSmall = 1024;
+
+__global__ __launch_bounds__(kPlocSmall) void k_ploc_finish(int m, int n, int max_rounds,
+                                                             const int32_t* __restrict__ id_in,
+                                                             const float4* __restrict__ lo_in,
+                                                             const float4* __restrict__ hi_in,
+                                                             int32_t* __restrict__ next_id, int32_t* __restrict__ left,
+                                                             int32_t* __restrict__ right, int32_t* __restrict__ parent,
+                                                             uint32_t* __restrict__ m_out) {
+    __shared__ float s[6][kPlocSmall];                 // lo.x, lo.y, lo.z, hi.x, hi.y, hi.z
+    __shared__ int32_t s_id[kPlocSmall];
+    __shared__ int32_t s_nn[kPlocSmall];
+    __shared__ uint32_t s_wave[kPlocSmall / 64];
+    const int i = threadIdx.x;
+    if (i < m) {
+        const float4 a = lo_in[i], b = hi_in[i];
+        s[0][i] = a.x; s[1][i] = a.y; s[2][i] = a.z;
+        s[3][i] = b.x; s[4][i] = b.y; s[5][i] = b.z;
+        s_id[i] = id_in[i];
+    }
+    __syncthreads();
+    for (int round = 0; m > 1 && round < max_rounds; ++round) {   // m is the same in every thread
+        // nearest neighbour among kPlocRadius clusters on each side (as k_ploc_nn)
+        if (i < m) {
+            float best = INFINITY;
+            int bj = -1, bdist = 0, bmin = 0;
+            for (int d = -kPlocRadius; d <= kPlocRadius; ++d) {
+                const int j = i + d;
+                if (d == 0 || j < 0 || j >= m) continue;
+                const float3 a = make_float3(fminf(s[0][i], s[0][j]), fminf(s[1][i], s[1][j]), fminf(s[2][i], s[2][j]));
+                const float3 b = make_float3(fmaxf(s[3][i], s[3][j]), fmaxf(s[4][i], s[4][j]), fmaxf(s[5][i], s[5][j]));
+                const float ar = half_area(a, b);
+                const int dist = d < 0 ? -d : d;
+                const int mn = j < i ? j : i;
+                bool take = ar < best;
+                if (!take && ar == best) {
+                    if (dist != bdist) take = dist < bdist;
+                    else if ((mn & 1) != (bmin & 1)) take = (mn & 1) == 0;
+                    else take = mn < bmin;
+                }
+                if (take || bj < 0) { best = ar; bj = j; bdist = dist; bmin = mn; }
+            }
+            s_nn[i] = bj;
+        }
+        __syncthreads();
+        // merge mutual pairs into the lower slot (as k_ploc_merge)
+        bool keep = i < m;
+        int32_t nid = 0;
+        float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f, b3 = 0.0f, b4 = 0.0f, b5 = 0.0f;
+        if (i < m) {
+            nid = s_id[i];
+            b0 = s[0][i]; b1 = s[1][i]; b2 = s[2][i]; b3 = s[3][i]; b4 = s[4][i]; b5 = s[5][i];
+            const int j = s_nn[i];
+            if (j >= 0 && s_nn[j] == i) {
+                if (i < j) {
+                    const int32_t node = atomicSub(next_id, 1);
+                    const int32_t ca = s_id[i], cb = s_id[j];
+                    left[node] = ca;
+                    right[node] = cb;
+                    parent[node_slot(ca, n)] = node;
+                    parent[node_slot(cb, n)] = node;
+                    nid = node;
+                    b0 = fminf(b0, s[0][j]); b1 = fminf(b1, s[1][j]); b2 = fminf(b2, s[2][j]);
+                    b3 = fmaxf(b3, s[3][j]); b4 = fmaxf(b4, s[4][j]); b5 = fmaxf(b5, s[5][j]);
+                } else {
+                    keep = false;   // merged into cluster j
+                }
+            }
+        }
+        // order-keeping compaction: exclusive prefix count of the kept clusters
+        const unsigned long long kb = __builtin_amdgcn_ballot_w64(keep);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(kb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)kb, 0u));
+        if ((i & 63) == 0) s_wave[i >> 6] = (uint32_t)__popcll(kb);
+        __syncthreads();   // every read of this round's clusters is done
+        uint32_t pos = below, total = 0;
+        for (int w = 0; w < kPlocSmall / 64; ++w) {
+            const uint32_t c = s_wave[w];
+            if (w < (i >> 6)) pos += c;
+            total += c;
+        }
+        if (keep) {
+            s[0][pos] = b0; s[1][pos] = b1; s[2][pos] = b2; s[3][pos] = b3; s[4][pos] = b4; s[5][pos] = b5;
+            s_id[pos] = nid;
+        }
+        m = (int)total;
+        __syncthreads();
+    }
+    if (i == 0) *m_out = (uint32_t)m;
+}
+
 // ---- bottom-up passes -----------------------------------------------------
 // A pass computes each inner node from its two children, one launch per tree
 // level, deepest first: the inner nodes are sorted by depth, and kernel
@@ -1100,6 +1197,21 @@ rcp_status ploc_build(int n, const float4* tlo, const float4* thi, uint32_t* sor
     const int max_rounds = 64 + 16 * log2n;
     int m = n, rounds = 0;
     while (m > 1) {
+        if (m <= kPlocSmall) {   // the remaining rounds in one workgroup
+            hipLaunchKernelGGL(k_ploc_finish, dim3(1), dim3(kPlocSmall), 0, stream, m, n, max_rounds - rounds,
+                               (const int32_t*)id, (const float4*)lo, (const float4*)hi, next_id, left, right,
+                               parent_tmp, m_out);
+            RCP_CHECK_LAUNCH();
+            uint32_t fin = 0;
+            RCP_HIP(hipMemcpyAsync(&fin, m_out, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+            RCP_HIP(hipStreamSynchronize(stream));
+            if (fin != 1u) {
+                set_error("PLOC's last rounds ended with %u of %d clusters", fin, m);
+                return RCP_ERR_INTERNAL;
+            }
+            m = 1;
+            break;
+        }
         if (++rounds > max_rounds) return RCP_ERR_NOT_READY;
         hipLaunchKernelGGL(k_ploc_nn, dim3(blocks(m)), dim3(kB), 0, stream, m, (const float4*)lo, (const float4*)hi,
                            nn);
