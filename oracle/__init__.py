@@ -79,6 +79,8 @@ def lib():
         L.orc_intersect.argtypes = [P, P, P, P, P, P, P]
         L.orc_closest_hit.restype = i32
         L.orc_closest_hit.argtypes = [P, P, P, i32, P, P, P]
+        L.orc_closest_hits.restype = i32
+        L.orc_closest_hits.argtypes = [P, P, P, i32, i32, P, P, P, i32]
         L.orc_shade.argtypes = [P, ctypes.c_int32, i32, P]
         L.orc_normal.argtypes = [P, ctypes.c_int32, P]
         L.orc_render_pass.restype = i32
@@ -155,6 +157,19 @@ class OracleScene:
         t = np.zeros(1, np.float32); i = np.zeros(1, np.int32); f = np.zeros(1, np.int32)
         hit = lib().orc_closest_hit(self.h, _ptr(o), _ptr(d), 1 if brute else 0, _ptr(t), _ptr(i), _ptr(f))
         return (True, float(t[0]), int(i[0]), bool(f[0])) if hit else (False, None, -1, None)
+
+    def closest_hits(self, o, d, brute: bool = False, nthreads: int = 0):
+        """Closest hits of rays o[n][3], d[n][3]: (t [n] with +inf on a miss,
+        id [n] with -1 on a miss, front [n] bool)."""
+        o = np.ascontiguousarray(o, np.float32).reshape(-1, 3)
+        d = np.ascontiguousarray(d, np.float32).reshape(-1, 3)
+        n = o.shape[0]
+        t = np.zeros(n, np.float32); i = np.zeros(n, np.int32); f = np.zeros(n, np.int32)
+        rc = lib().orc_closest_hits(self.h, _ptr(o), _ptr(d), n, 1 if brute else 0, _ptr(t), _ptr(i), _ptr(f),
+                                    int(nthreads))
+        if rc:
+            raise ValueError("orc_closest_hits failed")
+        return t, i, f.astype(bool)
 
     def shade(self, tri_id: int, front: bool):
         out = np.zeros(3, np.float32)

@@ -572,6 +572,46 @@ static void run_threads(void* (*fn)(void*), void* job, int nthreads) {
     free(th);
 }
 
+/* Closest hits of n rays, spread over threads: the same query as
+ * orc_closest_hit, one ray per call. */
+typedef struct {
+    const orc_scene* s;
+    const float* o;
+    const float* d;
+    int n, brute;
+    float* t;
+    int32_t* id;
+    int32_t* front;
+    atomic_int next;
+} hits_job;
+
+static void* hits_worker(void* arg) {
+    hits_job* j = (hits_job*)arg;
+    for (;;) {
+        int i = atomic_fetch_add(&j->next, 1);
+        if (i >= j->n) break;
+        float t;
+        int32_t id;
+        int fr;
+        if (orc_closest_hit(j->s, &j->o[3 * (size_t)i], &j->d[3 * (size_t)i], j->brute, &t, &id, &fr)) {
+            j->t[i] = t; j->id[i] = id; j->front[i] = fr;
+        } else {
+            j->t[i] = INFINITY; j->id[i] = -1; j->front[i] = 0;
+        }
+    }
+    return NULL;
+}
+
+int orc_closest_hits(const orc_scene* s, const float* o, const float* d, int n, int brute,
+                     float* t, int32_t* id, int32_t* front, int nthreads) {
+    if (!s || n < 0 || (n > 0 && (!o || !d || !t || !id || !front))) return -1;
+    hits_job j;
+    j.s = s; j.o = o; j.d = d; j.n = n; j.brute = brute; j.t = t; j.id = id; j.front = front;
+    atomic_init(&j.next, 0);
+    run_threads(hits_worker, &j, nthreads);
+    return 0;
+}
+
 int orc_render_pass(const orc_scene* s, const orc_camera* cam, int W, int H, int mode, float z0,
                     float lambda_eye, float lambda_dir, const float* prev, const float* prev_aux,
                     float* out, int32_t* ids, float* out_aux, int nthreads) {

@@ -68,6 +68,11 @@ int orc_intersect(const float o[3], const float d[3], const float v0[3],
 int orc_closest_hit(const orc_scene* s, const float o[3], const float d[3], int brute,
                     float* t, int32_t* id, int* front);
 
+/* orc_closest_hit for n rays o[n][3], d[n][3], threaded: t[n] (+inf on a
+ * miss), id[n] (-1 on a miss), front[n].  nthreads <= 0 uses every core. */
+int orc_closest_hits(const orc_scene* s, const float* o, const float* d, int n, int brute,
+                     float* t, int32_t* id, int32_t* front, int nthreads);
+
 /* Shaded colour of triangle id seen from its front (1) or back (0) side. */
 void orc_shade(const orc_scene* s, int32_t id, int front, float rgb[3]);
 /* Unit geometric normal cross(v1-v0, v2-v0) / |...| of triangle id. */

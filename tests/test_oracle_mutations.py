@@ -51,7 +51,14 @@ MUTATIONS = {
     "gather_mirror_off_by_one": ("return m < n ? m : p - 1 - m;", "return m < n ? m : p - m;"),
     "gather_wrap_negative": ("{ int m = i % n; return m < 0 ? m + n : m; }", "{ int m = i % n; return m < 0 ? 0 : m; }"),
     "gather_rounds_to_nearest": ("int sx = edge_index((int)floorf(px), W, edge);", "int sx = edge_index((int)roundf(px), W, edge);"),
+    # the BVH's boxes are no longer widened beyond the triangles' own bounds:
+    # rays along box faces then lose hits the brute-force scan finds
+    "bvh_box_widening_dropped": ("const double pad = ldexp(s->radius + omax, -18);", "const double pad = 0.0;"),
 }
+
+# Pin files each mutation runs against (default: the pin suite).
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_modes.py", "test_oracle_gather.py"]
+MUTATION_FILES = {"bvh_box_widening_dropped": ["test_oracle_bvh_fullsize.py"]}
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
@@ -64,9 +71,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     lib = tmp_path / "librcp_oracle_mut.so"
     subprocess.check_call(["gcc", *oracle.GCC_FLAGS, "-o", str(lib), str(tmp_path / "rcp_oracle.c"), "-lm"])
     env = dict(os.environ, RCP_ORACLE_LIB=str(lib))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_modes.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_gather.py")],
+    files = [os.path.join(ROOT, "tests", f) for f in MUTATION_FILES.get(name, PIN_FILES)]
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *files],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins did not catch mutation {name}:\n{r.stdout[-2000:]}"
