@@ -69,7 +69,7 @@ def algorithmic_bytes(counts, engine="chain"):
     K = len(counts)
     total = 0.0
     for k in range(K):
-        rays, nodes, tris, app = (float(x) for x in counts[k])
+        rays, nodes, tris, app = (float(x) for x in counts[k][:4])
         total += 112 * nodes + 48 * tris + (16 + 12 + 4) * rays
         if engine == "passes":
             total += 16 * app + (16 * rays if k > 0 else 0.0)

@@ -27,8 +27,15 @@
  *     errors are reported before anything is enqueued.
  *   - Every call returns an rcp_status; no exception crosses the ABI.
  *     rcp_last_error() gives a message for the calling thread's last error.
- *   - A scene may be used by one stream at a time: its render workspace is
- *     shared by the calls made on it.
+ *   - Calls on one scene must be ordered: made on one stream, or with the
+ *     earlier stream synchronised before another is used.  The scene's render
+ *     workspace is shared by those calls; when a call needs more of it, the
+ *     old buffers are released and new ones allocated in stream order on that
+ *     call's stream (no device-wide synchronisation).
+ *   - A ray that runs out of its traversal step budget (which only a
+ *     malformed BVH can cause) ends as a miss and raises the scene's error
+ *     flag; rcp_check, the synchronous calls and the server report it as
+ *     RCP_ERR_INTERNAL.
  */
 #ifndef RCP_H
 #define RCP_H
@@ -219,8 +226,11 @@ rcp_status rcp_render_pass(rcp_scene* scene, const rcp_camera* base_camera, int 
                            float* out_rgb, int32_t* out_ids, float* out_aux, void* hip_stream);
 
 /* rcp_render plus traversal counters (a separate instrumented kernel; not
- * for timing).  counts: HOST [K][4] uint64: rays traced, inner nodes
- * visited, triangles tested, rays appended for the next pass.  Synchronous. */
+ * for timing).  counts: HOST [K][6] uint64 per pass: rays traced, inner
+ * nodes visited, triangles tested, rays continued to the next pass, inner
+ * nodes read from the LDS copy of the tree's top levels (chain engine), and
+ * traversal stack entries spilled from LDS to the global overflow area.
+ * Synchronous; RCP_ERR_INTERNAL if a ray ran out of its step budget. */
 rcp_status rcp_render_stats(rcp_scene* scene, const rcp_camera* base_camera, int W, int H, int K,
                             const rcp_displacement* disp, float* out_images, int32_t* out_ids,
                             uint64_t* counts, void* hip_stream);
@@ -254,8 +264,12 @@ rcp_status rcp_render_batch(rcp_scene* scene, const rcp_view* views, int n_views
 /* A K-pass rcp_render call captured once as a HIP graph and replayed with a
  * single launch.  The graph holds the arguments given at creation (camera,
  * sizes, displacement, output buffers); rcp_graph_update replaces camera and
- * displacement in place.  Graph, scene and outputs are used on one stream at
- * a time.  Creation synchronises hip_stream. */
+ * displacement in place.  The graph owns the buffers its kernels use
+ * (allocated at creation, freed by rcp_graph_destroy), so other calls on the
+ * scene between replays are safe; an update after launch parameters changed
+ * so that more room is needed fails with RCP_ERR_INVALID_ARGUMENT (create a
+ * new graph).  Graph, scene and outputs are used on one stream at a time.
+ * Creation synchronises hip_stream. */
 typedef struct rcp_graph rcp_graph;
 rcp_status rcp_graph_create(rcp_scene* scene, const rcp_camera* base_camera, int W, int H, int K,
                             const rcp_displacement* disp, float* out_images, int32_t* out_ids,
@@ -360,6 +374,11 @@ rcp_status rcp_server_stats(rcp_server* server, uint64_t out[4]);
  * fail) and free the server.  NULL is ignored. */
 void rcp_server_destroy(rcp_server* server);
 
+/* Synchronise hip_stream, then report a ray of an earlier call on this scene
+ * that ran out of its traversal step budget (RCP_ERR_INTERNAL; the flag is
+ * cleared).  That ray's result was written as a miss. */
+rcp_status rcp_check(rcp_scene* scene, void* hip_stream);
+
 /* Screen-space variant (Section 6).  With the eye fixed, re-rendering a
  * pass reduces to fetching every pixel's new colour from the position its
  * own red and green point to: right by m_r and up (towards row 0) by m_g
@@ -432,6 +451,18 @@ rcp_status rcp_radix_sort_u64(uint64_t* keys, uint32_t* vals, int n, void* hip_s
 const char* rcp_status_string(rcp_status s);
 /* Message of the calling thread's last error ("" if none). */
 const char* rcp_last_error(void);
+
+/* Test hooks, process-wide, for exercising failure paths without faults:
+ *   RCP_DEBUG_FAIL_ALLOC_AFTER  value >= 0: that many more device (and
+ *                               pinned host) allocations of the library
+ *                               succeed, every later one fails with
+ *                               RCP_ERR_OUT_OF_MEMORY; value < 0: off.
+ *   RCP_DEBUG_STEP_BUDGET       traversal step budget per ray of scenes built
+ *                               afterwards (0: the default, which only a
+ *                               malformed tree can exhaust). */
+#define RCP_DEBUG_FAIL_ALLOC_AFTER 1
+#define RCP_DEBUG_STEP_BUDGET 2
+rcp_status rcp_debug_set(int what, int64_t value);
 
 #ifdef __cplusplus
 }

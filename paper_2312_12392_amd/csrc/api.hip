@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <new>
@@ -46,11 +47,47 @@ bool pools_supported() {
     cache[dev] = ok;
     return ok;
 }
+
+// Test hooks (rcp_debug_set): allocations left before every later one
+// fails (-1: off), and the traversal step budget of scenes built afterwards.
+std::atomic<long long> g_alloc_left{-1};
+std::atomic<uint32_t> g_step_budget{0};
+
 }  // namespace
+
+bool alloc_hook_fails() {
+    long long left = g_alloc_left.load();
+    while (left >= 0) {
+        if (left == 0) return true;
+        if (g_alloc_left.compare_exchange_weak(left, left - 1)) return false;
+    }
+    return false;
+}
+
+uint32_t debug_step_budget() { return g_step_budget.load(); }
+
+rcp_status dev_alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return RCP_OK;
+    if (alloc_hook_fails()) {
+        set_error("device allocation of %zu bytes failed (test hook)", bytes);
+        return RCP_ERR_OUT_OF_MEMORY;
+    }
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_status(e, "hipMalloc", __FILE__, __LINE__);
+    }
+    return RCP_OK;
+}
 
 rcp_status stream_alloc(void** p, size_t bytes, hipStream_t stream) {
     *p = nullptr;
     if (bytes == 0) return RCP_OK;
+    if (alloc_hook_fails()) {
+        set_error("device allocation of %zu bytes failed (test hook)", bytes);
+        return RCP_ERR_OUT_OF_MEMORY;
+    }
     const hipError_t e = pools_supported() ? hipMallocAsync(p, bytes, stream) : hipMalloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
@@ -65,19 +102,34 @@ void stream_free(void* p, hipStream_t stream) {
     else (void)hipFree(p);
 }
 
+rcp_status take_device_error(rcp_scene* s) {
+    if (s->err_host && __atomic_exchange_n(s->err_host, 0u, __ATOMIC_ACQ_REL) != 0u) {
+        set_error("a ray ran out of its traversal step budget (%u steps): the BVH is malformed, and that ray's "
+                  "result is a miss", s->dev.step_budget);
+        return RCP_ERR_INTERNAL;
+    }
+    return RCP_OK;
+}
+
 }  // namespace rcp
 
 using namespace rcp;
 
-namespace {
-
 #define FAIL(...) do { set_error(__VA_ARGS__); return RCP_ERR_INVALID_ARGUMENT; } while (0)
+
+namespace {
 
 bool finite_n(const float* v, int n) {
     for (int i = 0; i < n; ++i)
         if (!std::isfinite(v[i])) return false;
     return true;
 }
+
+}  // namespace
+
+namespace rcp {
+
+// Argument checks shared by the entry points (declared in rcp_internal.hpp).
 
 rcp_status check_camera(const rcp_camera* c, Camera& out) {
     if (!c) FAIL("camera is NULL");
@@ -132,7 +184,7 @@ rcp_status check_scene(const rcp_scene* s) {
     return RCP_OK;
 }
 
-}  // namespace
+}  // namespace rcp
 
 extern "C" {
 
@@ -196,14 +248,10 @@ void rcp_destroy_scene(rcp_scene* s) {
     if (s->tris) (void)hipFree(s->tris);
     if (s->shade) (void)hipFree(s->shade);
     if (s->normals) (void)hipFree(s->normals);
-    Workspace& w = s->ws;
-    for (int i = 0; i < 2; ++i) if (w.state[i]) (void)hipFree(w.state[i]);
-    for (int i = 0; i < 2; ++i) if (w.aux[i]) (void)hipFree(w.aux[i]);
-    if (w.counters) (void)hipFree(w.counters);
-    if (w.spill) (void)hipFree(w.spill);
-    if (w.stats) (void)hipFree(w.stats);
-    if (w.view) (void)hipFree(w.view);
-    free_batch_workspace(s->bws);
+    free_workspace(s->ws, nullptr);
+    free_batch_workspace(s->bws, nullptr);
+    if (s->err_host) (void)hipHostFree(s->err_host);
+    (void)hipDeviceSynchronize();
     delete s;
 }
 
@@ -228,7 +276,8 @@ static rcp_status render_common(rcp_scene* scene, const rcp_camera* cam, int W, 
     if (K < 1 || K > kMaxPasses) FAIL("K = %d must be in [1, %d]", K, kMaxPasses);
     if (!out_images) FAIL("out_images must not be NULL");
     Disp d{disp->lambda_eye, disp->lambda_dir, disp->z0, disp->mode};
-    return render(scene, c, W, H, K, d, out_images, out_ids, prev, prev_aux, out_aux, counts, (hipStream_t)stream);
+    return render(scene, scene->ws, c, W, H, K, d, out_images, out_ids, prev, prev_aux, out_aux, counts,
+                  (hipStream_t)stream);
 }
 
 rcp_status rcp_render(rcp_scene* scene, const rcp_camera* cam, int W, int H, int K, const rcp_displacement* disp,
@@ -335,6 +384,29 @@ rcp_status rcp_graph_update(rcp_graph* g, const rcp_camera* cam, const rcp_displ
     g->cam = c;
     g->disp = Disp{disp->lambda_eye, disp->lambda_dir, disp->z0, disp->mode};
     return graph_capture(g);
+}
+
+rcp_status rcp_check(rcp_scene* scene, void* hip_stream) {
+    clear_error();
+    rcp_status st = check_scene(scene);
+    if (st) return st;
+    hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_status(e, "hipStreamSynchronize", __FILE__, __LINE__);
+    return take_device_error(scene);
+}
+
+rcp_status rcp_debug_set(int what, int64_t value) {
+    clear_error();
+    switch (what) {
+        case RCP_DEBUG_FAIL_ALLOC_AFTER:
+            g_alloc_left.store(value < 0 ? -1 : (long long)value);
+            return RCP_OK;
+        case RCP_DEBUG_STEP_BUDGET:
+            if (value < 0 || value > 0xFFFFFFFFll) FAIL("step budget must be in [0, 2^32)");
+            g_step_budget.store((uint32_t)value);
+            return RCP_OK;
+    }
+    FAIL("unknown debug setting %d", what);
 }
 
 rcp_status rcp_graph_launch(rcp_graph* g, void* hip_stream) {
@@ -530,12 +602,12 @@ rcp_status rcp_radix_sort_u64(uint64_t* keys, uint32_t* vals, int n, void* hip_s
     if (n <= 1) return RCP_OK;
     uint64_t* k2 = nullptr;
     uint32_t* v2 = nullptr;
-    hipError_t e = hipMalloc((void**)&k2, sizeof(uint64_t) * (size_t)n);
-    if (e != hipSuccess) return hip_status(e, "hipMalloc", __FILE__, __LINE__);
-    e = hipMalloc((void**)&v2, sizeof(uint32_t) * (size_t)n);
-    if (e != hipSuccess) {
+    rcp_status st0 = dev_alloc((void**)&k2, sizeof(uint64_t) * (size_t)n);
+    if (st0 != RCP_OK) return st0;
+    st0 = dev_alloc((void**)&v2, sizeof(uint32_t) * (size_t)n);
+    if (st0 != RCP_OK) {
         (void)hipFree(k2);
-        return hip_status(e, "hipMalloc", __FILE__, __LINE__);
+        return st0;
     }
     rcp_status st = radix_sort_pairs(keys, vals, k2, v2, n, 64, (hipStream_t)hip_stream);
     (void)hipFree(k2);

@@ -1067,14 +1067,7 @@ __global__ __launch_bounds__(kB) void k_pack_tris(uint32_t n, const float* __res
 
 template <typename T>
 rcp_status dalloc(T** p, size_t count) {
-    *p = nullptr;
-    if (count == 0) return RCP_OK;
-    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return hip_status(e, "hipMalloc", __FILE__, __LINE__);
-    }
-    return RCP_OK;
+    return dev_alloc((void**)p, sizeof(T) * count);
 }
 
 // Scratch buffers of a build, released on its stream when the set goes out
@@ -1278,6 +1271,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                 if (s->tris) (void)hipFree(s->tris);
                 if (s->shade) (void)hipFree(s->shade);
                 if (s->normals) (void)hipFree(s->normals);
+                if (s->err_host) (void)hipHostFree(s->err_host);
                 delete s;
                 s = nullptr;
             }
@@ -1540,6 +1534,19 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     s->dev.max_depth = max_depth;
     s->dev.stack_bound = stack_bound;
     s->dev.top_count = top_count;
+    // every step of a ray enters a node or a leaf, each at most once
+    const uint64_t bound = 5ull * n_nodes + 16ull;
+    const uint32_t hook = debug_step_budget();
+    s->dev.step_budget = hook ? hook : (uint32_t)std::min<uint64_t>(bound, 0xFFFFFFFFull);
+    // the error flag the kernels raise when a ray runs out of that budget:
+    // pinned host memory, mapped into the device's address space
+    if (alloc_hook_fails()) {
+        set_error("pinned host allocation failed (test hook)");
+        return RCP_ERR_OUT_OF_MEMORY;
+    }
+    RCP_HIP(hipHostMalloc((void**)&s->err_host, sizeof(uint32_t), hipHostMallocMapped));
+    *s->err_host = 0u;
+    RCP_HIP(hipHostGetDevicePointer((void**)&s->dev.err_flag, s->err_host, 0));
     s->stats.n_nodes = n_nodes;
     s->stats.n_leaves = n_leaves;
     s->stats.max_depth = max_depth;

@@ -29,6 +29,7 @@
 // the compiler hoist its uniform float math into vector registers for the
 // whole loop, costing occupancy.)
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -64,7 +65,8 @@ struct ChainArgs {
     uint32_t exit_lanes;
     int32_t* spill;
     uint32_t spill_stride;
-    unsigned long long* stats;   // [K][4] (STATS): rays, inner nodes, triangles, rays continued
+    unsigned long long* stats;   // [K][kStatCols] (STATS): rays, inner nodes, triangles, rays continued,
+                                 // LDS node reads, stack entries spilled
 };
 
 
@@ -81,8 +83,8 @@ __device__ inline void chain_body(const ChainArgs& a) {
     extern __shared__ float4 smem[];
     float4* top = smem;
     char* lds = (char*)(smem + 8 * (size_t)a.sc.top_count);
-    unsigned long long* lstats = (unsigned long long*)lds;                // STATS: 4 * kMaxPasses
-    if (STATS) lds += sizeof(unsigned long long) * 4 * kMaxPasses;
+    unsigned long long* lstats = (unsigned long long*)lds;                // STATS: kStatCols * kMaxPasses
+    if (STATS) lds += sizeof(unsigned long long) * kStatCols * kMaxPasses;
     uint32_t* vbegin = (uint32_t*)lds;                                    // n_views + 1
     lds += sizeof(uint32_t) * (size_t)((a.n_views + 4) & ~3);
     int32_t* stack_area = (int32_t*)lds;                                  // kStack * kBlock
@@ -93,7 +95,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
     for (uint32_t i = threadIdx.x; i < 8u * a.sc.top_count; i += kBlock)
         if ((i & 7u) != 7u) top[i] = a.sc.nodes[i];   // the zero padding is never read
     if (STATS)
-        for (int i = threadIdx.x; i < 4 * kMaxPasses; i += kBlock) lstats[i] = 0ull;
+        for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += kBlock) lstats[i] = 0ull;
     __syncthreads();
 
     int v = 0;                 // the lane's view
@@ -114,7 +116,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
     int k = 0, x = 0, y = 0;
     float pr = 0.5f, pg = 0.5f, pb = 0.5f;              // previous colour (the seed I_0 at pass 0)
     float pa[4] = {INFINITY, 0.0f, 0.0f, 0.0f};         // previous hit data: view depth, unit normal
-    uint32_t dn = 0, dt = 0;                            // STATS: nodes and triangles of the current ray
+    TravCount cnt;                                      // STATS: counters of the current ray
     Trav tv;
     tv.node = -1;
 
@@ -176,12 +178,14 @@ __device__ inline void chain_body(const ChainArgs& a) {
                     }
                     const bool next = changed && k + 1 < vw.K;
                     if (STATS) {
-                        unsigned long long* sk = lstats + 4 * k;
+                        unsigned long long* sk = lstats + kStatCols * k;
                         atomicAdd(&sk[0], 1ull);
-                        atomicAdd(&sk[1], (unsigned long long)dn);
-                        atomicAdd(&sk[2], (unsigned long long)dt);
+                        atomicAdd(&sk[1], (unsigned long long)cnt.nodes);
+                        atomicAdd(&sk[2], (unsigned long long)cnt.tris);
                         if (next) atomicAdd(&sk[3], 1ull);
-                        dn = 0; dt = 0;
+                        atomicAdd(&sk[4], (unsigned long long)cnt.lds);
+                        atomicAdd(&sk[5], (unsigned long long)cnt.spill);
+                        cnt = TravCount();
                     }
                     if (next) {
                         ++k;
@@ -243,7 +247,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
                 float o[3], d[3];
                 make_ray<MODE>(vw.cam, vw.hw, vw.W, vw.H, x, y, pr, pg, pb, pa, vw.z0, vw.le, vw.ld, o, d);
                 trav_init(tv, a.sc, o, d, st);
-                if (STATS) { dn = 0; dt = 0; }
+                if (STATS) cnt = TravCount();
                 alive = true;
                 pending = false;
             }
@@ -254,7 +258,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
         }
 
         // ---- one traversal step -------------------------------------------------
-        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, top, st, a.exit_lanes, dn, dt);
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, top, st, a.exit_lanes, cnt);
 
         if (alive && tv.node == -1) {   // the pass is traced: finish it in the next round
             alive = false;
@@ -264,7 +268,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
 
     if (STATS) {
         __syncthreads();
-        for (int i = threadIdx.x; i < 4 * kMaxPasses; i += kBlock)
+        for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += kBlock)
             if (lstats[i]) atomicAdd(&a.stats[i], lstats[i]);
     }
 }
@@ -287,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_aux(ChainArgs a) {
 __global__ void k_clear_chain(uint32_t* fetch, int n, unsigned long long* stats) {
     for (int i = threadIdx.x; i < (int)kFetchWords * n; i += blockDim.x) fetch[i] = 0u;
     if (stats)
-        for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
+        for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
 }
 
 // Setup of a one-view launch (a single render, or a batch of one view): its
@@ -301,7 +305,7 @@ __global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint3
         for (uint32_t p = 0; p < kFetchParts; ++p) fetch[kFetchStride * p] = 0u;
     }
     if (stats)
-        for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
+        for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
 }
 
 // LDS of a workgroup: the staged top levels, the stack area and the view
@@ -309,7 +313,7 @@ __global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint3
 size_t chain_smem(const Launch& lp, bool stats, int n_views) {
     size_t b = kNodeBytes * (size_t)lp.top_count + sizeof(int32_t) * kStack * kBlock +
                sizeof(uint32_t) * (size_t)((n_views + 4) & ~3);
-    if (stats) b += sizeof(unsigned long long) * 4 * kMaxPasses;
+    if (stats) b += sizeof(unsigned long long) * kStatCols * kMaxPasses;
     return b;
 }
 
@@ -420,7 +424,7 @@ uint64_t view_items(const ViewDev& v) {
 
 }  // namespace
 
-rcp_status prepare_chain(rcp_scene* s, int mode) {
+rcp_status prepare_chain(rcp_scene* s, Workspace& ws, int mode, hipStream_t stream) {
     const Launch lp = launch_params(s);
     int b1 = 0, b2 = 0;
     size_t m1 = 0, m2 = 0;
@@ -428,22 +432,17 @@ rcp_status prepare_chain(rcp_scene* s, int mode) {
     if (st == RCP_OK) st = chain_grid_mode<true>(lp, 1, mode, b2, m2);
     if (st != RCP_OK) return st;
     const uint32_t threads = (uint32_t)std::max(b1, b2) * kBlock;
-    return ensure_workspace(s, 0, 0, spill_depth_of(s) * threads);
+    return ensure_workspace(s, ws, 0, 0, spill_depth_of(s) * threads, stream);
 }
 
-rcp_status render_chain(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& disp, float* out_images,
-                        int32_t* out_ids, unsigned long long* host_counts, hipStream_t stream) {
-    const bool stats = host_counts != nullptr;
-    const Launch lp = launch_params(s);
-    int blocks = 0;
-    size_t smem = 0;
-    rcp_status st = stats ? chain_grid_mode<true>(lp, 1, disp.mode, blocks, smem)
-                          : chain_grid_mode<false>(lp, 1, disp.mode, blocks, smem);
-    if (st != RCP_OK) return st;
+namespace {
+
+// Enqueue the setup kernel and the chain launch of one view on a workspace
+// that already fits `blocks` workgroups.
+rcp_status launch_one_view(rcp_scene* s, Workspace& w, const Launch& lp, int blocks, size_t smem, const Camera& cam,
+                           int W, int H, int K, const Disp& disp, float* out_images, int32_t* out_ids, bool stats,
+                           hipStream_t stream) {
     const uint32_t threads = (uint32_t)blocks * kBlock;
-    st = ensure_workspace(s, 0, 0, spill_depth_of(s) * threads);
-    if (st != RCP_OK) return st;
-    Workspace& w = s->ws;
     const ViewDev view = view_of(cam, W, H, K, disp, out_images, out_ids, lp.tile_log2w);
     ChainArgs a{};
     a.sc = s->dev;
@@ -463,12 +462,110 @@ rcp_status render_chain(rcp_scene* s, const Camera& cam, int W, int H, int K, co
     if (stats) launch_chain_mode<true>(disp.mode, blocks, smem, stream, a);
     else launch_chain_mode<false>(disp.mode, blocks, smem, stream, a);
     RCP_CHECK_LAUNCH();
+    return RCP_OK;
+}
+
+}  // namespace
+
+rcp_status render_chain(rcp_scene* s, Workspace& w, const Camera& cam, int W, int H, int K, const Disp& disp,
+                        float* out_images, int32_t* out_ids, unsigned long long* host_counts, hipStream_t stream) {
+    const bool stats = host_counts != nullptr;
+    const Launch lp = launch_params(s);
+    int blocks = 0;
+    size_t smem = 0;
+    rcp_status st = stats ? chain_grid_mode<true>(lp, 1, disp.mode, blocks, smem)
+                          : chain_grid_mode<false>(lp, 1, disp.mode, blocks, smem);
+    if (st != RCP_OK) return st;
+    st = ensure_workspace(s, w, 0, 0, spill_depth_of(s) * (size_t)blocks * kBlock, stream);
+    if (st != RCP_OK) return st;
+    st = launch_one_view(s, w, lp, blocks, smem, cam, W, H, K, disp, out_images, out_ids, stats, stream);
+    if (st != RCP_OK) return st;
     if (stats) {
-        RCP_HIP(hipMemcpyAsync(host_counts, w.stats, sizeof(unsigned long long) * 4 * K, hipMemcpyDeviceToHost,
-                               stream));
+        RCP_HIP(hipMemcpyAsync(host_counts, w.stats, sizeof(unsigned long long) * kStatCols * K,
+                               hipMemcpyDeviceToHost, stream));
         RCP_HIP(hipStreamSynchronize(stream));
+        return take_device_error(s);
     }
     return RCP_OK;
+}
+
+rcp_status render_chain_fixed(rcp_scene* s, Workspace& w, const Camera& cam, int W, int H, int K,
+                              const Disp& disp, float* out_images, int32_t* out_ids, hipStream_t stream) {
+    const Launch lp = launch_params(s);
+    int blocks = 0;
+    size_t smem = 0;
+    rcp_status st = chain_grid_mode<false>(lp, 1, disp.mode, blocks, smem);
+    if (st != RCP_OK) return st;
+    int dev = 0, cus = 0;
+    RCP_HIP(hipGetDevice(&dev));
+    RCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // as many workgroups as the overflow area holds (the grid size changes
+    // the speed only), but at least one per compute unit
+    const size_t per_block = spill_depth_of(s) * kBlock;
+    const size_t fit = w.spill_cap / per_block;
+    if (fit < (size_t)cus) {
+        set_error("the scene's traversal stack needs %zu bytes of overflow area per compute unit's workgroup; "
+                  "the preallocated scratch holds %zu for %d compute units",
+                  per_block * sizeof(int32_t), w.spill_cap * sizeof(int32_t), cus);
+        return RCP_ERR_INVALID_ARGUMENT;
+    }
+    if ((size_t)blocks > fit) blocks = (int)fit;
+    return launch_one_view(s, w, lp, blocks, smem, cam, W, H, K, disp, out_images, out_ids, false, stream);
+}
+
+namespace {
+
+// Grow a batch buffer in stream order.
+template <typename T>
+rcp_status grow(T** p, size_t& cap, size_t need, size_t bytes_each, hipStream_t stream) {
+    if (need <= cap && *p) return RCP_OK;
+    stream_free((void*)*p, stream);
+    *p = nullptr;
+    cap = 0;
+    rcp_status st = stream_alloc((void**)p, bytes_each * need, stream);
+    if (st != RCP_OK) return st;
+    cap = need;
+    return RCP_OK;
+}
+
+size_t view_table_bytes(size_t n_views) {
+    return ((sizeof(ViewDev) * n_views + 255) & ~(size_t)255) + sizeof(uint32_t) * (n_views + 3);
+}
+
+}  // namespace
+
+rcp_status prepare_batch_workspace(rcp_scene* s, BatchWorkspace& ws, int n_views, bool with_staging,
+                                   hipStream_t stream) {
+    const Launch lp = launch_params(s);
+    int max_blocks = 0;
+    for (int mode = 0; mode < 3; ++mode)
+        for (int nv : {1, 2}) {
+            int b = 0;
+            size_t m = 0;
+            rcp_status st = chain_grid_mode<false>(lp, nv, mode, b, m);
+            if (st != RCP_OK) return st;
+            max_blocks = std::max(max_blocks, b);
+        }
+    rcp_status st = RCP_OK;
+    if ((size_t)n_views > ws.view_cap || !ws.views) {
+        stream_free(ws.views, stream);
+        ws.views = nullptr;
+        ws.view_cap = 0;
+        st = stream_alloc(&ws.views, view_table_bytes((size_t)n_views), stream);
+        if (st == RCP_OK) ws.view_cap = (size_t)n_views;
+    }
+    size_t fetch_cap = ws.fetch ? kFetchWords * 3 : 0;
+    if (st == RCP_OK) st = grow(&ws.fetch, fetch_cap, kFetchWords * 3, sizeof(uint32_t), stream);
+    if (st == RCP_OK)
+        st = grow(&ws.spill, ws.spill_cap, spill_depth_of(s) * (size_t)max_blocks * kBlock, sizeof(int32_t), stream);
+    if (st == RCP_OK && with_staging && !ws.staging) {
+        if (alloc_hook_fails()) {
+            set_error("pinned host allocation failed (test hook)");
+            return RCP_ERR_OUT_OF_MEMORY;
+        }
+        RCP_HIP(hipHostMalloc(&ws.staging, view_table_bytes((size_t)n_views), hipHostMallocDefault));
+    }
+    return st;
 }
 
 rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchWorkspace& ws, hipStream_t stream) {
@@ -526,27 +623,46 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
     }
     const size_t spill_need = spill_depth_of(s) * (size_t)max_blocks * kBlock;
 
-    if ((size_t)n_views > ws.view_cap) {
-        if (ws.views) { RCP_HIP(hipFree(ws.views)); ws.views = nullptr; }
+    // buffers grow in stream order (a server's slots are sized at creation
+    // and never grow here)
+    if ((size_t)n_views > ws.view_cap || !ws.views) {
+        if (ws.staging) {
+            set_error("a batch of %d views exceeds the %zu views its workspace was sized for", n_views, ws.view_cap);
+            return RCP_ERR_INTERNAL;
+        }
+        stream_free(ws.views, stream);
+        ws.views = nullptr;
         ws.view_cap = 0;
-        RCP_HIP(hipMalloc(&ws.views, sizeof(ViewDev) * (size_t)n_views + sizeof(uint32_t) * (size_t)(n_views + 3) +
-                                         256));
+        rcp_status st = stream_alloc(&ws.views, view_table_bytes((size_t)n_views), stream);
+        if (st != RCP_OK) return st;
         ws.view_cap = (size_t)n_views;
     }
-    if (!ws.fetch) RCP_HIP(hipMalloc((void**)&ws.fetch, sizeof(uint32_t) * kFetchWords * 3));
-    if (spill_need > ws.spill_cap) {
-        if (ws.spill) { RCP_HIP(hipFree(ws.spill)); ws.spill = nullptr; }
-        ws.spill_cap = 0;
-        RCP_HIP(hipMalloc((void**)&ws.spill, sizeof(int32_t) * spill_need));
-        ws.spill_cap = spill_need;
+    if (ws.staging && spill_need > ws.spill_cap) {
+        set_error("the batch needs more stack overflow area than its workspace was sized for (launch parameters "
+                  "changed since)");
+        return RCP_ERR_INTERNAL;
     }
+    size_t fetch_cap = ws.fetch ? kFetchWords * 3 : 0;
+    rcp_status st = grow(&ws.fetch, fetch_cap, kFetchWords * 3, sizeof(uint32_t), stream);
+    if (st == RCP_OK) st = grow(&ws.spill, ws.spill_cap, spill_need, sizeof(int32_t), stream);
+    if (st != RCP_OK) return st;
     ViewDev* d_views = (ViewDev*)ws.views;
-    uint32_t* d_begin = (uint32_t*)((char*)ws.views + ((sizeof(ViewDev) * (size_t)n_views + 255) & ~(size_t)255));
+    const size_t begin_ofs = (sizeof(ViewDev) * (size_t)n_views + 255) & ~(size_t)255;
+    uint32_t* d_begin = (uint32_t*)((char*)ws.views + begin_ofs);
     if (n_views == 1) {
         // one view (a lone request of a server, say): the setup kernel writes
         // its table from the by-value argument, with no host copy
         hipLaunchKernelGGL(k_setup_single, dim3(1), dim3(256), 0, stream, hv[0], d_views, d_begin,
                            groups[0].items, ws.fetch, (unsigned long long*)nullptr);
+    } else if (ws.staging) {
+        // a server slot: copy from its pinned table (the slot's previous
+        // launch, the last reader, has finished)
+        std::memcpy(ws.staging, hv.data(), sizeof(ViewDev) * (size_t)n_views);
+        std::memcpy((char*)ws.staging + begin_ofs, hb.data(), sizeof(uint32_t) * bofs);
+        RCP_HIP(hipMemcpyAsync(d_views, ws.staging, begin_ofs + sizeof(uint32_t) * bofs, hipMemcpyHostToDevice,
+                               stream));
+        hipLaunchKernelGGL(k_clear_chain, dim3(1), dim3(64), 0, stream, ws.fetch, (int)groups.size(),
+                           (unsigned long long*)nullptr);
     } else {
         // pageable sources: the copies have read them when the calls return
         RCP_HIP(hipMemcpyAsync(d_views, hv.data(), sizeof(ViewDev) * (size_t)n_views, hipMemcpyHostToDevice,
@@ -574,10 +690,11 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
     return RCP_OK;
 }
 
-void free_batch_workspace(BatchWorkspace& ws) {
-    if (ws.views) (void)hipFree(ws.views);
-    if (ws.fetch) (void)hipFree(ws.fetch);
-    if (ws.spill) (void)hipFree(ws.spill);
+void free_batch_workspace(BatchWorkspace& ws, hipStream_t stream) {
+    stream_free(ws.views, stream);
+    stream_free(ws.fetch, stream);
+    stream_free(ws.spill, stream);
+    if (ws.staging) (void)hipHostFree(ws.staging);
     ws = BatchWorkspace{};
 }
 

@@ -44,6 +44,16 @@ void set_error(const char* fmt, ...);
 void clear_error();
 rcp_status hip_status(hipError_t e, const char* what, const char* file, int line);
 
+// Every device allocation of the library goes through dev_alloc or
+// stream_alloc, so that the test hook RCP_DEBUG_FAIL_ALLOC_AFTER can make
+// them fail.  dev_alloc is a plain hipMalloc.
+rcp_status dev_alloc(void** p, size_t bytes);
+// True when the allocation hook says the next device allocation fails.
+bool alloc_hook_fails();
+// Per-ray traversal step budget of scenes built from now on (0: the bound
+// that only a malformed tree can reach).
+uint32_t debug_step_budget();
+
 // Scratch device memory ordered on a stream: allocated for the work enqueued
 // after the call, released once the stream's earlier work is done, with no
 // device-wide synchronisation (hipMallocAsync / hipFreeAsync; plain
@@ -58,11 +68,25 @@ void stream_free(void* p, hipStream_t stream);
         if (e_ != hipSuccess) return ::rcp::hip_status(e_, #call, __FILE__, __LINE__); \
     } while (0)
 
+#define RCP_TRY_STATUS(expr)                                                   \
+    do {                                                                       \
+        rcp_status st_ = (expr);                                               \
+        if (st_ != RCP_OK) return st_;                                         \
+    } while (0)
+
 #define RCP_CHECK_LAUNCH()                                                     \
     do {                                                                       \
         hipError_t e_ = hipGetLastError();                                     \
         if (e_ != hipSuccess) return ::rcp::hip_status(e_, "kernel launch", __FILE__, __LINE__); \
     } while (0)
+
+// ---- argument checks of the entry points (RCP_ERR_INVALID_ARGUMENT with a
+// message; check_camera also converts) --------------------------------------
+struct Camera;
+rcp_status check_camera(const rcp_camera* c, Camera& out);
+rcp_status check_disp(const rcp_displacement* d);
+rcp_status check_size(int W, int H);
+rcp_status check_scene(const rcp_scene* s);
 
 // ---- device view of a scene -------------------------------------------------
 struct DevScene {
@@ -77,6 +101,8 @@ struct DevScene {
     uint32_t top_count;     // nodes of the first kTopLevels levels, at most kMaxStagedNodes (staged in LDS)
     float radius;      // largest |coordinate| of any vertex
     float bg[3];
+    uint32_t step_budget;   // traversal steps per ray (only a malformed tree reaches it)
+    uint32_t* err_flag;     // host-mapped; set when a ray ran out of step_budget
 };
 
 struct Camera {
@@ -84,22 +110,36 @@ struct Camera {
     float th;
 };
 
-// Per-render workspace (grown on demand, owned by the scene).
+// Per-render workspace.  The scene owns one, grown on demand with
+// stream-ordered allocations on the stream of the call that needs more room;
+// a captured graph owns its own, sized at capture and never grown, so that
+// later calls on the scene cannot move the buffers a graph holds.  An
+// external workspace (the preallocated scratch array of the allocation-free
+// entry point) is never grown or freed: a call that needs more is rejected.
 struct Workspace {
     float4* state[2] = {nullptr, nullptr};    // compact {pix, rgb} lists
     float4* aux[2] = {nullptr, nullptr};      // their {view depth, normal} (depth and normal modes)
     size_t aux_cap = 0;
     size_t state_cap = 0;                      // entries per list
-    uint32_t* counters = nullptr;              // [2 * kMaxPasses + 8]
+    uint32_t* counters = nullptr;              // kCounterWords
     int32_t* spill = nullptr;                  // traversal stack overflow
     size_t spill_cap = 0;                      // int32 entries
-    unsigned long long* stats = nullptr;       // [kMaxPasses][4]
+    unsigned long long* stats = nullptr;       // [kMaxPasses][kStatCols]
     void* view = nullptr;                      // chain engine: one-entry view table (kViewBytes)
+    bool fixed = false;                        // never grown: a call that needs more is rejected
+    bool external = false;                     // fixed, and the memory is not the workspace's to free
 };
+
+// Release a workspace's buffers on `stream` (stream-ordered).
+void free_workspace(Workspace& w, hipStream_t stream);
 
 constexpr size_t kViewBytes = 512;
 
 constexpr int kMaxPasses = 64;
+// Counters per pass of the instrumented kernels: rays traced, inner nodes
+// visited, triangles tested, rays continued to the next pass, inner nodes
+// read from LDS, stack entries spilled to global memory.
+constexpr int kStatCols = 6;
 // Defaults of the launch parameters, measured on the 1080p K=6 terrain frame.
 constexpr int kDefaultExitLanes = 16;
 // Levels of the 4-wide BVH the chain engine reads from LDS: LDS reads bypass
@@ -124,12 +164,15 @@ struct Disp {
 };
 
 // Buffers of one in-flight batch (view table, work counter, stack overflow).
+// Grown with stream-ordered allocations; a server sizes its slots' sets once,
+// at creation, for the largest batch.
 struct BatchWorkspace {
     void* views = nullptr;
     size_t view_cap = 0;
     uint32_t* fetch = nullptr;
     int32_t* spill = nullptr;
     size_t spill_cap = 0;
+    void* staging = nullptr;      // pinned host copy of the view table (servers only), view_cap views
 };
 
 struct Tuning {
@@ -150,6 +193,7 @@ struct rcp_scene {
     float4* shade = nullptr;
     float4* normals = nullptr;
     rcp_scene_stats stats{};
+    uint32_t* err_host = nullptr;   // pinned, device-mapped error flag (DevScene::err_flag)
     rcp::Workspace ws;
     rcp::BatchWorkspace bws;
     rcp::Tuning tuning;
@@ -166,6 +210,7 @@ struct rcp_graph {
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    rcp::Workspace ws;           // the graph's own buffers (sized at capture)
 };
 
 namespace rcp {
@@ -184,8 +229,8 @@ rcp_status radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* tmp_keys, 
 rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts, hipStream_t stream,
                        rcp_scene** out);
 
-rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& disp, float* out_images,
-                  int32_t* out_ids, const float* prev_rgb, const float* prev_aux, float* out_aux,
+rcp_status render(rcp_scene* s, Workspace& ws, const Camera& cam, int W, int H, int K, const Disp& disp,
+                  float* out_images, int32_t* out_ids, const float* prev_rgb, const float* prev_aux, float* out_aux,
                   unsigned long long* host_counts, hipStream_t stream);
 
 rcp_status generate_rays(const Camera& cam, int W, int H, const Disp& disp, const float* prev_rgb,
@@ -195,11 +240,24 @@ rcp_status gather_passes(const float* in, int W, int H, int n, float smudge, int
                          hipStream_t stream);
 
 rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchWorkspace& ws, hipStream_t stream);
+// Size a batch workspace for up to n_views views in every mode (no
+// allocation in render_batch afterwards); with_staging adds the pinned view
+// table the server copies from.
+rcp_status prepare_batch_workspace(rcp_scene* s, BatchWorkspace& ws, int n_views, bool with_staging,
+                                   hipStream_t stream);
 // The chain engine for a whole render from the seed: one launch, no pass barrier.
-rcp_status prepare_chain(rcp_scene* s, int mode);
-rcp_status render_chain(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& disp, float* out_images,
-                        int32_t* out_ids, unsigned long long* host_counts, hipStream_t stream);
-void free_batch_workspace(BatchWorkspace& ws);
+rcp_status prepare_chain(rcp_scene* s, Workspace& ws, int mode, hipStream_t stream);
+rcp_status render_chain(rcp_scene* s, Workspace& ws, const Camera& cam, int W, int H, int K, const Disp& disp,
+                        float* out_images, int32_t* out_ids, unsigned long long* host_counts, hipStream_t stream);
+// The chain engine on a caller-sized workspace that is never grown: the
+// grid is limited to the blocks whose stack overflow fits spill_cap.
+rcp_status render_chain_fixed(rcp_scene* s, Workspace& ws, const Camera& cam, int W, int H, int K,
+                              const Disp& disp, float* out_images, int32_t* out_ids, hipStream_t stream);
+void free_batch_workspace(BatchWorkspace& ws, hipStream_t stream);
+// Report (and clear) a ray that ran out of its step budget since the last
+// check, as RCP_ERR_INTERNAL.  Reads the host-mapped flag: the work that may
+// have set it must be complete.
+rcp_status take_device_error(rcp_scene* s);
 
 // The launch parameters a render of this scene uses (tuning or defaults).
 struct Launch {
@@ -211,12 +269,18 @@ struct Launch {
 };
 Launch launch_params(const rcp_scene* s);
 
-// Make sure the scene's render workspace fits a K-pass W x H render in
-// `mode` (no allocation happens in rcp_render afterwards for that size).
-rcp_status prepare_render(rcp_scene* s, int W, int H, int K, int mode);
-// Grow the scene's workspace: per-pass state and aux lists of n_state / n_aux
-// entries (0 = none), the counters, and spill_entries stack overflow words.
-rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t n_aux, size_t spill_entries);
+// Make sure a render workspace fits a K-pass W x H render in `mode` (no
+// allocation happens in render afterwards for that size).
+rcp_status prepare_render(rcp_scene* s, Workspace& ws, int W, int H, int K, int mode, hipStream_t stream);
+// Grow a workspace: per-pass state and aux lists of n_state / n_aux entries
+// (0 = none), the counters, and spill_entries stack overflow words.  Old
+// buffers are released and new ones allocated in stream order on `stream`;
+// calls on one scene are ordered (one stream, or synchronised between
+// streams), so no earlier work can still use a released buffer.
+rcp_status ensure_workspace(rcp_scene* s, Workspace& ws, size_t n_state, size_t n_aux, size_t spill_entries,
+                            hipStream_t stream);
+// Words of a workspace's counter array.
+size_t counter_words();
 
 rcp_status graph_capture(rcp_graph* g);
 void graph_free(rcp_graph* g);

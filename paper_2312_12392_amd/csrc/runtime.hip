@@ -9,13 +9,22 @@ namespace rcp {
 
 // Record the render into a fresh graph and instantiate it, or update the
 // existing executable graph in place when only kernel arguments changed.
+//
+// The graph renders into its own workspace, allocated before the first
+// capture and never grown afterwards, so that no later call on the scene can
+// move the buffers the graph's kernels hold.
 rcp_status graph_capture(rcp_graph* g) {
-    rcp_status st = prepare_render(g->scene, g->W, g->H, g->K, g->disp.mode);   // allocations happen here, not in the graph
-    if (st != RCP_OK) return st;
     if (!g->capture_stream) RCP_HIP(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
+    if (!g->ws.fixed) {
+        // allocations happen here, not in the graph
+        rcp_status st = prepare_render(g->scene, g->ws, g->W, g->H, g->K, g->disp.mode, g->capture_stream);
+        if (st != RCP_OK) return st;
+        RCP_HIP(hipStreamSynchronize(g->capture_stream));
+        g->ws.fixed = true;
+    }
     RCP_HIP(hipStreamBeginCapture(g->capture_stream, hipStreamCaptureModeThreadLocal));
-    st = render(g->scene, g->cam, g->W, g->H, g->K, g->disp, g->out, g->ids, nullptr, nullptr, nullptr, nullptr,
-                g->capture_stream);
+    rcp_status st = render(g->scene, g->ws, g->cam, g->W, g->H, g->K, g->disp, g->out, g->ids, nullptr, nullptr,
+                           nullptr, nullptr, g->capture_stream);
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(g->capture_stream, &graph);
     if (st != RCP_OK) {
@@ -47,7 +56,12 @@ rcp_status graph_capture(rcp_graph* g) {
 void graph_free(rcp_graph* g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    if (g->capture_stream) (void)hipStreamDestroy(g->capture_stream);
+    g->ws.fixed = false;
+    free_workspace(g->ws, g->capture_stream);
+    if (g->capture_stream) {
+        (void)hipStreamSynchronize(g->capture_stream);
+        (void)hipStreamDestroy(g->capture_stream);
+    }
     delete g;
 }
 
@@ -55,14 +69,14 @@ namespace {
 
 rcp_status time_render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids,
                        int repeats, hipStream_t stream, hipEvent_t e0, hipEvent_t e1, float& ms) {
-    rcp_status st = prepare_render(s, W, H, K, d.mode);
+    rcp_status st = prepare_render(s, s->ws, W, H, K, d.mode, stream);
     if (st != RCP_OK) return st;
-    st = render(s, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);   // warm-up
+    st = render(s, s->ws, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);   // warm-up
     if (st != RCP_OK) return st;
     std::vector<float> t;
     for (int r = 0; r < repeats; ++r) {
         RCP_HIP(hipEventRecord(e0, stream));
-        st = render(s, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);
+        st = render(s, s->ws, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);
         if (st != RCP_OK) return st;
         RCP_HIP(hipEventRecord(e1, stream));
         RCP_HIP(hipEventSynchronize(e1));
@@ -125,7 +139,10 @@ rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const 
     best_ms = cur_ms;
     s->tuning = cur;
     // leave a render made with the chosen parameters in the outputs
-    return render(s, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);
+    st = render(s, s->ws, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);
+    if (st != RCP_OK) return st;
+    RCP_HIP(hipStreamSynchronize(stream));
+    return take_device_error(s);
 }
 
 }  // namespace rcp

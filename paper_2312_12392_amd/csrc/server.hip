@@ -16,6 +16,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -25,6 +26,9 @@
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// Most requests in one batched launch (the batch entry point's limit).
+constexpr int kMaxBatch = 1024;
 
 struct Req {
     rcp_request r;
@@ -41,6 +45,7 @@ struct Slot {
     rcp::BatchWorkspace ws;
     std::vector<uint64_t> tickets;
     bool busy = false;
+    bool launching = false;     // its launch is being enqueued (lock released)
 };
 
 }  // namespace
@@ -109,17 +114,24 @@ size_t request_bytes(const rcp_request& r) {
 
 namespace {
 
-// One scheduling round, with the lock held: retire finished launches, admit
-// queued requests in order while they fit, launch the admitted ones.
-void schedule(rcp_server* s) {
+// One scheduling round, entered with the lock held: retire finished
+// launches, admit queued requests in order while they fit, launch the
+// admitted ones.  The launch itself is enqueued with the lock released (the
+// slot is marked busy first, and only this thread schedules), so submit and
+// poll never wait for it; it allocates nothing, since every slot's buffers
+// were sized when the server was created.
+void schedule(rcp_server* s, std::unique_lock<std::mutex>& lk) {
     for (Slot& sl : s->slots) {
-        if (!sl.busy) continue;
+        if (!sl.busy || sl.launching) continue;
         const hipError_t q = hipEventQuery(sl.done);
         if (q == hipErrorNotReady) continue;
         const double t = s->now();
+        // a ray that ran out of its step budget (a malformed tree) fails the
+        // requests of the launch that reported it
+        const bool ok = q == hipSuccess && take_device_error(s->scene) == RCP_OK;
         for (uint64_t id : sl.tickets) {
             Req& r = s->reqs[id];
-            r.state = q == hipSuccess ? RCP_REQ_DONE : RCP_REQ_FAILED;
+            r.state = ok ? RCP_REQ_DONE : RCP_REQ_FAILED;
             r.t_done = t;
         }
         if (q != hipSuccess) (void)hipGetLastError();
@@ -140,7 +152,7 @@ void schedule(rcp_server* s) {
     for (Slot& sl : s->slots)
         if (!sl.busy) { free_slot = &sl; break; }
     if (!free_slot) return;
-    const size_t n = std::min<size_t>(s->admitted.size(), 1024);
+    const size_t n = std::min<size_t>(s->admitted.size(), (size_t)kMaxBatch);
     std::vector<rcp_view> views(n);
     for (size_t i = 0; i < n; ++i) {
         Req& r = s->reqs[s->admitted[i]];
@@ -153,25 +165,36 @@ void schedule(rcp_server* s) {
                         ? (int32_t*)(s->pool + r.offset + ((12 * (size_t)r.r.W * r.r.H * r.r.K + 255) & ~(size_t)255))
                         : nullptr;
     }
-    const rcp_status st = render_batch(s->scene, views.data(), (int)n, free_slot->ws, free_slot->stream);
-    const double t = s->now();
     free_slot->tickets.assign(s->admitted.begin(), s->admitted.begin() + (long)n);
     s->admitted.erase(s->admitted.begin(), s->admitted.begin() + (long)n);
-    if (st != RCP_OK || hipEventRecord(free_slot->done, free_slot->stream) != hipSuccess) {
-        for (uint64_t id : free_slot->tickets) {
-            Req& r = s->reqs[id];
-            r.state = RCP_REQ_FAILED;
-            r.t_start = r.t_done = t;
-        }
-        free_slot->tickets.clear();
-        return;
-    }
+    free_slot->busy = true;
+    free_slot->launching = true;
+    const double t_launch = s->now();
     for (uint64_t id : free_slot->tickets) {
         Req& r = s->reqs[id];
         r.state = RCP_REQ_RUNNING;
-        r.t_start = t;
+        r.t_start = t_launch;
     }
-    free_slot->busy = true;
+    lk.unlock();
+    rcp_status st = render_batch(s->scene, views.data(), (int)n, free_slot->ws, free_slot->stream);
+    const bool recorded = st == RCP_OK && hipEventRecord(free_slot->done, free_slot->stream) == hipSuccess;
+    lk.lock();
+    free_slot->launching = false;
+    const double t = s->now();
+    if (!recorded) {
+        // nothing of a failed launch can still be running on the slot's
+        // stream once it is synchronised
+        (void)hipStreamSynchronize(free_slot->stream);
+        (void)hipGetLastError();
+        for (uint64_t id : free_slot->tickets) {
+            Req& r = s->reqs[id];
+            r.state = RCP_REQ_FAILED;
+            r.t_done = t;
+        }
+        free_slot->tickets.clear();
+        free_slot->busy = false;
+        return;
+    }
     ++s->launches;
 }
 
@@ -179,7 +202,7 @@ void run(rcp_server* s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        schedule(s);
+        schedule(s, lk);
         bool running = false;
         for (const Slot& sl : s->slots) running = running || sl.busy;
         if (s->stop && !running && (s->queue.empty() && s->admitted.empty())) break;
@@ -211,19 +234,28 @@ rcp_status server_create(rcp_scene* scene, size_t pool_bytes, int max_inflight, 
     s->queue_capacity = queue_capacity;
     s->t0 = Clock::now();
     s->pool_bytes = pool_bytes;
-    hipError_t e = hipMalloc((void**)&s->pool, pool_bytes);
-    if (e != hipSuccess) {
+    rcp_status st = dev_alloc((void**)&s->pool, pool_bytes);
+    if (st != RCP_OK) {
         delete s;
-        return hip_status(e, "server pool hipMalloc", __FILE__, __LINE__);
+        return st;
     }
     s->free_list[0] = pool_bytes;
     s->slots.resize((size_t)max_inflight);
     for (Slot& sl : s->slots) {
-        e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
         if (e != hipSuccess) {
             server_destroy(s);
             return hip_status(e, "server stream", __FILE__, __LINE__);
+        }
+        // every buffer a launch of this slot uses, sized for the largest batch
+        st = prepare_batch_workspace(scene, sl.ws, kMaxBatch, true, sl.stream);
+        if (st == RCP_OK && hipStreamSynchronize(sl.stream) != hipSuccess) st = RCP_ERR_DEVICE;
+        if (st != RCP_OK) {
+            const std::string msg = rcp_last_error();
+            server_destroy(s);
+            set_error("%s", msg.c_str());
+            return st;
         }
     }
     s->worker = std::thread(run, s);
@@ -243,7 +275,8 @@ void server_destroy(rcp_server* s) {
     }
     for (Slot& sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        free_batch_workspace(sl.ws);
+        free_batch_workspace(sl.ws, sl.stream);
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }

@@ -52,7 +52,7 @@ struct PassArgs {
     float* out_aux;                 // [H][W][4] of image k or NULL (single passes)
     int32_t* spill;
     uint32_t spill_stride;          // threads in the grid
-    unsigned long long* stats;      // [kMaxPasses][4] or NULL
+    unsigned long long* stats;      // [kMaxPasses][kStatCols] or NULL
 };
 
 // The scene's counter array: list sizes, then the band counters of each pass
@@ -63,12 +63,8 @@ constexpr size_t kCounterWords = kPassFetch + (size_t)kMaxPasses * kFetchWords;
 constexpr int kWaves = kBlock / 64;
 constexpr int kStage = 128;     // per-wave staging of appended entries (flushed 64 at a time)
 
-#ifndef RCP_WAVES_PER_EU
-#define RCP_WAVES_PER_EU 1
-#endif
-
 template <bool STATS, int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVES_PER_EU))) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
     constexpr bool AUX = MODE != RCP_MODE_COLOR;
     extern __shared__ float4 smem[];
     float4* stage_all = smem;                                           // kWaves * kStage (x2 with aux)
@@ -87,7 +83,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
     const uint32_t n_items = a.k == 0 ? a.n_items0 : a.counters[a.k];
     uint32_t* fetch = a.counters + kPassFetch + (size_t)a.k * kFetchWords;
     float* out_k = a.out + (size_t)a.k * P * 3;
-    uint32_t s_nodes = 0, s_tris = 0, s_rays = 0, s_app = 0;
+    TravCount cnt;                 // STATS
+    uint32_t s_rays = 0, s_app = 0;
 
     bool alive = false;
     bool drained = false;          // wave-uniform: the pass's list is used up
@@ -154,7 +151,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
         }
 
         // ---- one traversal step -------------------------------------------
-        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, nullptr, st, a.exit_lanes, s_nodes, s_tris);
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, nullptr, st, a.exit_lanes, cnt);
 
         // ---- finished rays: shade, write, compact ----------------------------
         const bool done = alive && tv.node == -1;
@@ -254,18 +251,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RCP_WAVE
         }
     }
     if (STATS) {
-        unsigned long long* sk = a.stats + 4 * a.k;
+        unsigned long long* sk = a.stats + kStatCols * a.k;
         atomicAdd(&sk[0], (unsigned long long)s_rays);
-        atomicAdd(&sk[1], (unsigned long long)s_nodes);
-        atomicAdd(&sk[2], (unsigned long long)s_tris);
+        atomicAdd(&sk[1], (unsigned long long)cnt.nodes);
+        atomicAdd(&sk[2], (unsigned long long)cnt.tris);
         atomicAdd(&sk[3], (unsigned long long)s_app);
+        atomicAdd(&sk[4], (unsigned long long)cnt.lds);
+        atomicAdd(&sk[5], (unsigned long long)cnt.spill);
     }
 }
 
 __global__ void k_clear_counters(uint32_t* c, int n, unsigned long long* stats) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0u;
     if (stats)
-        for (int i = threadIdx.x; i < 4 * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
+        for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
 }
 
 template <int MODE>
@@ -299,8 +298,8 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
         for (int c = 0; c < 3; ++c) { o[c] = org[3 * (size_t)r + c]; d[c] = dir[3 * (size_t)r + c]; }
         Trav tv;
         trav_init(tv, sc, o, d, st);
-        uint32_t dn = 0, dt = 0;
-        while (tv.node != -1) trav_step<false>(tv, sc, nullptr, st, 0u, dn, dt);
+        TravCount cnt;
+        while (tv.node != -1) trav_step<false>(tv, sc, nullptr, st, 0u, cnt);
         const bool hit = tv.h.id != INT_MAX;
         out_t[r] = hit ? tv.h.t : INFINITY;
         out_id[r] = hit ? tv.h.id : -1;
@@ -310,36 +309,83 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
 
 }  // namespace
 
-rcp_status ensure_workspace(rcp_scene* s, size_t n_state, size_t n_aux, size_t spill_entries) {
-    Workspace& w = s->ws;
-    if (n_aux > w.aux_cap) {
-        for (int i = 0; i < 2; ++i) {
-            if (w.aux[i]) { RCP_HIP(hipFree(w.aux[i])); w.aux[i] = nullptr; }
+size_t counter_words() { return kCounterWords; }
+
+namespace {
+
+// Replace *p by a buffer of `need` elements when it holds fewer, in stream
+// order on `stream`.
+template <typename T>
+rcp_status grow_buffer(T** p, size_t& cap, size_t need, hipStream_t stream) {
+    if (need <= cap && *p) return RCP_OK;
+    stream_free((void*)*p, stream);
+    *p = nullptr;
+    cap = 0;
+    rcp_status st = stream_alloc((void**)p, sizeof(T) * need, stream);
+    if (st != RCP_OK) return st;
+    cap = need;
+    return RCP_OK;
+}
+
+}  // namespace
+
+rcp_status ensure_workspace(rcp_scene* s, Workspace& w, size_t n_state, size_t n_aux, size_t spill_entries,
+                            hipStream_t stream) {
+    (void)s;
+    if (w.fixed || w.external) {
+        if (n_state > w.state_cap || n_aux > w.aux_cap || spill_entries > w.spill_cap || !w.counters) {
+            set_error(w.external ? "the render needs more workspace than the preallocated scratch holds"
+                                 : "the render needs more workspace than was sized when the graph was created "
+                                   "(launch parameters changed since); create a new graph");
+            return RCP_ERR_INVALID_ARGUMENT;
         }
+        return RCP_OK;
+    }
+    // the two lists of a pair are replaced together: the pair's capacity is
+    // zero from the moment the first is released until both are allocated,
+    // so a call that fails half way leaves a pair the next call regrows
+    if (n_aux > w.aux_cap) {
         w.aux_cap = 0;
-        for (int i = 0; i < 2; ++i) RCP_HIP(hipMalloc((void**)&w.aux[i], sizeof(float4) * n_aux));
+        for (int i = 0; i < 2; ++i) {
+            size_t cap = 0;
+            RCP_TRY_STATUS(grow_buffer(&w.aux[i], cap, n_aux, stream));
+        }
         w.aux_cap = n_aux;
     }
-    if (!w.counters) {
-        RCP_HIP(hipMalloc((void**)&w.counters, sizeof(uint32_t) * kCounterWords));
-        RCP_HIP(hipMalloc((void**)&w.stats, sizeof(unsigned long long) * 4 * kMaxPasses));
-    }
-    if (!w.view) RCP_HIP(hipMalloc(&w.view, kViewBytes));
     if (n_state > w.state_cap) {
-        for (int i = 0; i < 2; ++i) {
-            if (w.state[i]) { RCP_HIP(hipFree(w.state[i])); w.state[i] = nullptr; }
-        }
         w.state_cap = 0;
-        for (int i = 0; i < 2; ++i) RCP_HIP(hipMalloc((void**)&w.state[i], sizeof(float4) * n_state));
+        for (int i = 0; i < 2; ++i) {
+            size_t cap = 0;
+            RCP_TRY_STATUS(grow_buffer(&w.state[i], cap, n_state, stream));
+        }
         w.state_cap = n_state;
     }
-    if (spill_entries > w.spill_cap) {
-        if (w.spill) { RCP_HIP(hipFree(w.spill)); w.spill = nullptr; }
-        w.spill_cap = 0;
-        RCP_HIP(hipMalloc((void**)&w.spill, sizeof(int32_t) * spill_entries));
-        w.spill_cap = spill_entries;
-    }
+    // fixed-size buffers, each allocated once (a failed allocation leaves
+    // the others as they are, and the next call tries again)
+    size_t c0 = w.counters ? kCounterWords : 0;
+    RCP_TRY_STATUS(grow_buffer(&w.counters, c0, kCounterWords, stream));
+    size_t c1 = w.stats ? (size_t)kStatCols * kMaxPasses : 0;
+    RCP_TRY_STATUS(grow_buffer(&w.stats, c1, (size_t)kStatCols * kMaxPasses, stream));
+    size_t c2 = w.view ? kViewBytes : 0;
+    RCP_TRY_STATUS(grow_buffer((char**)&w.view, c2, kViewBytes, stream));
+    RCP_TRY_STATUS(grow_buffer(&w.spill, w.spill_cap, spill_entries, stream));
     return RCP_OK;
+}
+
+void free_workspace(Workspace& w, hipStream_t stream) {
+    if (w.external) {
+        w = Workspace{};
+        return;
+    }
+    for (int i = 0; i < 2; ++i) {
+        stream_free(w.state[i], stream);
+        stream_free(w.aux[i], stream);
+    }
+    stream_free(w.counters, stream);
+    stream_free(w.spill, stream);
+    stream_free(w.stats, stream);
+    stream_free(w.view, stream);
+    w = Workspace{};
 }
 
 namespace {
@@ -382,7 +428,7 @@ rcp_status pass_grid(rcp_scene* s, const Launch& lp, GridInfo& g) {
 }
 
 template <bool STATS, int MODE>
-rcp_status launch_passes(rcp_scene* s, PassArgs& a, int K, hipStream_t stream) {
+rcp_status launch_passes(rcp_scene* s, Workspace& w, PassArgs& a, int K, hipStream_t stream) {
     constexpr bool AUX = MODE != RCP_MODE_COLOR;
     const Launch lp = launch_params(s);
     GridInfo g;
@@ -391,9 +437,8 @@ rcp_status launch_passes(rcp_scene* s, PassArgs& a, int K, hipStream_t stream) {
     const uint32_t threads = (uint32_t)g.blocks * kBlock;
     const size_t P = (size_t)a.W * (size_t)a.H;
     const size_t spill_depth = spill_per_thread(s->dev);
-    st = ensure_workspace(s, K > 1 ? P : 1, (K > 1 && AUX) ? P : 0, spill_depth * threads);
+    st = ensure_workspace(s, w, K > 1 ? P : 1, (K > 1 && AUX) ? P : 0, spill_depth * threads, stream);
     if (st != RCP_OK) return st;
-    Workspace& w = s->ws;
     a.spill = w.spill;
     a.spill_stride = threads;
     a.counters = w.counters;
@@ -415,17 +460,17 @@ rcp_status launch_passes(rcp_scene* s, PassArgs& a, int K, hipStream_t stream) {
 }
 
 template <bool STATS>
-rcp_status launch_mode(rcp_scene* s, PassArgs& a, int K, int mode, hipStream_t stream) {
+rcp_status launch_mode(rcp_scene* s, Workspace& w, PassArgs& a, int K, int mode, hipStream_t stream) {
     switch (mode) {
-        case RCP_MODE_DEPTH: return launch_passes<STATS, RCP_MODE_DEPTH>(s, a, K, stream);
-        case RCP_MODE_NORMAL: return launch_passes<STATS, RCP_MODE_NORMAL>(s, a, K, stream);
-        default: return launch_passes<STATS, RCP_MODE_COLOR>(s, a, K, stream);
+        case RCP_MODE_DEPTH: return launch_passes<STATS, RCP_MODE_DEPTH>(s, w, a, K, stream);
+        case RCP_MODE_NORMAL: return launch_passes<STATS, RCP_MODE_NORMAL>(s, w, a, K, stream);
+        default: return launch_passes<STATS, RCP_MODE_COLOR>(s, w, a, K, stream);
     }
 }
 
 
 template <int MODE>
-rcp_status prepare_mode(rcp_scene* s, int W, int H, int K) {
+rcp_status prepare_mode(rcp_scene* s, Workspace& w, int W, int H, int K, hipStream_t stream) {
     const Launch lp = launch_params(s);
     GridInfo g1, g2;
     rcp_status st = pass_grid<false, MODE>(s, lp, g1);
@@ -434,26 +479,27 @@ rcp_status prepare_mode(rcp_scene* s, int W, int H, int K) {
     const uint32_t threads = (uint32_t)(g1.blocks > g2.blocks ? g1.blocks : g2.blocks) * kBlock;
     const size_t P = (size_t)W * (size_t)H;
     const size_t spill_depth = spill_per_thread(s->dev);
-    return ensure_workspace(s, K > 1 ? P : 1, (K > 1 && MODE != RCP_MODE_COLOR) ? P : 0, spill_depth * threads);
+    return ensure_workspace(s, w, K > 1 ? P : 1, (K > 1 && MODE != RCP_MODE_COLOR) ? P : 0, spill_depth * threads,
+                            stream);
 }
 }  // namespace
 
-rcp_status prepare_render(rcp_scene* s, int W, int H, int K, int mode) {
-    if (s->tuning.engine == RCP_ENGINE_CHAIN) return prepare_chain(s, mode);
+rcp_status prepare_render(rcp_scene* s, Workspace& w, int W, int H, int K, int mode, hipStream_t stream) {
+    if (s->tuning.engine == RCP_ENGINE_CHAIN) return prepare_chain(s, w, mode, stream);
     switch (mode) {
-        case RCP_MODE_DEPTH: return prepare_mode<RCP_MODE_DEPTH>(s, W, H, K);
-        case RCP_MODE_NORMAL: return prepare_mode<RCP_MODE_NORMAL>(s, W, H, K);
-        default: return prepare_mode<RCP_MODE_COLOR>(s, W, H, K);
+        case RCP_MODE_DEPTH: return prepare_mode<RCP_MODE_DEPTH>(s, w, W, H, K, stream);
+        case RCP_MODE_NORMAL: return prepare_mode<RCP_MODE_NORMAL>(s, w, W, H, K, stream);
+        default: return prepare_mode<RCP_MODE_COLOR>(s, w, W, H, K, stream);
     }
 }
 
-rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& disp, float* out_images,
-                  int32_t* out_ids, const float* prev_rgb, const float* prev_aux, float* out_aux,
+rcp_status render(rcp_scene* s, Workspace& w, const Camera& cam, int W, int H, int K, const Disp& disp,
+                  float* out_images, int32_t* out_ids, const float* prev_rgb, const float* prev_aux, float* out_aux,
                   unsigned long long* host_counts, hipStream_t stream) {
     // whole renders from the seed take the chain engine unless the per-pass
     // engine is selected; single passes with given inputs take the pass kernel
     if (s->tuning.engine == RCP_ENGINE_CHAIN && !prev_rgb && !prev_aux && !out_aux)
-        return render_chain(s, cam, W, H, K, disp, out_images, out_ids, host_counts, stream);
+        return render_chain(s, w, cam, W, H, K, disp, out_images, out_ids, host_counts, stream);
     const bool stats = host_counts != nullptr;
     const Launch lp = launch_params(s);
     const int tw = 1 << lp.tile_log2w;
@@ -476,13 +522,14 @@ rcp_status render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Di
     a.out_aux = out_aux;
     a.prev_img = prev_rgb;
     a.prev_aux = prev_aux;
-    rcp_status st = stats ? launch_mode<true>(s, a, K, disp.mode, stream)
-                          : launch_mode<false>(s, a, K, disp.mode, stream);
+    rcp_status st = stats ? launch_mode<true>(s, w, a, K, disp.mode, stream)
+                          : launch_mode<false>(s, w, a, K, disp.mode, stream);
     if (st != RCP_OK) return st;
     if (stats) {
-        RCP_HIP(hipMemcpyAsync(host_counts, s->ws.stats, sizeof(unsigned long long) * 4 * K, hipMemcpyDeviceToHost,
-                               stream));
+        RCP_HIP(hipMemcpyAsync(host_counts, w.stats, sizeof(unsigned long long) * kStatCols * K,
+                               hipMemcpyDeviceToHost, stream));
         RCP_HIP(hipStreamSynchronize(stream));
+        return take_device_error(s);
     }
     return RCP_OK;
 }
@@ -516,7 +563,7 @@ rcp_status trace_rays(rcp_scene* s, const float* org, const float* dir, int n, f
     if (st != RCP_OK) return st;
     const uint32_t threads = (uint32_t)g.blocks * kBlock;
     const size_t spill_depth = spill_per_thread(s->dev);
-    st = ensure_workspace(s, 1, 0, spill_depth * threads);
+    st = ensure_workspace(s, s->ws, 1, 0, spill_depth * threads, stream);
     if (st != RCP_OK) return st;
     DevScene sc = s->dev;
     sc.top_count = 0;            // this kernel stages nothing in LDS

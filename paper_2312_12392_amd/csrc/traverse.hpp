@@ -284,10 +284,12 @@ struct Stack {
     }
     // Push np (0..3) entries, e0 deepest, with one check for room: three ring
     // slots are written whatever np is (those above the new top are unused).
-    __device__ inline void push_up_to_3(int32_t e0, int32_t e1, int32_t e2, uint32_t np) {
+    // n_spill counts the entries moved to the global area.
+    __device__ inline void push_up_to_3(int32_t e0, int32_t e1, int32_t e2, uint32_t np, uint32_t& n_spill) {
         while (sp + 3u - lo > (uint32_t)kStack) {
             spill[(size_t)lo * stride] = *ring(lo);
             ++lo;
+            ++n_spill;
         }
         *ring(sp) = e0;
         *ring(sp + 1u) = e1;
@@ -376,9 +378,10 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
     }
     tv.node = sc.n_nodes > 0 ? 0 : -1;
     // Every step of a ray enters a node or a leaf, each at most once per ray
-    // (a wide node has at most 4 children); the bound on steps only
-    // guarantees termination should the tree ever be malformed.
-    tv.budget = 5u * sc.n_nodes + 16u;
+    // (a wide node has at most 4 children); the bound on steps
+    // (5 n_nodes + 16 unless a test lowers it) only guarantees termination
+    // should the tree ever be malformed.
+    tv.budget = sc.step_budget;
     tv.h.t = INFINITY;
     tv.h.id = INT_MAX;
     tv.h.slot = 0;
@@ -386,6 +389,14 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
     st.sp = 0;
     st.lo = 0;
 }
+
+// Traversal counters of the instrumented kernels (dead code otherwise).
+struct TravCount {
+    uint32_t nodes = 0;   // inner nodes visited
+    uint32_t tris = 0;    // triangles tested
+    uint32_t lds = 0;     // inner nodes read from the LDS copy of the top levels
+    uint32_t spill = 0;   // stack entries moved to the global overflow area
+};
 
 __device__ inline float lane_of(const float4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
@@ -411,7 +422,7 @@ __device__ inline float4 f4(V4 v) { return make_float4(v.x, v.y, v.z, v.w); }
 
 template <bool STATS>
 __device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& sc, const float4* top, Stack& st,
-                                       uint32_t& n_nodes) {
+                                       TravCount& cnt) {
     // byte offsets of the entry and exit planes of the three axes (the
     // node array is limited to 4 GB, so offsets fit 32 bits)
     const uint32_t base = (uint32_t)node << 7;
@@ -434,7 +445,10 @@ __device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& s
         n2 = *(const float4*)(g + e2); x2 = *(const float4*)(g + (e2 ^ 16u));
         lk = *(const float4*)(g + base + 96u);
     }
-    if (STATS) ++n_nodes;
+    if (STATS) {
+        ++cnt.nodes;
+        if ((uint32_t)node < sc.top_count) ++cnt.lds;
+    }
     const float lim = tv.h.t * kSlack;
     uint32_t key[4];    // entry distance bits of hit children (t >= 0), all ones for the rest
     int32_t val[4];
@@ -470,14 +484,14 @@ __device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& s
         const uint32_t np = nh - 1u;
         const int32_t e0 = np == 3u ? val[3] : (np == 2u ? val[2] : val[1]);
         const int32_t e1 = np == 3u ? val[2] : val[1];
-        st.push_up_to_3(e0, e1, val[1], np);
+        st.push_up_to_3(e0, e1, val[1], np, cnt.spill);
     }
     return val[0];
 }
 
 // Test the triangles of leaf `link` against the ray, keeping the closest hit.
 template <bool STATS>
-__device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, uint32_t& n_tris) {
+__device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, TravCount& cnt) {
     const int32_t node = link;
     // leaf: triangles [first, first + count)
     const uint32_t first = ((uint32_t)node >> 3) & 0x0FFFFFFFu;
@@ -485,7 +499,7 @@ __device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, ui
     for (uint32_t j = 0; j < count; ++j) {
         const float4* tp = sc.tris + 3 * (size_t)(tv.rw.tri_base + first + j);
         const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
-        if (STATS) ++n_tris;
+        if (STATS) ++cnt.tris;
         float t;
         bool front;
         if (hit_triangle(tv.rw, v0, v1, v2, t, front)) {
@@ -517,8 +531,14 @@ constexpr int kMaxDescent = 256;   // node visits of one step (the step ends, th
 
 template <bool STATS>
 __device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* top, Stack& st, uint32_t exit_lanes,
-                                 uint32_t& n_nodes, uint32_t& n_tris) {
-    if (--tv.budget == 0u) { tv.node = -1; return; }
+                                 TravCount& cnt) {
+    if (--tv.budget == 0u) {
+        // only a malformed tree gets here: end the ray and raise the scene's
+        // error flag, which the host reports as an internal error
+        __hip_atomic_store(sc.err_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        tv.node = -1;
+        return;
+    }
     int32_t node = tv.node;
     int32_t leaf = -1;
     for (int it = 0; it < kMaxDescent; ++it) {
@@ -530,9 +550,9 @@ __device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* top
         if (it > 0 && (uint32_t)__popcll(searching) <= exit_lanes &&
             __popcll(wave_ballot(leaf != -1)) >= __popcll(searching))
             break;
-        if (node >= 0) node = visit_inner4<STATS>(tv, node, sc, top, st, n_nodes);
+        if (node >= 0) node = visit_inner4<STATS>(tv, node, sc, top, st, cnt);
     }
-    if (leaf != -1) visit_leaf<STATS>(tv, leaf, sc, n_tris);
+    if (leaf != -1) visit_leaf<STATS>(tv, leaf, sc, cnt);
     tv.node = node;
 }
 

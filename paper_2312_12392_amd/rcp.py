@@ -48,8 +48,11 @@ EXPORTED = [
     "rcp_status_string", "rcp_last_error", "rcp_gather_passes", "rcp_render_batch", "rcp_graph_create",
     "rcp_graph_update", "rcp_graph_launch", "rcp_graph_destroy", "rcp_get_tuning", "rcp_set_tuning", "rcp_autotune",
     "rcp_server_create", "rcp_submit", "rcp_poll", "rcp_result", "rcp_result_copy", "rcp_release", "rcp_server_stats",
-    "rcp_server_destroy",
+    "rcp_server_destroy", "rcp_check", "rcp_debug_set",
 ]
+STAT_COLS = 6
+RCP_DEBUG_FAIL_ALLOC_AFTER = 1
+RCP_DEBUG_STEP_BUDGET = 2
 
 
 class RcpError(RuntimeError):
@@ -164,6 +167,8 @@ def load(path: str | None = None):
         "rcp_set_tuning": (st, [P, ctypes.POINTER(rcp_tuning)]),
         "rcp_autotune": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, i32, ctypes.POINTER(rcp_displacement), P, P, i32,
                               ctypes.POINTER(rcp_tuning), ctypes.POINTER(ctypes.c_float), P]),
+        "rcp_check": (st, [P, P]),
+        "rcp_debug_set": (st, [i32, ctypes.c_int64]),
         "rcp_status_string": (ctypes.c_char_p, [st]),
         "rcp_last_error": (ctypes.c_char_p, []),
     }
@@ -292,14 +297,25 @@ def rcp_render_pass(handle: int, cam, W: int, H: int, disp: rcp_displacement, pr
 
 def rcp_render_stats(handle: int, cam, W: int, H: int, K: int, disp: rcp_displacement, out_images, out_ids=None,
                      stream=None) -> np.ndarray:
-    """Returns uint64 [K][4]: rays traced, inner nodes visited, triangles
-    tested, rays appended for the next pass."""
+    """Returns uint64 [K][6]: rays traced, inner nodes visited, triangles
+    tested, rays continued to the next pass, inner nodes read from LDS, stack
+    entries spilled to global memory."""
     c = make_camera(cam)
-    counts = np.zeros((K, 4), dtype=np.uint64)
+    counts = np.zeros((K, STAT_COLS), dtype=np.uint64)
     st = load().rcp_render_stats(handle, ctypes.byref(c), int(W), int(H), int(K), ctypes.byref(disp),
                                  _dev_ptr(out_images), _dev_ptr(out_ids), counts.ctypes.data, _stream(stream))
     _check(st, "rcp_render_stats")
     return counts
+
+
+def rcp_check(handle: int, stream=None) -> None:
+    """Synchronise the stream; raise if a ray of an earlier call ran out of
+    its traversal step budget."""
+    _check(load().rcp_check(handle, _stream(stream)), "rcp_check")
+
+
+def rcp_debug_set(what: int, value: int) -> None:
+    _check(load().rcp_debug_set(int(what), int(value)), "rcp_debug_set")
 
 
 def rcp_generate_rays(cam, W: int, H: int, disp: rcp_displacement, prev_rgb, out_org, out_dir, stream=None,

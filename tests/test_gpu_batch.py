@@ -99,7 +99,9 @@ def test_batch_mixed_modes_equal_single_views_and_oracle():
 
 
 def test_batch_orbit_mix_on_terrain1m():
-    """The 64-view orbit mix (256^2 .. 1024^2, K 1..8) of the 1M scene."""
+    """The 64-view orbit mix (256^2 .. 1024^2, K 1..8) of the 1M scene: every
+    view equals rcp_render of that view alone (the oracle checks every pixel
+    of every view in test_gpu_wholeframe.py)."""
     w = scenegen.workload("terrain1m")
     views = scenegen.orbit_views(3, 64)
     say("orbit mix", len(views))
@@ -108,16 +110,9 @@ def test_batch_orbit_mix_on_terrain1m():
     outs = [torch.empty((K, H, W, 3), device="cuda") for (_, W, H, K) in views]
     rcp.rcp_render_batch(s.handle, [(cam, W, H, K, d, o, None) for (cam, W, H, K), o in zip(views, outs)])
     torch.cuda.synchronize()
-    orc = oracle.OracleScene(w.scene, use_bvh=True)
-    rng = np.random.default_rng(1)
     for n, ((cam, W, H, K), o) in enumerate(zip(views, outs)):
         ref, _ = single(s, cam, W, H, K, 0.0, 0.01)
         assert torch.equal(o, ref), n
-        if n % 8 == 0:
-            pix = rng.choice(W * H, size=300, replace=False).astype(np.int32)
-            oi, _ = orc.render_pixels(cam, W, H, K, 0.0, 0.01, pix)
-            g = o.reshape(K, W * H, 3)[:, torch.from_numpy(pix.astype(np.int64)).cuda()].permute(1, 0, 2).cpu().numpy()
-            assert np.array_equal(g, oi), n
     s.close()
 
 

@@ -116,23 +116,3 @@ def test_render_pass_chain_with_hit_data(mode):
         prev, prev_aux = out, aux
         o_prev, o_aux = r_img, r_aux
     s.close()
-
-
-@pytest.mark.parametrize("mode,z0", [(DEPTH, 1.2), (NORMAL, 0.0)])
-def test_full_size_terrain1m_modes_sampled(mode, z0):
-    w = scenegen.workload("terrain1m")
-    say("full size mode", mode)
-    s = rcp.Scene(w.scene)
-    imgs, ids = s.render(w.camera, w.width, w.height, w.passes, w.lambda_eye, 0.03, mode=mode, z0=z0)
-    torch.cuda.synchronize()
-    P = w.width * w.height
-    rng = np.random.default_rng(7)
-    pix = rng.choice(P, size=6000, replace=False)
-    pt = torch.from_numpy(pix).cuda()
-    g_img = imgs.reshape(w.passes, P, 3)[:, pt].cpu().numpy()
-    g_ids = ids.reshape(w.passes, P)[:, pt].cpu().numpy()
-    o_img, o_ids = oracle.OracleScene(w.scene, use_bvh=True).render_pixels(
-        w.camera, w.width, w.height, w.passes, w.lambda_eye, 0.03, pix.astype(np.int32), mode=mode, z0=z0)
-    r = assert_parity(g_img, g_ids, o_img.transpose(1, 0, 2), o_ids.T, f"terrain1m mode {mode}")
-    assert r["exact_images"] and r["exact_ids"], r
-    s.close()

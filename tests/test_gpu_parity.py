@@ -293,47 +293,9 @@ def test_stats_kernel_counts_and_images(engine):
 
 
 # ---------------------------------------------------------------------------
-# Full-size workloads: sampled pixels, each checked through its whole chain
+# The largest image (whole-frame checks of the full-size workloads are in
+# test_gpu_wholeframe.py)
 # ---------------------------------------------------------------------------
-
-def _sampled_parity(w, n_sample, seed, extra=()):
-    s = rcp.Scene(w.scene)
-    imgs, ids = s.render(w.camera, w.width, w.height, w.passes, w.lambda_eye, w.lambda_dir)
-    torch.cuda.synchronize()
-    P = w.width * w.height
-    rng = np.random.default_rng(seed)
-    pix = np.unique(np.concatenate([rng.choice(P, size=n_sample, replace=False), np.asarray(extra, np.int64)]))
-    pix_t = torch.from_numpy(pix).cuda()
-    g_img = imgs.reshape(w.passes, P, 3)[:, pix_t].permute(1, 0, 2).cpu().numpy()
-    g_ids = ids.reshape(w.passes, P)[:, pix_t].T.cpu().numpy()
-    o = oracle.OracleScene(w.scene, use_bvh=True)
-    o_img, o_ids = o.render_pixels(w.camera, w.width, w.height, w.passes, w.lambda_eye, w.lambda_dir,
-                                   pix.astype(np.int32))
-    # arrange as [K][n][3] for the shared checker
-    r = assert_parity(g_img.transpose(1, 0, 2), g_ids.T, o_img.transpose(1, 0, 2), o_ids.T, w.name)
-    full = imgs.cpu().numpy()
-    assert full.min() >= 0.0 and full.max() <= 1.0
-    s.close()
-    return r
-
-
-def test_full_size_terrain1m_sampled():
-    w = scenegen.workload("terrain1m")
-    say("full size", w.name, w.width, w.height, w.passes)
-    W, H = w.width, w.height
-    corners = [0, W - 1, (H - 1) * W, H * W - 1]
-    row = [540 * W + x for x in range(0, W, 3)]
-    col = [y * W + 960 for y in range(H)]
-    r = _sampled_parity(w, 20000, 0, corners + row + col)
-    assert r["exact_images"] and r["exact_ids"], r
-
-
-def test_full_size_terrain1m_literal_eye_sampled():
-    w = scenegen.workload("terrain1m", literal_eye=True)
-    say("full size literal eye", w.name)
-    r = _sampled_parity(w, 8000, 1)
-    assert r["exact_images"] and r["exact_ids"], r
-
 
 def test_maximum_image_size():
     """W * H = 2^27 (the limit) on a small scene; sampled chains."""
