@@ -209,6 +209,25 @@ rcp_status rcp_render(rcp_scene* scene, const rcp_camera* base_camera, int W, in
                       const rcp_displacement* disp, float* out_images, int32_t* out_ids,
                       void* hip_stream);
 
+/* rcp_render for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, validation and results as rcp_render (always the chain
+ * engine); the call allocates nothing.  Its working memory (the launch's
+ * view table, work counters and traversal stack overflow) is a fixed area of
+ * rcp_render_noalloc_scratch_bytes() = 64 MiB inside the library's device
+ * code, one per GPU, held until the process ends.  The launch uses as many
+ * persistent workgroups as that area's overflow part holds for the scene's
+ * tree (at most the occupancy limit; the count changes the speed only);
+ * RCP_ERR_INVALID_ARGUMENT if it cannot hold one workgroup per compute unit
+ * (a tree over about 80 levels deep).  All calls on one GPU share the area
+ * and leave their contents in it: calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller.
+ * Asynchronous on hip_stream. */
+rcp_status rcp_render_noalloc(rcp_scene* scene, const rcp_camera* base_camera, int W, int H, int K,
+                              const rcp_displacement* disp, float* out_images, int32_t* out_ids,
+                              void* hip_stream);
+uint64_t rcp_render_noalloc_scratch_bytes(void);
+
 /* One pass of F: out = F(prev) for a caller-supplied previous image.
  *   prev_rgb  device [H][W][3] float32, or NULL for the grey seed
  *   prev_aux  device [H][W][4] float32 (view depth, unit normal) of the

@@ -48,7 +48,7 @@ EXPORTED = [
     "rcp_status_string", "rcp_last_error", "rcp_gather_passes", "rcp_render_batch", "rcp_graph_create",
     "rcp_graph_update", "rcp_graph_launch", "rcp_graph_destroy", "rcp_get_tuning", "rcp_set_tuning", "rcp_autotune",
     "rcp_server_create", "rcp_submit", "rcp_poll", "rcp_result", "rcp_result_copy", "rcp_release", "rcp_server_stats",
-    "rcp_server_destroy", "rcp_check", "rcp_debug_set",
+    "rcp_server_destroy", "rcp_check", "rcp_debug_set", "rcp_render_noalloc", "rcp_render_noalloc_scratch_bytes",
 ]
 STAT_COLS = 6
 RCP_DEBUG_FAIL_ALLOC_AFTER = 1
@@ -167,6 +167,9 @@ def load(path: str | None = None):
         "rcp_set_tuning": (st, [P, ctypes.POINTER(rcp_tuning)]),
         "rcp_autotune": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, i32, ctypes.POINTER(rcp_displacement), P, P, i32,
                               ctypes.POINTER(rcp_tuning), ctypes.POINTER(ctypes.c_float), P]),
+        "rcp_render_noalloc": (st, [P, ctypes.POINTER(rcp_camera), i32, i32, i32, ctypes.POINTER(rcp_displacement),
+                                    P, P, P]),
+        "rcp_render_noalloc_scratch_bytes": (ctypes.c_uint64, []),
         "rcp_check": (st, [P, P]),
         "rcp_debug_set": (st, [i32, ctypes.c_int64]),
         "rcp_status_string": (ctypes.c_char_p, [st]),
@@ -284,6 +287,18 @@ def rcp_render(handle: int, cam, W: int, H: int, K: int, disp: rcp_displacement,
     st = load().rcp_render(handle, ctypes.byref(c), int(W), int(H), int(K), ctypes.byref(disp),
                            _dev_ptr(out_images), _dev_ptr(out_ids), _stream(stream))
     _check(st, "rcp_render")
+
+
+def rcp_render_noalloc(handle: int, cam, W: int, H: int, K: int, disp: rcp_displacement, out_images, out_ids=None,
+                       stream=None) -> None:
+    c = make_camera(cam)
+    st = load().rcp_render_noalloc(handle, ctypes.byref(c), int(W), int(H), int(K), ctypes.byref(disp),
+                                   _dev_ptr(out_images), _dev_ptr(out_ids), _stream(stream))
+    _check(st, "rcp_render_noalloc")
+
+
+def rcp_render_noalloc_scratch_bytes() -> int:
+    return int(load().rcp_render_noalloc_scratch_bytes())
 
 
 def rcp_render_pass(handle: int, cam, W: int, H: int, disp: rcp_displacement, prev_rgb, out_rgb, out_ids=None,
