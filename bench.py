@@ -24,6 +24,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU peak of MI355X without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 39.32 T lane-operations per second (the 157.3 TFLOP/s FP32 figure
+# counts an FMA as 2 and packed dual-FP32 issue as 2; the build disables
+# packed FP32 and counts an FMA as one operation).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU lane-operations the method needs per unit of work, counted from the
+# arithmetic of each step as written (not from the compiled code):
+#   inner-node visit: 4 children x (6 slab-plane FMAs, 3 max and 2 min for
+#     the entry and exit, 2 compares) + 1 multiply of the best-hit bound = 53
+#   triangle test (watertight): 9 subtractions to the origin, 6 x (multiply,
+#     subtract) of the shear, 3 x (2 multiplies, subtract) edge functions,
+#     3 zero tests, 6 sign tests, 2 adds and 1 test of det, 3 multiplies of
+#     the z terms, 5 for T, 1 division, 1 test of t, 2 compares against the
+#     best hit = 54
+#   traced ray: its displaced camera ray (68), the traversal's ray constants
+#     (72), the shade lookup and convergence test (10) = 150
+OPS_PER_NODE = 53
+OPS_PER_TRI = 54
+OPS_PER_RAY = 150
 KERNEL_OF_ENGINE = {"chain": "k_chain", "passes": "k_pass"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2312_12392_amd", "csrc", f)
                   for f in ("chain.hip", "trace.hip", "traverse.hpp", "rcp_internal.hpp", "bvh_build.hip")]
@@ -31,6 +50,22 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2312_12392_amd", "csrc", f)
 
 def traffic_file(kernel: str, workload: str) -> str:
     return os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+
+
+def counters_file(kernel: str, workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.json")
+
+
+def load_profile(path: str, workload: str):
+    """A profile summary (JSON) if it was taken on the current kernel sources."""
+    try:
+        with open(path) as f:
+            pr = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if pr.get("kernel_source_sha256") != kernel_source_hash() or pr.get("workload") != workload:
+        return None
+    return pr
 
 
 def log(*a):
@@ -76,6 +111,21 @@ def algorithmic_bytes(counts, engine="chain"):
         converged = rays - app if k + 1 < K else 0.0
         total += 16 * converged * (K - 1 - k)
     return total
+
+
+def algorithmic_ops(counts):
+    """VALU lane-operations of one frame the method needs (OPS_PER_*)."""
+    tot = counts[:, :3].astype("float64").sum(0)
+    return OPS_PER_RAY * tot[0] + OPS_PER_NODE * tot[1] + OPS_PER_TRI * tot[2]
+
+
+def logical_bytes_by_tier(counts):
+    """Bytes the traversal reads and writes, by the memory that serves them:
+    node visits staged in LDS; node visits, triangle tests and the shade
+    lookup through the L1/L2 caches; the images and IDs written."""
+    tot = counts.astype("float64").sum(0)
+    rays, nodes, tris, _, lds_nodes = tot[:5]
+    return {"lds": round(112 * lds_nodes), "l1_l2": round(112 * (nodes - lds_nodes) + 48 * tris + 16 * rays)}
 
 
 def cpu_baseline(w, min_seconds=10.0, min_reps=3, max_reps=60):
@@ -125,6 +175,13 @@ def main():
     ap.add_argument("--builder", choices=["ploc", "lbvh"], default="ploc", help="binary tree builder (build option)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--no-served", action="store_true", help="skip the served leg of the default line")
+    ap.add_argument("--served-seconds", type=float, default=3.0, help="served leg: seconds of arrivals at 200/s")
+    ap.add_argument("--saturating-rate", type=float, default=600.0,
+                    help="served leg: an arrival rate above what the GPU serves")
+    ap.add_argument("--saturating-seconds", type=float, default=1.5,
+                    help="served leg: seconds of arrivals at the saturating rate")
+    ap.add_argument("--max-inflight", type=int, default=2, help="server: concurrent batched launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the render would shard "
@@ -229,19 +286,21 @@ def bench_frame(args):
     value = nominal * args.steps / (ms_total * 1e-3) / 1e6
     # the frame is one k_chain launch (or K k_pass launches) plus one setup
     # launch of a few microseconds; the average launch lasts ms / launches
-    # and carries bytes_frame / launches, so the rate is the frame's
-    achieved_gbs = bytes_frame / (ms * 1e-3) / 1e9
+    # and carries 1 / launches of the frame's work, so the rates are the
+    # frame's
+    ops_frame = algorithmic_ops(counts)
+    achieved_tops = ops_frame / (ms * 1e-3) / 1e12
 
     copy_gbs = copy_bandwidth_gbs(stream)
 
-    traffic = None
-    try:
-        with open(traffic_file(kernel, w.name)) as f:
-            tr = json.load(f)
-        if tr.get("kernel_source_sha256") == kernel_source_hash() and tr.get("workload") == w.name:
-            traffic = tr["hbm_bytes_per_launch"]
-    except (OSError, ValueError, KeyError):
-        traffic = None
+    # HBM traffic and SQ counters of this kernel from the committed profiles,
+    # when they were taken on the current sources (null otherwise)
+    tr = load_profile(traffic_file(kernel, w.name), w.name)
+    traffic = tr["hbm_bytes_per_launch"] if tr else None
+    write_bytes = round(tr["write_kib_per_dispatch"] * 1024 * tr["write_scale"]) if tr else None
+    sq = load_profile(counters_file(kernel, w.name), w.name)
+    compulsory_writes = 16 * W * H * K          # every image (12 B) and ID (4 B) of every pass
+    literal = literal_eye_leg(args, scene, w, imgs, ids, stream) if not args.literal_eye else None
 
     result = {
         "metric": "Mrays/s (nominal W*H*K rays) of the K=6 frame at 1080p/1M tris; frame ms in ms_per_step",
@@ -269,29 +328,95 @@ def bench_frame(args):
         "bvh": {"nodes": info["n_nodes"], "sah_cost": round(info["sah_cost"], 3), "max_depth": info["max_depth"],
                 "builder": args.builder, "collapse": args.collapse, "max_leaf": args.max_leaf,
                 "c_trav": args.c_trav, "c_isect": args.c_isect},
+        # The traversal is bound on chip by VALU issue (no dense contraction,
+        # no MFMA; HBM runs far below its peak), so the roofline is the VALU
+        # one: the method's lane-operations per frame (OPS_PER_*) over the
+        # frame time, against the VALU peak.  Beside it, from the committed
+        # counter profiles of the same sources: how busy the VALU issue is and
+        # what fraction of its lanes is active, and the HBM side.
         "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved_gbs, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+            "bound": "alu",
+            "achieved": round(achieved_tops, 3),
+            "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "T lane-op/s",
+            "frac": round(achieved_tops / VALU_PEAK_TOPS, 4),
             "traffic": traffic,
             "kernel": kernel,
             "launches_per_step": launches,
-            "algorithmic_bytes_per_launch": round(bytes_frame / launches),
-            "bytes_per_traced_ray": round(bytes_frame / traced, 1),
-            # HBM-side rate of the measured traffic, and what a plain device
-            # copy reaches on the same GPU (read + write bytes / time)
-            "traffic_gbs": None if traffic is None else round(traffic / (ms * 1e-3) / 1e9, 1),
-            "copy_gbs": round(copy_gbs, 1),
+            "algorithmic_ops_per_launch": round(ops_frame / launches),
+            "ops_per_unit": {"inner_node_visit": OPS_PER_NODE, "triangle_test": OPS_PER_TRI,
+                             "traced_ray": OPS_PER_RAY},
+            "valu_issue": None if sq is None else {
+                "busy": sq["valu_busy"], "lane_utilisation": sq["lane_utilisation"],
+                "useful_lane_frac": round(sq["valu_busy"] * sq["lane_utilisation"], 4),
+                "ta_busy": sq["ta_busy"], "source": os.path.basename(counters_file(kernel, w.name))},
+            "hbm": {
+                "achieved": None if traffic is None else round(traffic / (ms * 1e-3) / 1e9, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None if traffic is None else round(traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "write_bytes": write_bytes,
+                "compulsory_write_bytes": compulsory_writes,
+                "write_amplification": None if write_bytes is None else round(write_bytes / compulsory_writes, 3),
+                "source": os.path.basename(traffic_file(kernel, w.name)),
+                # what a plain 1 GiB device copy reaches on the same GPU
+                "copy_gbs": round(copy_gbs, 1),
+            },
+            "logical_bytes_per_launch": dict(logical_bytes_by_tier(counts),
+                                             hbm_measured=traffic,
+                                             total=round(bytes_frame / launches)),
         },
     }
+    if literal is not None:
+        result["literal_eye"] = literal
+    scene.close()
+    if not args.no_served and args.engine == "chain" and w.name == "terrain1m":
+        result["served"] = served_leg(args)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores ...")
         result["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(result), flush=True)
-    scene.close()
 
+
+def literal_eye_leg(args, scene, w, imgs, ids, stream, reps=10):
+    """The same frame with the eye displaced too, lambda_eye = lambda_dir
+    (the configuration's literal wording): mean of `reps` frames."""
+    import torch
+
+    from paper_2312_12392_amd import rcp
+    d = rcp.make_displacement(w.lambda_dir, w.lambda_dir)
+    for _ in range(2):
+        rcp.rcp_render(scene.handle, w.camera, w.width, w.height, w.passes, d, imgs, ids, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        rcp.rcp_render(scene.handle, w.camera, w.width, w.height, w.passes, d, imgs, ids, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"lambda_eye": w.lambda_dir, "lambda_dir": w.lambda_dir, "ms_per_frame": round(ms, 4),
+            "mrays_per_s": round(w.width * w.height * w.passes / (ms * 1e-3) / 1e6, 2), "frames": reps}
+
+
+def served_leg(args):
+    """Compact served measurement for the default line: the continuous-
+    batching server against the plain per-request loop on the 4M-triangle
+    scene, at 200 requests/s and at a rate above what the GPU can serve."""
+    import torch
+
+    import scenegen
+    from paper_2312_12392_amd import rcp
+    w = scenegen.workload("terrain4m")
+    log(f"served leg: terrain4m, {w.scene.n_tris} triangles")
+    scene = rcp.Scene(w.scene, build_options(args))
+    rates = [(200.0, args.served_seconds), (args.saturating_rate, args.saturating_seconds)]
+    out = {"scene": f"terrain4m: {w.scene.n_tris} triangles", "max_inflight": args.max_inflight,
+           "requests": "Poisson arrivals; 512^2/720p/1080p/4K; K 3..8; spline cameras; lambda_dir 0.01"}
+    for i, (rate, seconds) in enumerate(rates):
+        r = served_rate(rcp, scene, w, rate, seconds, 5 + i, args.max_inflight, torch.cuda.current_stream())
+        out[f"{int(rate)}_per_s"] = r
+        log(f"served rate {rate}: {r}")
+    scene.close()
+    return out
 
 def _percentiles(x):
     import numpy as np
@@ -371,11 +496,63 @@ def _retire(rcp, srv, pending, late, lat):
     return still
 
 
+def served_rate(rcp, scene, w, rate, duration, seed, max_inflight, stream):
+    """One arrival rate: the server, then the plain loop, on the same trace.
+    Latency = completion - arrival time (host clock); throughput = nominal
+    rays / wall time from the first arrival to the last completion."""
+    import time
+
+    import torch
+
+    import scenegen
+    d = rcp.make_displacement(0.0, w.lambda_dir)
+    trace = scenegen.served_trace(seed, rate, duration)
+    rays = sum(W * H * K for (_, _, W, H, K) in trace)
+    # warm-up of both paths (kernels loaded, workspaces sized)
+    big = torch.empty((8, 2160, 3840, 3), device="cuda")
+    rcp.rcp_render(scene.handle, trace[0][1], 3840, 2160, 8, d, big, None, stream)
+    torch.cuda.synchronize()
+    # --- server ---
+    srv = rcp.rcp_server_create(scene.handle, 48 << 30, max_inflight=max_inflight)
+    t0 = time.perf_counter()
+    pending = []
+    lat = []
+    late = {}
+    for (arr, cam, W, H, K) in trace:
+        while time.perf_counter() - t0 < arr:
+            time.sleep(0.0002)
+        t = rcp.rcp_submit(srv, cam, W, H, K, d)
+        late[t] = time.perf_counter() - t0 - arr        # submitted this long after its arrival time
+        pending.append(t)
+        if len(pending) > 16:                           # retire finished requests as we go
+            pending = _retire(rcp, srv, pending, late, lat)
+    while pending:
+        pending = _retire(rcp, srv, pending, late, lat)
+        time.sleep(0.0005)
+    t_srv = time.perf_counter() - t0
+    launches = rcp.rcp_server_stats(srv)["launches"]
+    rcp.rcp_server_destroy(srv)
+    # --- plain loop: one synchronous rcp_render at a time, in arrival order ---
+    lat_loop = []
+    t0 = time.perf_counter()
+    for (arr, cam, W, H, K) in trace:
+        now = time.perf_counter() - t0
+        if now < arr:
+            time.sleep(arr - now)
+        out = big.view(-1)[:K * H * W * 3].view(K, H, W, 3)
+        rcp.rcp_render(scene.handle, cam, W, H, K, d, out, None, stream)
+        stream.synchronize()
+        lat_loop.append((time.perf_counter() - t0 - arr) * 1e3)
+    t_loop = time.perf_counter() - t0
+    del big
+    return {"requests": len(trace), "seconds_of_arrivals": duration, "nominal_rays": rays, "launches": launches,
+            "server_latency_ms": _percentiles(lat), "loop_latency_ms": _percentiles(lat_loop),
+            "server_mrays_per_s": round(rays / t_srv / 1e6, 1), "loop_mrays_per_s": round(rays / t_loop / 1e6, 1)}
+
+
 def bench_served(args):
     """Poisson arrivals on the 4M-triangle scene: the continuous-batching
     server vs a plain first-in-first-out loop of synchronous rcp_render."""
-    import time
-
     import torch
 
     import scenegen
@@ -384,58 +561,10 @@ def bench_served(args):
     stream = torch.cuda.current_stream()
     w = scenegen.workload("terrain4m")
     scene = rcp.Scene(w.scene, build_options(args))
-    d = rcp.make_displacement(0.0, w.lambda_dir)
     rates = [float(r) for r in args.rates.split(",")]
     per_rate = {}
-    total_rays = 0
     for ri, rate in enumerate(rates):
-        trace = scenegen.served_trace(5 + ri, rate, args.duration)
-        rays = sum(W * H * K for (_, _, W, H, K) in trace)
-        total_rays += rays
-        # warm-up of both paths (kernels loaded, workspaces sized)
-        big = torch.empty((8, 2160, 3840, 3), device="cuda")
-        rcp.rcp_render(scene.handle, trace[0][1], 3840, 2160, 8, d, big, None, stream)
-        torch.cuda.synchronize()
-        # --- server ---
-        srv = rcp.rcp_server_create(scene.handle, 48 << 30, max_inflight=2)
-        tickets = []
-        t0 = time.perf_counter()
-        pending = []
-        lat = []
-        late = {}
-        for (arr, cam, W, H, K) in trace:
-            while time.perf_counter() - t0 < arr:
-                time.sleep(0.0002)
-            t = rcp.rcp_submit(srv, cam, W, H, K, d)
-            late[t] = time.perf_counter() - t0 - arr        # submitted this long after its arrival time
-            tickets.append(t)
-            pending.append(t)
-            if len(pending) > 16:                           # retire finished requests as we go
-                pending = _retire(rcp, srv, pending, late, lat)
-        while pending:
-            pending = _retire(rcp, srv, pending, late, lat)
-            time.sleep(0.0005)
-        t_srv = time.perf_counter() - t0
-        launches = rcp.rcp_server_stats(srv)["launches"]
-        rcp.rcp_server_destroy(srv)
-        # --- plain loop: one request at a time, in arrival order ---
-        lat_loop = []
-        t0 = time.perf_counter()
-        for (arr, cam, W, H, K) in trace:
-            now = time.perf_counter() - t0
-            if now < arr:
-                time.sleep(arr - now)
-            out = big[:K].view(-1)[:K * H * W * 3].view(K, H, W, 3)
-            rcp.rcp_render(scene.handle, cam, W, H, K, d, out, None, stream)
-            stream.synchronize()
-            lat_loop.append((time.perf_counter() - t0 - arr) * 1e3)
-        t_loop = time.perf_counter() - t0
-        del big
-        per_rate[str(int(rate))] = {
-            "requests": len(trace), "nominal_rays": rays, "launches": launches,
-            "server_latency_ms": _percentiles(lat), "loop_latency_ms": _percentiles(lat_loop),
-            "server_mrays_per_s": round(rays / t_srv / 1e6, 1), "loop_mrays_per_s": round(rays / t_loop / 1e6, 1),
-        }
+        per_rate[str(int(rate))] = served_rate(rcp, scene, w, rate, args.duration, 5 + ri, args.max_inflight, stream)
         log(f"rate {rate}: {per_rate[str(int(rate))]}")
     scene.close()
     top = per_rate[str(int(rates[-1]))]
@@ -445,7 +574,7 @@ def bench_served(args):
         "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"served: terrain4m ({w.scene.n_tris} triangles), Poisson arrivals at {args.rates} "
                                f"req/s for {args.duration} s each, 512^2/720p/1080p/4K, K 3..8, spline cameras",
-                   "rates": rates, "duration_s": args.duration},
+                   "rates": rates, "duration_s": args.duration, "max_inflight": args.max_inflight},
         "per_rate": per_rate,
     }
 

@@ -217,9 +217,9 @@ rcp_status rcp_render(rcp_scene* scene, const rcp_camera* base_camera, int W, in
  * rcp_render_noalloc_scratch_bytes() = 64 MiB inside the library's device
  * code, one per GPU, held until the process ends.  The launch uses as many
  * persistent workgroups as that area's overflow part holds for the scene's
- * tree (at most the occupancy limit; the count changes the speed only);
- * RCP_ERR_INVALID_ARGUMENT if it cannot hold one workgroup per compute unit
- * (a tree over about 80 levels deep).  All calls on one GPU share the area
+ * tree (at most the occupancy limit, reached by trees of up to 18 inner
+ * levels; the count changes the speed only); RCP_ERR_INVALID_ARGUMENT if it
+ * cannot hold one workgroup per compute unit (a tree over 89 levels deep).  All calls on one GPU share the area
  * and leave their contents in it: calls that overlap on one GPU (other
  * streams or threads) race and must be serialised by the caller.
  * Asynchronous on hip_stream. */
