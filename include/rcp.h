@@ -305,7 +305,8 @@ void rcp_graph_destroy(rcp_graph* graph);
  *   exit_lanes     a wave's descent to the leaves ends once no more than this
  *                  many lanes (0..64, default 16) are still looking for one
  *                  and at least as many hold one
- *   blocks_per_cu  resident workgroups per compute unit (0 = occupancy limit)
+ *   blocks_per_cu  resident workgroups of 256 threads per compute unit (0 =
+ *                  occupancy limit; a workgroup of 512 counts as two)
  *   tile_log2w     pixel tile of 64: width 2^tile_log2w (0..6)
  *   engine         how rcp_render (and rcp_render_stats, graphs, the
  *                  autotuner) run the K passes:
@@ -316,7 +317,16 @@ void rcp_graph_destroy(rcp_graph* graph);
  *                  RCP_ENGINE_PASSES one launch per pass; the pixels whose
  *                                    colour changed are compacted into a list
  *                                    in HBM for the next pass
- *                  rcp_render_pass always runs one pass launch. */
+ *                  rcp_render_pass always runs one pass launch.
+ *   top_levels     levels of the 4-wide BVH the chain engine copies into
+ *                  each workgroup's LDS and reads from there (0..4, default
+ *                  4; at most 80 nodes)
+ *   stack_entries  traversal stack entries per lane kept in LDS by the chain
+ *                  engine's colour-mode kernel (8 or 16, default 16); deeper
+ *                  entries go to a global overflow area
+ *   block_size     that kernel's workgroup size (256 or 512, default 256)
+ * The instrumented kernel and the depth and normal modes always use 16
+ * stack entries and workgroups of 256. */
 #define RCP_ENGINE_CHAIN 0
 #define RCP_ENGINE_PASSES 1
 typedef struct {
@@ -325,18 +335,30 @@ typedef struct {
     int32_t blocks_per_cu;
     int32_t tile_log2w;
     int32_t engine;
+    int32_t top_levels;
+    int32_t stack_entries;
+    int32_t block_size;
 } rcp_tuning;
 
 rcp_status rcp_get_tuning(const rcp_scene* scene, rcp_tuning* out);
 rcp_status rcp_set_tuning(rcp_scene* scene, const rcp_tuning* tuning);
 
 /* Autotuner: times rcp_render of this workload (median of `repeats` runs,
- * HIP events on hip_stream) over a grid of rcp_tuning candidates, sets the
- * fastest on the scene and returns it with its time.  The outputs receive a
- * valid render.  Synchronous. */
+ * HIP events on hip_stream) and descends over the rcp_tuning fields, one
+ * field at a time with the others fixed, twice over: refill_min, exit_lanes,
+ * blocks_per_cu, tile_log2w, engine, top_levels, stack_entries, block_size.
+ * Sets the fastest on the scene and returns it with its time.  The outputs
+ * receive a valid render.  Synchronous. */
 rcp_status rcp_autotune(rcp_scene* scene, const rcp_camera* base_camera, int W, int H, int K,
                         const rcp_displacement* disp, float* out_images, int32_t* out_ids, int repeats,
                         rcp_tuning* best, float* best_ms, void* hip_stream);
+
+/* The autotuner on a batch: times rcp_render_batch of these views over the
+ * same candidates (except the engine: batches always run the chain engine),
+ * sets the fastest on the scene and returns it.  The outputs receive a valid
+ * render.  Synchronous. */
+rcp_status rcp_autotune_batch(rcp_scene* scene, const rcp_view* views, int n_views, int repeats, rcp_tuning* best,
+                              float* best_ms, void* hip_stream);
 
 /* ---------------------------------------------------------------------- */
 /* Continuous-batching server                                              */

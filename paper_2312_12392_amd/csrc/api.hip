@@ -7,6 +7,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -318,18 +319,23 @@ rcp_status rcp_generate_rays(const rcp_camera* cam, int W, int H, const rcp_disp
     return generate_rays(c, W, H, d, prev_rgb, prev_aux, out_org, out_dir, (hipStream_t)hip_stream);
 }
 
-rcp_status rcp_render_batch(rcp_scene* scene, const rcp_view* views, int n_views, void* hip_stream) {
-    clear_error();
-    rcp_status st = check_scene(scene);
-    if (st) return st;
+namespace {
+
+rcp_status check_views(const rcp_view* views, int n_views) {
+    rcp_status st = RCP_OK;
     if (!views || n_views < 1 || n_views > 1024) FAIL("n_views = %d must be in [1, 1024] with views not NULL", n_views);
     std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     for (int i = 0; i < n_views; ++i) {
         const rcp_view& v = views[i];
         Camera c;
-        if ((st = check_camera(&v.camera, c))) { set_error("view %d: %s", i, rcp_last_error()); return st; }
-        if ((st = check_disp(&v.disp))) { set_error("view %d: %s", i, rcp_last_error()); return st; }
-        if ((st = check_size(v.W, v.H))) { set_error("view %d: %s", i, rcp_last_error()); return st; }
+        st = check_camera(&v.camera, c);
+        if (!st) st = check_disp(&v.disp);
+        if (!st) st = check_size(v.W, v.H);
+        if (st) {
+            const std::string msg = rcp_last_error();   // set_error must not read its own buffer
+            set_error("view %d: %s", i, msg.c_str());
+            return st;
+        }
         if (v.K < 1 || v.K > kMaxPasses) FAIL("view %d: K = %d must be in [1, %d]", i, v.K, kMaxPasses);
         if (!v.out_images) FAIL("view %d: out_images must not be NULL", i);
         const size_t n = (size_t)v.W * (size_t)v.H * (size_t)v.K;
@@ -339,7 +345,45 @@ rcp_status rcp_render_batch(rcp_scene* scene, const rcp_view* views, int n_views
     std::sort(spans.begin(), spans.end());
     for (size_t i = 1; i < spans.size(); ++i)
         if (spans[i].first < spans[i - 1].second) FAIL("output buffers of the batch overlap");
+    return st;
+}
+
+void tuning_out(const Tuning& t, rcp_tuning* out) {
+    out->refill_min = t.refill_min;
+    out->exit_lanes = t.exit_lanes;
+    out->blocks_per_cu = t.blocks_per_cu;
+    out->tile_log2w = t.tile_log2w;
+    out->engine = t.engine;
+    out->top_levels = t.top_levels;
+    out->stack_entries = t.stack;
+    out->block_size = t.block;
+}
+
+}  // namespace
+
+rcp_status rcp_render_batch(rcp_scene* scene, const rcp_view* views, int n_views, void* hip_stream) {
+    clear_error();
+    rcp_status st = check_scene(scene);
+    if (st) return st;
+    if ((st = check_views(views, n_views))) return st;
     return render_batch(scene, views, n_views, scene->bws, (hipStream_t)hip_stream);
+}
+
+rcp_status rcp_autotune_batch(rcp_scene* scene, const rcp_view* views, int n_views, int repeats, rcp_tuning* best,
+                              float* best_ms, void* hip_stream) {
+    clear_error();
+    rcp_status st = check_scene(scene);
+    if (st) return st;
+    if ((st = check_views(views, n_views))) return st;
+    if (!best) FAIL("best must not be NULL");
+    if (repeats < 1 || repeats > 100) FAIL("repeats must be in [1, 100]");
+    Tuning t;
+    float ms = 0.0f;
+    st = autotune_batch(scene, views, n_views, repeats, t, ms, (hipStream_t)hip_stream);
+    if (st != RCP_OK) return st;
+    tuning_out(t, best);
+    if (best_ms) *best_ms = ms;
+    return RCP_OK;
 }
 
 rcp_status rcp_graph_create(rcp_scene* scene, const rcp_camera* cam, int W, int H, int K, const rcp_displacement* disp,
@@ -432,6 +476,9 @@ rcp_status rcp_get_tuning(const rcp_scene* s, rcp_tuning* out) {
     out->blocks_per_cu = l.blocks_per_cu;
     out->tile_log2w = l.tile_log2w;
     out->engine = s->tuning.engine;
+    out->top_levels = s->tuning.top_levels;
+    out->stack_entries = s->tuning.stack;
+    out->block_size = s->tuning.block;
     return RCP_OK;
 }
 
@@ -443,6 +490,12 @@ rcp_status rcp_set_tuning(rcp_scene* s, const rcp_tuning* t) {
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) FAIL("blocks_per_cu must be in [0, 64]");
     if (t->tile_log2w < 0 || t->tile_log2w > 6) FAIL("tile_log2w must be in [0, 6]");
     if (t->engine != RCP_ENGINE_CHAIN && t->engine != RCP_ENGINE_PASSES) FAIL("unknown engine %d", t->engine);
+    if (t->top_levels < 0 || t->top_levels > kTopLevels) FAIL("top_levels must be in [0, %d]", kTopLevels);
+    if (t->stack_entries != 8 && t->stack_entries != 16) FAIL("stack_entries must be 8 or 16");
+    if (t->block_size != 256 && t->block_size != 512) FAIL("block_size must be 256 or 512");
+    s->tuning.top_levels = t->top_levels;
+    s->tuning.stack = t->stack_entries;
+    s->tuning.block = t->block_size;
     s->tuning.refill_min = t->refill_min;
     s->tuning.exit_lanes = t->exit_lanes;
     s->tuning.blocks_per_cu = t->blocks_per_cu;
@@ -469,11 +522,7 @@ rcp_status rcp_autotune(rcp_scene* scene, const rcp_camera* cam, int W, int H, i
     st = autotune(scene, c, W, H, K, Disp{disp->lambda_eye, disp->lambda_dir, disp->z0, disp->mode}, out_images,
                   out_ids, repeats, t, ms, (hipStream_t)hip_stream);
     if (st != RCP_OK) return st;
-    best->refill_min = t.refill_min;
-    best->exit_lanes = t.exit_lanes;
-    best->blocks_per_cu = t.blocks_per_cu;
-    best->tile_log2w = t.tile_log2w;
-    best->engine = t.engine;
+    tuning_out(t, best);
     if (best_ms) *best_ms = ms;
     return RCP_OK;
 }

@@ -1432,7 +1432,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                 begin = end;
                 end = next;
                 ++levels;
-                if (levels == (uint32_t)kTopLevels) top_count = begin;   // slots of levels < kTopLevels
+                if (levels <= (uint32_t)kTopLevels) s->top_nodes[levels] = begin;   // nodes of levels < `levels`
             }
             if (end != n_nodes) {
                 set_error("optimal collapse emitted %u of %u wide nodes", end, n_nodes);
@@ -1488,12 +1488,13 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                 begin = end;
                 end = next;
                 ++levels;
-                if (levels == (uint32_t)kTopLevels) top_count = begin;   // slots of levels < kTopLevels
+                if (levels <= (uint32_t)kTopLevels) s->top_nodes[levels] = begin;   // nodes of levels < `levels`
             }
             n_nodes = end;
         }
-        if (levels < (uint32_t)kTopLevels) top_count = n_nodes;
-        if (top_count > kMaxStagedNodes) top_count = kMaxStagedNodes;
+        // a tree of fewer levels is staged whole
+        for (uint32_t l = levels + 1u; l <= (uint32_t)kTopLevels; ++l) s->top_nodes[l] = n_nodes;
+        top_count = std::min(s->top_nodes[kTopLevels], kMaxStagedNodes);
         if (n_nodes > kMaxNodes) {
             set_error("the scene needs %u BVH nodes, more than the %u a scene can hold", n_nodes, kMaxNodes);
             return RCP_ERR_INVALID_ARGUMENT;

@@ -75,7 +75,7 @@ struct ChainArgs {
 // vector-memory path, which the traversal keeps busy.
 typedef __attribute__((address_space(4))) ViewDev ConstView;
 
-template <bool STATS, int MODE, bool ONE>
+template <bool STATS, int MODE, bool ONE, int STACK, int BLOCK>
 __device__ inline void chain_body(const ChainArgs& a) {
     constexpr bool AUX = MODE != RCP_MODE_COLOR;
     // LDS: the staged top levels (128-byte nodes, as in HBM, so the same
@@ -87,21 +87,21 @@ __device__ inline void chain_body(const ChainArgs& a) {
     if (STATS) lds += sizeof(unsigned long long) * kStatCols * kMaxPasses;
     uint32_t* vbegin = (uint32_t*)lds;                                    // n_views + 1
     lds += sizeof(uint32_t) * (size_t)((a.n_views + 4) & ~3);
-    int32_t* stack_area = (int32_t*)lds;                                  // kStack * kBlock
+    int32_t* stack_area = (int32_t*)lds;                                  // STACK * BLOCK
 
     const ConstView* views = (const ConstView*)a.views;
     if (!ONE)
-        for (int i = threadIdx.x; i <= a.n_views; i += kBlock) vbegin[i] = a.begin[i];
-    for (uint32_t i = threadIdx.x; i < 8u * a.sc.top_count; i += kBlock)
+        for (int i = threadIdx.x; i <= a.n_views; i += BLOCK) vbegin[i] = a.begin[i];
+    for (uint32_t i = threadIdx.x; i < 8u * a.sc.top_count; i += BLOCK)
         if ((i & 7u) != 7u) top[i] = a.sc.nodes[i];   // the zero padding is never read
     if (STATS)
-        for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += kBlock) lstats[i] = 0ull;
+        for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += BLOCK) lstats[i] = 0ull;
     __syncthreads();
 
     int v = 0;                 // the lane's view
 
-    const uint32_t gtid = blockIdx.x * kBlock + threadIdx.x;
-    Stack st;
+    const uint32_t gtid = blockIdx.x * BLOCK + threadIdx.x;
+    StackT<STACK, BLOCK> st;
     st.lds = stack_area + threadIdx.x;
     st.spill = a.spill + gtid;
     st.stride = a.spill_stride;
@@ -268,7 +268,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
 
     if (STATS) {
         __syncthreads();
-        for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += kBlock)
+        for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += BLOCK)
             if (lstats[i]) atomicAdd(&a.stats[i], lstats[i]);
     }
 }
@@ -276,15 +276,18 @@ __device__ inline void chain_body(const ChainArgs& a) {
 // Colour mode, the default: asking for 6 waves per SIMD (at most 80 VGPRs)
 // was measured faster than the 5 the compiler picks alone; 7 and 8 spill and
 // are slower.  The depth and normal modes keep the compiler's choice (6
-// spills there and measured 1% slower).
-template <bool STATS, bool ONE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_chain(ChainArgs a) {
-    chain_body<STATS, RCP_MODE_COLOR, ONE>(a);
+// spills there and measured 1% slower).  STACK (LDS stack entries per lane)
+// and BLOCK (workgroup size) are launch parameters the autotuner chooses
+// among for the colour mode's timed kernel; the instrumented kernel and the
+// depth and normal modes use kStack and kBlock.
+template <bool STATS, bool ONE, int STACK, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_chain(ChainArgs a) {
+    chain_body<STATS, RCP_MODE_COLOR, ONE, STACK, BLOCK>(a);
 }
 
 template <bool STATS, int MODE, bool ONE>
 __global__ __launch_bounds__(kBlock) void k_chain_aux(ChainArgs a) {
-    chain_body<STATS, MODE, ONE>(a);
+    chain_body<STATS, MODE, ONE, kStack, kBlock>(a);
 }
 
 // Zero the work counters (kFetchParts per launch) and the stats.
@@ -308,30 +311,57 @@ __global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint3
         for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
 }
 
+// A chain kernel instantiation with its workgroup size and stack depth.
+struct ChainKernel {
+    const void* fn;
+    int block;
+    int stack;
+};
+
+template <bool STATS, bool ONE>
+ChainKernel colour_kernel(int stack, int block) {
+    if constexpr (!STATS) {
+        if (stack == 8 && block == 512) return {(const void*)k_chain<false, ONE, 8, 512>, 512, 8};
+        if (stack == 8) return {(const void*)k_chain<false, ONE, 8, kBlock>, kBlock, 8};
+        if (block == 512) return {(const void*)k_chain<false, ONE, kStack, 512>, 512, kStack};
+    }
+    return {(const void*)k_chain<STATS, ONE, kStack, kBlock>, kBlock, kStack};
+}
+
+template <bool STATS, bool ONE>
+ChainKernel chain_kernel1(int mode, const Launch& lp) {
+    switch (mode) {
+        case RCP_MODE_DEPTH: return {(const void*)k_chain_aux<STATS, RCP_MODE_DEPTH, ONE>, kBlock, kStack};
+        case RCP_MODE_NORMAL: return {(const void*)k_chain_aux<STATS, RCP_MODE_NORMAL, ONE>, kBlock, kStack};
+        default: return colour_kernel<STATS, ONE>(lp.stack, lp.block);
+    }
+}
+
+// The kernel of a launch over n_views views in `mode` (the single-view
+// kernels when n_views == 1).
+ChainKernel chain_kernel(bool stats, int n_views, int mode, const Launch& lp) {
+    if (stats) return n_views == 1 ? chain_kernel1<true, true>(mode, lp) : chain_kernel1<true, false>(mode, lp);
+    return n_views == 1 ? chain_kernel1<false, true>(mode, lp) : chain_kernel1<false, false>(mode, lp);
+}
+
 // LDS of a workgroup: the staged top levels, the stack area and the view
 // starts (and the stats).
-size_t chain_smem(const Launch& lp, bool stats, int n_views) {
-    size_t b = kNodeBytes * (size_t)lp.top_count + sizeof(int32_t) * kStack * kBlock +
+size_t chain_smem(const Launch& lp, const ChainKernel& k, bool stats, int n_views) {
+    size_t b = kNodeBytes * (size_t)lp.top_count + sizeof(int32_t) * (size_t)k.stack * (size_t)k.block +
                sizeof(uint32_t) * (size_t)((n_views + 4) & ~3);
     if (stats) b += sizeof(unsigned long long) * kStatCols * kMaxPasses;
     return b;
 }
 
-template <bool STATS, int MODE, bool ONE>
-const void* chain_kernel() {
-    if constexpr (MODE == RCP_MODE_COLOR) return (const void*)k_chain<STATS, ONE>;
-    else return (const void*)k_chain_aux<STATS, MODE, ONE>;
-}
-
 // Resident workgroups per CU and CU count of a kernel at an LDS size, on the
 // current device.  The runtime's answers are cached: they cannot change in a
 // process, and asking costs more than a launch.
-rcp_status occupancy(const void* kernel, size_t smem, int& per_cu, int& cus) {
+rcp_status occupancy(const ChainKernel& k, size_t smem, int& per_cu, int& cus) {
     static std::mutex mu;
     static std::map<std::tuple<const void*, size_t, int>, std::pair<int, int>> cache;
     int dev = 0;
     RCP_HIP(hipGetDevice(&dev));
-    const auto key = std::make_tuple(kernel, smem, dev);
+    const auto key = std::make_tuple(k.fn, smem, dev);
     {
         std::lock_guard<std::mutex> lk(mu);
         const auto it = cache.find(key);
@@ -341,67 +371,46 @@ rcp_status occupancy(const void* kernel, size_t smem, int& per_cu, int& cus) {
             return RCP_OK;
         }
     }
-    RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, smem));
+    RCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k.fn, k.block, smem));
     RCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     std::lock_guard<std::mutex> lk(mu);
     cache[key] = std::make_pair(per_cu, cus);
     return RCP_OK;
 }
 
-template <bool STATS, int MODE, bool ONE>
-rcp_status chain_grid(const Launch& lp, int n_views, int& blocks, size_t& smem) {
-    smem = chain_smem(lp, STATS, n_views);
+// Kernel, grid and LDS size of a launch over n_views views in `mode`.
+struct ChainGrid {
+    ChainKernel k;
+    int blocks = 0;
+    size_t smem = 0;
+    uint32_t threads() const { return (uint32_t)blocks * (uint32_t)k.block; }
+};
+
+rcp_status chain_grid(const Launch& lp, bool stats, int n_views, int mode, ChainGrid& g) {
+    g.k = chain_kernel(stats, n_views, mode, lp);
+    g.smem = chain_smem(lp, g.k, stats, n_views);
     int per_cu = 0, cus = 0;
-    const rcp_status st = occupancy(chain_kernel<STATS, MODE, ONE>(), smem, per_cu, cus);
+    const rcp_status st = occupancy(g.k, g.smem, per_cu, cus);
     if (st != RCP_OK) return st;
     if (per_cu < 1) per_cu = 1;
-    if (lp.blocks_per_cu > 0 && lp.blocks_per_cu < per_cu) per_cu = lp.blocks_per_cu;
-    blocks = per_cu * cus;
+    // blocks_per_cu counts workgroups of kBlock threads; a larger workgroup
+    // counts as several
+    if (lp.blocks_per_cu > 0) {
+        const int cap = std::max(1, lp.blocks_per_cu * kBlock / g.k.block);
+        if (cap < per_cu) per_cu = cap;
+    }
+    g.blocks = per_cu * cus;
     return RCP_OK;
 }
 
-template <bool STATS, bool ONE>
-rcp_status chain_grid_mode1(const Launch& lp, int n_views, int mode, int& blocks, size_t& smem) {
-    switch (mode) {
-        case RCP_MODE_DEPTH: return chain_grid<STATS, RCP_MODE_DEPTH, ONE>(lp, n_views, blocks, smem);
-        case RCP_MODE_NORMAL: return chain_grid<STATS, RCP_MODE_NORMAL, ONE>(lp, n_views, blocks, smem);
-        default: return chain_grid<STATS, RCP_MODE_COLOR, ONE>(lp, n_views, blocks, smem);
-    }
+rcp_status launch_chain(const ChainGrid& g, hipStream_t stream, ChainArgs a) {
+    void* args[] = {(void*)&a};
+    RCP_HIP(hipLaunchKernel(g.k.fn, dim3((unsigned)g.blocks), dim3((unsigned)g.k.block), args, g.smem, stream));
+    return RCP_OK;
 }
 
-// Grid of a launch over n_views views in `mode` (the single-view kernels
-// when n_views == 1).
-template <bool STATS>
-rcp_status chain_grid_mode(const Launch& lp, int n_views, int mode, int& blocks, size_t& smem) {
-    return n_views == 1 ? chain_grid_mode1<STATS, true>(lp, n_views, mode, blocks, smem)
-                        : chain_grid_mode1<STATS, false>(lp, n_views, mode, blocks, smem);
-}
-
-template <bool STATS, bool ONE>
-void launch_chain_mode1(int mode, int blocks, size_t smem, hipStream_t stream, const ChainArgs& a) {
-    switch (mode) {
-        case RCP_MODE_DEPTH:
-            hipLaunchKernelGGL((k_chain_aux<STATS, RCP_MODE_DEPTH, ONE>), dim3(blocks), dim3(kBlock), smem, stream,
-                               a);
-            break;
-        case RCP_MODE_NORMAL:
-            hipLaunchKernelGGL((k_chain_aux<STATS, RCP_MODE_NORMAL, ONE>), dim3(blocks), dim3(kBlock), smem, stream,
-                               a);
-            break;
-        default:
-            hipLaunchKernelGGL((k_chain<STATS, ONE>), dim3(blocks), dim3(kBlock), smem, stream, a);
-            break;
-    }
-}
-
-template <bool STATS>
-void launch_chain_mode(int mode, int blocks, size_t smem, hipStream_t stream, const ChainArgs& a) {
-    if (a.n_views == 1) launch_chain_mode1<STATS, true>(mode, blocks, smem, stream, a);
-    else launch_chain_mode1<STATS, false>(mode, blocks, smem, stream, a);
-}
-
-size_t spill_depth_of(const rcp_scene* s) {
-    return spill_per_thread(s->dev);
+size_t spill_depth_of(const rcp_scene* s, const ChainKernel& k) {
+    return spill_per_thread(s->dev, k.stack);
 }
 
 ViewDev view_of(const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids, int tile_log2w) {
@@ -426,26 +435,25 @@ uint64_t view_items(const ViewDev& v) {
 
 rcp_status prepare_chain(rcp_scene* s, Workspace& ws, int mode, hipStream_t stream) {
     const Launch lp = launch_params(s);
-    int b1 = 0, b2 = 0;
-    size_t m1 = 0, m2 = 0;
-    rcp_status st = chain_grid_mode<false>(lp, 1, mode, b1, m1);
-    if (st == RCP_OK) st = chain_grid_mode<true>(lp, 1, mode, b2, m2);
+    ChainGrid g1, g2;
+    rcp_status st = chain_grid(lp, false, 1, mode, g1);
+    if (st == RCP_OK) st = chain_grid(lp, true, 1, mode, g2);
     if (st != RCP_OK) return st;
-    const uint32_t threads = (uint32_t)std::max(b1, b2) * kBlock;
-    return ensure_workspace(s, ws, 0, 0, spill_depth_of(s) * threads, stream);
+    const size_t need = std::max(spill_depth_of(s, g1.k) * g1.threads(), spill_depth_of(s, g2.k) * g2.threads());
+    return ensure_workspace(s, ws, 0, 0, need, stream);
 }
 
 namespace {
 
 // Enqueue the setup kernel and the chain launch of one view on a workspace
-// that already fits `blocks` workgroups.
-rcp_status launch_one_view(rcp_scene* s, Workspace& w, const Launch& lp, int blocks, size_t smem, const Camera& cam,
+// that already fits the grid.
+rcp_status launch_one_view(rcp_scene* s, Workspace& w, const Launch& lp, const ChainGrid& g, const Camera& cam,
                            int W, int H, int K, const Disp& disp, float* out_images, int32_t* out_ids, bool stats,
                            hipStream_t stream) {
-    const uint32_t threads = (uint32_t)blocks * kBlock;
     const ViewDev view = view_of(cam, W, H, K, disp, out_images, out_ids, lp.tile_log2w);
     ChainArgs a{};
     a.sc = s->dev;
+    a.sc.top_count = lp.top_count;
     a.views = (const ViewDev*)w.view;
     a.begin = (const uint32_t*)((char*)w.view + ((sizeof(ViewDev) + 63) & ~(size_t)63));
     a.n_views = 1;
@@ -454,15 +462,12 @@ rcp_status launch_one_view(rcp_scene* s, Workspace& w, const Launch& lp, int blo
     a.refill_min = lp.refill_min;
     a.exit_lanes = (uint32_t)lp.exit_lanes;
     a.spill = w.spill;
-    a.spill_stride = threads;
+    a.spill_stride = g.threads();
     a.stats = stats ? w.stats : nullptr;
     hipLaunchKernelGGL(k_setup_single, dim3(1), dim3(256), 0, stream, view, (ViewDev*)a.views, (uint32_t*)a.begin,
                        a.n_items, w.counters, a.stats);
     RCP_CHECK_LAUNCH();
-    if (stats) launch_chain_mode<true>(disp.mode, blocks, smem, stream, a);
-    else launch_chain_mode<false>(disp.mode, blocks, smem, stream, a);
-    RCP_CHECK_LAUNCH();
-    return RCP_OK;
+    return launch_chain(g, stream, a);
 }
 
 }  // namespace
@@ -471,14 +476,12 @@ rcp_status render_chain(rcp_scene* s, Workspace& w, const Camera& cam, int W, in
                         float* out_images, int32_t* out_ids, unsigned long long* host_counts, hipStream_t stream) {
     const bool stats = host_counts != nullptr;
     const Launch lp = launch_params(s);
-    int blocks = 0;
-    size_t smem = 0;
-    rcp_status st = stats ? chain_grid_mode<true>(lp, 1, disp.mode, blocks, smem)
-                          : chain_grid_mode<false>(lp, 1, disp.mode, blocks, smem);
+    ChainGrid g;
+    rcp_status st = chain_grid(lp, stats, 1, disp.mode, g);
     if (st != RCP_OK) return st;
-    st = ensure_workspace(s, w, 0, 0, spill_depth_of(s) * (size_t)blocks * kBlock, stream);
+    st = ensure_workspace(s, w, 0, 0, spill_depth_of(s, g.k) * g.threads(), stream);
     if (st != RCP_OK) return st;
-    st = launch_one_view(s, w, lp, blocks, smem, cam, W, H, K, disp, out_images, out_ids, stats, stream);
+    st = launch_one_view(s, w, lp, g, cam, W, H, K, disp, out_images, out_ids, stats, stream);
     if (st != RCP_OK) return st;
     if (stats) {
         RCP_HIP(hipMemcpyAsync(host_counts, w.stats, sizeof(unsigned long long) * kStatCols * K,
@@ -492,16 +495,15 @@ rcp_status render_chain(rcp_scene* s, Workspace& w, const Camera& cam, int W, in
 rcp_status render_chain_fixed(rcp_scene* s, Workspace& w, const Camera& cam, int W, int H, int K,
                               const Disp& disp, float* out_images, int32_t* out_ids, hipStream_t stream) {
     const Launch lp = launch_params(s);
-    int blocks = 0;
-    size_t smem = 0;
-    rcp_status st = chain_grid_mode<false>(lp, 1, disp.mode, blocks, smem);
+    ChainGrid g;
+    rcp_status st = chain_grid(lp, false, 1, disp.mode, g);
     if (st != RCP_OK) return st;
     int dev = 0, cus = 0;
     RCP_HIP(hipGetDevice(&dev));
     RCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     // as many workgroups as the overflow area holds (the grid size changes
     // the speed only), but at least one per compute unit
-    const size_t per_block = spill_depth_of(s) * kBlock;
+    const size_t per_block = spill_depth_of(s, g.k) * (size_t)g.k.block;
     const size_t fit = w.spill_cap / per_block;
     if (fit < (size_t)cus) {
         set_error("the scene's traversal stack needs %zu bytes of overflow area per compute unit's workgroup; "
@@ -509,8 +511,8 @@ rcp_status render_chain_fixed(rcp_scene* s, Workspace& w, const Camera& cam, int
                   per_block * sizeof(int32_t), w.spill_cap * sizeof(int32_t), cus);
         return RCP_ERR_INVALID_ARGUMENT;
     }
-    if ((size_t)blocks > fit) blocks = (int)fit;
-    return launch_one_view(s, w, lp, blocks, smem, cam, W, H, K, disp, out_images, out_ids, false, stream);
+    if ((size_t)g.blocks > fit) g.blocks = (int)fit;
+    return launch_one_view(s, w, lp, g, cam, W, H, K, disp, out_images, out_ids, false, stream);
 }
 
 namespace {
@@ -537,14 +539,13 @@ size_t view_table_bytes(size_t n_views) {
 rcp_status prepare_batch_workspace(rcp_scene* s, BatchWorkspace& ws, int n_views, bool with_staging,
                                    hipStream_t stream) {
     const Launch lp = launch_params(s);
-    int max_blocks = 0;
+    size_t spill_need = 0;
     for (int mode = 0; mode < 3; ++mode)
         for (int nv : {1, 2}) {
-            int b = 0;
-            size_t m = 0;
-            rcp_status st = chain_grid_mode<false>(lp, nv, mode, b, m);
+            ChainGrid g;
+            rcp_status st = chain_grid(lp, false, nv, mode, g);
             if (st != RCP_OK) return st;
-            max_blocks = std::max(max_blocks, b);
+            spill_need = std::max(spill_need, spill_depth_of(s, g.k) * g.threads());
         }
     rcp_status st = RCP_OK;
     if ((size_t)n_views > ws.view_cap || !ws.views) {
@@ -557,7 +558,7 @@ rcp_status prepare_batch_workspace(rcp_scene* s, BatchWorkspace& ws, int n_views
     size_t fetch_cap = ws.fetch ? kFetchWords * 3 : 0;
     if (st == RCP_OK) st = grow(&ws.fetch, fetch_cap, kFetchWords * 3, sizeof(uint32_t), stream);
     if (st == RCP_OK)
-        st = grow(&ws.spill, ws.spill_cap, spill_depth_of(s) * (size_t)max_blocks * kBlock, sizeof(int32_t), stream);
+        st = grow(&ws.spill, ws.spill_cap, spill_need, sizeof(int32_t), stream);
     if (st == RCP_OK && with_staging && !ws.staging) {
         if (alloc_hook_fails()) {
             set_error("pinned host allocation failed (test hook)");
@@ -613,15 +614,13 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
     hb[bofs++] = (uint32_t)items;
     groups.back().items = (uint32_t)items;
 
-    int max_blocks = 0;
-    std::vector<int> gblocks(groups.size());
-    std::vector<size_t> gsmem(groups.size());
+    size_t spill_need = 0;
+    std::vector<ChainGrid> grids(groups.size());
     for (size_t g = 0; g < groups.size(); ++g) {
-        rcp_status st = chain_grid_mode<false>(lp, groups[g].count, groups[g].mode, gblocks[g], gsmem[g]);
+        rcp_status st = chain_grid(lp, false, groups[g].count, groups[g].mode, grids[g]);
         if (st != RCP_OK) return st;
-        max_blocks = std::max(max_blocks, gblocks[g]);
+        spill_need = std::max(spill_need, spill_depth_of(s, grids[g].k) * grids[g].threads());
     }
-    const size_t spill_need = spill_depth_of(s) * (size_t)max_blocks * kBlock;
 
     // buffers grow in stream order (a server's slots are sized at creation
     // and never grow here)
@@ -675,6 +674,7 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
     for (size_t g = 0; g < groups.size(); ++g) {
         ChainArgs a{};
         a.sc = s->dev;
+        a.sc.top_count = lp.top_count;
         a.views = d_views + groups[g].first;
         a.begin = d_begin + groups[g].bofs;
         a.n_views = groups[g].count;
@@ -683,9 +683,9 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
         a.refill_min = lp.refill_min;
         a.exit_lanes = (uint32_t)lp.exit_lanes;
         a.spill = ws.spill;
-        a.spill_stride = (uint32_t)gblocks[g] * kBlock;
-        launch_chain_mode<false>(groups[g].mode, gblocks[g], gsmem[g], stream, a);
-        RCP_CHECK_LAUNCH();
+        a.spill_stride = grids[g].threads();
+        rcp_status st2 = launch_chain(grids[g], stream, a);
+        if (st2 != RCP_OK) return st2;
     }
     return RCP_OK;
 }

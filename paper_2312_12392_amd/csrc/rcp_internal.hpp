@@ -181,6 +181,9 @@ struct Tuning {
     int blocks_per_cu = 0;        // 0: occupancy limit
     int tile_log2w = 3;           // 8x8 tiles
     int engine = RCP_ENGINE_CHAIN;
+    int top_levels = kTopLevels;  // levels of the 4-wide tree the chain engine reads from LDS (0..kTopLevels)
+    int stack = 16;               // LDS stack entries per lane of the chain engine's colour kernel (8 or 16)
+    int block = 256;              // its workgroup size (256 or 512)
 };
 
 }  // namespace rcp
@@ -193,6 +196,7 @@ struct rcp_scene {
     float4* shade = nullptr;
     float4* normals = nullptr;
     rcp_scene_stats stats{};
+    uint32_t top_nodes[rcp::kTopLevels + 1] = {};   // nodes in the tree's first L levels, L = 0..kTopLevels
     uint32_t* err_host = nullptr;   // pinned, device-mapped error flag (DevScene::err_flag)
     rcp::Workspace ws;
     rcp::BatchWorkspace bws;
@@ -266,6 +270,8 @@ struct Launch {
     int exit_lanes;
     int blocks_per_cu;
     int tile_log2w;
+    int stack;               // chain engine, colour mode: LDS stack entries per lane
+    int block;               // and workgroup size
 };
 Launch launch_params(const rcp_scene* s);
 
@@ -286,6 +292,8 @@ rcp_status graph_capture(rcp_graph* g);
 void graph_free(rcp_graph* g);
 rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids,
                     int repeats, Tuning& best, float& best_ms, hipStream_t stream);
+rcp_status autotune_batch(rcp_scene* s, const rcp_view* views, int n_views, int repeats, Tuning& best,
+                          float& best_ms, hipStream_t stream);
 
 size_t request_bytes(const rcp_request& r);
 rcp_status server_create(rcp_scene* scene, size_t pool_bytes, int max_inflight, int queue_capacity, rcp_server** out);

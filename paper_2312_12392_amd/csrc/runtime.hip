@@ -67,16 +67,16 @@ void graph_free(rcp_graph* g) {
 
 namespace {
 
-rcp_status time_render(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids,
-                       int repeats, hipStream_t stream, hipEvent_t e0, hipEvent_t e1, float& ms) {
-    rcp_status st = prepare_render(s, s->ws, W, H, K, d.mode, stream);
-    if (st != RCP_OK) return st;
-    st = render(s, s->ws, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);   // warm-up
+// Median of `repeats` timed runs of one workload (after one untimed run,
+// which also sizes any buffer it needs).
+template <class Run>
+rcp_status time_runs(Run&& run, int repeats, hipStream_t stream, hipEvent_t e0, hipEvent_t e1, float& ms) {
+    rcp_status st = run();
     if (st != RCP_OK) return st;
     std::vector<float> t;
     for (int r = 0; r < repeats; ++r) {
         RCP_HIP(hipEventRecord(e0, stream));
-        st = render(s, s->ws, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);
+        st = run();
         if (st != RCP_OK) return st;
         RCP_HIP(hipEventRecord(e1, stream));
         RCP_HIP(hipEventSynchronize(e1));
@@ -89,12 +89,15 @@ rcp_status time_render(rcp_scene* s, const Camera& cam, int W, int H, int K, con
     return RCP_OK;
 }
 
-}  // namespace
-
 // Coordinate descent over the launch parameters: each round tries every
 // candidate of one parameter with the others fixed and keeps the fastest.
-rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids,
-                    int repeats, Tuning& best, float& best_ms, hipStream_t stream) {
+// The parameters: refill threshold, early-exit lanes, workgroups per CU,
+// tile width, engine (single renders only; batches always run the chain
+// engine), LDS-staged tree levels, LDS stack depth and workgroup size (the
+// last two select among instantiations of the chain kernel).
+template <class Run>
+rcp_status descend(rcp_scene* s, Run&& run, bool tune_engine, int repeats, Tuning& best, float& best_ms,
+                   hipStream_t stream) {
     hipEvent_t e0, e1;
     RCP_HIP(hipEventCreate(&e0));
     RCP_HIP(hipEventCreate(&e1));
@@ -104,31 +107,41 @@ rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const 
     const std::vector<int> blocks = {0, 4, 3, 2};
     const std::vector<int> tiles = {3, 4, 2, 5};
     const std::vector<int> engines = {RCP_ENGINE_CHAIN, RCP_ENGINE_PASSES};
+    const std::vector<int> top_levels = {4, 3, 2, 0};
+    const std::vector<int> stacks = {16, 8};
+    const std::vector<int> blocks_sz = {256, 512};
     Tuning cur = s->tuning;
     if (cur.refill_min <= 0) cur.refill_min = kDefaultRefill;
     s->tuning = cur;
     float cur_ms = 0.0f;
-    rcp_status st = time_render(s, cam, W, H, K, d, out, ids, repeats, stream, e0, e1, cur_ms);
+    rcp_status st = time_runs(run, repeats, stream, e0, e1, cur_ms);
     if (st != RCP_OK) return st;
     for (int round = 0; round < 2; ++round) {
-        for (int param = 0; param < 5; ++param) {
+        for (int param = 0; param < 8; ++param) {
+            if (param == 4 && !tune_engine) continue;
             const std::vector<int>& cands = param == 0   ? refill
                                             : param == 1 ? exits
                                             : param == 2 ? blocks
                                             : param == 3 ? tiles
-                                                         : engines;
+                                            : param == 4 ? engines
+                                            : param == 5 ? top_levels
+                                            : param == 6 ? stacks
+                                                         : blocks_sz;
             for (int c : cands) {
                 Tuning t = cur;
                 int& field = param == 0   ? t.refill_min
                              : param == 1 ? t.exit_lanes
                              : param == 2 ? t.blocks_per_cu
                              : param == 3 ? t.tile_log2w
-                                          : t.engine;
+                             : param == 4 ? t.engine
+                             : param == 5 ? t.top_levels
+                             : param == 6 ? t.stack
+                                          : t.block;
                 if (field == c) continue;
                 field = c;
                 s->tuning = t;
                 float ms = 0.0f;
-                st = time_render(s, cam, W, H, K, d, out, ids, repeats, stream, e0, e1, ms);
+                st = time_runs(run, repeats, stream, e0, e1, ms);
                 if (st != RCP_OK) { s->tuning = cur; return st; }
                 if (ms < cur_ms) { cur = t; cur_ms = ms; }
             }
@@ -138,11 +151,27 @@ rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const 
     best = cur;
     best_ms = cur_ms;
     s->tuning = cur;
-    // leave a render made with the chosen parameters in the outputs
-    st = render(s, s->ws, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);
+    // leave a result made with the chosen parameters in the outputs
+    st = run();
     if (st != RCP_OK) return st;
     RCP_HIP(hipStreamSynchronize(stream));
     return take_device_error(s);
+}
+
+}  // namespace
+
+rcp_status autotune(rcp_scene* s, const Camera& cam, int W, int H, int K, const Disp& d, float* out, int32_t* ids,
+                    int repeats, Tuning& best, float& best_ms, hipStream_t stream) {
+    auto run = [&]() -> rcp_status {
+        return render(s, s->ws, cam, W, H, K, d, out, ids, nullptr, nullptr, nullptr, nullptr, stream);
+    };
+    return descend(s, run, true, repeats, best, best_ms, stream);
+}
+
+rcp_status autotune_batch(rcp_scene* s, const rcp_view* views, int n_views, int repeats, Tuning& best,
+                          float& best_ms, hipStream_t stream) {
+    auto run = [&]() -> rcp_status { return render_batch(s, views, n_views, s->bws, stream); };
+    return descend(s, run, false, repeats, best, best_ms, stream);
 }
 
 }  // namespace rcp

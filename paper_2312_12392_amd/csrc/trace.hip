@@ -415,9 +415,13 @@ Launch launch_params(const rcp_scene* s) {
     Launch l;
     l.refill_min = s->tuning.refill_min > 0 ? s->tuning.refill_min : kDefaultRefill;
     l.exit_lanes = s->tuning.exit_lanes;
-    l.top_count = s->dev.top_count;
+    const int lv = s->tuning.top_levels < 0 ? 0 : (s->tuning.top_levels > kTopLevels ? kTopLevels
+                                                                                    : s->tuning.top_levels);
+    l.top_count = s->top_nodes[lv] < kMaxStagedNodes ? s->top_nodes[lv] : kMaxStagedNodes;
     l.blocks_per_cu = s->tuning.blocks_per_cu;
     l.tile_log2w = s->tuning.tile_log2w;
+    l.stack = s->tuning.stack;
+    l.block = s->tuning.block;
     return l;
 }
 

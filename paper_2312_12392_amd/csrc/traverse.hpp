@@ -20,10 +20,11 @@ constexpr int kBlock = 256;
 constexpr int kStack = 16;                       // per-lane LDS stack entries (a power of two)
 constexpr float kSlack = 1.0f + 1.0f / 65536.0f; // relative widening of the best-hit bound
 
-// Global overflow entries per thread: the LDS ring holds kStack entries, and
-// a 4-wide visit keeps room for three pushes in it.
-inline size_t spill_per_thread(const DevScene& d) {
-    return d.stack_bound + 3u > (uint32_t)kStack ? d.stack_bound + 3u - (uint32_t)kStack : 1u;
+// Global overflow entries per thread: the LDS ring holds `stack` entries
+// (kStack unless the chain engine is tuned otherwise), and a 4-wide visit
+// keeps room for three pushes in it.
+inline size_t spill_per_thread(const DevScene& d, int stack = kStack) {
+    return d.stack_bound + 3u > (uint32_t)stack ? d.stack_bound + 3u - (uint32_t)stack : 1u;
 }
 
 
@@ -268,25 +269,25 @@ struct Hit {
     bool front;
 };
 
-// Per-lane traversal stack: the newest kStack entries live in LDS (column
-// `lane_col` of the block's stack area), older ones in the lane's global
-// overflow area.
-static_assert((kStack & (kStack - 1)) == 0, "the LDS stack ring is indexed with a mask");
-
-struct Stack {
-    int32_t* lds;       // &stack_area[tid]; entry e at lds[(e % kStack) * kBlock]
+// Per-lane traversal stack: the newest STACK entries live in LDS (column
+// threadIdx.x of the workgroup's STACK x BLOCK stack area), older ones in the
+// lane's global overflow area.
+template <int STACK, int BLOCK>
+struct StackT {
+    static_assert((STACK & (STACK - 1)) == 0 && STACK >= 4, "the LDS stack ring is indexed with a mask");
+    int32_t* lds;       // &stack_area[tid]; entry e at lds[(e % STACK) * BLOCK]
     int32_t* spill;     // &spill[gtid]; entry e at spill[e * stride]
     uint32_t stride;
     uint32_t sp, lo;    // entries [0, lo) spilled, [lo, sp) in LDS
 
     __device__ inline LdsI32* ring(uint32_t e) const {
-        return (LdsI32*)lds + (e & (uint32_t)(kStack - 1)) * kBlock;
+        return (LdsI32*)lds + (e & (uint32_t)(STACK - 1)) * BLOCK;
     }
     // Push np (0..3) entries, e0 deepest, with one check for room: three ring
     // slots are written whatever np is (those above the new top are unused).
     // n_spill counts the entries moved to the global area.
     __device__ inline void push_up_to_3(int32_t e0, int32_t e1, int32_t e2, uint32_t np, uint32_t& n_spill) {
-        while (sp + 3u - lo > (uint32_t)kStack) {
+        while (sp + 3u - lo > (uint32_t)STACK) {
             spill[(size_t)lo * stride] = *ring(lo);
             ++lo;
             ++n_spill;
@@ -330,6 +331,8 @@ struct Stack {
 // The traversal state of one ray lives in registers (plus its stack), so a
 // lane can advance its ray one step at a time and take a new ray as soon as
 // the current one is finished.
+using Stack = StackT<kStack, kBlock>;   // the stack of the per-pass and single-step kernels
+
 struct Trav {
     RayW rw;
     // Box test constants per axis, in the order kx, ky, kz of the watertight
@@ -348,6 +351,7 @@ struct Trav {
     Hit h;
 };
 
+template <class Stack>
 __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3], const float d[3], Stack& st) {
     const int kz = dominant_axis(d);
     tv.rw = ray_setup(o, d, kz, sc.n_tris);
@@ -420,7 +424,7 @@ typedef __attribute__((address_space(3))) V4 LdsV4;
 
 __device__ inline float4 f4(V4 v) { return make_float4(v.x, v.y, v.z, v.w); }
 
-template <bool STATS>
+template <bool STATS, class Stack>
 __device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& sc, const float4* top, Stack& st,
                                        TravCount& cnt) {
     // byte offsets of the entry and exit planes of the three axes (the
@@ -529,7 +533,7 @@ __device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, Tr
 // threshold and 5% faster at the new default of 16.)
 constexpr int kMaxDescent = 256;   // node visits of one step (the step ends, the ray goes on)
 
-template <bool STATS>
+template <bool STATS, class Stack>
 __device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* top, Stack& st, uint32_t exit_lanes,
                                  TravCount& cnt) {
     if (--tv.budget == 0u) {

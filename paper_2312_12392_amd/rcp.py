@@ -49,6 +49,7 @@ EXPORTED = [
     "rcp_graph_update", "rcp_graph_launch", "rcp_graph_destroy", "rcp_get_tuning", "rcp_set_tuning", "rcp_autotune",
     "rcp_server_create", "rcp_submit", "rcp_poll", "rcp_result", "rcp_result_copy", "rcp_release", "rcp_server_stats",
     "rcp_server_destroy", "rcp_check", "rcp_debug_set", "rcp_render_noalloc", "rcp_render_noalloc_scratch_bytes",
+    "rcp_autotune_batch",
 ]
 STAT_COLS = 6
 RCP_DEBUG_FAIL_ALLOC_AFTER = 1
@@ -89,7 +90,8 @@ class rcp_view(ctypes.Structure):
 
 class rcp_tuning(ctypes.Structure):
     _fields_ = [("refill_min", ctypes.c_int32), ("exit_lanes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("tile_log2w", ctypes.c_int32), ("engine", ctypes.c_int32)]
+                ("tile_log2w", ctypes.c_int32), ("engine", ctypes.c_int32), ("top_levels", ctypes.c_int32),
+                ("stack_entries", ctypes.c_int32), ("block_size", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -172,6 +174,8 @@ def load(path: str | None = None):
         "rcp_render_noalloc_scratch_bytes": (ctypes.c_uint64, []),
         "rcp_check": (st, [P, P]),
         "rcp_debug_set": (st, [i32, ctypes.c_int64]),
+        "rcp_autotune_batch": (st, [P, ctypes.POINTER(rcp_view), i32, i32, ctypes.POINTER(rcp_tuning),
+                                    ctypes.POINTER(ctypes.c_float), P]),
         "rcp_status_string": (ctypes.c_char_p, [st]),
         "rcp_last_error": (ctypes.c_char_p, []),
     }
@@ -370,8 +374,7 @@ def rcp_radix_sort_u64(keys, vals, n: int, stream=None) -> None:
     _check(st, "rcp_radix_sort_u64")
 
 
-def rcp_render_batch(handle: int, views, stream=None) -> None:
-    """views: sequence of (camera, W, H, K, displacement, out_images, out_ids)."""
+def _view_array(views):
     arr = (rcp_view * len(views))()
     for i, (cam, W, H, K, disp, out, ids) in enumerate(views):
         arr[i].camera = make_camera(cam)
@@ -379,8 +382,24 @@ def rcp_render_batch(handle: int, views, stream=None) -> None:
         arr[i].disp = disp
         arr[i].out_images = _dev_ptr(out)
         arr[i].out_ids = _dev_ptr(ids)
-    st = load().rcp_render_batch(handle, arr, len(views), _stream(stream))
+    return arr
+
+
+def rcp_render_batch(handle: int, views, stream=None) -> None:
+    """views: sequence of (camera, W, H, K, displacement, out_images, out_ids)."""
+    st = load().rcp_render_batch(handle, _view_array(views), len(views), _stream(stream))
     _check(st, "rcp_render_batch")
+
+
+def rcp_autotune_batch(handle: int, views, repeats: int = 3, stream=None):
+    """Autotune on a batch (same views as rcp_render_batch); returns
+    (tuning dict, median ms of the chosen parameters)."""
+    t = rcp_tuning()
+    ms = ctypes.c_float()
+    st = load().rcp_autotune_batch(handle, _view_array(views), len(views), int(repeats), ctypes.byref(t),
+                                   ctypes.byref(ms), _stream(stream))
+    _check(st, "rcp_autotune_batch")
+    return t.as_dict(), float(ms.value)
 
 
 def rcp_graph_create(handle: int, cam, W: int, H: int, K: int, disp: rcp_displacement, out_images, out_ids=None,
@@ -412,15 +431,17 @@ def rcp_get_tuning(handle: int) -> dict:
     return t.as_dict()
 
 
-def rcp_set_tuning(handle: int, refill_min: int, blocks_per_cu: int, tile_log2w: int,
-                   engine: int | None = None, exit_lanes: int | None = None) -> None:
-    """engine / exit_lanes None keep the scene's current values."""
-    if engine is None or exit_lanes is None:
-        cur = rcp_get_tuning(handle)
-        engine = cur["engine"] if engine is None else engine
-        exit_lanes = cur["exit_lanes"] if exit_lanes is None else exit_lanes
-    t = rcp_tuning(refill_min=int(refill_min), exit_lanes=int(exit_lanes), blocks_per_cu=int(blocks_per_cu),
-                   tile_log2w=int(tile_log2w), engine=int(engine))
+def rcp_set_tuning(handle: int, refill_min: int | None = None, blocks_per_cu: int | None = None,
+                   tile_log2w: int | None = None, engine: int | None = None, exit_lanes: int | None = None,
+                   top_levels: int | None = None, stack_entries: int | None = None,
+                   block_size: int | None = None) -> None:
+    """Fields left None keep the scene's current values."""
+    t = rcp_tuning(**rcp_get_tuning(handle))
+    for k, v in (("refill_min", refill_min), ("blocks_per_cu", blocks_per_cu), ("tile_log2w", tile_log2w),
+                 ("engine", engine), ("exit_lanes", exit_lanes), ("top_levels", top_levels),
+                 ("stack_entries", stack_entries), ("block_size", block_size)):
+        if v is not None:
+            setattr(t, k, int(v))
     _check(load().rcp_set_tuning(handle, ctypes.byref(t)), "rcp_set_tuning")
 
 
@@ -455,8 +476,7 @@ def autotune_cached(handle: int, scene_key: str, cam, W: int, H: int, K: int, di
             cache = {}
     if key in cache:
         t = cache[key]["tuning"]
-        rcp_set_tuning(handle, t["refill_min"], t["blocks_per_cu"], t["tile_log2w"],
-                       t.get("engine", ENGINE_CHAIN), t.get("exit_lanes"))
+        rcp_set_tuning(handle, **t)
         return t
     t, ms = rcp_autotune(handle, cam, W, H, K, disp, out_images, out_ids, repeats, stream)
     cache[key] = {"tuning": t, "ms": ms}
@@ -556,8 +576,7 @@ class Scene:
     def set_engine(self, engine: int) -> None:
         """RCP_ENGINE_CHAIN or RCP_ENGINE_PASSES for rcp_render; the other
         launch parameters stay as they are."""
-        t = rcp_get_tuning(self.handle)
-        rcp_set_tuning(self.handle, t["refill_min"], t["blocks_per_cu"], t["tile_log2w"], engine)
+        rcp_set_tuning(self.handle, engine=engine)
 
     def render(self, cam, W, H, K, lambda_eye, lambda_dir, with_ids=True, stream=None, mode=RCP_MODE_COLOR,
                z0=0.0):

@@ -172,13 +172,19 @@ def test_graph_replays_equal_eager_render(engine):
     dict(refill_min=40, blocks_per_cu=3, tile_log2w=2, engine=1, exit_lanes=64),
     dict(refill_min=1, blocks_per_cu=1, tile_log2w=0, engine=1, exit_lanes=1),
     dict(refill_min=64, blocks_per_cu=0, tile_log2w=3, engine=0, exit_lanes=1),
+    dict(refill_min=56, blocks_per_cu=0, tile_log2w=3, engine=0, exit_lanes=16, top_levels=0),
+    dict(refill_min=56, blocks_per_cu=0, tile_log2w=3, engine=0, exit_lanes=16, top_levels=2, stack_entries=8),
+    dict(refill_min=48, blocks_per_cu=0, tile_log2w=3, engine=0, exit_lanes=8, block_size=512),
+    dict(refill_min=30, blocks_per_cu=2, tile_log2w=4, engine=0, exit_lanes=12, top_levels=3, stack_entries=8,
+         block_size=512),
 ])
 def test_tuning_does_not_change_images(tuning):
     say("tuning", tuning)
     sc = scenegen.terrain_patch(12, 40, 20)
     s = rcp.Scene(sc)
     ref_img, ref_ids = single(s, PATCH_CAM, 67, 45, 5, 0.0, 0.1)
-    t = dict(tuning)
+    t = dict(top_levels=4, stack_entries=16, block_size=256)
+    t.update(tuning)
     rcp.rcp_set_tuning(s.handle, **t)
     assert rcp.rcp_get_tuning(s.handle) == t
     img, ids = single(s, PATCH_CAM, 67, 45, 5, 0.0, 0.1)
@@ -206,8 +212,29 @@ def test_autotune_and_cache(tmp_path):
     t1 = rcp.autotune_cached(s.handle, "soup256", w.camera, 64, 64, 6, rcp.make_displacement(0.0, 0.02), out,
                              cache_path=path, repeats=1)
     assert os.path.exists(path) and len(json.load(open(path))) == 1
-    rcp.rcp_set_tuning(s.handle, 40, 0, 3)
+    rcp.rcp_set_tuning(s.handle, refill_min=40, blocks_per_cu=0, tile_log2w=3, top_levels=1, stack_entries=8)
     t2 = rcp.autotune_cached(s.handle, "soup256", w.camera, 64, 64, 6, rcp.make_displacement(0.0, 0.02), out,
                              cache_path=path, repeats=1)
     assert t2 == t1 and rcp.rcp_get_tuning(s.handle) == t1
+    s.close()
+
+
+def test_autotune_batch():
+    """The autotuner on a batch picks valid parameters (the engine stays the
+    chain engine) and leaves the batch's images in the outputs."""
+    sc = scenegen.terrain_patch(12, 40, 20)
+    s = rcp.Scene(sc)
+    specs = [(PATCH_CAM, 67, 45, 4), (PATCH_CAM, 33, 21, 2), (PATCH_CAM, 96, 72, 6)]
+    refs = [single(s, cam, W, H, K, 0.0, 0.05) for (cam, W, H, K) in specs]
+    outs = [torch.full((K, H, W, 3), -1.0, device="cuda") for (_, W, H, K) in specs]
+    d = rcp.make_displacement(0.0, 0.05)
+    say("autotune batch")
+    t, ms = rcp.rcp_autotune_batch(s.handle, [(cam, W, H, K, d, o, None) for (cam, W, H, K), o in zip(specs, outs)],
+                                   repeats=1)
+    torch.cuda.synchronize()
+    assert ms > 0 and t["engine"] == rcp.RCP_ENGINE_CHAIN
+    assert t["stack_entries"] in (8, 16) and t["block_size"] in (256, 512) and 0 <= t["top_levels"] <= 4
+    assert rcp.rcp_get_tuning(s.handle) == t
+    for o, (ref, _) in zip(outs, refs):
+        assert torch.equal(o, ref)
     s.close()

@@ -60,6 +60,29 @@ def stacked_quads(n_quads, seed=0, half=1.0, dz=0.002):
                           rgb=rgb.astype(np.float32), name=f"stacked{n_quads}")
 
 
+def test_stack_overflow_with_the_shallow_lds_stack():
+    """The chain kernel with 8 LDS stack entries (and workgroups of 512)
+    spills more often; its images stay equal to the oracle's."""
+    sc = stacked_quads(2048, seed=1)
+    W, H, K = 40, 32, 4
+    say("stacked quads, 8-entry stack")
+    s = rcp.Scene(sc, rcp.build_options(max_leaf=1))
+    o_img, o_ids = oracle.OracleScene(sc, use_bvh=True).render(AXIS_CAM, W, H, K, 0.0, 0.05)
+    for stack, block in [(8, 256), (8, 512), (16, 512)]:
+        rcp.rcp_set_tuning(s.handle, stack_entries=stack, block_size=block)
+        img, ids = s.render(AXIS_CAM, W, H, K, 0.0, 0.05)
+        torch.cuda.synchronize()
+        assert np.array_equal(img.cpu().numpy(), o_img) and np.array_equal(ids.cpu().numpy(), o_ids), (stack, block)
+        # and through the batch kernel
+        o = torch.empty_like(img)
+        rcp.rcp_render_batch(s.handle, [(AXIS_CAM, W, H, K, rcp.make_displacement(0.0, 0.05), o, None),
+                                        (AXIS_CAM, 9, 7, 2, rcp.make_displacement(0.0, 0.05), torch.empty(
+                                            (2, 7, 9, 3), device="cuda"), None)])
+        torch.cuda.synchronize()
+        assert np.array_equal(o.cpu().numpy(), o_img), (stack, block)
+    s.close()
+
+
 @pytest.mark.parametrize("engine", [rcp.RCP_ENGINE_CHAIN, rcp.RCP_ENGINE_PASSES], ids=["chain", "passes"])
 def test_stack_overflow_path_is_reached_and_exact(engine):
     sc = stacked_quads(4096)
