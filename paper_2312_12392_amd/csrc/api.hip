@@ -190,7 +190,12 @@ rcp_status check_scene(const rcp_scene* s) {
 extern "C" {
 
 const char* rcp_status_string(rcp_status s) {
-    switch (s) {
+    // A C caller may pass any int; reading it through the enum type would be
+    // undefined in C++ for values outside the enumerators' range.
+    int v;
+    static_assert(sizeof v == sizeof s, "rcp_status is int-sized");
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
         case RCP_OK: return "ok";
         case RCP_ERR_INVALID_ARGUMENT: return "invalid argument";
         case RCP_ERR_OUT_OF_MEMORY: return "out of memory";
