@@ -491,6 +491,8 @@ def _retire(rcp, srv, pending, late, lat):
     still = []
     for t in pending:
         st, (ts, tb, td) = rcp.rcp_poll(srv, t)
+        if st == rcp.RCP_REQ_FAILED:
+            raise RuntimeError(f"served request {t} failed")
         if st == rcp.RCP_REQ_DONE:
             lat.append((td - ts + late[t]) * 1e3)
             rcp.rcp_release(srv, t)
@@ -535,6 +537,7 @@ def served_rate(rcp, scene, w, rate, duration, seed, max_inflight, stream):
     t_srv = time.perf_counter() - t0
     launches = rcp.rcp_server_stats(srv)["launches"]
     rcp.rcp_server_destroy(srv)
+    log(f"  rate {rate}: server done ({len(trace)} requests, {t_srv:.1f} s); running the plain loop")
     # --- plain loop: one synchronous rcp_render at a time, in arrival order ---
     lat_loop = []
     t0 = time.perf_counter()
@@ -546,6 +549,8 @@ def served_rate(rcp, scene, w, rate, duration, seed, max_inflight, stream):
         rcp.rcp_render(scene.handle, cam, W, H, K, d, out, None, stream)
         stream.synchronize()
         lat_loop.append((time.perf_counter() - t0 - arr) * 1e3)
+        if len(lat_loop) % 2000 == 0:
+            log(f"  loop: {len(lat_loop)} of {len(trace)} requests")
     t_loop = time.perf_counter() - t0
     del big
     return {"requests": len(trace), "seconds_of_arrivals": duration, "nominal_rays": rays, "launches": launches,
@@ -612,6 +617,25 @@ def bench_walk(args):
     ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.frames)])
     rays = W * H * K * args.frames
     scene.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle (its own BVH, all host cores) on the walk-through's first
+        # two frames
+        import oracle
+        log("timing the oracle on the first two frames ...")
+        t0 = time.perf_counter()
+        o = oracle.OracleScene(w.scene, use_bvh=True)
+        t_bvh = time.perf_counter() - t0
+        times = []
+        for cam in cams[:2]:
+            t0 = time.perf_counter()
+            o.render(cam, W, H, K, 0.0, w.lambda_dir)
+            times.append(time.perf_counter() - t0)
+        o.close()
+        cpu = {"value": round(2 * W * H * K / sum(times) / 1e6, 3), "unit": "Mrays/s",
+               "cores": oracle.default_threads(), "kind": "oracle",
+               "sample": f"the first 2 frames of the walk-through, {times[0]:.1f} s and {times[1]:.1f} s "
+                         f"(oracle BVH build {t_bvh:.1f} s, not timed)"}
     return {
         "metric": "Mrays/s of a 4K K=8 walk-through of the 16M-triangle scene; frame ms p50/p99",
         "value": round(rays / (ms.sum() * 1e-3) / 1e6, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.frames,
@@ -619,7 +643,7 @@ def bench_walk(args):
         "data": "synthetic",
         "config": {"workload": f"terrain16m: {W}x{H}, K={K}, {w.scene.n_tris} triangles, {args.frames}-frame spline "
                                "walk-through, lambda_dir 0.01", "frames": args.frames},
-        "frame_ms": _percentiles(ms), "bvh_build_ms": round(info["build_ms"], 2),
+        "frame_ms": _percentiles(ms), "bvh_build_ms": round(info["build_ms"], 2), "cpu_baseline": cpu,
         "bvh": {"nodes": info["n_nodes"], "sah_cost": round(info["sah_cost"], 3), "max_depth": info["max_depth"],
                 "builder": args.builder, "collapse": args.collapse, "max_leaf": args.max_leaf,
                 "c_trav": args.c_trav, "c_isect": args.c_isect},
