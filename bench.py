@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--no-served", action="store_true", help="skip the served leg of the default line")
+    ap.add_argument("--no-literal-eye", action="store_true",
+                    help="skip the literal-eye leg (profiling runs: only the default frame's launches)")
     ap.add_argument("--served-seconds", type=float, default=3.0, help="served leg: seconds of arrivals at 200/s")
     ap.add_argument("--saturating-rate", type=float, default=600.0,
                     help="served leg: an arrival rate above what the GPU serves")
@@ -300,7 +302,7 @@ def bench_frame(args):
     write_bytes = round(tr["write_kib_per_dispatch"] * 1024 * tr["write_scale"]) if tr else None
     sq = load_profile(counters_file(kernel, w.name), w.name)
     compulsory_writes = 16 * W * H * K          # every image (12 B) and ID (4 B) of every pass
-    literal = literal_eye_leg(args, scene, w, imgs, ids, stream) if not args.literal_eye else None
+    literal = None if args.literal_eye or args.no_literal_eye else literal_eye_leg(args, scene, w, imgs, ids, stream)
 
     result = {
         "metric": "Mrays/s (nominal W*H*K rays) of the K=6 frame at 1080p/1M tris; frame ms in ms_per_step",
