@@ -44,6 +44,7 @@ struct Slot {
     hipEvent_t done = nullptr;
     rcp::BatchWorkspace ws;
     std::vector<uint64_t> tickets;
+    std::vector<rcp_view> views;   // the launch's views (capacity kMaxBatch, reserved at creation)
     bool busy = false;
     bool launching = false;     // its launch is being enqueued (lock released)
 };
@@ -78,8 +79,13 @@ struct rcp_server {
             if (it->second >= bytes) {
                 off = it->first;
                 const size_t rest = it->second - bytes;
-                free_list.erase(it);
-                if (rest) free_list[off + bytes] = rest;
+                // the block's own map node carries the remainder (no allocation)
+                auto node = free_list.extract(it);
+                if (rest) {
+                    node.key() = off + bytes;
+                    node.mapped() = rest;
+                    free_list.insert(std::move(node));
+                }
                 return true;
             }
         }
@@ -118,8 +124,10 @@ namespace {
 // launches, admit queued requests in order while they fit, launch the
 // admitted ones.  The launch itself is enqueued with the lock released (the
 // slot is marked busy first, and only this thread schedules), so submit and
-// poll never wait for it; it allocates nothing, since every slot's buffers
-// were sized when the server was created.
+// poll never wait for it.  It allocates nothing, on the device or the host:
+// every slot's device buffers were sized when the server was created, and its
+// host arrays hold a full batch (admission stops at one batch of requests
+// waiting for a slot).
 void schedule(rcp_server* s, std::unique_lock<std::mutex>& lk) {
     for (Slot& sl : s->slots) {
         if (!sl.busy || sl.launching) continue;
@@ -138,7 +146,7 @@ void schedule(rcp_server* s, std::unique_lock<std::mutex>& lk) {
         sl.tickets.clear();
         sl.busy = false;
     }
-    while (!s->queue.empty()) {
+    while (!s->queue.empty() && s->admitted.size() < (size_t)kMaxBatch) {
         Req& r = s->reqs[s->queue.front()];
         size_t off = 0;
         if (!s->pool_alloc(r.bytes, off)) break;       // first in, first served: wait for space
@@ -153,7 +161,8 @@ void schedule(rcp_server* s, std::unique_lock<std::mutex>& lk) {
         if (!sl.busy) { free_slot = &sl; break; }
     if (!free_slot) return;
     const size_t n = std::min<size_t>(s->admitted.size(), (size_t)kMaxBatch);
-    std::vector<rcp_view> views(n);
+    std::vector<rcp_view>& views = free_slot->views;
+    views.resize(n);
     for (size_t i = 0; i < n; ++i) {
         Req& r = s->reqs[s->admitted[i]];
         rcp_view& v = views[i];
@@ -240,8 +249,11 @@ rcp_status server_create(rcp_scene* scene, size_t pool_bytes, int max_inflight, 
         return st;
     }
     s->free_list[0] = pool_bytes;
+    s->admitted.reserve((size_t)kMaxBatch);
     s->slots.resize((size_t)max_inflight);
     for (Slot& sl : s->slots) {
+        sl.tickets.reserve((size_t)kMaxBatch);
+        sl.views.reserve((size_t)kMaxBatch);
         hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
         if (e != hipSuccess) {
