@@ -164,6 +164,11 @@ typedef struct {
     float build_ms;          /* device time of the build kernels */
     uint64_t device_bytes;   /* HBM held by the scene */
     uint32_t node_bytes;     /* bytes per packed BVH node (rcp_export_bvh) */
+    uint32_t leaf_hist[8];   /* leaf links by triangle count: leaf_hist[c - 1]
+                                links to leaves of c triangles (they sum to
+                                n_leaves; the count times c sums to n_tris,
+                                except for a scene of one leaf, whose root
+                                links it twice) */
 } rcp_scene_stats;
 
 /* ---------------------------------------------------------------------- */
@@ -182,6 +187,9 @@ typedef struct {
  * is set to NULL. */
 rcp_status rcp_build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts,
                            void* hip_stream, rcp_scene** out);
+/* With the environment variable RCP_LOG=1, every successful build prints one
+ * line of its statistics (rcp_scene_stats, with the leaf histogram) to
+ * stderr. */
 
 /* Release the scene's device memory (synchronises the device first).
  * NULL is ignored. */
@@ -500,9 +508,23 @@ const char* rcp_last_error(void);
  *                               RCP_ERR_OUT_OF_MEMORY; value < 0: off.
  *   RCP_DEBUG_STEP_BUDGET       traversal step budget per ray of scenes built
  *                               afterwards (0: the default, which only a
- *                               malformed tree can exhaust). */
+ *                               malformed tree can exhaust).
+ *   RCP_DEBUG_LIST_CANARY       1: the per-pass engine (Section 2's passes
+ *                               one launch each) fills each pass's list of
+ *                               continuing pixels, and their hit data, with an
+ *                               all-ones canary before the pass and checks it
+ *                               after: every entry below the list's count
+ *                               written, with a pixel index below W * H and
+ *                               colours in [0, 1]; every entry above it
+ *                               untouched.  A violation is reported by
+ *                               rcp_check and rcp_render_stats as
+ *                               RCP_ERR_INTERNAL.  2: the same, with the check
+ *                               told that each list is one entry shorter (a
+ *                               test of the check itself: a non-empty list
+ *                               then fails).  0: off (the default). */
 #define RCP_DEBUG_FAIL_ALLOC_AFTER 1
 #define RCP_DEBUG_STEP_BUDGET 2
+#define RCP_DEBUG_LIST_CANARY 3
 rcp_status rcp_debug_set(int what, int64_t value);
 
 #ifdef __cplusplus

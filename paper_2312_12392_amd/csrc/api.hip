@@ -1,6 +1,8 @@
 // C ABI of the renderer: argument validation, error reporting, dispatch.
 #include <cmath>
 #include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <atomic>
@@ -53,6 +55,7 @@ bool pools_supported() {
 // fails (-1: off), and the traversal step budget of scenes built afterwards.
 std::atomic<long long> g_alloc_left{-1};
 std::atomic<uint32_t> g_step_budget{0};
+std::atomic<int> g_list_canary{0};
 
 }  // namespace
 
@@ -66,6 +69,8 @@ bool alloc_hook_fails() {
 }
 
 uint32_t debug_step_budget() { return g_step_budget.load(); }
+
+int debug_list_canary() { return g_list_canary.load(); }
 
 rcp_status dev_alloc(void** p, size_t bytes) {
     *p = nullptr;
@@ -104,7 +109,13 @@ void stream_free(void* p, hipStream_t stream) {
 }
 
 rcp_status take_device_error(rcp_scene* s) {
-    if (s->err_host && __atomic_exchange_n(s->err_host, 0u, __ATOMIC_ACQ_REL) != 0u) {
+    const uint32_t e = s->err_host ? __atomic_exchange_n(s->err_host, 0u, __ATOMIC_ACQ_REL) : 0u;
+    if (e == kErrListCanary) {
+        set_error("a list of continuing pixels failed its canary check (an entry below the list's count left "
+                  "unwritten or invalid, or one above it overwritten)");
+        return RCP_ERR_INTERNAL;
+    }
+    if (e != 0u) {
         set_error("a ray ran out of its traversal step budget (%u steps): the BVH is malformed, and that ray's "
                   "result is a miss", s->dev.step_budget);
         return RCP_ERR_INTERNAL;
@@ -239,12 +250,25 @@ rcp_status rcp_build_scene(const rcp_scene_desc* desc, const rcp_build_options* 
         if (opts->collapse != RCP_COLLAPSE_SAH && opts->collapse != RCP_COLLAPSE_GREEDY)
             FAIL("unknown collapse %d", (int)opts->collapse);
     }
+    rcp_status st;
     try {
-        return build_scene(desc, opts, (hipStream_t)hip_stream, out);
+        st = build_scene(desc, opts, (hipStream_t)hip_stream, out);
     } catch (const std::bad_alloc&) {
         set_error("host allocation failed");
         return RCP_ERR_OUT_OF_MEMORY;
     }
+    const char* log = std::getenv("RCP_LOG");
+    if (st == RCP_OK && log && std::strcmp(log, "1") == 0) {
+        const rcp_scene_stats& t = (*out)->stats;
+        std::fprintf(stderr,
+                     "rcp: scene built: %u triangles, %u nodes, %u leaves, depth %u, max_leaf %u, SAH %.4f, "
+                     "%.3f ms, %llu device bytes; leaves by triangle count 1..8: %u %u %u %u %u %u %u %u\n",
+                     t.n_tris, t.n_nodes, t.n_leaves, t.max_depth, t.max_leaf, (double)t.sah_cost,
+                     (double)t.build_ms, (unsigned long long)t.device_bytes, t.leaf_hist[0], t.leaf_hist[1],
+                     t.leaf_hist[2], t.leaf_hist[3], t.leaf_hist[4], t.leaf_hist[5], t.leaf_hist[6],
+                     t.leaf_hist[7]);
+    }
+    return st;
 }
 
 void rcp_destroy_scene(rcp_scene* s) {
@@ -453,6 +477,10 @@ rcp_status rcp_debug_set(int what, int64_t value) {
         case RCP_DEBUG_STEP_BUDGET:
             if (value < 0 || value > 0xFFFFFFFFll) FAIL("step budget must be in [0, 2^32)");
             g_step_budget.store((uint32_t)value);
+            return RCP_OK;
+        case RCP_DEBUG_LIST_CANARY:
+            if (value < 0 || value > 2) FAIL("list canary setting must be 0, 1 or 2");
+            g_list_canary.store((int)value);
             return RCP_OK;
     }
     FAIL("unknown debug setting %d", what);

@@ -683,11 +683,13 @@ __global__ void k_pack_single(int n, const float4* __restrict__ tlo, const float
 // node it expands in src[], and its inner children get slots of the next
 // level from one counter.
 // ---------------------------------------------------------------------------
-// Statistics of the emitted wide tree, accumulated exactly: leaf links, and
-// the SAH cost relative to the root box in 2^-32 fixed point.
+// Statistics of the emitted wide tree, accumulated exactly: leaf links, the
+// SAH cost relative to the root box in 2^-32 fixed point, and the leaves by
+// their triangle count (hist[c - 1] leaves of c triangles).
 struct WideStats {
     unsigned long long leaves;
     unsigned long long sah_fx;
+    unsigned long long hist[8];
 };
 
 __device__ inline void wide_stat(WideStats* ws, float node_area, float leaf_cost, uint32_t n_leaves, float c_trav,
@@ -776,6 +778,7 @@ __global__ __launch_bounds__(kB) void k_collapse4(const float4* __restrict__ n2,
         if (c[i].link & kLeafBit) {
             leaf_cost += (c_isect * (float)((c[i].link & 7u) + 1u) + kLeafEntry * c_trav) * c[i].area;
             ++n_leaves;
+            atomicAdd(&stats->hist[c[i].link & 7u], 1ull);
         }
     }
     wide_stat(stats, half_area(u), leaf_cost, n_leaves, c_trav, inv_root_area);
@@ -964,6 +967,7 @@ __global__ __launch_bounds__(kB) void k_emit4(const int32_t* __restrict__ left, 
             leaf_cost += (c_isect * (float)cnt + kLeafEntry * c_trav) *
                          half_area(make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z));
             ++n_leaves;
+            atomicAdd(&stats->hist[cnt - 1u], 1ull);
         }
         lo[0][m] = pad_lo(a.x); hi[0][m] = pad_hi(b.x);
         lo[1][m] = pad_lo(a.y); hi[1][m] = pad_hi(b.y);
@@ -1507,6 +1511,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
             RCP_HIP(hipStreamSynchronize(stream));
             n_leaves = (uint32_t)hst.leaves;
             sah = (float)((double)hst.sah_fx / 4294967296.0);
+            for (int c = 0; c < 8; ++c) s->stats.leaf_hist[c] = (uint32_t)hst.hist[c];
             if (single) sah = c_isect * (float)n;   // one leaf of every triangle, relative to its own box
         }
         RCP_TRY(dalloc(&s->tris, 9 * (size_t)n));   // three rotated copies

@@ -53,6 +53,12 @@ bool alloc_hook_fails();
 // Per-ray traversal step budget of scenes built from now on (0: the bound
 // that only a malformed tree can reach).
 uint32_t debug_step_budget();
+// Canary checks of the per-pass engine's lists: 0 off, 1 on, 2 on with each
+// list taken as one entry shorter (a test of the check itself).
+int debug_list_canary();
+// Values of the scene's device error flag.
+constexpr uint32_t kErrStepBudget = 1u;   // a ray ran out of its step budget
+constexpr uint32_t kErrListCanary = 2u;   // a compaction list failed its canary check
 
 // Scratch device memory ordered on a stream: allocated for the work enqueued
 // after the call, released once the stream's earlier work is done, with no
@@ -102,7 +108,7 @@ struct DevScene {
     float radius;      // largest |coordinate| of any vertex
     float bg[3];
     uint32_t step_budget;   // traversal steps per ray (only a malformed tree reaches it)
-    uint32_t* err_flag;     // host-mapped; set when a ray ran out of step_budget
+    uint32_t* err_flag;     // host-mapped; kErrStepBudget or kErrListCanary once raised
 };
 
 struct Camera {

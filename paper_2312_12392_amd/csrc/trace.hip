@@ -426,6 +426,43 @@ Launch launch_params(const rcp_scene* s) {
 }
 
 namespace {
+// Debug canary of the per-pass lists (rcp_debug_set RCP_DEBUG_LIST_CANARY):
+// an all-ones entry, which no list entry can be (its pixel index is below
+// W * H <= 2^27 and its colours lie in [0, 1]).
+__device__ inline bool is_canary(float4 v) {
+    return (__float_as_uint(v.x) & __float_as_uint(v.y) & __float_as_uint(v.z) & __float_as_uint(v.w)) ==
+           0xFFFFFFFFu;
+}
+
+__global__ void k_canary_fill(float4* __restrict__ st, float4* __restrict__ aux, size_t n) {
+    const float4 c = make_float4(__uint_as_float(0xFFFFFFFFu), __uint_as_float(0xFFFFFFFFu),
+                                 __uint_as_float(0xFFFFFFFFu), __uint_as_float(0xFFFFFFFFu));
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        st[i] = c;
+        if (aux) aux[i] = c;
+    }
+}
+
+// Entries [0, count - shrink) must be written, with a pixel index below P and
+// colours in [0, 1]; entries [count - shrink, cap) must still hold the canary.
+__global__ void k_canary_check(const float4* __restrict__ st, const float4* __restrict__ aux, size_t cap,
+                               const uint32_t* __restrict__ count, uint32_t shrink, uint32_t P,
+                               uint32_t* err_flag) {
+    const uint32_t c = *count;
+    const size_t n = c >= shrink ? c - shrink : 0;
+    bool bad = (size_t)c > cap;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (size_t)gridDim.x * blockDim.x) {
+        const float4 v = st[i];
+        if (i < n) {
+            bad = bad || is_canary(v) || __float_as_uint(v.x) >= P || !(v.y >= 0.0f && v.y <= 1.0f) ||
+                  !(v.z >= 0.0f && v.z <= 1.0f) || !(v.w >= 0.0f && v.w <= 1.0f) || (aux && is_canary(aux[i]));
+        } else {
+            bad = bad || !is_canary(v) || (aux && !is_canary(aux[i]));
+        }
+    }
+    if (bad) __hip_atomic_store(err_flag, kErrListCanary, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <bool STATS, int MODE>
 rcp_status pass_grid(rcp_scene* s, const Launch& lp, GridInfo& g) {
     return persistent_grid(k_pass<STATS, MODE>, s->dev, g, MODE != RCP_MODE_COLOR, lp.blocks_per_cu);
@@ -450,6 +487,9 @@ rcp_status launch_passes(rcp_scene* s, Workspace& w, PassArgs& a, int K, hipStre
     hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(256), 0, stream, w.counters, (int)kCounterWords,
                        STATS ? w.stats : (unsigned long long*)nullptr);
     RCP_CHECK_LAUNCH();
+    const int canary = debug_list_canary();
+    // the lists hold P entries (the workspace may hold more)
+    const size_t cap = P;
     for (int k = 0; k < K; ++k) {
         a.k = k;
         a.state_in = k == 0 ? nullptr : w.state[(k - 1) & 1];
@@ -457,8 +497,18 @@ rcp_status launch_passes(rcp_scene* s, Workspace& w, PassArgs& a, int K, hipStre
         a.state_out = k + 1 < K ? w.state[k & 1] : nullptr;
         a.aux_out = (k + 1 < K && AUX) ? w.aux[k & 1] : nullptr;
         if (k > 0) { a.prev_img = nullptr; a.prev_aux = nullptr; }
+        if (canary && a.state_out) {
+            hipLaunchKernelGGL(k_canary_fill, dim3(1024), dim3(256), 0, stream, a.state_out, a.aux_out, cap);
+            RCP_CHECK_LAUNCH();
+        }
         hipLaunchKernelGGL((k_pass<STATS, MODE>), dim3(g.blocks), dim3(kBlock), g.smem, stream, a);
         RCP_CHECK_LAUNCH();
+        if (canary && a.state_out) {
+            hipLaunchKernelGGL(k_canary_check, dim3(1024), dim3(256), 0, stream, (const float4*)a.state_out,
+                               (const float4*)a.aux_out, cap, (const uint32_t*)(w.counters + k + 1),
+                               canary == 2 ? 1u : 0u, (uint32_t)P, s->dev.err_flag);
+            RCP_CHECK_LAUNCH();
+        }
     }
     return RCP_OK;
 }

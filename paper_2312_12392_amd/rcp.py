@@ -54,6 +54,7 @@ EXPORTED = [
 STAT_COLS = 6
 RCP_DEBUG_FAIL_ALLOC_AFTER = 1
 RCP_DEBUG_STEP_BUDGET = 2
+RCP_DEBUG_LIST_CANARY = 3
 
 
 class RcpError(RuntimeError):
@@ -106,10 +107,12 @@ class rcp_scene_stats(ctypes.Structure):
     _fields_ = [("n_tris", ctypes.c_uint32), ("n_nodes", ctypes.c_uint32), ("n_leaves", ctypes.c_uint32),
                 ("max_depth", ctypes.c_uint32), ("max_leaf", ctypes.c_uint32),
                 ("sah_cost", ctypes.c_float), ("build_ms", ctypes.c_float), ("device_bytes", ctypes.c_uint64),
-                ("node_bytes", ctypes.c_uint32)]
+                ("node_bytes", ctypes.c_uint32), ("leaf_hist", ctypes.c_uint32 * 8)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["leaf_hist"] = list(self.leaf_hist)
+        return d
 
 
 _lib = None

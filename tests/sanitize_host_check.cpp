@@ -6,7 +6,8 @@
 // (scene build, the K-pass render in both engines, the single pass, the
 // instrumented render, batches, graphs, the server, the allocation-free
 // render, the autotuner, tracing, sorting, the screen-space passes, forced
-// allocation failures) and checks that the paths that must agree do.
+// allocation failures, the list canary and the build log) and checks that the
+// paths that must agree do.
 //
 // Exit status 0 when every call returns what it must.  The leak check runs
 // explicitly at the end of main, and the process then ends without running
@@ -261,7 +262,9 @@ static void device() {
         if (r == RCP_OK) break;
     }
     rcp_scene* sc = nullptr;
+    setenv("RCP_LOG", "1", 1);   // the build's log line
     OK(rcp_build_scene(&desc, nullptr, st, &sc));
+    unsetenv("RCP_LOG");
     if (!sc) return;
     rcp_scene_stats info{};
     OK(rcp_scene_info(sc, &info));
@@ -287,7 +290,9 @@ static void device() {
         OK(rcp_render(sc, &cam, W, H, K, &d, a.p, ia.p, st));
         t.engine = RCP_ENGINE_PASSES;
         OK(rcp_set_tuning(sc, &t));
+        OK(rcp_debug_set(RCP_DEBUG_LIST_CANARY, 1));   // the lists canary-checked (rcp_check below)
         OK(rcp_render(sc, &cam, W, H, K, &d, b.p, ib.p, st));
+        OK(rcp_debug_set(RCP_DEBUG_LIST_CANARY, 0));
         t.engine = RCP_ENGINE_CHAIN;
         OK(rcp_set_tuning(sc, &t));
         std::vector<uint64_t> counts((size_t)K * 6);

@@ -61,6 +61,9 @@ def check_bvh(scene, info, nodes, tri_ids):
     first = (lf >> 3) & 0x0FFFFFFF
     cnt = (lf & 7) + 1
     assert (first + cnt <= n).all()
+    # the build's leaf histogram counts exactly these leaf links by size
+    hist = np.bincount(cnt - 1, minlength=8)
+    assert list(hist) == info["leaf_hist"] and hist.sum() == info["n_leaves"]
     single = nn == 1 and bool((links[0, :2] & LEAF).all()) and links[0, 0] == links[0, 1]
     assert (cnt <= info["max_leaf"]).all() or single
     lo_t, hi_t = tri_boxes(scene)

@@ -187,6 +187,66 @@ def test_step_budget_exhaustion_is_reported():
     s.close()
 
 
+@pytest.mark.parametrize("mode", [rcp.RCP_MODE_COLOR, rcp.RCP_MODE_DEPTH], ids=["colour", "depth"])
+def test_list_canary_mode(mode):
+    """The per-pass engine's lists of continuing pixels, canary-filled before
+    each pass and checked after it: clean renders pass the check with
+    unchanged images; a check told that each list is one entry shorter
+    reports the last entry as written past the end."""
+    sc = scenegen.terrain_patch(12, 40, 20)
+    W, H, K = 61, 47, 5
+    d = rcp.make_displacement(0.0, 0.05, mode=mode, z0=1.2)
+    s = rcp.Scene(sc)
+    s.set_engine(rcp.RCP_ENGINE_PASSES)
+    ref = torch.empty((K, H, W, 3), device="cuda")
+    rcp.rcp_render(s.handle, PATCH_CAM, W, H, K, d, ref, None)
+    counts = rcp.rcp_render_stats(s.handle, PATCH_CAM, W, H, K, d, torch.empty_like(ref), None)
+    assert counts[0, 3] > 0                        # the first list is not empty
+    img = torch.empty_like(ref)
+    try:
+        say("list canary on, mode", mode)
+        rcp.rcp_debug_set(rcp.RCP_DEBUG_LIST_CANARY, 1)
+        rcp.rcp_render(s.handle, PATCH_CAM, W, H, K, d, img, None)
+        rcp.rcp_check(s.handle)
+        assert torch.equal(img, ref)
+        say("list canary with the count shortened by one")
+        rcp.rcp_debug_set(rcp.RCP_DEBUG_LIST_CANARY, 2)
+        rcp.rcp_render(s.handle, PATCH_CAM, W, H, K, d, img, None)
+        with pytest.raises(rcp.RcpError) as e:
+            rcp.rcp_check(s.handle)
+        assert e.value.status == rcp.RCP_ERR_INTERNAL and "canary" in str(e.value)
+        assert torch.equal(img, ref)                # the check reads only
+    finally:
+        rcp.rcp_debug_set(rcp.RCP_DEBUG_LIST_CANARY, 0)
+    rcp.rcp_render(s.handle, PATCH_CAM, W, H, K, d, img, None)
+    rcp.rcp_check(s.handle)
+    s.close()
+
+
+def test_build_log_line_and_leaf_histogram(capfd, monkeypatch):
+    """RCP_LOG=1 prints the build statistics; the leaf histogram sums to the
+    leaf count and, weighted by leaf size, to the triangle count."""
+    sc = scenegen.terrain_patch(12, 40, 20)
+    monkeypatch.setenv("RCP_LOG", "1")
+    for ml in (1, 3, 8):
+        s = rcp.Scene(sc, rcp.build_options(max_leaf=ml))
+        info = s.info()
+        s.close()
+        h = info["leaf_hist"]
+        assert sum(h) == info["n_leaves"]
+        assert sum((c + 1) * n for c, n in enumerate(h)) == sc.n_tris
+        assert all(n == 0 for n in h[ml:])
+        err = capfd.readouterr().err
+        line = [ln for ln in err.splitlines() if ln.startswith("rcp: scene built:")]
+        assert len(line) == 1, err
+        assert f"{sc.n_tris} triangles, {info['n_nodes']} nodes, {info['n_leaves']} leaves" in line[0]
+        assert line[0].endswith(" ".join(str(n) for n in h))
+    monkeypatch.delenv("RCP_LOG")
+    s = rcp.Scene(sc)
+    s.close()
+    assert "rcp: scene built" not in capfd.readouterr().err
+
+
 def test_allocation_failures_everywhere():
     sc = scenegen.terrain_patch(11, 24, 8)
     W, H, K = 40, 30, 3
