@@ -116,6 +116,44 @@ def test_batch_orbit_mix_on_terrain1m():
     s.close()
 
 
+def test_batch_of_the_maximum_view_count():
+    """1024 views (the limit) of mixed tiny sizes, K 1..6 and all three
+    modes in one call: each equals its single render, every 32nd the oracle;
+    1025 views are rejected."""
+    sc = scenegen.terrain_patch(11, 24, 8)
+    s = rcp.Scene(sc)
+    rng = np.random.default_rng(11)
+    specs = []
+    for i in range(1024):
+        ang = rng.uniform(-0.7, 0.7)
+        cam = scenegen.camera_look_at([1.4 * np.sin(ang), rng.uniform(0.3, 0.7), -1.4 * np.cos(ang)],
+                                      [0, 0.05, 0], [0, 1, 0], 60.0)
+        W, H, K = int(rng.integers(1, 13)), int(rng.integers(1, 13)), int(rng.integers(1, 7))
+        d = rcp.make_displacement(0.0, float(rng.uniform(0.0, 0.1)), mode=i % 3, z0=1.2)
+        specs.append((cam, W, H, K, d))
+    outs = [(torch.full((K, H, W, 3), -1.0, device="cuda"), torch.full((K, H, W), -7, dtype=torch.int32, device="cuda"))
+            for (_, W, H, K, _) in specs]
+    say("batch of 1024 views")
+    rcp.rcp_render_batch(s.handle, [(cam, W, H, K, d, o, i) for (cam, W, H, K, d), (o, i) in zip(specs, outs)])
+    torch.cuda.synchronize()
+    orc = oracle.OracleScene(sc, use_bvh=True)
+    for n, ((cam, W, H, K, d), (o, i)) in enumerate(zip(specs, outs)):
+        ref_o = torch.empty_like(o)
+        ref_i = torch.empty_like(i)
+        rcp.rcp_render(s.handle, cam, W, H, K, d, ref_o, ref_i)
+        torch.cuda.synchronize()
+        assert torch.equal(o, ref_o) and torch.equal(i, ref_i), n
+        if n % 32 == 0:
+            oi, oid = orc.render(cam, W, H, K, d.lambda_eye, d.lambda_dir, mode=d.mode, z0=d.z0)
+            assert np.array_equal(o.cpu().numpy(), oi) and np.array_equal(i.cpu().numpy(), oid), n
+    orc.close()
+    extra = torch.empty((1, 1, 1, 3), device="cuda")
+    views = [(cam, W, H, K, d, o, None) for (cam, W, H, K, d), (o, _) in zip(specs, outs)]
+    with pytest.raises(rcp.RcpError):
+        rcp.rcp_render_batch(s.handle, views + [(specs[0][0], 1, 1, 1, specs[0][4], extra, None)])
+    s.close()
+
+
 def test_batch_rejects_bad_views():
     w = scenegen.workload("soup256")
     s = rcp.Scene(w.scene)

@@ -181,6 +181,8 @@ RENDER_CASES = [
     ("empty_scene", lambda: scenegen.empty_scene(), AXIS_CAM, 23, 19, 4, 0.0, 0.02),
     ("one_triangle", lambda: scenegen.soup_scene(7, 1, extent=1.2), AXIS_CAM, 40, 40, 4, 0.0, 0.1),
     ("many_passes", lambda: scenegen.soup_scene(2, 300), AXIS_CAM, 48, 40, 20, 0.0, 0.05),
+    # the largest pass count; 427 of the 851 pixels still change at pass 63
+    ("max_passes", lambda: scenegen.terrain_patch(12, 40, 20), PATCH_CAM, 37, 23, 64, 0.0, 0.3),
     # views of 16 or more tiles a side take their work in super-tiles of
     # 16 x 16 tiles, padded at the right and bottom edges
     ("supertiles_padded", lambda: scenegen.terrain_patch(11, 24, 8), PATCH_CAM, 200, 150, 4, 0.0, 0.05),

@@ -157,6 +157,29 @@ def test_budget_and_queue_limits(scene):
     rcp.rcp_server_destroy(srv)
 
 
+def test_more_requests_than_one_launch_holds(scene):
+    """1500 tiny requests submitted at once: a launch takes at most 1024, and
+    admission stops at one launch's worth waiting for a slot, so they run in
+    several launches; each equals the request rendered alone."""
+    rng = np.random.default_rng(21)
+    reqs = []
+    for i in range(1500):
+        ang = rng.uniform(-0.7, 0.7)
+        cam = scenegen.camera_look_at([1.4 * np.sin(ang), rng.uniform(0.3, 0.7), -1.4 * np.cos(ang)],
+                                      [0, 0.05, 0], [0, 1, 0], 60.0)
+        reqs.append((cam, int(rng.integers(1, 9)), int(rng.integers(1, 9)), int(rng.integers(1, 4)),
+                     rcp.make_displacement(0.0, float(rng.uniform(0.0, 0.1)))))
+    srv = rcp.rcp_server_create(scene.handle, 64 << 20, max_inflight=1, queue_capacity=4096)
+    say("1500 requests, one launch slot")
+    tickets = [rcp.rcp_submit(srv, cam, W, H, K, d, with_ids=True) for (cam, W, H, K, d) in reqs]
+    wait_done(srv, tickets, timeout=120.0)
+    launches = rcp.rcp_server_stats(srv)["launches"]
+    assert launches >= 2, launches
+    check_against_alone(scene, srv, reqs, tickets)
+    assert rcp.rcp_server_stats(srv)["live"] == 0
+    rcp.rcp_server_destroy(srv)
+
+
 def test_destroy_with_requests_in_flight(scene):
     say("server destroy")
     srv = rcp.rcp_server_create(scene.handle, 128 << 20, max_inflight=2)
