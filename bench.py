@@ -591,7 +591,9 @@ def bench_served(args):
 
 def bench_walk(args):
     """The 16M-triangle scene: a walk-through of 4K, K=8 frames, each frame
-    restarting from the grey seed with a new camera."""
+    restarting from the grey seed with a new camera; timed with the default
+    launch parameters and with the ones the autotuner picks on the first
+    frame (the line's value is the faster of the two walks)."""
     import numpy as np
     import torch
 
@@ -610,13 +612,25 @@ def bench_walk(args):
     cams = [scenegen.walk_camera(pts, i / args.frames) for i in range(args.frames)]
     rcp.rcp_render(scene.handle, cams[0], W, H, K, d, imgs, None, stream)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.frames + 1)]
-    ev[0].record(stream)
-    for i, cam in enumerate(cams):
-        rcp.rcp_render(scene.handle, cam, W, H, K, d, imgs, None, stream)
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.frames)])
+
+    def walk():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.frames + 1)]
+        ev[0].record(stream)
+        for i, cam in enumerate(cams):
+            rcp.rcp_render(scene.handle, cam, W, H, K, d, imgs, None, stream)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        return np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.frames)])
+
+    defaults = rcp.rcp_get_tuning(scene.handle)
+    ms_default = walk()
+    # launch parameters tuned on the first frame (scene and resolution), then
+    # the whole walk-through again with them
+    t0 = time.perf_counter()
+    tuned, _ = rcp.rcp_autotune(scene.handle, cams[0], W, H, K, d, imgs, None, repeats=2, stream=stream)
+    tune_s = time.perf_counter() - t0
+    ms_tuned = walk()
+    ms = ms_tuned if ms_tuned.sum() < ms_default.sum() else ms_default
     rays = W * H * K * args.frames
     scene.close()
     cpu = None
@@ -646,6 +660,8 @@ def bench_walk(args):
         "config": {"workload": f"terrain16m: {W}x{H}, K={K}, {w.scene.n_tris} triangles, {args.frames}-frame spline "
                                "walk-through, lambda_dir 0.01", "frames": args.frames},
         "frame_ms": _percentiles(ms), "bvh_build_ms": round(info["build_ms"], 2), "cpu_baseline": cpu,
+        "default_tuning": defaults, "default_frame_ms": _percentiles(ms_default),
+        "autotuned": tuned, "autotuned_frame_ms": _percentiles(ms_tuned), "autotune_seconds": round(tune_s, 1),
         "bvh": {"nodes": info["n_nodes"], "sah_cost": round(info["sah_cost"], 3), "max_depth": info["max_depth"],
                 "builder": args.builder, "collapse": args.collapse, "max_leaf": args.max_leaf,
                 "c_trav": args.c_trav, "c_isect": args.c_isect},
