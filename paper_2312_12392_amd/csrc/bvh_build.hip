@@ -692,11 +692,20 @@ struct WideStats {
     unsigned long long hist[8];
 };
 
-__device__ inline void wide_stat(WideStats* ws, float node_area, float leaf_cost, uint32_t n_leaves, float c_trav,
-                                 float inv_root_area) {
+// leaf_sizes: the node's leaves by size in 4-bit fields (field c counts the
+// leaves of c + 1 triangles; a node has at most 4).  Every atomic has the
+// same address in all lanes, so the compiler sums each over the wave first:
+// one memory atomic per wave and counter.
+__device__ inline void wide_stat(WideStats* ws, float node_area, float leaf_cost, uint32_t n_leaves,
+                                 uint32_t leaf_sizes, float c_trav, float inv_root_area) {
     const float rel = (c_trav * node_area + leaf_cost) * inv_root_area;
     atomicAdd(&ws->sah_fx, (unsigned long long)((double)rel * 4294967296.0 + 0.5));
     if (n_leaves) atomicAdd(&ws->leaves, (unsigned long long)n_leaves);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint32_t v = (leaf_sizes >> (4 * c)) & 15u;
+        if (v) atomicAdd(&ws->hist[c], (unsigned long long)v);
+    }
 }
 
 struct WideCand {
@@ -772,16 +781,16 @@ __global__ __launch_bounds__(kB) void k_collapse4(const float4* __restrict__ n2,
     o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     WideCand u = c[0];
     float leaf_cost = 0.0f;
-    uint32_t n_leaves = 0;
+    uint32_t n_leaves = 0, leaf_sizes = 0;
     for (int i = 0; i < m; ++i) {
         for (int a = 0; a < 3; ++a) { u.lo[a] = fminf(u.lo[a], c[i].lo[a]); u.hi[a] = fmaxf(u.hi[a], c[i].hi[a]); }
         if (c[i].link & kLeafBit) {
             leaf_cost += (c_isect * (float)((c[i].link & 7u) + 1u) + kLeafEntry * c_trav) * c[i].area;
             ++n_leaves;
-            atomicAdd(&stats->hist[c[i].link & 7u], 1ull);
+            leaf_sizes += 1u << (4u * (c[i].link & 7u));
         }
     }
-    wide_stat(stats, half_area(u), leaf_cost, n_leaves, c_trav, inv_root_area);
+    wide_stat(stats, half_area(u), leaf_cost, n_leaves, leaf_sizes, c_trav, inv_root_area);
 }
 
 // ---------------------------------------------------------------------------
@@ -929,7 +938,7 @@ __global__ __launch_bounds__(kB) void k_emit4(const int32_t* __restrict__ left, 
     int32_t inner[4];
     int m = 0;
     float leaf_cost = 0.0f;
-    uint32_t n_leaves = 0;
+    uint32_t n_leaves = 0, leaf_sizes = 0;
     for (int guard = 0; sp > 0 && guard < 256; ++guard) {
         const int32_t c = wn[--sp];
         const int j = wj[sp];
@@ -967,7 +976,7 @@ __global__ __launch_bounds__(kB) void k_emit4(const int32_t* __restrict__ left, 
             leaf_cost += (c_isect * (float)cnt + kLeafEntry * c_trav) *
                          half_area(make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z));
             ++n_leaves;
-            atomicAdd(&stats->hist[cnt - 1u], 1ull);
+            leaf_sizes += 1u << (4u * (cnt - 1u));
         }
         lo[0][m] = pad_lo(a.x); hi[0][m] = pad_hi(b.x);
         lo[1][m] = pad_lo(a.y); hi[1][m] = pad_hi(b.y);
@@ -1002,7 +1011,7 @@ __global__ __launch_bounds__(kB) void k_emit4(const int32_t* __restrict__ left, 
     o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float4 xa = nd.lo[x], xb = nd.hi[x];
     wide_stat(stats, half_area(make_float3(xa.x, xa.y, xa.z), make_float3(xb.x, xb.y, xb.z)), leaf_cost, n_leaves,
-              c_trav, inv_root_area);
+              leaf_sizes, c_trav, inv_root_area);
 }
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) {
