@@ -18,7 +18,6 @@
 //                                 thread of the grid
 // Every call on a GPU shares that GPU's array and leaves its contents behind:
 // calls that overlap on one GPU (two streams, or two threads) race.
-#include <map>
 #include <mutex>
 
 #include "traverse.hpp"
@@ -36,16 +35,21 @@ static_assert(kViewBytes <= kCountersOfs, "the view table fits before the counte
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 // Device address of `scratch` on the current device, looked up on the first
-// call there.
+// call there and kept in a fixed table (the lookup allocates nothing either).
+constexpr int kMaxDevices = 64;
+
 rcp_status scratch_address(void** out) {
     static std::mutex mu;
-    static std::map<int, void*> addr;
+    static void* addr[kMaxDevices] = {};
     int dev = 0;
     RCP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d is beyond the %d devices the allocation-free render supports", dev, kMaxDevices);
+        return RCP_ERR_INVALID_ARGUMENT;
+    }
     std::lock_guard<std::mutex> lk(mu);
-    const auto it = addr.find(dev);
-    if (it != addr.end()) {
-        *out = it->second;
+    if (addr[dev]) {
+        *out = addr[dev];
         return RCP_OK;
     }
     void* p = nullptr;
