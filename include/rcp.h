@@ -220,7 +220,7 @@ rcp_status rcp_render(rcp_scene* scene, const rcp_camera* base_camera, int W, in
 /* rcp_render for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation.
  * Same arguments, validation and results as rcp_render (always the chain
- * engine); the call allocates nothing.  Its working memory (the launch's
+ * engine, tiles in screen order); the call allocates nothing.  Its working memory (the launch's
  * view table, work counters and traversal stack overflow) is a fixed area of
  * rcp_render_noalloc_scratch_bytes() = 64 MiB inside the library's device
  * code, one per GPU, held until the process ends.  The launch uses as many
@@ -333,6 +333,14 @@ void rcp_graph_destroy(rcp_graph* graph);
  *                  engine's colour-mode kernel (8 or 16, default 16); deeper
  *                  entries go to a global overflow area
  *   block_size     that kernel's workgroup size (256 or 512, default 256)
+ *   tile_order     single renders of the chain engine (rcp_render,
+ *                  rcp_render_stats, graphs): 1 (default) hands out each
+ *                  band's tiles by decreasing estimated cost -- the occupied
+ *                  cells of a coarse occupancy grid of the scene that the
+ *                  undisplaced ray through the tile's centre crosses, found
+ *                  by two small kernels before the launch -- so that long
+ *                  chains start first; 0 in screen order.  Batches and
+ *                  rcp_render_noalloc always use the screen order.
  * The instrumented kernel and the depth and normal modes always use 16
  * stack entries and workgroups of 256. */
 #define RCP_ENGINE_CHAIN 0
@@ -346,6 +354,7 @@ typedef struct {
     int32_t top_levels;
     int32_t stack_entries;
     int32_t block_size;
+    int32_t tile_order;
 } rcp_tuning;
 
 rcp_status rcp_get_tuning(const rcp_scene* scene, rcp_tuning* out);

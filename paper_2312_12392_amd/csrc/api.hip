@@ -278,6 +278,7 @@ void rcp_destroy_scene(rcp_scene* s) {
     if (s->tris) (void)hipFree(s->tris);
     if (s->shade) (void)hipFree(s->shade);
     if (s->normals) (void)hipFree(s->normals);
+    if (s->occ.bits) (void)hipFree(s->occ.bits);
     free_workspace(s->ws, nullptr);
     free_batch_workspace(s->bws, nullptr);
     if (s->err_host) (void)hipHostFree(s->err_host);
@@ -386,6 +387,7 @@ void tuning_out(const Tuning& t, rcp_tuning* out) {
     out->top_levels = t.top_levels;
     out->stack_entries = t.stack;
     out->block_size = t.block;
+    out->tile_order = t.tile_order;
 }
 
 }  // namespace
@@ -512,6 +514,7 @@ rcp_status rcp_get_tuning(const rcp_scene* s, rcp_tuning* out) {
     out->top_levels = s->tuning.top_levels;
     out->stack_entries = s->tuning.stack;
     out->block_size = s->tuning.block;
+    out->tile_order = s->tuning.tile_order;
     return RCP_OK;
 }
 
@@ -526,9 +529,11 @@ rcp_status rcp_set_tuning(rcp_scene* s, const rcp_tuning* t) {
     if (t->top_levels < 0 || t->top_levels > kTopLevels) FAIL("top_levels must be in [0, %d]", kTopLevels);
     if (t->stack_entries != 8 && t->stack_entries != 16) FAIL("stack_entries must be 8 or 16");
     if (t->block_size != 256 && t->block_size != 512) FAIL("block_size must be 256 or 512");
+    if (t->tile_order != 0 && t->tile_order != 1) FAIL("tile_order must be 0 or 1");
     s->tuning.top_levels = t->top_levels;
     s->tuning.stack = t->stack_entries;
     s->tuning.block = t->block_size;
+    s->tuning.tile_order = t->tile_order;
     s->tuning.refill_min = t->refill_min;
     s->tuning.exit_lanes = t->exit_lanes;
     s->tuning.blocks_per_cu = t->blocks_per_cu;

@@ -656,6 +656,27 @@ __global__ __launch_bounds__(kB) void k_pack_nodes(int n, const int32_t* __restr
     o[3] = make_float4(__uint_as_float(link[0]), __uint_as_float(link[1]), 0.0f, 0.0f);
 }
 
+// Occupancy grid of the scene box: the cell of each triangle's centroid is
+// set.  Most triangles find their cell already set, so the word is read
+// first and only a clear bit takes an atomic.
+__global__ void k_occupancy(const float* __restrict__ verts, const uint32_t* __restrict__ idx, uint32_t n,
+                            OccGrid g, uint32_t* bits) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        int q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float c = (verts[3 * (size_t)idx[3 * (size_t)t] + a] + verts[3 * (size_t)idx[3 * (size_t)t + 1] + a] +
+                             verts[3 * (size_t)idx[3 * (size_t)t + 2] + a]) * (1.0f / 3.0f);
+            const int v = (int)floorf((c - g.lo[a]) / g.cell[a]);
+            q[a] = v < 0 ? 0 : (v >= g.n[a] ? g.n[a] - 1 : v);
+        }
+        const uint32_t cell = (uint32_t)((q[2] * g.n[1] + q[1]) * g.n[0] + q[0]);
+        const uint32_t m = 1u << (cell & 31u);
+        if (!(__hip_atomic_load(&bits[cell >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & m))
+            atomicOr(&bits[cell >> 5], m);
+    }
+}
+
 // Whole scene in one leaf (n <= max_leaf): a root whose two children are the
 // same leaf; visiting it twice cannot change the closest hit.
 __global__ void k_pack_single(int n, const float4* __restrict__ tlo, const float4* __restrict__ thi,
@@ -1284,6 +1305,7 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
                 if (s->tris) (void)hipFree(s->tris);
                 if (s->shade) (void)hipFree(s->shade);
                 if (s->normals) (void)hipFree(s->normals);
+                if (s->occ.bits) (void)hipFree(s->occ.bits);
                 if (s->err_host) (void)hipHostFree(s->err_host);
                 delete s;
                 s = nullptr;
@@ -1303,6 +1325,18 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     RCP_HIP(hipEventCreate(&e1));
     struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } evg{e0, e1};
 
+    // the box of the vertices (for the occupancy grid) and the largest
+    // |coordinate| (for the traversal's box widening), in one pass
+    float blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float radius = 0.0f;
+    for (size_t i = 0; i < (size_t)desc->n_verts && n > 0; ++i)
+        for (int a = 0; a < 3; ++a) {
+            const float v = desc->verts[3 * i + a];
+            blo[a] = fminf(blo[a], v);
+            bhi[a] = fmaxf(bhi[a], v);
+            radius = fmaxf(radius, fabsf(v));
+        }
+
     TempSet tmp(stream);
     float* d_verts = nullptr;
     uint32_t* d_idx = nullptr;
@@ -1317,6 +1351,26 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
         RCP_HIP(hipMemcpyAsync(d_rgb, desc->tri_rgb, sizeof(float) * 3 * (size_t)n, hipMemcpyHostToDevice, stream));
     }
     RCP_HIP(hipEventRecord(e0, stream));
+    if (n > 0) {
+        // the occupancy grid over the box of the vertices
+        const float emax = fmaxf(fmaxf(bhi[0] - blo[0], bhi[1] - blo[1]), bhi[2] - blo[2]);
+        OccGrid& g = s->occ;
+        for (int a = 0; a < 3; ++a) {
+            const float ext = bhi[a] - blo[a];
+            const int c = emax > 0.0f ? (int)ceilf((float)kOccCells * ext / emax) : 1;
+            // about cubic cells, but at least a quarter of the longest axis's
+            // count along a thin axis (a flat scene's height still resolves)
+            g.n[a] = ext <= 0.0f ? 1 : (c < kOccCells / 4 ? kOccCells / 4 : (c > kOccCells ? kOccCells : c));
+            g.lo[a] = blo[a];
+            g.cell[a] = ext > 0.0f ? ext / (float)g.n[a] : 1.0f;
+        }
+        g.words = (uint32_t)(((size_t)g.n[0] * g.n[1] * g.n[2] + 31) / 32);
+        RCP_TRY(dalloc(&g.bits, g.words));
+        RCP_HIP(hipMemsetAsync(g.bits, 0, sizeof(uint32_t) * g.words, stream));
+        hipLaunchKernelGGL(k_occupancy, dim3(std::min(blocks(n), 4096u)), dim3(kB), 0, stream, (const float*)d_verts,
+                           (const uint32_t*)d_idx, n, g, g.bits);
+        RCP_CHECK_LAUNCH();
+    }
 
     uint32_t n_nodes = 0, n_leaves = 0, max_depth = 0, stack_bound = 0, top_count = 0;
     float sah = 0.0f;
@@ -1541,8 +1595,6 @@ rcp_status build_scene(const rcp_scene_desc* desc, const rcp_build_options* opts
     s->dev.tris = s->tris;
     s->dev.shade = s->shade;
     s->dev.normals = s->normals;
-    float radius = 0.0f;
-    for (size_t i = 0; i < 3 * (size_t)desc->n_verts && n > 0; ++i) radius = fmaxf(radius, fabsf(desc->verts[i]));
     s->dev.radius = radius;
     s->dev.n_nodes = n_nodes;
     s->dev.n_tris = n;

@@ -67,6 +67,7 @@ struct ChainArgs {
     uint32_t spill_stride;
     unsigned long long* stats;   // [K][kStatCols] (STATS): rays, inner nodes, triangles, rays continued,
                                  // LDS node reads, stack entries spilled
+    const uint32_t* order;       // single view, or NULL: item i is pixel (i & 63) of tile order[i >> 6]
 };
 
 
@@ -214,7 +215,8 @@ __device__ inline void chain_body(const ChainArgs& a) {
                         }
                         v = lo;
                     }
-                    const uint32_t local = ONE ? item : item - vbegin[v];
+                    const uint32_t local = ONE ? (a.order ? (a.order[item >> 6] << 6) | (item & 63u) : item)
+                                               : item - vbegin[v];
                     {
                         const ConstView& vw = views[ONE ? 0 : v];
                         tile_pixel(local, (uint32_t)vw.tiles_x, (uint32_t)vw.tile_log2w, (uint32_t)vw.super_log2, x, y);
@@ -299,8 +301,9 @@ __global__ void k_clear_chain(uint32_t* fetch, int n, unsigned long long* stats)
 
 // Setup of a one-view launch (a single render, or a batch of one view): its
 // one-entry view table, item range, band counters and stats.
-__global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint32_t n_items, uint32_t* fetch,
-                               unsigned long long* stats) {
+// A single render's one-entry view table, zeroed band counters (and stats).
+__device__ inline void setup_single(const ViewDev& v, ViewDev* table, uint32_t* begin, uint32_t n_items,
+                                    uint32_t* fetch, unsigned long long* stats) {
     if (threadIdx.x == 0) {
         *table = v;
         begin[0] = 0u;
@@ -309,6 +312,143 @@ __global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint3
     }
     if (stats)
         for (int i = threadIdx.x; i < kStatCols * kMaxPasses; i += blockDim.x) stats[i] = 0ull;
+}
+
+// ---- Cost order of a single render's tiles -----------------------------------
+// A tile's score is the number of occupied cells of the scene's occupancy
+// grid that the undisplaced ray through its centre pixel crosses (a voxel
+// walk after Amanatides and Woo, "A Fast Voxel Traversal Algorithm for Ray
+// Tracing", Eurographics 1987).  Rays that skim many occupied cells tend to
+// start long chains; within each band the tiles are handed out by decreasing
+// score, so that those chains start first and the launch's tail, set by the
+// chains started last, gets shorter.  The order decides only when a pixel is
+// rendered, never its result.
+constexpr uint32_t kScoreBins = 256;
+
+constexpr uint32_t kScoreBlock = 256;
+
+__global__ __launch_bounds__(kScoreBlock) void k_tile_scores(ViewDev v, OccGrid g, uint32_t n_tiles, uint32_t* score) {
+    extern __shared__ uint32_t occ[];
+    for (uint32_t i = threadIdx.x; i < g.words; i += kScoreBlock) occ[i] = g.bits[i];
+    __syncthreads();
+    const uint32_t t = blockIdx.x * kScoreBlock + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t tw = 1u << (uint32_t)v.tile_log2w, th = 64u >> (uint32_t)v.tile_log2w;
+    int x0, y0, x, y;
+    tile_pixel(t << 6, (uint32_t)v.tiles_x, (uint32_t)v.tile_log2w, (uint32_t)v.super_log2, x0, y0);
+    if (x0 >= v.W || y0 >= v.H) {   // a padding tile beyond the image: no work
+        score[t] = 0u;
+        return;
+    }
+    tile_pixel((t << 6) + (th / 2u) * tw + tw / 2u, (uint32_t)v.tiles_x, (uint32_t)v.tile_log2w,
+               (uint32_t)v.super_log2, x, y);
+    x = x < v.W ? x : v.W - 1;
+    y = y < v.H ? y : v.H - 1;
+    const float fx = (float)(2 * x + 1) / (float)v.W - 1.0f;
+    const float fy = 1.0f - (float)(2 * y + 1) / (float)v.H;
+    float o[3], d[3], inv[3];
+    float tmin = 0.0f, tmax = INFINITY;
+    bool miss = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o[a] = v.cam.eye[a];
+        d[a] = v.cam.forward[a] + fx * v.hw * v.cam.right[a] + fy * v.cam.th * v.cam.up[a];
+        const float lo = g.lo[a], hi = g.lo[a] + g.cell[a] * (float)g.n[a];
+        if (d[a] == 0.0f) {
+            inv[a] = INFINITY;
+            miss = miss || o[a] < lo || o[a] > hi;
+        } else {
+            inv[a] = 1.0f / d[a];
+            const float t0 = (lo - o[a]) * inv[a], t1 = (hi - o[a]) * inv[a];
+            tmin = fmaxf(tmin, fminf(t0, t1));
+            tmax = fminf(tmax, fmaxf(t0, t1));
+        }
+    }
+    uint32_t count = 0;
+    if (!miss && tmin <= tmax) {
+        int c[3], step[3];
+        float tnext[3], tdelta[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float p = o[a] + tmin * d[a];
+            int q = (int)floorf((p - g.lo[a]) / g.cell[a]);
+            q = q < 0 ? 0 : (q >= g.n[a] ? g.n[a] - 1 : q);
+            c[a] = q;
+            step[a] = d[a] > 0.0f ? 1 : (d[a] < 0.0f ? -1 : 0);
+            tnext[a] = step[a] == 0 ? INFINITY
+                                    : (g.lo[a] + (float)(q + (step[a] > 0 ? 1 : 0)) * g.cell[a] - o[a]) * inv[a];
+            tdelta[a] = step[a] == 0 ? INFINITY : g.cell[a] * fabsf(inv[a]);
+        }
+        const int steps = g.n[0] + g.n[1] + g.n[2];
+        for (int it = 0; it < steps; ++it) {
+            const uint32_t cell = (uint32_t)((c[2] * g.n[1] + c[1]) * g.n[0] + c[0]);
+            count += (occ[cell >> 5] >> (cell & 31u)) & 1u;
+            // the next cell along the axis whose boundary comes first
+            if (tnext[0] <= tnext[1] && tnext[0] <= tnext[2]) {
+                if (tnext[0] > tmax) break;
+                c[0] += step[0];
+                tnext[0] += tdelta[0];
+                if (c[0] < 0 || c[0] >= g.n[0]) break;
+            } else if (tnext[1] <= tnext[2]) {
+                if (tnext[1] > tmax) break;
+                c[1] += step[1];
+                tnext[1] += tdelta[1];
+                if (c[1] < 0 || c[1] >= g.n[1]) break;
+            } else {
+                if (tnext[2] > tmax) break;
+                c[2] += step[2];
+                tnext[2] += tdelta[2];
+                if (c[2] < 0 || c[2] >= g.n[2]) break;
+            }
+        }
+    }
+    score[t] = count;
+}
+
+// One workgroup per band: a counting sort of the band's tiles by decreasing
+// score (order within a score is the order of arrival, which only moves
+// work in time).  Every tile of the band lands in exactly one slot of the
+// band's range, so order[] is a permutation of the tiles.  One more
+// workgroup does the launch's setup (the work of k_setup_single).
+__global__ __launch_bounds__(1024) void k_band_order(const uint32_t* __restrict__ score, uint32_t n_items,
+                                                     uint32_t* __restrict__ order, ViewDev v, ViewDev* table,
+                                                     uint32_t* begin, uint32_t* fetch, unsigned long long* stats) {
+    if (blockIdx.x == kFetchParts) {
+        setup_single(v, table, begin, n_items, fetch, stats);
+        return;
+    }
+    __shared__ uint32_t hist[kScoreBins];
+    const uint32_t lo = part_begin(n_items, blockIdx.x) >> 6, hi = part_begin(n_items, blockIdx.x + 1u) >> 6;
+    for (uint32_t i = threadIdx.x; i < kScoreBins; i += 1024) hist[i] = 0u;
+    __syncthreads();
+    for (uint32_t t = lo + threadIdx.x; t < hi; t += 1024) {
+        const uint32_t b = score[t] < kScoreBins ? score[t] : kScoreBins - 1u;
+        atomicAdd(&hist[b], 1u);
+    }
+    __syncthreads();
+    // each bin's first slot: the tiles of all higher scores come before it
+    // (a scan over the bins from the highest down, kScoreBins threads)
+    __shared__ uint32_t scan[kScoreBins];
+    const uint32_t own = threadIdx.x < kScoreBins ? hist[kScoreBins - 1u - threadIdx.x] : 0u;
+    if (threadIdx.x < kScoreBins) scan[threadIdx.x] = own;
+    __syncthreads();
+    for (uint32_t off = 1; off < kScoreBins; off <<= 1) {
+        const uint32_t add = (threadIdx.x < kScoreBins && threadIdx.x >= off) ? scan[threadIdx.x - off] : 0u;
+        __syncthreads();
+        if (threadIdx.x < kScoreBins) scan[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (threadIdx.x < kScoreBins) hist[kScoreBins - 1u - threadIdx.x] = scan[threadIdx.x] - own;
+    __syncthreads();
+    for (uint32_t t = lo + threadIdx.x; t < hi; t += 1024) {
+        const uint32_t b = score[t] < kScoreBins ? score[t] : kScoreBins - 1u;
+        order[lo + atomicAdd(&hist[b], 1u)] = t;
+    }
+}
+
+__global__ void k_setup_single(ViewDev v, ViewDev* table, uint32_t* begin, uint32_t n_items, uint32_t* fetch,
+                               unsigned long long* stats) {
+    setup_single(v, table, begin, n_items, fetch, stats);
 }
 
 // A chain kernel instantiation with its workgroup size and stack depth.
@@ -431,16 +571,23 @@ uint64_t view_items(const ViewDev& v) {
     return view_tile_items(v.W, v.H, v.tile_log2w, v.super_log2);
 }
 
+// Entries of a view's score and order buffer: two per tile.
+size_t order_entries(int W, int H, int tile_log2w) {
+    return 2 * (size_t)(view_tile_items(W, H, tile_log2w, super_log2_for(W, H, tile_log2w)) >> 6);
+}
+
 }  // namespace
 
-rcp_status prepare_chain(rcp_scene* s, Workspace& ws, int mode, hipStream_t stream) {
+rcp_status prepare_chain(rcp_scene* s, Workspace& ws, int W, int H, int mode, hipStream_t stream) {
     const Launch lp = launch_params(s);
     ChainGrid g1, g2;
     rcp_status st = chain_grid(lp, false, 1, mode, g1);
     if (st == RCP_OK) st = chain_grid(lp, true, 1, mode, g2);
     if (st != RCP_OK) return st;
     const size_t need = std::max(spill_depth_of(s, g1.k) * g1.threads(), spill_depth_of(s, g2.k) * g2.threads());
-    return ensure_workspace(s, ws, 0, 0, need, stream);
+    st = ensure_workspace(s, ws, 0, 0, need, stream);
+    if (st != RCP_OK) return st;
+    return ensure_order(ws, order_entries(W, H, lp.tile_log2w), stream);
 }
 
 namespace {
@@ -464,9 +611,22 @@ rcp_status launch_one_view(rcp_scene* s, Workspace& w, const Launch& lp, const C
     a.spill = w.spill;
     a.spill_stride = g.threads();
     a.stats = stats ? w.stats : nullptr;
-    hipLaunchKernelGGL(k_setup_single, dim3(1), dim3(256), 0, stream, view, (ViewDev*)a.views, (uint32_t*)a.begin,
-                       a.n_items, w.counters, a.stats);
-    RCP_CHECK_LAUNCH();
+    a.order = nullptr;
+    const uint32_t n_tiles = a.n_items >> 6;
+    if (s->tuning.tile_order && s->occ.bits && w.order && w.order_cap >= 2 * (size_t)n_tiles && n_tiles > 0) {
+        // tile scores in the second half of the buffer, the order in the first
+        uint32_t* score = w.order + n_tiles;
+        hipLaunchKernelGGL(k_tile_scores, dim3((n_tiles + kScoreBlock - 1) / kScoreBlock), dim3(kScoreBlock),
+                           sizeof(uint32_t) * s->occ.words, stream, view, s->occ, n_tiles, score);
+        hipLaunchKernelGGL(k_band_order, dim3(kFetchParts + 1), dim3(1024), 0, stream, (const uint32_t*)score,
+                           a.n_items, w.order, view, (ViewDev*)a.views, (uint32_t*)a.begin, w.counters, a.stats);
+        RCP_CHECK_LAUNCH();
+        a.order = w.order;
+    } else {
+        hipLaunchKernelGGL(k_setup_single, dim3(1), dim3(256), 0, stream, view, (ViewDev*)a.views,
+                           (uint32_t*)a.begin, a.n_items, w.counters, a.stats);
+        RCP_CHECK_LAUNCH();
+    }
     return launch_chain(g, stream, a);
 }
 
@@ -480,6 +640,8 @@ rcp_status render_chain(rcp_scene* s, Workspace& w, const Camera& cam, int W, in
     rcp_status st = chain_grid(lp, stats, 1, disp.mode, g);
     if (st != RCP_OK) return st;
     st = ensure_workspace(s, w, 0, 0, spill_depth_of(s, g.k) * g.threads(), stream);
+    if (st != RCP_OK) return st;
+    st = ensure_order(w, order_entries(W, H, lp.tile_log2w), stream);
     if (st != RCP_OK) return st;
     st = launch_one_view(s, w, lp, g, cam, W, H, K, disp, out_images, out_ids, stats, stream);
     if (st != RCP_OK) return st;

@@ -116,6 +116,21 @@ struct Camera {
     float th;
 };
 
+// Occupancy of the scene's bounding box on a coarse grid (a cell is set when
+// a triangle's centroid lies in it), kept for ordering the work of a render:
+// the occupied cells a pixel's undisplaced ray crosses estimate how long its
+// chain will take.  kOccCells cells along the box's longest axis, about
+// cubic cells, and at least kOccCells / 4 along the others (a single cell
+// along an axis of zero extent).
+constexpr int kOccCells = 48;
+struct OccGrid {
+    uint32_t* bits = nullptr;   // device, one bit per cell, x fastest, then y, then z
+    int n[3] = {0, 0, 0};
+    float lo[3] = {0.0f, 0.0f, 0.0f};
+    float cell[3] = {1.0f, 1.0f, 1.0f};
+    uint32_t words = 0;
+};
+
 // Per-render workspace.  The scene owns one, grown on demand with
 // stream-ordered allocations on the stream of the call that needs more room;
 // a captured graph owns its own, sized at capture and never grown, so that
@@ -125,6 +140,8 @@ struct Camera {
 struct Workspace {
     float4* state[2] = {nullptr, nullptr};    // compact {pix, rgb} lists
     float4* aux[2] = {nullptr, nullptr};      // their {view depth, normal} (depth and normal modes)
+    uint32_t* order = nullptr;                 // chain engine: tile scores, then the tile order
+    size_t order_cap = 0;                      // uint32 entries
     size_t aux_cap = 0;
     size_t state_cap = 0;                      // entries per list
     uint32_t* counters = nullptr;              // kCounterWords
@@ -138,6 +155,9 @@ struct Workspace {
 
 // Release a workspace's buffers on `stream` (stream-ordered).
 void free_workspace(Workspace& w, hipStream_t stream);
+// Room for `entries` uint32 of tile scores and order in a growable workspace
+// (fixed and external workspaces are left as they are).
+rcp_status ensure_order(Workspace& w, size_t entries, hipStream_t stream);
 
 constexpr size_t kViewBytes = 512;
 
@@ -190,6 +210,8 @@ struct Tuning {
     int top_levels = kTopLevels;  // levels of the 4-wide tree the chain engine reads from LDS (0..kTopLevels)
     int stack = 16;               // LDS stack entries per lane of the chain engine's colour kernel (8 or 16)
     int block = 256;              // its workgroup size (256 or 512)
+    int tile_order = 1;           // single renders of the chain engine: 1 hands out each band's tiles
+                                  // by decreasing estimated cost, 0 in screen order
 };
 
 }  // namespace rcp
@@ -204,6 +226,7 @@ struct rcp_scene {
     rcp_scene_stats stats{};
     uint32_t top_nodes[rcp::kTopLevels + 1] = {};   // nodes in the tree's first L levels, L = 0..kTopLevels
     uint32_t* err_host = nullptr;   // pinned, device-mapped error flag (DevScene::err_flag)
+    rcp::OccGrid occ;
     rcp::Workspace ws;
     rcp::BatchWorkspace bws;
     rcp::Tuning tuning;
@@ -256,7 +279,7 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
 rcp_status prepare_batch_workspace(rcp_scene* s, BatchWorkspace& ws, int n_views, bool with_staging,
                                    hipStream_t stream);
 // The chain engine for a whole render from the seed: one launch, no pass barrier.
-rcp_status prepare_chain(rcp_scene* s, Workspace& ws, int mode, hipStream_t stream);
+rcp_status prepare_chain(rcp_scene* s, Workspace& ws, int W, int H, int mode, hipStream_t stream);
 rcp_status render_chain(rcp_scene* s, Workspace& ws, const Camera& cam, int W, int H, int K, const Disp& disp,
                         float* out_images, int32_t* out_ids, unsigned long long* host_counts, hipStream_t stream);
 // The chain engine on a caller-sized workspace that is never grown: the

@@ -92,9 +92,10 @@ rcp_status time_runs(Run&& run, int repeats, hipStream_t stream, hipEvent_t e0, 
 // Coordinate descent over the launch parameters: each round tries every
 // candidate of one parameter with the others fixed and keeps the fastest.
 // The parameters: refill threshold, early-exit lanes, workgroups per CU,
-// tile width, engine (single renders only; batches always run the chain
-// engine), LDS-staged tree levels, LDS stack depth and workgroup size (the
-// last two select among instantiations of the chain kernel).
+// tile width, engine and tile order (single renders only; batches always run
+// the chain engine in screen order), LDS-staged tree levels, LDS stack depth
+// and workgroup size (the last two select among instantiations of the chain
+// kernel).
 template <class Run>
 rcp_status descend(rcp_scene* s, Run&& run, bool tune_engine, int repeats, Tuning& best, float& best_ms,
                    hipStream_t stream) {
@@ -110,6 +111,7 @@ rcp_status descend(rcp_scene* s, Run&& run, bool tune_engine, int repeats, Tunin
     const std::vector<int> top_levels = {4, 3, 2, 0};
     const std::vector<int> stacks = {16, 8};
     const std::vector<int> blocks_sz = {256, 512};
+    const std::vector<int> orders = {1, 0};
     Tuning cur = s->tuning;
     if (cur.refill_min <= 0) cur.refill_min = kDefaultRefill;
     s->tuning = cur;
@@ -117,8 +119,8 @@ rcp_status descend(rcp_scene* s, Run&& run, bool tune_engine, int repeats, Tunin
     rcp_status st = time_runs(run, repeats, stream, e0, e1, cur_ms);
     if (st != RCP_OK) return st;
     for (int round = 0; round < 2; ++round) {
-        for (int param = 0; param < 8; ++param) {
-            if (param == 4 && !tune_engine) continue;
+        for (int param = 0; param < 9; ++param) {
+            if ((param == 4 || param == 8) && !tune_engine) continue;
             const std::vector<int>& cands = param == 0   ? refill
                                             : param == 1 ? exits
                                             : param == 2 ? blocks
@@ -126,7 +128,8 @@ rcp_status descend(rcp_scene* s, Run&& run, bool tune_engine, int repeats, Tunin
                                             : param == 4 ? engines
                                             : param == 5 ? top_levels
                                             : param == 6 ? stacks
-                                                         : blocks_sz;
+                                            : param == 7 ? blocks_sz
+                                                         : orders;
             for (int c : cands) {
                 Tuning t = cur;
                 int& field = param == 0   ? t.refill_min
@@ -136,7 +139,8 @@ rcp_status descend(rcp_scene* s, Run&& run, bool tune_engine, int repeats, Tunin
                              : param == 4 ? t.engine
                              : param == 5 ? t.top_levels
                              : param == 6 ? t.stack
-                                          : t.block;
+                             : param == 7 ? t.block
+                                          : t.tile_order;
                 if (field == c) continue;
                 field = c;
                 s->tuning = t;

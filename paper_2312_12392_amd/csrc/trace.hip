@@ -372,6 +372,11 @@ rcp_status ensure_workspace(rcp_scene* s, Workspace& w, size_t n_state, size_t n
     return RCP_OK;
 }
 
+rcp_status ensure_order(Workspace& w, size_t entries, hipStream_t stream) {
+    if (w.fixed || w.external) return RCP_OK;   // renders without room for it keep the screen order
+    return grow_buffer(&w.order, w.order_cap, entries, stream);
+}
+
 void free_workspace(Workspace& w, hipStream_t stream) {
     if (w.external) {
         w = Workspace{};
@@ -385,6 +390,7 @@ void free_workspace(Workspace& w, hipStream_t stream) {
     stream_free(w.spill, stream);
     stream_free(w.stats, stream);
     stream_free(w.view, stream);
+    stream_free(w.order, stream);
     w = Workspace{};
 }
 
@@ -539,7 +545,7 @@ rcp_status prepare_mode(rcp_scene* s, Workspace& w, int W, int H, int K, hipStre
 }  // namespace
 
 rcp_status prepare_render(rcp_scene* s, Workspace& w, int W, int H, int K, int mode, hipStream_t stream) {
-    if (s->tuning.engine == RCP_ENGINE_CHAIN) return prepare_chain(s, w, mode, stream);
+    if (s->tuning.engine == RCP_ENGINE_CHAIN) return prepare_chain(s, w, W, H, mode, stream);
     switch (mode) {
         case RCP_MODE_DEPTH: return prepare_mode<RCP_MODE_DEPTH>(s, w, W, H, K, stream);
         case RCP_MODE_NORMAL: return prepare_mode<RCP_MODE_NORMAL>(s, w, W, H, K, stream);

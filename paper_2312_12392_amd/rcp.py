@@ -92,7 +92,7 @@ class rcp_view(ctypes.Structure):
 class rcp_tuning(ctypes.Structure):
     _fields_ = [("refill_min", ctypes.c_int32), ("exit_lanes", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("tile_log2w", ctypes.c_int32), ("engine", ctypes.c_int32), ("top_levels", ctypes.c_int32),
-                ("stack_entries", ctypes.c_int32), ("block_size", ctypes.c_int32)]
+                ("stack_entries", ctypes.c_int32), ("block_size", ctypes.c_int32), ("tile_order", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -437,12 +437,12 @@ def rcp_get_tuning(handle: int) -> dict:
 def rcp_set_tuning(handle: int, refill_min: int | None = None, blocks_per_cu: int | None = None,
                    tile_log2w: int | None = None, engine: int | None = None, exit_lanes: int | None = None,
                    top_levels: int | None = None, stack_entries: int | None = None,
-                   block_size: int | None = None) -> None:
+                   block_size: int | None = None, tile_order: int | None = None) -> None:
     """Fields left None keep the scene's current values."""
     t = rcp_tuning(**rcp_get_tuning(handle))
     for k, v in (("refill_min", refill_min), ("blocks_per_cu", blocks_per_cu), ("tile_log2w", tile_log2w),
                  ("engine", engine), ("exit_lanes", exit_lanes), ("top_levels", top_levels),
-                 ("stack_entries", stack_entries), ("block_size", block_size)):
+                 ("stack_entries", stack_entries), ("block_size", block_size), ("tile_order", tile_order)):
         if v is not None:
             setattr(t, k, int(v))
     _check(load().rcp_set_tuning(handle, ctypes.byref(t)), "rcp_set_tuning")

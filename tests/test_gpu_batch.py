@@ -215,13 +215,15 @@ def test_graph_replays_equal_eager_render(engine):
     dict(refill_min=48, blocks_per_cu=0, tile_log2w=3, engine=0, exit_lanes=8, block_size=512),
     dict(refill_min=30, blocks_per_cu=2, tile_log2w=4, engine=0, exit_lanes=12, top_levels=3, stack_entries=8,
          block_size=512),
+    dict(refill_min=56, blocks_per_cu=0, tile_log2w=3, engine=0, exit_lanes=16, tile_order=0),
+    dict(refill_min=64, blocks_per_cu=1, tile_log2w=6, engine=0, exit_lanes=4, tile_order=0),
 ])
 def test_tuning_does_not_change_images(tuning):
     say("tuning", tuning)
     sc = scenegen.terrain_patch(12, 40, 20)
     s = rcp.Scene(sc)
     ref_img, ref_ids = single(s, PATCH_CAM, 67, 45, 5, 0.0, 0.1)
-    t = dict(top_levels=4, stack_entries=16, block_size=256)
+    t = dict(top_levels=4, stack_entries=16, block_size=256, tile_order=1)
     t.update(tuning)
     rcp.rcp_set_tuning(s.handle, **t)
     assert rcp.rcp_get_tuning(s.handle) == t
