@@ -307,12 +307,14 @@ void rcp_graph_destroy(rcp_graph* graph);
 
 /* Launch parameters of the persistent kernels, per scene.  They change only
  * the speed, never an image.
- *   refill_min     lanes (1..64, default 56) needing a ray that make a wave
- *                  run a setup round (new pixels, and pixels moving to their
- *                  next pass)
+ *   refill_min     lanes (1..64) needing a ray that make a wave run a setup
+ *                  round (new pixels, and pixels moving to their next pass);
+ *                  -1 (default): 64 for single renders with the tiles in cost
+ *                  order (tile_order below), 56 for launches in screen order
  *   exit_lanes     a wave's descent to the leaves ends once no more than this
- *                  many lanes (0..64, default 16) are still looking for one
- *                  and at least as many hold one
+ *                  many lanes (0..64) are still looking for one and at least
+ *                  as many hold one; -1 (default): 32 in cost order, 16 in
+ *                  screen order
  *   blocks_per_cu  resident workgroups of 256 threads per compute unit (0 =
  *                  occupancy limit; a workgroup of 512 counts as two)
  *   tile_log2w     pixel tile of 64: width 2^tile_log2w (0..6)

@@ -505,11 +505,11 @@ void rcp_graph_destroy(rcp_graph* g) {
 rcp_status rcp_get_tuning(const rcp_scene* s, rcp_tuning* out) {
     clear_error();
     if (!s || !out) FAIL("scene and out must not be NULL");
-    const Launch l = launch_params(s);
-    out->refill_min = l.refill_min;
-    out->exit_lanes = l.exit_lanes;
-    out->blocks_per_cu = l.blocks_per_cu;
-    out->tile_log2w = l.tile_log2w;
+    // the parameters as set (-1: the library's default for each launch)
+    out->refill_min = s->tuning.refill_min > 0 ? s->tuning.refill_min : -1;
+    out->exit_lanes = s->tuning.exit_lanes >= 0 ? s->tuning.exit_lanes : -1;
+    out->blocks_per_cu = s->tuning.blocks_per_cu;
+    out->tile_log2w = s->tuning.tile_log2w;
     out->engine = s->tuning.engine;
     out->top_levels = s->tuning.top_levels;
     out->stack_entries = s->tuning.stack;
@@ -521,8 +521,8 @@ rcp_status rcp_get_tuning(const rcp_scene* s, rcp_tuning* out) {
 rcp_status rcp_set_tuning(rcp_scene* s, const rcp_tuning* t) {
     clear_error();
     if (!s || !t) FAIL("scene and tuning must not be NULL");
-    if (t->refill_min < 1 || t->refill_min > 64) FAIL("refill_min must be in [1, 64]");
-    if (t->exit_lanes < 0 || t->exit_lanes > 64) FAIL("exit_lanes must be in [0, 64]");
+    if (t->refill_min != -1 && (t->refill_min < 1 || t->refill_min > 64)) FAIL("refill_min must be -1 or in [1, 64]");
+    if (t->exit_lanes < -1 || t->exit_lanes > 64) FAIL("exit_lanes must be -1 or in [0, 64]");
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) FAIL("blocks_per_cu must be in [0, 64]");
     if (t->tile_log2w < 0 || t->tile_log2w > 6) FAIL("tile_log2w must be in [0, 6]");
     if (t->engine != RCP_ENGINE_CHAIN && t->engine != RCP_ENGINE_PASSES) FAIL("unknown engine %d", t->engine);

@@ -579,7 +579,7 @@ size_t order_entries(int W, int H, int tile_log2w) {
 }  // namespace
 
 rcp_status prepare_chain(rcp_scene* s, Workspace& ws, int W, int H, int mode, hipStream_t stream) {
-    const Launch lp = launch_params(s);
+    const Launch lp = launch_params(s, chain_ordered(s));
     ChainGrid g1, g2;
     rcp_status st = chain_grid(lp, false, 1, mode, g1);
     if (st == RCP_OK) st = chain_grid(lp, true, 1, mode, g2);
@@ -635,7 +635,7 @@ rcp_status launch_one_view(rcp_scene* s, Workspace& w, const Launch& lp, const C
 rcp_status render_chain(rcp_scene* s, Workspace& w, const Camera& cam, int W, int H, int K, const Disp& disp,
                         float* out_images, int32_t* out_ids, unsigned long long* host_counts, hipStream_t stream) {
     const bool stats = host_counts != nullptr;
-    const Launch lp = launch_params(s);
+    const Launch lp = launch_params(s, chain_ordered(s));
     ChainGrid g;
     rcp_status st = chain_grid(lp, stats, 1, disp.mode, g);
     if (st != RCP_OK) return st;

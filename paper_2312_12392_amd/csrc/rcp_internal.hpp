@@ -167,7 +167,14 @@ constexpr int kMaxPasses = 64;
 // read from LDS, stack entries spilled to global memory.
 constexpr int kStatCols = 6;
 // Defaults of the launch parameters, measured on the 1080p K=6 terrain frame.
+// Launches in screen order (batches, the per-pass engine, the allocation-free
+// render): refill at 56 idle lanes, early exit at 16.  Single renders with the
+// tiles in cost order: a wave refills only once all its lanes are idle (it
+// then takes one whole tile) and exits at 32 lanes -- 3.0% faster there, but
+// 5% slower on a batch in screen order.
 constexpr int kDefaultExitLanes = 16;
+constexpr int kDefaultExitLanesOrdered = 32;
+constexpr int kDefaultRefillOrdered = 64;
 // Levels of the 4-wide BVH the chain engine reads from LDS: LDS reads bypass
 // the vector-memory address unit, the busiest unit of the traversal.
 // Measured: 2 levels no gain, 3 levels 2% faster, 4 levels 1% more as long as
@@ -202,8 +209,8 @@ struct BatchWorkspace {
 };
 
 struct Tuning {
-    int refill_min = -1;          // < 0: the library default
-    int exit_lanes = kDefaultExitLanes;
+    int refill_min = -1;          // < 0: the library default for the launch
+    int exit_lanes = -1;          // likewise
     int blocks_per_cu = 0;        // 0: occupancy limit
     int tile_log2w = 3;           // 8x8 tiles
     int engine = RCP_ENGINE_CHAIN;
@@ -302,7 +309,11 @@ struct Launch {
     int stack;               // chain engine, colour mode: LDS stack entries per lane
     int block;               // and workgroup size
 };
-Launch launch_params(const rcp_scene* s);
+// ordered: a single render with its tiles in cost order (the defaults of
+// refill_min and exit_lanes depend on it).
+Launch launch_params(const rcp_scene* s, bool ordered = false);
+// Whether single renders of the chain engine on this scene use the cost order.
+inline bool chain_ordered(const rcp_scene* s) { return s->tuning.tile_order != 0 && s->occ.bits != nullptr; }
 
 // Make sure a render workspace fits a K-pass W x H render in `mode` (no
 // allocation happens in render afterwards for that size).

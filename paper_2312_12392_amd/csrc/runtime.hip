@@ -112,8 +112,13 @@ rcp_status descend(rcp_scene* s, Run&& run, bool tune_engine, int repeats, Tunin
     const std::vector<int> stacks = {16, 8};
     const std::vector<int> blocks_sz = {256, 512};
     const std::vector<int> orders = {1, 0};
+    // start from the parameters the launches use now (defaults made explicit)
     Tuning cur = s->tuning;
-    if (cur.refill_min <= 0) cur.refill_min = kDefaultRefill;
+    {
+        const Launch l = launch_params(s, tune_engine && chain_ordered(s));
+        cur.refill_min = l.refill_min;
+        cur.exit_lanes = l.exit_lanes;
+    }
     s->tuning = cur;
     float cur_ms = 0.0f;
     rcp_status st = time_runs(run, repeats, stream, e0, e1, cur_ms);

@@ -417,10 +417,12 @@ rcp_status persistent_grid(KernelT kernel, const DevScene& sc, GridInfo& g, bool
 
 }  // namespace
 
-Launch launch_params(const rcp_scene* s) {
+Launch launch_params(const rcp_scene* s, bool ordered) {
     Launch l;
-    l.refill_min = s->tuning.refill_min > 0 ? s->tuning.refill_min : kDefaultRefill;
-    l.exit_lanes = s->tuning.exit_lanes;
+    l.refill_min = s->tuning.refill_min > 0 ? s->tuning.refill_min
+                                            : (ordered ? kDefaultRefillOrdered : kDefaultRefill);
+    l.exit_lanes = s->tuning.exit_lanes >= 0 ? s->tuning.exit_lanes
+                                             : (ordered ? kDefaultExitLanesOrdered : kDefaultExitLanes);
     const int lv = s->tuning.top_levels < 0 ? 0 : (s->tuning.top_levels > kTopLevels ? kTopLevels
                                                                                     : s->tuning.top_levels);
     l.top_count = s->top_nodes[lv] < kMaxStagedNodes ? s->top_nodes[lv] : kMaxStagedNodes;
