@@ -17,14 +17,17 @@ namespace rcp {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kStack = 16;                       // per-lane LDS stack entries (a power of two)
+constexpr int kStack = 16;                       // per-lane LDS stack entries
 constexpr float kSlack = 1.0f + 1.0f / 65536.0f; // relative widening of the best-hit bound
 
-// Global overflow entries per thread: the LDS ring holds `stack` entries
-// (kStack unless the chain engine is tuned otherwise), and a 4-wide visit
-// keeps room for three pushes in it.
+// Global overflow entries per thread.  The LDS part holds `stack` entries
+// (kStack unless the chain engine is tuned otherwise), and entries move to
+// the overflow area stack / 2 at a time, when a push finds fewer than three
+// free LDS slots: at most stack_bound - (stack - 2) + stack / 2 entries
+// are then in the overflow area (three more kept as a margin).
 inline size_t spill_per_thread(const DevScene& d, int stack = kStack) {
-    return d.stack_bound + 3u > (uint32_t)stack ? d.stack_bound + 3u - (uint32_t)stack : 1u;
+    const uint32_t keep = (uint32_t)(stack - stack / 2);
+    return d.stack_bound + 3u > keep ? d.stack_bound + 3u - keep : 1u;
 }
 
 
@@ -269,42 +272,54 @@ struct Hit {
     bool front;
 };
 
-// Per-lane traversal stack: the newest STACK entries live in LDS (column
-// threadIdx.x of the workgroup's STACK x BLOCK stack area), older ones in the
-// lane's global overflow area.
+// Per-lane traversal stack: the newest entries live in LDS (column
+// threadIdx.x of the workgroup's STACK x BLOCK stack area, LDS entry i at
+// lds[i * BLOCK]), older ones in the lane's global overflow area (entry j at
+// spill[j * stride]).  A push that would not fit moves the oldest STACK / 2
+// LDS entries to the overflow area and the others down; a pop with no LDS
+// entry takes the newest overflow entry directly.  The order of the entries
+// is that of one plain stack, and LDS addresses are linear in the stack
+// pointer: one address per push or pop, the pushed entries at constant
+// offsets from it.
 template <int STACK, int BLOCK>
 struct StackT {
-    static_assert((STACK & (STACK - 1)) == 0 && STACK >= 4, "the LDS stack ring is indexed with a mask");
-    int32_t* lds;       // &stack_area[tid]; entry e at lds[(e % STACK) * BLOCK]
-    int32_t* spill;     // &spill[gtid]; entry e at spill[e * stride]
+    static_assert(STACK / 2 >= 3, "moving half the LDS entries leaves room for three pushes");
+    static constexpr uint32_t kMove = STACK / 2;
+    int32_t* lds;       // &stack_area[tid]
+    int32_t* spill;     // &spill[gtid]
     uint32_t stride;
-    uint32_t sp, lo;    // entries [0, lo) spilled, [lo, sp) in LDS
+    uint32_t sp;        // entries in LDS
+    uint32_t ns;        // entries in the overflow area (all older than those in LDS)
 
-    __device__ inline LdsI32* ring(uint32_t e) const {
-        return (LdsI32*)lds + (e & (uint32_t)(STACK - 1)) * BLOCK;
-    }
-    // Push np (0..3) entries, e0 deepest, with one check for room: three ring
+    // Push np (1..3) entries, e0 deepest, with one check for room: three LDS
     // slots are written whatever np is (those above the new top are unused).
     // n_spill counts the entries moved to the global area.
     __device__ inline void push_up_to_3(int32_t e0, int32_t e1, int32_t e2, uint32_t np, uint32_t& n_spill) {
-        while (sp + 3u - lo > (uint32_t)STACK) {
-            spill[(size_t)lo * stride] = *ring(lo);
-            ++lo;
-            ++n_spill;
+        LdsI32* l = (LdsI32*)lds;
+        if (sp + 3u > (uint32_t)STACK) {
+#pragma unroll
+            for (uint32_t i = 0; i < kMove; ++i) spill[(size_t)(ns + i) * stride] = l[i * BLOCK];
+#pragma unroll
+            for (uint32_t i = kMove; i < (uint32_t)STACK; ++i)
+                if (i < sp) l[(i - kMove) * BLOCK] = l[i * BLOCK];
+            ns += kMove;
+            sp -= kMove;
+            n_spill += kMove;
         }
-        *ring(sp) = e0;
-        *ring(sp + 1u) = e1;
-        *ring(sp + 2u) = e2;
+        LdsI32* top = l + sp * BLOCK;
+        top[0] = e0;
+        top[BLOCK] = e1;
+        top[2 * BLOCK] = e2;
         sp += np;
     }
     __device__ inline int32_t pop() {
-        if (sp == 0u) return -1;
-        --sp;
-        if (sp < lo) {       // the LDS part is empty: take the newest spilled entry
-            lo = sp;
-            return spill[(size_t)sp * stride];
+        if (sp != 0u) {
+            --sp;
+            return ((LdsI32*)lds)[sp * BLOCK];
         }
-        return *ring(sp);
+        if (ns == 0u) return -1;
+        --ns;
+        return spill[(size_t)ns * stride];
     }
 };
 
@@ -391,7 +406,7 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
     tv.h.slot = 0;
     tv.h.front = false;
     st.sp = 0;
-    st.lo = 0;
+    st.ns = 0;
 }
 
 // Traversal counters of the instrumented kernels (dead code otherwise).
