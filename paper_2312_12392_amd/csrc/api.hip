@@ -115,6 +115,11 @@ rcp_status take_device_error(rcp_scene* s) {
                   "unwritten or invalid, or one above it overwritten)");
         return RCP_ERR_INTERNAL;
     }
+    if (e == kErrLdsLayout) {
+        set_error("the chain kernel's dynamic LDS does not start at address 0, where the traversal reads the "
+                  "staged BVH levels: nothing was rendered");
+        return RCP_ERR_INTERNAL;
+    }
     if (e != 0u) {
         set_error("a ray ran out of its traversal step budget (%u steps): the BVH is malformed, and that ray's "
                   "result is a miss", s->dev.step_budget);

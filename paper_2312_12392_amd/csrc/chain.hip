@@ -83,6 +83,14 @@ __device__ inline void chain_body(const ChainArgs& a) {
     // plane offsets serve both), then the stats, view starts and stack area
     extern __shared__ float4 smem[];
     float4* top = smem;
+    // the traversal reads staged node i at LDS byte address 128 i: the
+    // dynamic LDS must begin at address 0, as it does while the kernel
+    // declares no LDS of its own (otherwise the launch does nothing and
+    // raises the scene's error flag)
+    if ((uint32_t)(size_t)(const LdsV4*)top != 0u) {
+        if (threadIdx.x == 0) __hip_atomic_store(a.sc.err_flag, kErrLdsLayout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        return;
+    }
     char* lds = (char*)(smem + 8 * (size_t)a.sc.top_count);
     unsigned long long* lstats = (unsigned long long*)lds;                // STATS: kStatCols * kMaxPasses
     if (STATS) lds += sizeof(unsigned long long) * kStatCols * kMaxPasses;
@@ -260,7 +268,7 @@ __device__ inline void chain_body(const ChainArgs& a) {
         }
 
         // ---- one traversal step -------------------------------------------------
-        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, top, st, a.exit_lanes, cnt);
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, st, a.exit_lanes, cnt);
 
         if (alive && tv.node == -1) {   // the pass is traced: finish it in the next round
             alive = false;

@@ -59,6 +59,7 @@ int debug_list_canary();
 // Values of the scene's device error flag.
 constexpr uint32_t kErrStepBudget = 1u;   // a ray ran out of its step budget
 constexpr uint32_t kErrListCanary = 2u;   // a compaction list failed its canary check
+constexpr uint32_t kErrLdsLayout = 3u;    // the chain kernel's LDS did not start at address 0
 
 // Scratch device memory ordered on a stream: allocated for the work enqueued
 // after the call, released once the stream's earlier work is done, with no
@@ -108,7 +109,7 @@ struct DevScene {
     float radius;      // largest |coordinate| of any vertex
     float bg[3];
     uint32_t step_budget;   // traversal steps per ray (only a malformed tree reaches it)
-    uint32_t* err_flag;     // host-mapped; kErrStepBudget or kErrListCanary once raised
+    uint32_t* err_flag;     // host-mapped; one of the kErr values once raised
 };
 
 struct Camera {

@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
         }
 
         // ---- one traversal step -------------------------------------------
-        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, nullptr, st, a.exit_lanes, cnt);
+        if (alive && tv.node != -1) trav_step<STATS>(tv, a.sc, st, a.exit_lanes, cnt);
 
         // ---- finished rays: shade, write, compact ----------------------------
         const bool done = alive && tv.node == -1;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_rays(DevScene sc, const float*
         Trav tv;
         trav_init(tv, sc, o, d, st);
         TravCount cnt;
-        while (tv.node != -1) trav_step<false>(tv, sc, nullptr, st, 0u, cnt);
+        while (tv.node != -1) trav_step<false>(tv, sc, st, 0u, cnt);
         const bool hit = tv.h.id != INT_MAX;
         out_t[r] = hit ? tv.h.t : INFINITY;
         out_id[r] = hit ? tv.h.id : -1;

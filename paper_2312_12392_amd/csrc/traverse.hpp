@@ -363,6 +363,7 @@ struct Trav {
                             // the exit plane is at off ^ 16
     int32_t node;           // >= 0 inner node, other negative: leaf link, -1: finished
     uint32_t budget;
+    float lim;              // h.t * kSlack
     Hit h;
 };
 
@@ -402,6 +403,7 @@ __device__ inline void trav_init(Trav& tv, const DevScene& sc, const float o[3],
     // should the tree ever be malformed.
     tv.budget = sc.step_budget;
     tv.h.t = INFINITY;
+    tv.lim = INFINITY;
     tv.h.id = INT_MAX;
     tv.h.slot = 0;
     tv.h.front = false;
@@ -432,43 +434,47 @@ __device__ inline void order2(uint32_t& ka, int32_t& va, uint32_t& kb, int32_t& 
 // as above), continue with the nearest hit child and push the other hit
 // children farthest first, or pop when none is hit.  Node layout (8 float4,
 // 128 bytes): lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of children 0..3, then their
-// links.  The top levels staged in LDS keep the same 128-byte layout, so one
-// set of offsets serves both.
+// links.  The first sc.top_count nodes, when a kernel stages them, sit in LDS
+// from address 0 of the workgroup's LDS in the same layout, so one set of
+// byte offsets addresses a node in either place.
 typedef float V4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) V4 LdsV4;
 
 __device__ inline float4 f4(V4 v) { return make_float4(v.x, v.y, v.z, v.w); }
 
+// The 16 bytes at LDS byte address `byte` of the workgroup.
+__device__ inline float4 lds_f4(uint32_t byte) { return f4(*(const LdsV4*)(size_t)byte); }
+
 template <bool STATS, class Stack>
-__device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& sc, const float4* top, Stack& st,
-                                       TravCount& cnt) {
+__device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& sc, Stack& st, TravCount& cnt) {
     // byte offsets of the entry and exit planes of the three axes (the
-    // node array is limited to 4 GB, so offsets fit 32 bits)
+    // node array is limited to 4 GB, so offsets fit 32 bits), the same in
+    // LDS and in the node array
     const uint32_t base = (uint32_t)node << 7;
     const uint32_t e0 = base + tv.off[0], e1 = base + tv.off[1], e2 = base + tv.off[2];
+    const uint32_t f0 = e0 ^ 16u, f1 = e1 ^ 16u, f2 = e2 ^ 16u;
     float4 n0, x0, n1, x1, n2, x2, lk;
     if ((uint32_t)node < sc.top_count) {
         // the top levels, staged in LDS: LDS reads do not use the vector
         // memory address path (the compiler barrier keeps the two paths from
         // being merged into flat loads)
-        const char __attribute__((address_space(3)))* t = (const char __attribute__((address_space(3)))*)top;
-        n0 = f4(*(const LdsV4*)(t + e0)); x0 = f4(*(const LdsV4*)(t + (e0 ^ 16u)));
-        n1 = f4(*(const LdsV4*)(t + e1)); x1 = f4(*(const LdsV4*)(t + (e1 ^ 16u)));
-        n2 = f4(*(const LdsV4*)(t + e2)); x2 = f4(*(const LdsV4*)(t + (e2 ^ 16u)));
-        lk = f4(*(const LdsV4*)(t + base + 96u));
+        n0 = lds_f4(e0); x0 = lds_f4(f0);
+        n1 = lds_f4(e1); x1 = lds_f4(f1);
+        n2 = lds_f4(e2); x2 = lds_f4(f2);
+        lk = lds_f4(base + 96u);
         __asm__ volatile("" ::: "memory");
     } else {
         const char* g = (const char*)sc.nodes;
-        n0 = *(const float4*)(g + e0); x0 = *(const float4*)(g + (e0 ^ 16u));
-        n1 = *(const float4*)(g + e1); x1 = *(const float4*)(g + (e1 ^ 16u));
-        n2 = *(const float4*)(g + e2); x2 = *(const float4*)(g + (e2 ^ 16u));
+        n0 = *(const float4*)(g + e0); x0 = *(const float4*)(g + f0);
+        n1 = *(const float4*)(g + e1); x1 = *(const float4*)(g + f1);
+        n2 = *(const float4*)(g + e2); x2 = *(const float4*)(g + f2);
         lk = *(const float4*)(g + base + 96u);
     }
     if (STATS) {
         ++cnt.nodes;
         if ((uint32_t)node < sc.top_count) ++cnt.lds;
     }
-    const float lim = tv.h.t * kSlack;
+    const float lim = tv.lim;
     uint32_t key[4];    // entry distance bits of hit children (t >= 0), all ones for the rest
     int32_t val[4];
     uint32_t nh = 0;
@@ -525,6 +531,7 @@ __device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, Tr
             const int32_t id = __float_as_int(v0.w);
             if (t < tv.h.t || (t == tv.h.t && id < tv.h.id)) {
                 tv.h.t = t;
+                tv.lim = t * kSlack;
                 tv.h.id = id;
                 tv.h.slot = first + j;
                 tv.h.front = front;
@@ -549,8 +556,7 @@ __device__ inline void visit_leaf(Trav& tv, int32_t link, const DevScene& sc, Tr
 constexpr int kMaxDescent = 256;   // node visits of one step (the step ends, the ray goes on)
 
 template <bool STATS, class Stack>
-__device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* top, Stack& st, uint32_t exit_lanes,
-                                 TravCount& cnt) {
+__device__ inline void trav_step(Trav& tv, const DevScene& sc, Stack& st, uint32_t exit_lanes, TravCount& cnt) {
     if (--tv.budget == 0u) {
         // only a malformed tree gets here: end the ray and raise the scene's
         // error flag, which the host reports as an internal error
@@ -569,7 +575,7 @@ __device__ inline void trav_step(Trav& tv, const DevScene& sc, const float4* top
         if (it > 0 && (uint32_t)__popcll(searching) <= exit_lanes &&
             __popcll(wave_ballot(leaf != -1)) >= __popcll(searching))
             break;
-        if (node >= 0) node = visit_inner4<STATS>(tv, node, sc, top, st, cnt);
+        if (node >= 0) node = visit_inner4<STATS>(tv, node, sc, st, cnt);
     }
     if (leaf != -1) visit_leaf<STATS>(tv, leaf, sc, cnt);
     tv.node = node;
