@@ -80,7 +80,8 @@ template <bool STATS, int MODE, bool ONE, int STACK, int BLOCK>
 __device__ inline void chain_body(const ChainArgs& a) {
     constexpr bool AUX = MODE != RCP_MODE_COLOR;
     // LDS: the staged top levels (128-byte nodes, as in HBM, so the same
-    // plane offsets serve both), then the stats, view starts and stack area
+    // plane offsets serve both), then the stack area, the stats and the view
+    // starts
     extern __shared__ float4 smem[];
     float4* top = smem;
     // the traversal reads staged node i at LDS byte address 128 i: the
@@ -91,12 +92,14 @@ __device__ inline void chain_body(const ChainArgs& a) {
         if (threadIdx.x == 0) __hip_atomic_store(a.sc.err_flag, kErrLdsLayout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         return;
     }
+    // (the stack directly after the nodes: its column addresses then carry no
+    // constant offset, which the paired LDS writes of a push could not encode)
     char* lds = (char*)(smem + 8 * (size_t)a.sc.top_count);
+    int32_t* stack_area = (int32_t*)lds;                                  // STACK * BLOCK
+    lds += sizeof(int32_t) * STACK * BLOCK;
     unsigned long long* lstats = (unsigned long long*)lds;                // STATS: kStatCols * kMaxPasses
     if (STATS) lds += sizeof(unsigned long long) * kStatCols * kMaxPasses;
     uint32_t* vbegin = (uint32_t*)lds;                                    // n_views + 1
-    lds += sizeof(uint32_t) * (size_t)((a.n_views + 4) & ~3);
-    int32_t* stack_area = (int32_t*)lds;                                  // STACK * BLOCK
 
     const ConstView* views = (const ConstView*)a.views;
     if (!ONE)

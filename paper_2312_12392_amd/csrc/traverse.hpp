@@ -38,6 +38,12 @@ __device__ inline float sel3(float x, float y, float z, int k) {
 // Mask of the wave's lanes where p holds (straight to a scalar register).
 __device__ inline unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Lanes set in a wave mask, counted as two 32-bit halves: a count taken on
+// the 64-bit value was compared in 64 bits, which the scalar unit cannot do.
+__device__ inline uint32_t popc_u32(unsigned long long m) {
+    return (uint32_t)__builtin_popcount((uint32_t)m) + (uint32_t)__builtin_popcount((uint32_t)(m >> 32));
+}
+
 __device__ inline uint32_t lanes_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
@@ -477,7 +483,7 @@ __device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& s
     const float lim = tv.lim;
     uint32_t key[4];    // entry distance bits of hit children (t >= 0), all ones for the rest
     int32_t val[4];
-    uint32_t nh = 0;
+    bool any = false;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float a0 = __builtin_fmaf(lane_of(n0, i), tv.inv[0], -tv.ent[0]);
@@ -493,23 +499,23 @@ __device__ inline int32_t visit_inner4(Trav& tv, int32_t node, const DevScene& s
         // slot has NaN planes: tmax and a2 are NaN and both tests fail (its
         // link, a one-triangle leaf, is never followed)
         const bool hit = tmin <= tmax && a2 <= lim;
-        key[i] = hit ? __float_as_uint(tmin) : 0xFFFFFFFFu;
+        key[i] = hit ? __float_as_uint(tmin) : 0xFFFFFFFFu;   // a hit's tmin is never NaN
         val[i] = (int32_t)link;
-        nh += hit ? 1u : 0u;
+        any = any || hit;
     }
-    // a full sorting network: hits ascending, then the misses, so that
-    // val[0 .. nh) are exactly the hit children
+    // a full sorting network: hits ascending, then the misses, so that the
+    // hit children are val[0 .. n) for the n keys that are not all ones
     order2(key[0], val[0], key[1], val[1]);
     order2(key[2], val[2], key[3], val[3]);
     order2(key[0], val[0], key[2], val[2]);
     order2(key[1], val[1], key[3], val[3]);
     order2(key[1], val[1], key[2], val[2]);
-    if (nh == 0u) return st.pop();
-    if (nh > 1u) {
-        const uint32_t np = nh - 1u;
-        const int32_t e0 = np == 3u ? val[3] : (np == 2u ? val[2] : val[1]);
-        const int32_t e1 = np == 3u ? val[2] : val[1];
-        st.push_up_to_3(e0, e1, val[1], np, cnt.spill);
+    if (!any) return st.pop();
+    if (key[1] != 0xFFFFFFFFu) {   // two hits or more: push all but the nearest
+        const bool h2 = key[2] != 0xFFFFFFFFu, h3 = key[3] != 0xFFFFFFFFu;
+        const int32_t e0 = h3 ? val[3] : (h2 ? val[2] : val[1]);
+        const int32_t e1 = h3 ? val[2] : val[1];
+        st.push_up_to_3(e0, e1, val[1], 1u + (h2 ? 1u : 0u) + (h3 ? 1u : 0u), cnt.spill);
     }
     return val[0];
 }
@@ -560,7 +566,7 @@ __device__ inline void trav_step(Trav& tv, const DevScene& sc, Stack& st, uint32
     if (--tv.budget == 0u) {
         // only a malformed tree gets here: end the ray and raise the scene's
         // error flag, which the host reports as an internal error
-        __hip_atomic_store(sc.err_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(sc.err_flag, kErrStepBudget, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         tv.node = -1;
         return;
     }
@@ -568,13 +574,15 @@ __device__ inline void trav_step(Trav& tv, const DevScene& sc, Stack& st, uint32
     int32_t leaf = -1;
     for (int it = 0; it < kMaxDescent; ++it) {
         if (node < -1 && leaf == -1) { leaf = node; node = st.pop(); }
-        const unsigned long long searching = wave_ballot(leaf == -1 && node >= 0);
+        // (the ballot of each compare alone maps onto one VALU compare; a
+        // ballot of their conjunction was materialised through a select)
+        const unsigned long long holding = wave_ballot(leaf != -1);
+        const unsigned long long searching = ~holding & wave_ballot(node >= 0);
         if (searching == 0ull) break;
         // only a few lanes still looking for a leaf: let the others test
         // theirs (every searching lane has advanced one node this step)
-        if (it > 0 && (uint32_t)__popcll(searching) <= exit_lanes &&
-            __popcll(wave_ballot(leaf != -1)) >= __popcll(searching))
-            break;
+        const uint32_t n_search = popc_u32(searching);
+        if (it > 0 && n_search <= exit_lanes && popc_u32(holding) >= n_search) break;
         if (node >= 0) node = visit_inner4<STATS>(tv, node, sc, st, cnt);
     }
     if (leaf != -1) visit_leaf<STATS>(tv, leaf, sc, cnt);
