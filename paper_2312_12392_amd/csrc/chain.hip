@@ -377,40 +377,45 @@ __global__ __launch_bounds__(kScoreBlock) void k_tile_scores(ViewDev v, OccGrid 
     }
     uint32_t count = 0;
     if (!miss && tmin <= tmax) {
-        int c[3], step[3];
+        // per axis: the next boundary's t, its spacing, the cell index stride
+        // of a step and the steps left inside the grid
         float tnext[3], tdelta[3];
+        int stride[3];
+        uint32_t left[3];
+        int cell = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const float p = o[a] + tmin * d[a];
             int q = (int)floorf((p - g.lo[a]) / g.cell[a]);
             q = q < 0 ? 0 : (q >= g.n[a] ? g.n[a] - 1 : q);
-            c[a] = q;
-            step[a] = d[a] > 0.0f ? 1 : (d[a] < 0.0f ? -1 : 0);
-            tnext[a] = step[a] == 0 ? INFINITY
-                                    : (g.lo[a] + (float)(q + (step[a] > 0 ? 1 : 0)) * g.cell[a] - o[a]) * inv[a];
-            tdelta[a] = step[a] == 0 ? INFINITY : g.cell[a] * fabsf(inv[a]);
+            const int step = d[a] > 0.0f ? 1 : (d[a] < 0.0f ? -1 : 0);
+            tnext[a] = step == 0 ? INFINITY
+                                 : (g.lo[a] + (float)(q + (step > 0 ? 1 : 0)) * g.cell[a] - o[a]) * inv[a];
+            tdelta[a] = step == 0 ? INFINITY : g.cell[a] * fabsf(inv[a]);
+            const int unit = a == 0 ? 1 : (a == 1 ? g.n[0] : g.n[0] * g.n[1]);
+            stride[a] = step * unit;
+            left[a] = step > 0 ? (uint32_t)(g.n[a] - 1 - q) : (step < 0 ? (uint32_t)q : 0u);
+            cell += q * unit;
         }
+        // one step per iteration, without branches: the axis whose boundary
+        // comes first (x, then y, then z among equal ones); the walk ends past
+        // tmax or at the grid's side
         const int steps = g.n[0] + g.n[1] + g.n[2];
         for (int it = 0; it < steps; ++it) {
-            const uint32_t cell = (uint32_t)((c[2] * g.n[1] + c[1]) * g.n[0] + c[0]);
-            count += (occ[cell >> 5] >> (cell & 31u)) & 1u;
-            // the next cell along the axis whose boundary comes first
-            if (tnext[0] <= tnext[1] && tnext[0] <= tnext[2]) {
-                if (tnext[0] > tmax) break;
-                c[0] += step[0];
-                tnext[0] += tdelta[0];
-                if (c[0] < 0 || c[0] >= g.n[0]) break;
-            } else if (tnext[1] <= tnext[2]) {
-                if (tnext[1] > tmax) break;
-                c[1] += step[1];
-                tnext[1] += tdelta[1];
-                if (c[1] < 0 || c[1] >= g.n[1]) break;
-            } else {
-                if (tnext[2] > tmax) break;
-                c[2] += step[2];
-                tnext[2] += tdelta[2];
-                if (c[2] < 0 || c[2] >= g.n[2]) break;
-            }
+            count += (occ[(uint32_t)cell >> 5] >> ((uint32_t)cell & 31u)) & 1u;
+            const bool ax = tnext[0] <= tnext[1] && tnext[0] <= tnext[2];
+            const bool ay = !ax && tnext[1] <= tnext[2];
+            const bool az = !ax && !ay;
+            const float tn = ax ? tnext[0] : (ay ? tnext[1] : tnext[2]);
+            const uint32_t l = ax ? left[0] : (ay ? left[1] : left[2]);
+            if (tn > tmax || l == 0u) break;
+            cell += ax ? stride[0] : (ay ? stride[1] : stride[2]);
+            tnext[0] += ax ? tdelta[0] : 0.0f;
+            tnext[1] += ay ? tdelta[1] : 0.0f;
+            tnext[2] += az ? tdelta[2] : 0.0f;
+            left[0] -= ax ? 1u : 0u;
+            left[1] -= ay ? 1u : 0u;
+            left[2] -= az ? 1u : 0u;
         }
     }
     score[t] = count;
