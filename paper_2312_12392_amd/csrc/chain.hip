@@ -71,6 +71,11 @@ struct ChainArgs {
 };
 
 
+// Lanes waiting for a setup round that start one once the bands are used up
+// (measured on the terrain frame: 1 -- a round for every waiting lane --
+// 0.6% slower; 4 and 12 within 0.2%; 16 and 24 slower again).
+constexpr uint32_t kDrainedRound = 8;
+
 // ONE: the launch holds a single view.  Its entry is then read with scalar
 // loads (the table is constant during the launch), not per lane through the
 // vector-memory path, which the traversal keeps busy.
@@ -136,9 +141,15 @@ __device__ inline void chain_body(const ChainArgs& a) {
         // ---- setup round, when enough lanes wait: finish the traced passes,
         // fetch new pixels for idle lanes, and set up the rays of new pixels and
         // of next passes together (work done by a few lanes alone wastes the wave)
+        // Once the bands are used up, lanes waiting for their next pass no
+        // longer wait for refill_min idle lanes (their chains decide when the
+        // launch ends), but for kDrainedRound of them, or for the wave's last
+        // ray to end: a round costs the same for 1 lane as for 64.
         const unsigned long long need = wave_ballot(!alive);
         const unsigned long long waiting = wave_ballot(ended || pending);
-        if ((uint32_t)__popcll(need) >= (uint32_t)a.refill_min || (drained && waiting != 0ull)) {
+        const uint32_t n_need = popc_u32(need), n_wait = popc_u32(waiting);
+        if (n_need >= (uint32_t)a.refill_min ||
+            (drained && n_wait != 0u && (n_wait >= kDrainedRound || n_need == 64u))) {
             // lanes whose pass is traced: shade, write, and keep the inputs
             // of the next pass or end the chain
             if (ended) {
