@@ -341,8 +341,10 @@ void rcp_graph_destroy(rcp_graph* graph);
  *                  cells of a coarse occupancy grid of the scene that the
  *                  undisplaced ray through the tile's centre crosses, found
  *                  by two small kernels before the launch -- so that long
- *                  chains start first; 0 in screen order.  Batches and
- *                  rcp_render_noalloc always use the screen order.
+ *                  chains start first; 0 in screen order.  A batch of one
+ *                  view follows it too (a server slot only up to 2^18
+ *                  tiles); batches of more views and rcp_render_noalloc
+ *                  always use the screen order.
  * The instrumented kernel and the depth and normal modes always use 16
  * stack entries and workgroups of 256. */
 #define RCP_ENGINE_CHAIN 0

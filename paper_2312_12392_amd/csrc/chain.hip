@@ -748,6 +748,8 @@ rcp_status prepare_batch_workspace(rcp_scene* s, BatchWorkspace& ws, int n_views
     if (st == RCP_OK) st = grow(&ws.fetch, fetch_cap, kFetchWords * 3, sizeof(uint32_t), stream);
     if (st == RCP_OK)
         st = grow(&ws.spill, ws.spill_cap, spill_need, sizeof(int32_t), stream);
+    if (st == RCP_OK && with_staging && ws.order_cap < 2 * kServerOrderTiles)
+        st = grow(&ws.order, ws.order_cap, 2 * kServerOrderTiles, sizeof(uint32_t), stream);
     if (st == RCP_OK && with_staging && !ws.staging) {
         if (alloc_hook_fails()) {
             set_error("pinned host allocation failed (test hook)");
@@ -837,9 +839,28 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
     ViewDev* d_views = (ViewDev*)ws.views;
     const size_t begin_ofs = (sizeof(ViewDev) * (size_t)n_views + 255) & ~(size_t)255;
     uint32_t* d_begin = (uint32_t*)((char*)ws.views + begin_ofs);
-    if (n_views == 1) {
-        // one view (a lone request of a server, say): the setup kernel writes
-        // its table from the by-value argument, with no host copy
+    // One view (a lone request of a server, say) is a single render: its
+    // tiles go out in cost order, as rcp_render's do, with the launch
+    // parameters of that order.  A server slot, whose buffers never grow,
+    // keeps the screen order for a view beyond its order buffer.
+    const uint32_t n_tiles1 = n_views == 1 ? groups[0].items >> 6 : 0u;
+    bool ordered1 = n_views == 1 && s->tuning.tile_order && s->occ.bits && n_tiles1 > 0;
+    if (ordered1 && 2 * (size_t)n_tiles1 > ws.order_cap) {
+        if (ws.staging) ordered1 = false;
+        else if ((st = grow(&ws.order, ws.order_cap, 2 * (size_t)n_tiles1, sizeof(uint32_t), stream)) != RCP_OK)
+            return st;
+    }
+    const Launch lpr = ordered1 ? launch_params(s, true) : lp;
+    if (ordered1) {
+        uint32_t* score = ws.order + n_tiles1;
+        hipLaunchKernelGGL(k_tile_scores, dim3((n_tiles1 + kScoreBlock - 1) / kScoreBlock), dim3(kScoreBlock),
+                           sizeof(uint32_t) * s->occ.words, stream, hv[0], s->occ, n_tiles1, score);
+        hipLaunchKernelGGL(k_band_order, dim3(kFetchParts + 1), dim3(1024), 0, stream, (const uint32_t*)score,
+                           groups[0].items, ws.order, hv[0], d_views, d_begin, ws.fetch,
+                           (unsigned long long*)nullptr);
+    } else if (n_views == 1) {
+        // the setup kernel writes the view's table from the by-value
+        // argument, with no host copy
         hipLaunchKernelGGL(k_setup_single, dim3(1), dim3(256), 0, stream, hv[0], d_views, d_begin,
                            groups[0].items, ws.fetch, (unsigned long long*)nullptr);
     } else if (ws.staging) {
@@ -869,10 +890,11 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
         a.n_views = groups[g].count;
         a.n_items = groups[g].items;
         a.fetch = ws.fetch + kFetchWords * g;
-        a.refill_min = lp.refill_min;
-        a.exit_lanes = (uint32_t)lp.exit_lanes;
+        a.refill_min = lpr.refill_min;
+        a.exit_lanes = (uint32_t)lpr.exit_lanes;
         a.spill = ws.spill;
         a.spill_stride = grids[g].threads();
+        a.order = ordered1 ? ws.order : nullptr;
         rcp_status st2 = launch_chain(grids[g], stream, a);
         if (st2 != RCP_OK) return st2;
     }
@@ -880,6 +902,7 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
 }
 
 void free_batch_workspace(BatchWorkspace& ws, hipStream_t stream) {
+    stream_free(ws.order, stream);
     stream_free(ws.views, stream);
     stream_free(ws.fetch, stream);
     stream_free(ws.spill, stream);

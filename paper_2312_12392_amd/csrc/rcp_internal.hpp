@@ -207,7 +207,14 @@ struct BatchWorkspace {
     int32_t* spill = nullptr;
     size_t spill_cap = 0;
     void* staging = nullptr;      // pinned host copy of the view table (servers only), view_cap views
+    uint32_t* order = nullptr;    // a one-view batch's tile order and scores (chain engine, cost order)
+    size_t order_cap = 0;         // uint32 entries
 };
+
+// Tiles of the largest one-view batch a server slot hands out in cost order
+// (2^18 tiles: 16.8M pixels, a 4K view with room to spare); larger views keep
+// the screen order, since a slot's buffers never grow.
+constexpr size_t kServerOrderTiles = size_t(1) << 18;
 
 struct Tuning {
     int refill_min = -1;          // < 0: the library default for the launch

@@ -154,6 +154,25 @@ def test_batch_of_the_maximum_view_count():
     s.close()
 
 
+def test_one_view_batch_is_a_single_render():
+    """A batch of one view hands its tiles out in cost order, as rcp_render
+    does (and in screen order with tile_order 0): the same images either way."""
+    sc = scenegen.terrain_patch(14, 40, 20)
+    s = rcp.Scene(sc)
+    for W, H, K in [(67, 45, 5), (1, 1, 3), (200, 9, 6), (128, 128, 2)]:
+        ref_img, ref_ids = single(s, PATCH_CAM, W, H, K, 0.0, 0.07)
+        for order in (1, 0):
+            say("one-view batch", W, H, K, "tile_order", order)
+            rcp.rcp_set_tuning(s.handle, tile_order=order)
+            o = torch.full((K, H, W, 3), -1.0, device="cuda")
+            i = torch.full((K, H, W), -7, dtype=torch.int32, device="cuda")
+            rcp.rcp_render_batch(s.handle, [(PATCH_CAM, W, H, K, rcp.make_displacement(0.0, 0.07), o, i)])
+            torch.cuda.synchronize()
+            assert torch.equal(o, ref_img) and torch.equal(i, ref_ids), (W, H, K, order)
+        rcp.rcp_set_tuning(s.handle, tile_order=1)
+    s.close()
+
+
 def test_batch_rejects_bad_views():
     w = scenegen.workload("soup256")
     s = rcp.Scene(w.scene)

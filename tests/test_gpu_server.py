@@ -107,6 +107,23 @@ def test_staggered_and_single_equal_alone(scene):
     rcp.rcp_server_destroy(srv)
 
 
+def test_single_requests_in_cost_order_and_beyond_the_slot_order_buffer(scene):
+    """A launch of one request hands its tiles out in cost order; a request
+    with more tiles than a slot's order buffer holds (2^18) keeps the screen
+    order.  Both equal the request rendered alone."""
+    say("server single requests, small and 4200x4100")
+    srv = rcp.rcp_server_create(scene.handle, 640 << 20, max_inflight=1)
+    cam = scenegen.camera_look_at([0, 0.5, -1.4], [0, 0.05, 0], [0, 1, 0], 60.0)
+    reqs = [(cam, 96, 64, 4, rcp.make_displacement(0.0, 0.05)),
+            (cam, 4200, 4100, 1, rcp.make_displacement(0.0, 0.05))]
+    for req in reqs:
+        cam, W, H, K, d = req
+        t = rcp.rcp_submit(srv, cam, W, H, K, d, with_ids=True)
+        wait_done(srv, [t])
+        check_against_alone(scene, srv, [req], [t])
+    rcp.rcp_server_destroy(srv)
+
+
 def test_mixed_modes_equal_alone(scene):
     say("server mixed modes")
     srv = rcp.rcp_server_create(scene.handle, 64 << 20, max_inflight=2)
