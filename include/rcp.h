@@ -405,9 +405,12 @@ typedef struct rcp_server rcp_server;
  * once and hold the output images of admitted requests (12 B per pixel and
  * pass, plus 4 B with ids, each rounded up to 256 B); requests are admitted
  * first-in first-out while they fit, and up to max_inflight (1..8) batched
- * launches run at once, each on its own stream.  A request submitted while
- * others run joins the next launch as soon as pool space and a launch slot
- * are free; every request's images equal those of rcp_render alone.  At most
+ * launches run at once, each on its own stream.  A launch takes the
+ * admitted requests of the oldest one's size class (more than 2^24 pixels
+ * times passes is big), so small requests do not wait for large ones in the
+ * same launch.  A request submitted while others run joins the next launch
+ * of its class as soon as pool space and a launch slot are free; every
+ * request's images equal those of rcp_render alone.  At most
  * queue_capacity requests wait for admission.  The scene must outlive the
  * server. */
 rcp_status rcp_server_create(rcp_scene* scene, uint64_t pool_bytes, int max_inflight, int queue_capacity,

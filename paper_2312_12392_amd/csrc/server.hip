@@ -3,9 +3,10 @@
 // Requests (a camera, image size, pass count and displacement, any mode)
 // enter a FIFO queue.  A scheduler thread admits them in order while their output
 // images fit in a device pool of fixed size (the HBM budget), packs every
-// admitted request that is not yet running into one batched launch
-// (rcp_render_batch's kernel: each pixel's pass chain is independent, so
-// requests of any size and pass count share a launch), and keeps up to
+// admitted request of the oldest one's size class that is not yet running
+// into one batched launch (rcp_render_batch's kernel: each pixel's pass
+// chain is independent, so requests of any size and pass count can share a
+// launch), and keeps up to
 // `max_inflight` launches running at once on separate streams.  Requests
 // that arrive while others are on the GPU join the next launch as soon as
 // pool space and a launch slot free up, and that launch overlaps the running
@@ -40,6 +41,12 @@ struct Req {
     int state = RCP_REQ_QUEUED;
     double t_submit = 0, t_start = 0, t_done = 0;
 };
+
+// Size classes of requests: more than 2^24 pixel-passes (1080p with 8
+// passes is below) is big.
+constexpr uint64_t kBigPixelPasses = uint64_t(1) << 24;
+
+inline bool is_big(const Req& r) { return (uint64_t)r.r.W * (uint64_t)r.r.H * (uint64_t)r.r.K > kBigPixelPasses; }
 
 struct Slot {
     hipStream_t stream = nullptr;
@@ -162,7 +169,14 @@ void schedule(rcp_server* s, std::unique_lock<std::mutex>& lk) {
     for (Slot& sl : s->slots)
         if (!sl.busy) { free_slot = &sl; break; }
     if (!free_slot) return;
-    const size_t n = std::min<size_t>(s->admitted.size(), (size_t)kMaxBatch);
+    // The launch takes the admitted requests of the oldest one's size class,
+    // in admission order: a small request does not wait for a 4K one in the
+    // same launch, and the oldest request still goes first.
+    const bool big = is_big(s->reqs[s->admitted.front()]);
+    size_t n = 0;
+    for (size_t i = 0; i < s->admitted.size() && n < (size_t)kMaxBatch; ++i)
+        if (is_big(s->reqs[s->admitted[i]]) == big) std::swap(s->admitted[n++], s->admitted[i]);
+    std::sort(s->admitted.begin() + (long)n, s->admitted.end());   // the rest in admission (ticket) order
     std::vector<rcp_view>& views = free_slot->views;
     views.resize(n);
     for (size_t i = 0; i < n; ++i) {

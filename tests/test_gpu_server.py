@@ -124,6 +124,25 @@ def test_single_requests_in_cost_order_and_beyond_the_slot_order_buffer(scene):
     rcp.rcp_server_destroy(srv)
 
 
+def test_launches_split_by_size_class(scene):
+    """A launch takes the admitted requests of the oldest request's size class
+    (above 2^24 pixel-passes is big): with one launch slot, a big request and
+    two small ones submitted together run in two launches, the big one alone
+    first; every result equals its render alone."""
+    say("server size classes")
+    srv = rcp.rcp_server_create(scene.handle, 512 << 20, max_inflight=1)
+    cam = scenegen.camera_look_at([0.3, 0.6, -1.3], [0, 0.05, 0], [0, 1, 0], 55.0)
+    d = rcp.make_displacement(0.0, 0.05)
+    reqs = [(cam, 2048, 2048, 5, d), (cam, 96, 64, 3, d), (cam, 130, 70, 6, d)]
+    tickets = [rcp.rcp_submit(srv, c, W, H, K, dd, with_ids=True) for (c, W, H, K, dd) in reqs]
+    wait_done(srv, tickets)
+    assert rcp.rcp_server_stats(srv)["launches"] == 2
+    starts = [rcp.rcp_poll(srv, t)[1][1] for t in tickets]
+    assert starts[0] < starts[1] == starts[2]
+    check_against_alone(scene, srv, reqs, tickets)
+    rcp.rcp_server_destroy(srv)
+
+
 def test_mixed_modes_equal_alone(scene):
     say("server mixed modes")
     srv = rcp.rcp_server_create(scene.handle, 64 << 20, max_inflight=2)
