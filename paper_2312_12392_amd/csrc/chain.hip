@@ -337,14 +337,15 @@ __device__ inline void setup_single(const ViewDev& v, ViewDev* table, uint32_t* 
 }
 
 // ---- Cost order of a single render's tiles -----------------------------------
-// A tile's score is the number of occupied cells of the scene's occupancy
-// grid that the undisplaced ray through its centre pixel crosses (a voxel
-// walk after Amanatides and Woo, "A Fast Voxel Traversal Algorithm for Ray
-// Tracing", Eurographics 1987).  Rays that skim many occupied cells tend to
-// start long chains; within each band the tiles are handed out by decreasing
-// score, so that those chains start first and the launch's tail, set by the
-// chains started last, gets shorter.  The order decides only when a pixel is
-// rendered, never its result.
+// A tile's score is the largest number of occupied cells of the scene's
+// occupancy grid that one of four undisplaced rays crosses, through the
+// centres of the tile's quadrants (a voxel walk after Amanatides and Woo, "A
+// Fast Voxel Traversal Algorithm for Ray Tracing", Eurographics 1987): a
+// tile's wave is as slow as its slowest lane.  Rays that skim many occupied
+// cells tend to start long chains; within each band the tiles are handed out
+// by decreasing score, so that those chains start first and the launch's
+// tail, set by the chains started last, gets shorter.  The order decides only
+// when a pixel is rendered, never its result.
 constexpr uint32_t kScoreBins = 256;
 
 constexpr uint32_t kScoreBlock = 256;
@@ -353,16 +354,16 @@ __global__ __launch_bounds__(kScoreBlock) void k_tile_scores(ViewDev v, OccGrid 
     extern __shared__ uint32_t occ[];
     for (uint32_t i = threadIdx.x; i < g.words; i += kScoreBlock) occ[i] = g.bits[i];
     __syncthreads();
-    const uint32_t t = blockIdx.x * kScoreBlock + threadIdx.x;
-    if (t >= n_tiles) return;
+    // four neighbouring threads per tile, one per quadrant; every thread
+    // reaches the shuffles at the end
+    const uint32_t gt = blockIdx.x * kScoreBlock + threadIdx.x;
+    const uint32_t t = gt >> 2, sub = gt & 3u;
     const uint32_t tw = 1u << (uint32_t)v.tile_log2w, th = 64u >> (uint32_t)v.tile_log2w;
-    int x0, y0, x, y;
-    tile_pixel(t << 6, (uint32_t)v.tiles_x, (uint32_t)v.tile_log2w, (uint32_t)v.super_log2, x0, y0);
-    if (x0 >= v.W || y0 >= v.H) {   // a padding tile beyond the image: no work
-        score[t] = 0u;
-        return;
-    }
-    tile_pixel((t << 6) + (th / 2u) * tw + tw / 2u, (uint32_t)v.tiles_x, (uint32_t)v.tile_log2w,
+    int x0 = 0, y0 = 0, x = 0, y = 0;
+    if (t < n_tiles) tile_pixel(t << 6, (uint32_t)v.tiles_x, (uint32_t)v.tile_log2w, (uint32_t)v.super_log2, x0, y0);
+    const bool live = t < n_tiles && x0 < v.W && y0 < v.H;
+    const uint32_t sx = (sub & 1u) ? (3u * tw) / 4u : tw / 4u, sy = (sub & 2u) ? (3u * th) / 4u : th / 4u;
+    tile_pixel((t << 6) + sy * tw + sx, (uint32_t)v.tiles_x, (uint32_t)v.tile_log2w,
                (uint32_t)v.super_log2, x, y);
     x = x < v.W ? x : v.W - 1;
     y = y < v.H ? y : v.H - 1;
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(kScoreBlock) void k_tile_scores(ViewDev v, OccGrid 
         }
     }
     uint32_t count = 0;
-    if (!miss && tmin <= tmax) {
+    if (live && !miss && tmin <= tmax) {
         // per axis: the next boundary's t, its spacing, the cell index stride
         // of a step and the steps left inside the grid
         float tnext[3], tdelta[3];
@@ -429,7 +430,9 @@ __global__ __launch_bounds__(kScoreBlock) void k_tile_scores(ViewDev v, OccGrid 
             left[2] -= az ? 1u : 0u;
         }
     }
-    score[t] = count;
+    count = max(count, (uint32_t)__shfl_xor((int)count, 1));
+    count = max(count, (uint32_t)__shfl_xor((int)count, 2));
+    if (sub == 0u && t < n_tiles) score[t] = count;
 }
 
 // One workgroup per band: a counting sort of the band's tiles by decreasing
@@ -643,7 +646,7 @@ rcp_status launch_one_view(rcp_scene* s, Workspace& w, const Launch& lp, const C
     if (s->tuning.tile_order && s->occ.bits && w.order && w.order_cap >= 2 * (size_t)n_tiles && n_tiles > 0) {
         // tile scores in the second half of the buffer, the order in the first
         uint32_t* score = w.order + n_tiles;
-        hipLaunchKernelGGL(k_tile_scores, dim3((n_tiles + kScoreBlock - 1) / kScoreBlock), dim3(kScoreBlock),
+        hipLaunchKernelGGL(k_tile_scores, dim3((4 * n_tiles + kScoreBlock - 1) / kScoreBlock), dim3(kScoreBlock),
                            sizeof(uint32_t) * s->occ.words, stream, view, s->occ, n_tiles, score);
         hipLaunchKernelGGL(k_band_order, dim3(kFetchParts + 1), dim3(1024), 0, stream, (const uint32_t*)score,
                            a.n_items, w.order, view, (ViewDev*)a.views, (uint32_t*)a.begin, w.counters, a.stats);
@@ -853,7 +856,7 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
     const Launch lpr = ordered1 ? launch_params(s, true) : lp;
     if (ordered1) {
         uint32_t* score = ws.order + n_tiles1;
-        hipLaunchKernelGGL(k_tile_scores, dim3((n_tiles1 + kScoreBlock - 1) / kScoreBlock), dim3(kScoreBlock),
+        hipLaunchKernelGGL(k_tile_scores, dim3((4 * n_tiles1 + kScoreBlock - 1) / kScoreBlock), dim3(kScoreBlock),
                            sizeof(uint32_t) * s->occ.words, stream, hv[0], s->occ, n_tiles1, score);
         hipLaunchKernelGGL(k_band_order, dim3(kFetchParts + 1), dim3(1024), 0, stream, (const uint32_t*)score,
                            groups[0].items, ws.order, hv[0], d_views, d_begin, ws.fetch,
