@@ -337,10 +337,11 @@ void rcp_graph_destroy(rcp_graph* graph);
  *   block_size     that kernel's workgroup size (256 or 512, default 256)
  *   tile_order     single renders of the chain engine (rcp_render,
  *                  rcp_render_stats, graphs): 1 (default) hands out each
- *                  band's tiles by decreasing estimated cost -- the occupied
- *                  cells of a coarse occupancy grid of the scene that the
- *                  undisplaced ray through the tile's centre crosses, found
- *                  by two small kernels before the launch -- so that long
+ *                  band's tiles by decreasing estimated cost -- the most
+ *                  occupied cells of a coarse occupancy grid of the scene
+ *                  that one of four undisplaced rays, through the centres of
+ *                  the tile's quadrants, crosses, found by two small kernels
+ *                  before the launch -- so that long
  *                  chains start first; 0 in screen order.  A batch of one
  *                  view follows it too (a server slot only up to 2^18
  *                  tiles); batches of more views and rcp_render_noalloc
