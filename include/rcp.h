@@ -220,14 +220,18 @@ rcp_status rcp_render(rcp_scene* scene, const rcp_camera* base_camera, int W, in
 /* rcp_render for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation.
  * Same arguments, validation and results as rcp_render (always the chain
- * engine, tiles in screen order); the call allocates nothing.  Its working memory (the launch's
- * view table, work counters and traversal stack overflow) is a fixed area of
- * rcp_render_noalloc_scratch_bytes() = 64 MiB inside the library's device
- * code, one per GPU, held until the process ends.  The launch uses as many
+ * engine); the call allocates nothing.  Its working memory (the launch's
+ * view table, work counters, tile scores and order, and traversal stack
+ * overflow) is a fixed area of rcp_render_noalloc_scratch_bytes() = 64 MiB
+ * inside the library's device code, one per GPU, held until the process
+ * ends.  Views of up to 2^16 tiles of 64 pixels (1440p and below) are
+ * rendered in the cost order of the tile_order tuning, larger ones in screen
+ * order (the order changes the speed only).  The launch uses as many
  * persistent workgroups as that area's overflow part holds for the scene's
- * tree (at most the occupancy limit, reached by trees of up to 18 inner
+ * tree (at most the occupancy limit, reached by trees of up to 15 inner
  * levels; the count changes the speed only); RCP_ERR_INVALID_ARGUMENT if it
- * cannot hold one workgroup per compute unit (a tree over 89 levels deep).  All calls on one GPU share the area
+ * cannot hold one workgroup per compute unit (a tree over 85 levels deep).
+ * All calls on one GPU share the area
  * and leave their contents in it: calls that overlap on one GPU (other
  * streams or threads) race and must be serialised by the caller.
  * Asynchronous on hip_stream. */
@@ -344,8 +348,8 @@ void rcp_graph_destroy(rcp_graph* graph);
  *                  before the launch -- so that long
  *                  chains start first; 0 in screen order.  A batch of one
  *                  view follows it too (a server slot only up to 2^18
- *                  tiles); batches of more views and rcp_render_noalloc
- *                  always use the screen order.
+ *                  tiles, rcp_render_noalloc up to 2^16); batches of more
+ *                  views always use the screen order.
  * The instrumented kernel and the depth and normal modes always use 16
  * stack entries and workgroups of 256. */
 #define RCP_ENGINE_CHAIN 0

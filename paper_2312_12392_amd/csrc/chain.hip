@@ -686,7 +686,10 @@ rcp_status render_chain(rcp_scene* s, Workspace& w, const Camera& cam, int W, in
 
 rcp_status render_chain_fixed(rcp_scene* s, Workspace& w, const Camera& cam, int W, int H, int K,
                               const Disp& disp, float* out_images, int32_t* out_ids, hipStream_t stream) {
-    const Launch lp = launch_params(s);
+    // the cost order where the workspace's order area holds the view's tiles
+    const bool ordered = chain_ordered(s) && w.order &&
+                         w.order_cap >= order_entries(W, H, launch_params(s, true).tile_log2w);
+    const Launch lp = launch_params(s, ordered);
     ChainGrid g;
     rcp_status st = chain_grid(lp, false, 1, disp.mode, g);
     if (st != RCP_OK) return st;

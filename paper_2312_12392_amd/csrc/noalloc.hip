@@ -14,6 +14,9 @@
 //   [0, kViewBytes)               the one-entry view table of the launch
 //   [kCountersOfs, +kCountersBytes) band counters (zeroed by the setup kernel
 //                                 of every call)
+//   [kOrderOfs, +kOrderBytes)     tile scores and the cost order of views of
+//                                 up to kOrderTiles tiles (written before each
+//                                 launch; larger views take the screen order)
 //   [kSpillOfs, kScratchBytes)    traversal stack overflow, one column per
 //                                 thread of the grid
 // Every call on a GPU shares that GPU's array and leaves its contents behind:
@@ -28,7 +31,10 @@ namespace {
 constexpr size_t kScratchBytes = size_t(64) << 20;   // 64 MiB per GPU
 constexpr size_t kCountersOfs = 4096;
 constexpr size_t kCountersBytes = 4096;
-constexpr size_t kSpillOfs = kCountersOfs + kCountersBytes;
+constexpr size_t kOrderOfs = kCountersOfs + kCountersBytes;
+constexpr size_t kOrderTiles = size_t(1) << 16;   // 1080p and 1440p frames, with their padding
+constexpr size_t kOrderBytes = 2 * kOrderTiles * sizeof(uint32_t);
+constexpr size_t kSpillOfs = kOrderOfs + kOrderBytes;
 
 static_assert(kViewBytes <= kCountersOfs, "the view table fits before the counters");
 
@@ -75,6 +81,8 @@ rcp_status render_noalloc(rcp_scene* s, const Camera& cam, int W, int H, int K, 
     w.external = true;
     w.view = base;
     w.counters = (uint32_t*)((char*)base + kCountersOfs);
+    w.order = (uint32_t*)((char*)base + kOrderOfs);
+    w.order_cap = kOrderBytes / sizeof(uint32_t);
     w.spill = (int32_t*)((char*)base + kSpillOfs);
     w.spill_cap = (kScratchBytes - kSpillOfs) / sizeof(int32_t);
     return render_chain_fixed(s, w, cam, W, H, K, disp, out_images, out_ids, stream);

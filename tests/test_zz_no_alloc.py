@@ -84,3 +84,16 @@ def test_noalloc_rejects_invalid_arguments():
     with pytest.raises(rcp.RcpError):
         rcp.rcp_render_noalloc(0, w.camera, 8, 8, 2, d, out)
     s.close()
+
+
+def test_noalloc_beyond_the_order_area_then_within():
+    """A view of more than 2^16 tiles (screen order: the scratch's order area
+    holds 2^16), then a smaller one (cost order), each equal to rcp_render."""
+    sc = scenegen.terrain_patch(12, 40, 20)
+    s = rcp.Scene(sc)
+    d = rcp.make_displacement(0.01, 0.05)
+    for (W, H, K) in [(2600, 1800, 2), (1920, 1080, 2)]:
+        say("noalloc order area", W, H, K)
+        a, ai, b, bi = both(s, PATCH_CAM, W, H, K, d)
+        assert torch.equal(a, b) and torch.equal(ai, bi), (W, H, K)
+    s.close()
