@@ -341,11 +341,13 @@ __device__ inline void setup_single(const ViewDev& v, ViewDev* table, uint32_t* 
 // occupancy grid that one of four undisplaced rays crosses, through the
 // centres of the tile's quadrants (a voxel walk after Amanatides and Woo, "A
 // Fast Voxel Traversal Algorithm for Ray Tracing", Eurographics 1987): a
-// tile's wave is as slow as its slowest lane.  Rays that skim many occupied
-// cells tend to start long chains; within each band the tiles are handed out
-// by decreasing score, so that those chains start first and the launch's
-// tail, set by the chains started last, gets shorter.  The order decides only
-// when a pixel is rendered, never its result.
+// tile's wave is as slow as its slowest lane.  Each ray's segment inside the
+// grid is walked in two halves by two threads, which halves the longest walk,
+// the one that sets the kernel's time.  Rays that skim many occupied cells
+// tend to start long chains; within each band the tiles are handed out by
+// decreasing score, so that those chains start first and the launch's tail,
+// set by the chains started last, gets shorter.  The order decides only when
+// a pixel is rendered, never its result.
 constexpr uint32_t kScoreBins = 256;
 
 constexpr uint32_t kScoreBlock = 256;
@@ -354,10 +356,11 @@ __global__ __launch_bounds__(kScoreBlock) void k_tile_scores(ViewDev v, OccGrid 
     extern __shared__ uint32_t occ[];
     for (uint32_t i = threadIdx.x; i < g.words; i += kScoreBlock) occ[i] = g.bits[i];
     __syncthreads();
-    // four neighbouring threads per tile, one per quadrant; every thread
-    // reaches the shuffles at the end
+    // eight neighbouring threads per tile: the quadrant in the low two bits,
+    // the half of the ray's walk in the third; every thread reaches the
+    // shuffles at the end
     const uint32_t gt = blockIdx.x * kScoreBlock + threadIdx.x;
-    const uint32_t t = gt >> 2, sub = gt & 3u;
+    const uint32_t t = gt >> 3, sub = gt & 3u, half = (gt >> 2) & 1u;
     const uint32_t tw = 1u << (uint32_t)v.tile_log2w, th = 64u >> (uint32_t)v.tile_log2w;
     int x0 = 0, y0 = 0, x = 0, y = 0;
     if (t < n_tiles) tile_pixel(t << 6, (uint32_t)v.tiles_x, (uint32_t)v.tile_log2w, (uint32_t)v.super_log2, x0, y0);
@@ -389,6 +392,8 @@ __global__ __launch_bounds__(kScoreBlock) void k_tile_scores(ViewDev v, OccGrid 
     }
     uint32_t count = 0;
     if (live && !miss && tmin <= tmax) {
+        const float tmid = 0.5f * (tmin + tmax);
+        const float tbeg = half ? tmid : tmin, tend = half ? tmax : tmid;
         // per axis: the next boundary's t, its spacing, the cell index stride
         // of a step and the steps left inside the grid
         float tnext[3], tdelta[3];
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(kScoreBlock) void k_tile_scores(ViewDev v, OccGrid 
         int cell = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const float p = o[a] + tmin * d[a];
+            const float p = o[a] + tbeg * d[a];
             int q = (int)floorf((p - g.lo[a]) / g.cell[a]);
             q = q < 0 ? 0 : (q >= g.n[a] ? g.n[a] - 1 : q);
             const int step = d[a] > 0.0f ? 1 : (d[a] < 0.0f ? -1 : 0);
@@ -411,16 +416,17 @@ __global__ __launch_bounds__(kScoreBlock) void k_tile_scores(ViewDev v, OccGrid 
         }
         // one step per iteration, without branches: the axis whose boundary
         // comes first (x, then y, then z among equal ones); the walk ends past
-        // tmax or at the grid's side
+        // tend or at the grid's side.  The second half's first cell is the
+        // first half's last, counted there.
         const int steps = g.n[0] + g.n[1] + g.n[2];
         for (int it = 0; it < steps; ++it) {
-            count += (occ[(uint32_t)cell >> 5] >> ((uint32_t)cell & 31u)) & 1u;
+            count += (it > 0 || half == 0u) ? (occ[(uint32_t)cell >> 5] >> ((uint32_t)cell & 31u)) & 1u : 0u;
             const bool ax = tnext[0] <= tnext[1] && tnext[0] <= tnext[2];
             const bool ay = !ax && tnext[1] <= tnext[2];
             const bool az = !ax && !ay;
             const float tn = ax ? tnext[0] : (ay ? tnext[1] : tnext[2]);
             const uint32_t l = ax ? left[0] : (ay ? left[1] : left[2]);
-            if (tn > tmax || l == 0u) break;
+            if (tn > tend || l == 0u) break;
             cell += ax ? stride[0] : (ay ? stride[1] : stride[2]);
             tnext[0] += ax ? tdelta[0] : 0.0f;
             tnext[1] += ay ? tdelta[1] : 0.0f;
@@ -430,9 +436,10 @@ __global__ __launch_bounds__(kScoreBlock) void k_tile_scores(ViewDev v, OccGrid 
             left[2] -= az ? 1u : 0u;
         }
     }
+    count += (uint32_t)__shfl_xor((int)count, 4);   // the ray's two halves
     count = max(count, (uint32_t)__shfl_xor((int)count, 1));
     count = max(count, (uint32_t)__shfl_xor((int)count, 2));
-    if (sub == 0u && t < n_tiles) score[t] = count;
+    if (sub == 0u && half == 0u && t < n_tiles) score[t] = count;
 }
 
 // One workgroup per band: a counting sort of the band's tiles by decreasing
@@ -646,7 +653,7 @@ rcp_status launch_one_view(rcp_scene* s, Workspace& w, const Launch& lp, const C
     if (s->tuning.tile_order && s->occ.bits && w.order && w.order_cap >= 2 * (size_t)n_tiles && n_tiles > 0) {
         // tile scores in the second half of the buffer, the order in the first
         uint32_t* score = w.order + n_tiles;
-        hipLaunchKernelGGL(k_tile_scores, dim3((4 * n_tiles + kScoreBlock - 1) / kScoreBlock), dim3(kScoreBlock),
+        hipLaunchKernelGGL(k_tile_scores, dim3((8 * n_tiles + kScoreBlock - 1) / kScoreBlock), dim3(kScoreBlock),
                            sizeof(uint32_t) * s->occ.words, stream, view, s->occ, n_tiles, score);
         hipLaunchKernelGGL(k_band_order, dim3(kFetchParts + 1), dim3(1024), 0, stream, (const uint32_t*)score,
                            a.n_items, w.order, view, (ViewDev*)a.views, (uint32_t*)a.begin, w.counters, a.stats);
@@ -859,7 +866,7 @@ rcp_status render_batch(rcp_scene* s, const rcp_view* views, int n_views, BatchW
     const Launch lpr = ordered1 ? launch_params(s, true) : lp;
     if (ordered1) {
         uint32_t* score = ws.order + n_tiles1;
-        hipLaunchKernelGGL(k_tile_scores, dim3((4 * n_tiles1 + kScoreBlock - 1) / kScoreBlock), dim3(kScoreBlock),
+        hipLaunchKernelGGL(k_tile_scores, dim3((8 * n_tiles1 + kScoreBlock - 1) / kScoreBlock), dim3(kScoreBlock),
                            sizeof(uint32_t) * s->occ.words, stream, hv[0], s->occ, n_tiles1, score);
         hipLaunchKernelGGL(k_band_order, dim3(kFetchParts + 1), dim3(1024), 0, stream, (const uint32_t*)score,
                            groups[0].items, ws.order, hv[0], d_views, d_begin, ws.fetch,
